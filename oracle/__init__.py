@@ -1,0 +1,1 @@
+"""Plain sequential FP64 CPU oracle -- test infrastructure only (see oracle.py)."""

@@ -1,0 +1,636 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a literal
+transcription of the paper's set-based algorithm, a dense textbook operator,
+a closed form, an exact rational solve or a library routine used on a
+*different* formulation.  CPU only.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import oracle as O
+from paper_2208_08594_amd import synth
+
+
+# --------------------------------------------------------------------------
+# helpers
+# --------------------------------------------------------------------------
+def csr_from_dense_pattern(P):
+    P = np.asarray(P, dtype=bool)
+    n = P.shape[0]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(P.sum(1))
+    ci = np.nonzero(P)[1].astype(np.int32)
+    return rp, ci
+
+
+def sym_adjacency(rp, ci):
+    n = len(rp) - 1
+    S = [set() for _ in range(n)]
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            j = int(ci[k])
+            if j != i:
+                S[i].add(j)
+                S[j].add(i)
+    return S
+
+
+def literal_grouping(n, S):
+    """Alg. 4.2 around Alg. 4.1 written with Python sets, line by line, with the
+    paper's else-branch.  'Undetermined' = not yet placed in any group; the
+    second-ring candidates therefore may include vertices already pushed to
+    W-bar, which the else-branch discards."""
+    deg = [len(S[i]) for i in range(n)]
+    key = lambda v: (-deg[v], v)
+    assigned = set()
+    Vcur = set(range(n))
+    groups = []
+    while Vcur:
+        Vin = set(Vcur)
+        V = set(Vcur)
+        W, Wbar, What = set(), set(), set()
+        while V:
+            i = min(What, key=key) if What else min(V, key=key)
+            if not (S[i] & W):
+                W.add(i)
+                V.discard(i)
+                What.discard(i)
+                Wbar |= (S[i] & Vin)
+                V -= S[i]
+                second = set()
+                for k in S[i]:
+                    second |= S[k]
+                second -= S[i] | {i}
+                What |= {j for j in second if j not in assigned and j not in W}
+            else:
+                Wbar.add(i)
+                V.discard(i)
+                What.discard(i)
+        groups.append(W)
+        assigned |= W
+        Vcur = Wbar - W
+    return groups
+
+
+def dense_from_csr(rp, ci, val, n=None):
+    n = n or len(rp) - 1
+    A = np.zeros((n, n))
+    for i in range(len(rp) - 1):
+        A[i, ci[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    return A
+
+
+def bsr_b1(rp, ci, val):
+    return val.reshape(-1, 1, 1)
+
+
+def random_pattern(n, density, seed, symmetric):
+    rng = np.random.default_rng(seed)
+    P = rng.random((n, n)) < density
+    if symmetric:
+        P = P | P.T
+    np.fill_diagonal(P, True)
+    return csr_from_dense_pattern(P)
+
+
+# --------------------------------------------------------------------------
+# generator
+# --------------------------------------------------------------------------
+def test_generator_is_seeded_and_well_formed():
+    a = synth.config(0, seed=3)
+    b = synth.config(0, seed=3)
+    c = synth.config(0, seed=4)
+    assert np.array_equal(a.vals, b.vals) and np.array_equal(a.rhs, b.rhs)
+    assert not np.array_equal(a.vals, c.vals)
+    assert a.n == 1000 and a.N == 4000 and a.nnzb == 6400
+    assert O.validate(a.n, a.b, a.p, a.row_ptr, a.col_ind, a.vals) == 0
+    for w in a.wells:
+        blk = a.vals[a.diag_pos[w]]
+        assert np.array_equal(blk[a.p], np.eye(a.b)[a.p])
+
+
+# --------------------------------------------------------------------------
+# O4: VerticesGrouping (Alg. 4.1/4.2) -- pins P2, P3, P4
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_coloring_matches_literal_algorithm(seed, symmetric):
+    n = 20 + 7 * seed
+    rp, ci = random_pattern(n, 0.08 + 0.01 * (seed % 4), seed, symmetric)
+    col, g = O.color(rp, ci)
+    groups = literal_grouping(n, sym_adjacency(rp, ci))
+    lit = np.zeros(n, dtype=np.int32)
+    for gi, W in enumerate(groups):
+        for v in W:
+            lit[v] = gi + 1
+    assert g == len(groups)
+    assert np.array_equal(col, lit)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_coloring_principles(seed):
+    """(i) cover, (ii) disjoint, (iii) no edge inside a group (a_ij = a_ji = 0),
+    and every group is a maximal independent set of what was left."""
+    n = 150
+    rp, ci = random_pattern(n, 0.03, 100 + seed, symmetric=False)
+    col, g = O.color(rp, ci)
+    S = sym_adjacency(rp, ci)
+    assert col.min() == 1 and col.max() == g
+    for i in range(n):
+        for j in S[i]:
+            assert col[i] != col[j]
+    for i in range(n):
+        for earlier in range(1, col[i]):
+            assert any(col[j] == earlier for j in S[i]), "group not maximal"
+
+
+@pytest.mark.parametrize("shape", [(10, 10, 10), (7, 5, 3), (64, 1, 1), (6, 9, 1), (64, 64, 4)])
+def test_coloring_seven_point_is_red_black(shape):
+    nx, ny, nz = shape
+    rp, ci, _ = synth.poisson_csr(shape)
+    col, g = O.color(rp, ci)
+    assert g == 2
+    c = np.arange(nx * ny * nz)
+    parity = (c % nx + (c // nx) % ny + c // (nx * ny)) % 2
+    # both colors are parity classes: red-black GS is the g = 2 case
+    assert len(set(zip(parity.tolist(), col.tolist()))) == 2
+
+
+def test_coloring_complete_graph_is_classical_gs():
+    n = 9
+    rp, ci = csr_from_dense_pattern(np.ones((n, n), bool))
+    col, g = O.color(rp, ci)
+    assert g == n and sorted(col.tolist()) == list(range(1, n + 1))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_color_submatrix_is_diagonal(seed):
+    rp, ci = random_pattern(60, 0.07, 200 + seed, symmetric=False)
+    col, g = O.color(rp, ci)
+    A = dense_from_csr(rp, ci, np.ones(len(ci)))
+    for l in range(1, g + 1):
+        idx = np.nonzero(col == l)[0]
+        sub = A[np.ix_(idx, idx)]
+        assert np.count_nonzero(sub - np.diag(np.diag(sub))) == 0
+
+
+# --------------------------------------------------------------------------
+# O10 sweep -- pin P5
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(4))
+def test_gs_sweep_is_dense_triangular_solve(seed):
+    rng = np.random.default_rng(seed)
+    n = 80
+    rp, ci = random_pattern(n, 0.06, 300 + seed, symmetric=bool(seed % 2))
+    val = rng.uniform(-1, 1, len(ci))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    val[rows == ci] = 8.0 + rng.random(n)
+    col, g = O.color(rp, ci)
+    A = dense_from_csr(rp, ci, val)
+    f = rng.uniform(-1, 1, n)
+    x0 = rng.uniform(-1, 1, n)
+    perm = np.argsort(col, kind="stable")
+    Ap = A[np.ix_(perm, perm)]
+    L = np.tril(Ap, -1)
+    U = np.triu(Ap, 1)
+    D = np.diag(np.diag(Ap))
+    fwd = scipy.linalg.solve_triangular(D + L, f[perm] - U @ x0[perm], lower=True)
+    bwd = scipy.linalg.solve_triangular(D + U, f[perm] - L @ x0[perm], lower=False)
+    xf = O.gs_sweep(rp, ci, val, col, g, f, x0, forward=True)
+    xb = O.gs_sweep(rp, ci, val, col, g, f, x0, forward=False)
+    np.testing.assert_allclose(xf[perm], fwd, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(xb[perm], bwd, rtol=1e-12, atol=1e-13)
+
+
+def test_gs_sweep_rows_independent_inside_color():
+    """Inside one color rows do not see each other (Alg. 4.3 runs them in
+    parallel): updating all rows of a color at once from the values left by
+    the previous colors gives the sequential sweep."""
+    rng = np.random.default_rng(5)
+    rp, ci = random_pattern(90, 0.05, 77, symmetric=False)
+    n = len(rp) - 1
+    val = rng.uniform(-1, 1, len(ci))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    val[rows == ci] = 6.0 + rng.random(n)
+    col, g = O.color(rp, ci)
+    A = dense_from_csr(rp, ci, val)
+    f = rng.uniform(-1, 1, n)
+    x0 = rng.uniform(-1, 1, n)
+    d = np.diag(A)
+    off = A - np.diag(d)
+    x = x0.copy()
+    for l in range(1, g + 1):
+        idx = col == l
+        x[idx] = (f[idx] - off[idx] @ x) / d[idx]
+    np.testing.assert_allclose(O.gs_sweep(rp, ci, val, col, g, f, x0), x, rtol=1e-14, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# O5/O6: aggregation and Galerkin -- pin P7 and invariants
+# --------------------------------------------------------------------------
+def _decoupled_level0(sys):
+    om, ap = O.decouple(sys.n, sys.b, sys.p, sys.row_ptr, sys.col_ind, sys.vals)
+    return sys.row_ptr, sys.col_ind, ap
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_npair_invariants(seed):
+    sys = synth.lognormal_grid(9, 8, 5, 3, seed, 1.5, 0.1, "lateral4")
+    rp, ci, ap = _decoupled_level0(sys)
+    agg, nc = O.npair_pass(rp, ci, ap)
+    n = sys.n
+    sizes = np.bincount(agg, minlength=nc)
+    assert sizes.min() >= 1 and sizes.max() <= 2 and sizes.sum() == n
+    # aggregates numbered in order of creation = order of their first vertex
+    first = np.array([np.min(np.nonzero(agg == a)[0]) for a in range(nc)])
+    assert np.all(np.diff(first) > 0)
+    A = dense_from_csr(rp, ci, ap)
+    S = -(A + A.T) / 2
+    np.fill_diagonal(S, -np.inf)
+    for w in sys.wells:
+        assert sizes[agg[w]] == 1, "Dirichlet rows stay single"
+    for a in range(nc):
+        mem = np.nonzero(agg == a)[0]
+        if len(mem) == 2:
+            i, j = mem
+            smax = S[i][np.isfinite(S[i]) & (A[i] != 0) | (A[:, i] != 0)].max()
+            assert S[i, j] > 0 and S[i, j] >= 0.25 * smax - 1e-15
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_galerkin_is_dense_ptap(seed):
+    sys = synth.lognormal_grid(7, 6, 4, 4, seed, 1.0, 1.0, "corners2")
+    rp, ci, ap = _decoupled_level0(sys)
+    agg, nc = O.npair_pass(rp, ci, ap)
+    crp, cci, cval = O.galerkin(rp, ci, ap, agg, nc)
+    P = np.zeros((sys.n, nc))
+    P[np.arange(sys.n), agg] = 1.0
+    A = dense_from_csr(rp, ci, ap)
+    Ac = P.T @ A @ P
+    np.testing.assert_allclose(dense_from_csr(crp, cci, cval, nc), Ac, rtol=1e-13, atol=1e-14)
+    # structural pattern: (I,J) stored iff some stored (i,j) maps onto it
+    S0 = dense_from_csr(rp, ci, np.ones(len(ci)))
+    pat = (P.T @ S0 @ P) > 0
+    stored = dense_from_csr(crp, cci, np.ones(len(cci)), nc) > 0
+    assert np.array_equal(pat, stored)
+    for I in range(nc):
+        assert np.all(np.diff(cci[crp[I]:crp[I + 1]]) > 0)
+
+
+def test_hierarchy_levels_and_coarsest():
+    sys = synth.config(0)
+    s = O.OracleSolver(max_coarse=64)
+    s.setup(sys)
+    ns = [s.level(l)["n"] for l in range(s.nlevels)]
+    assert ns[0] == 1000 and ns[-1] <= 64 and all(a > b for a, b in zip(ns, ns[1:]))
+    for l in range(s.nlevels - 1):
+        L = s.level(l)
+        sizes = np.bincount(L["agg"], minlength=ns[l + 1])
+        assert sizes.min() >= 1 and sizes.max() <= 4
+
+
+# --------------------------------------------------------------------------
+# O2 decoupling -- pin P10
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [3, 4, 7])
+def test_abf_decoupling(b):
+    sys = synth.lognormal_grid(5, 4, 3, b, 11, 1.0, 1.0, "corners2")
+    om, ap = O.decouple(sys.n, sys.b, sys.p, sys.row_ptr, sys.col_ind, sys.vals)
+    for c in range(sys.n):
+        D = sys.vals[sys.diag_pos[c]]
+        np.testing.assert_allclose(om[c], np.linalg.inv(D)[sys.p], rtol=1e-12, atol=1e-14)
+        # w_c^T D_c = e_p^T: the decoupled diagonal block is the identity on row p
+        np.testing.assert_allclose(om[c] @ D, np.eye(b)[sys.p], atol=1e-14)
+    np.testing.assert_allclose(ap[sys.diag_pos], 1.0, rtol=1e-13)
+
+
+def test_abf_singular_block_is_reported():
+    sys = synth.lognormal_grid(3, 3, 1, 3, 0, 1.0, 1.0, "none")
+    vals = sys.vals.copy()
+    vals[sys.diag_pos[4]] = 0.0
+    with pytest.raises(O.OracleError) as e:
+        O.decouple(sys.n, sys.b, sys.p, sys.row_ptr, sys.col_ind, vals)
+    assert e.value.code == -3
+
+
+# --------------------------------------------------------------------------
+# O7 block ILU(0) -- pin P8
+# --------------------------------------------------------------------------
+def _dense_lu_from_factors(sys_rp, sys_ci, F, D, n, b):
+    L = np.eye(n * b)
+    U = np.zeros((n * b, n * b))
+    for i in range(n):
+        for k in range(sys_rp[i], sys_rp[i + 1]):
+            j = sys_ci[k]
+            if j < i:
+                L[i * b:(i + 1) * b, j * b:(j + 1) * b] = F[k]
+            elif j > i:
+                U[i * b:(i + 1) * b, j * b:(j + 1) * b] = F[k]
+        U[i * b:(i + 1) * b, i * b:(i + 1) * b] = np.linalg.inv(D[i])
+    return L, U
+
+
+@pytest.mark.parametrize("b", [1, 3, 4])
+def test_bilu0_defining_property(b):
+    sys = synth.lognormal_grid(5, 4, 3, b, 21, 1.0, 1.0, "corners2")
+    F, D = O.bilu0_factor(sys.n, b, sys.row_ptr, sys.col_ind, sys.vals)
+    L, U = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, F, D, sys.n, b)
+    LU = L @ U
+    A = sys.to_dense()
+    for i in range(sys.n):
+        for k in range(sys.row_ptr[i], sys.row_ptr[i + 1]):
+            j = sys.col_ind[k]
+            np.testing.assert_allclose(LU[i * b:(i + 1) * b, j * b:(j + 1) * b],
+                                       A[i * b:(i + 1) * b, j * b:(j + 1) * b],
+                                       rtol=1e-11, atol=1e-11)
+    r = np.random.default_rng(0).uniform(-1, 1, sys.N)
+    z = O.bilu0_solve(sys.n, b, sys.row_ptr, sys.col_ind, F, D, r)
+    np.testing.assert_allclose(LU @ z, r, rtol=1e-10, atol=1e-12)
+
+
+def test_bilu0_exact_on_block_tridiagonal_one_iteration():
+    """1-D grid: ILU(0) has no dropped fill, so LU = A and the preconditioner is
+    the exact inverse: FGMRES converges in one iteration (the paper's remark
+    that one iteration means an exact inverse)."""
+    sys = synth.lognormal_grid(40, 1, 1, 4, 2, 1.0, 1.0, "corners2")
+    F, D = O.bilu0_factor(sys.n, sys.b, sys.row_ptr, sys.col_ind, sys.vals)
+    L, U = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, F, D, sys.n, sys.b)
+    np.testing.assert_allclose(L @ U, sys.to_dense(), rtol=1e-12, atol=1e-10)
+    s = O.OracleSolver(max_coarse=8)
+    s.setup(sys)
+    x, it, rr, st = s.solve(sys.rhs, 1e-10)
+    assert it == 1 and rr <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# O9 apply -- pins P1, P9 (Alg. 3.1 and eq. MSP)
+# --------------------------------------------------------------------------
+def _dense_operator(fn, n):
+    return np.stack([fn(np.eye(n)[:, j]) for j in range(n)], axis=1)
+
+
+@pytest.mark.parametrize("max_coarse", [10000, 4])
+def test_reduced_apply_equals_literal_alg31(max_coarse):
+    sys = synth.lognormal_grid(3, 3, 2, 3, 7, 1.0, 1.0, [0])
+    n, b, p, N = sys.n, sys.b, sys.p, sys.N
+    s = O.OracleSolver(max_coarse=max_coarse)
+    s.setup(sys)
+    A = sys.to_dense()
+    W = np.zeros((N, N))
+    for c in range(n):
+        W[c * b:(c + 1) * b, c * b:(c + 1) * b] = np.linalg.inv(sys.vals[sys.diag_pos[c]])
+    Ah = W @ A
+    PiP = np.zeros((N, n))
+    PiP[np.arange(n) * b + p, np.arange(n)] = 1.0
+    # pressure block of the decoupled system is the oracle's level-0 matrix
+    L0 = s.level(0)
+    np.testing.assert_allclose(dense_from_csr(L0["row_ptr"], L0["col_ind"], L0["val"]),
+                               PiP.T @ Ah @ PiP, rtol=1e-12, atol=1e-13)
+    BP = _dense_operator(s.vcycle, n)
+    # R = (ILU0(W A))^{-1}: factor the decoupled blocks (a different input)
+    vals_hat = np.stack([np.linalg.inv(sys.vals[sys.diag_pos[c]]) @ sys.vals[k]
+                         for c in range(n) for k in range(sys.row_ptr[c], sys.row_ptr[c + 1])])
+    Fh, Dh = O.bilu0_factor(n, b, sys.row_ptr, sys.col_ind, vals_hat)
+    Lh, Uh = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, Fh, Dh, n, b)
+    R = np.linalg.inv(Lh @ Uh)
+    # Alg. 3.1 with w = 0, stages P then R: the operator on g
+    I = np.eye(N)
+    Bg = PiP @ BP @ PiP.T + R @ (I - Ah @ PiP @ BP @ PiP.T)
+    # eq. MSP: I - B A = (I - R A)(I - Pi_P B_P Pi_P^T A)
+    np.testing.assert_allclose(I - Bg @ Ah, (I - R @ Ah) @ (I - PiP @ BP @ PiP.T @ Ah),
+                               atol=1e-10)
+    Bor = _dense_operator(s.apply, N)
+    np.testing.assert_allclose(Bor, Bg @ W, rtol=1e-9, atol=1e-11)
+    if max_coarse >= n:
+        # single level: B_P is the exact inverse of the pressure block
+        np.testing.assert_allclose(BP @ (PiP.T @ Ah @ PiP), np.eye(n), atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# O10 V-cycle -- pin P6
+# --------------------------------------------------------------------------
+def _vcycle_dense(levels, l, coarse_inv):
+    L = levels[l]
+    n = L["n"]
+    A = dense_from_csr(L["row_ptr"], L["col_ind"], L["val"])
+    if L["color"] is None:
+        return coarse_inv
+    perm = np.argsort(L["color"], kind="stable")
+    inv = np.argsort(perm)
+    Ap = A[np.ix_(perm, perm)]
+    Mf = np.tril(Ap)
+    Mb = np.triu(Ap)
+    # M^{-1} in natural numbering
+    Mf_inv = np.linalg.inv(Mf)[np.ix_(inv, inv)]
+    Mb_inv = np.linalg.inv(Mb)[np.ix_(inv, inv)]
+    P = np.zeros((n, L["nc"]))
+    P[np.arange(n), L["agg"]] = 1.0
+    Bc = _vcycle_dense(levels, l + 1, coarse_inv)
+    I = np.eye(n)
+    X1 = Mf_inv
+    X2 = X1 + P @ Bc @ P.T @ (I - A @ X1)
+    X3 = X2 + Mb_inv @ (I - A @ X2)
+    return X3
+
+
+@pytest.mark.parametrize("shape,max_coarse", [((64,), 20), ((64,), 4), ((8, 8, 8), 40), ((6, 6, 6), 10)])
+def test_vcycle_is_textbook_multigrid(shape, max_coarse):
+    rp, ci, val = synth.poisson_csr(shape)
+    n = len(rp) - 1
+    s = O.OracleSolver(max_coarse=max_coarse)
+    s.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=bsr_b1(rp, ci, val))
+    levels = [s.level(l) for l in range(s.nlevels)]
+    assert s.nlevels >= 2
+    Lc = levels[-1]
+    coarse_inv = np.linalg.inv(dense_from_csr(Lc["row_ptr"], Lc["col_ind"], Lc["val"]))
+    Bd = _vcycle_dense(levels, 0, coarse_inv)
+    Bo = _dense_operator(s.vcycle, n)
+    np.testing.assert_allclose(Bo, Bd, rtol=1e-10, atol=1e-12)
+    A0 = dense_from_csr(levels[0]["row_ptr"], levels[0]["col_ind"], levels[0]["val"])
+    E = np.eye(n) - Bo @ A0
+    rho = max(abs(np.linalg.eigvals(E)))
+    assert rho < 1.0
+    # the stationary iteration x <- x + V(f - A x) contracts at rate rho
+    rng = np.random.default_rng(1)
+    e = rng.uniform(-1, 1, n)
+    for _ in range(60):
+        e = E @ e
+    e2 = E @ e
+    rate = np.linalg.norm(e2) / np.linalg.norm(e)
+    assert rate <= rho * 1.05 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# O8 coarse direct solve -- pin P11 (exact rational arithmetic)
+# --------------------------------------------------------------------------
+def _exact_solve(A, f):
+    n = len(A)
+    M = [[Fraction(int(A[i][j])) for j in range(n)] + [Fraction(int(f[i]))] for i in range(n)]
+    for k in range(n):
+        piv = next(r for r in range(k, n) if M[r][k] != 0)
+        M[k], M[piv] = M[piv], M[k]
+        for r in range(n):
+            if r != k and M[r][k] != 0:
+                fac = M[r][k] / M[k][k]
+                M[r] = [a - fac * b for a, b in zip(M[r], M[k])]
+    return [float(M[i][n] / M[i][i]) for i in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_coarse_lu_solve_exact(seed):
+    rng = np.random.default_rng(seed)
+    n = 7
+    A = rng.integers(-9, 10, size=(n, n)).astype(float)
+    A[0, 0] = 0.0  # forces a row interchange
+    while abs(np.linalg.det(A)) < 1:
+        A = rng.integers(-9, 10, size=(n, n)).astype(float)
+    f = rng.integers(-9, 10, size=n).astype(float)
+    lu, piv = O.lu_factor(A)
+    x = O.lu_solve(lu, piv, f)
+    np.testing.assert_allclose(x, _exact_solve(A, f), rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# O11 FGMRES -- pins P12, P13
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("max_coarse", [10000, 64])
+def test_fgmres_matches_dense_solve(max_coarse):
+    sys = synth.config(0)
+    s = O.OracleSolver(max_coarse=max_coarse)
+    s.setup(sys)
+    x, it, rr, st = s.solve(sys.rhs, 1e-6)
+    A = sys.to_dense()
+    xd = np.linalg.solve(A, sys.rhs)
+    kappa = np.linalg.cond(A)
+    assert st == 0 and 1 <= it <= 30
+    true_rr = np.linalg.norm(sys.rhs - A @ x) / np.linalg.norm(sys.rhs)
+    assert true_rr <= 1e-6 and abs(true_rr - rr) <= 1e-12
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= kappa * 1e-6
+
+
+def test_exact_pressure_stage_one_iteration():
+    """b = 1 and a single AMG level: the pressure stage is an exact solve and
+    FGMRES stops after one iteration."""
+    rp, ci, val = synth.poisson_csr((9, 7, 5))
+    n = len(rp) - 1
+    rhs = np.random.default_rng(2).uniform(-1, 1, n)
+    s = O.OracleSolver(max_coarse=10000)
+    s.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=bsr_b1(rp, ci, val))
+    x, it, rr, st = s.solve(rhs, 1e-10)
+    assert it == 1 and rr < 1e-10
+
+
+def test_zero_rhs_gives_zero_solution_without_iterations():
+    sys = synth.config(0)
+    s = O.OracleSolver()
+    s.setup(sys)
+    x, it, rr, st = s.solve(np.zeros(sys.N), 1e-6, x0=np.ones(sys.N))
+    assert it == 0 and np.count_nonzero(x) == 0
+
+
+def test_max_iter_reports_not_converged():
+    sys = synth.config(0)
+    s = O.OracleSolver(max_iter=2, max_coarse=64)
+    s.setup(sys)
+    x, it, rr, st = s.solve(sys.rhs, 1e-14)
+    assert st == 1 and it == 2 and rr > 1e-14
+
+
+def test_fp32_preconditioner_converges_like_fp64():
+    sys = synth.config(0)
+    r64 = O.OracleSolver(max_coarse=64)
+    r64.setup(sys)
+    x64, it64, rr64, _ = r64.solve(sys.rhs, 1e-6)
+    r32 = O.OracleSolver(max_coarse=64, precond_fp32=True)
+    r32.setup(sys)
+    x32, it32, rr32, _ = r32.solve(sys.rhs, 1e-6)
+    assert abs(it32 - it64) <= 1 and rr32 <= 1e-6
+    v = np.random.default_rng(0).uniform(-1, 1, sys.N)
+    z64, z32 = r64.apply(v), r32.apply(v)
+    rel = np.linalg.norm(z64 - z32) / np.linalg.norm(z64)
+    assert 1e-9 < rel < 1e-4  # FP32 rounding, not a different operator
+
+
+# --------------------------------------------------------------------------
+# O12 adaptive SETUP -- pin P14 (Sec. 3.2; mu = 0 is standard MSP)
+# --------------------------------------------------------------------------
+def _newton_sequence(sys, steps):
+    out = [sys]
+    for t in range(1, steps):
+        out.append(synth.newton_step(sys, t, 77))
+    return out
+
+
+def test_adaptive_setup_rules():
+    sys = synth.lognormal_grid(6, 6, 4, 3, 9, 1.0, 1.0, "corners2")
+    seq = _newton_sequence(sys, 4)
+    # mu = 0: every system regenerates the preconditioner (SetupCalls = NumNSteps)
+    s0 = O.OracleSolver(mu=0, max_coarse=16)
+    its = []
+    for t, A in enumerate(seq):
+        assert s0.setup(A) is True
+        its.append(s0.solve(A.rhs, 1e-6)[1])
+    assert s0.setup_calls == len(seq)
+    # large mu: only the first system builds B; the others reuse it
+    sb = O.OracleSolver(mu=1000, max_coarse=16)
+    flags = []
+    for A in seq:
+        flags.append(sb.setup(A))
+        x, it, rr, st = sb.solve(A.rhs, 1e-6)
+        assert rr <= 1e-6
+    assert flags == [True, False, False, False] and sb.setup_calls == 1
+    # mu = It - 1 forces a rebuild, mu = It reuses
+    it0 = its[0]
+    for mu, expect in [(it0 - 1, True), (it0, False)]:
+        s = O.OracleSolver(mu=mu, max_coarse=16)
+        s.setup(seq[0])
+        assert s.solve(seq[0].rhs, 1e-6)[1] == it0
+        assert s.setup(seq[1]) is expect
+    # a size change always regenerates (the remark of Sec. 3.2)
+    s = O.OracleSolver(mu=1000, max_coarse=16)
+    s.setup(seq[0])
+    s.solve(seq[0].rhs, 1e-6)
+    other = synth.lognormal_grid(5, 6, 4, 3, 9, 1.0, 1.0, "corners2")
+    assert s.setup(other) is True and s.setup_calls == 2
+
+
+def test_reuse_uses_current_matrix_for_krylov():
+    """On reuse the old B is applied but the residual is that of the new A."""
+    sys = synth.lognormal_grid(6, 5, 4, 3, 4, 1.0, 1.0, "corners2")
+    nxt = synth.newton_step(sys, 1, 5)
+    s = O.OracleSolver(mu=1000, max_coarse=16)
+    s.setup(sys)
+    s.solve(sys.rhs, 1e-6)
+    assert s.setup(nxt) is False
+    x, it, rr, st = s.solve(nxt.rhs, 1e-8)
+    A = nxt.to_dense()
+    assert np.linalg.norm(nxt.rhs - A @ x) / np.linalg.norm(nxt.rhs) <= 1e-8
+
+
+# --------------------------------------------------------------------------
+# O1 validation
+# --------------------------------------------------------------------------
+def test_validation_errors():
+    sys = synth.config(0)
+    n, b, p = sys.n, sys.b, sys.p
+    rp, ci, v = sys.row_ptr, sys.col_ind, sys.vals
+    assert O.validate(n, b, p, rp, ci, v) == 0
+    assert O.validate(n, b, b, rp, ci, v) == -1
+    assert O.validate(n, 0, 0, rp, ci, v) == -1
+    bad = ci.copy()
+    bad[1], bad[2] = bad[2], bad[1]
+    assert O.validate(n, b, p, rp, bad, v) == -2
+    bad = ci.copy()
+    bad[0] = n
+    assert O.validate(n, b, p, rp, bad, v) == -2
+    vv = v.copy()
+    vv[5, 1, 2] = np.nan
+    assert O.validate(n, b, p, rp, ci, vv) == -4
+    # a block row without its diagonal block
+    rp2 = np.array([0, 1, 2], dtype=np.int32)
+    ci2 = np.array([1, 0], dtype=np.int32)
+    assert O.validate(2, 1, 0, rp2, ci2, np.ones((2, 1, 1))) == -2
