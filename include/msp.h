@@ -1,0 +1,157 @@
+/*
+ * msp.h -- C-ABI of libmsp: a multi-stage (CPR-type) preconditioned FGMRES
+ * solver for the block-sparse Jacobians of fully implicit compositional
+ * reservoir simulation, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: L. Zhao, C.-S. Zhang, C.-S. Feng, S. Shu, "An Improved Multi-Stage
+ * Preconditioner on GPUs for Compositional Reservoir Simulation" (2022):
+ *   - the block system of Sec. 2.3 (n_c+1 unknowns per cell, pressure first);
+ *   - the multiplicative multi-stage preconditioner of eq. (MSP) applied as
+ *     in Alg. 3.1, here with two stages: a pressure stage (unsmoothed
+ *     aggregation AMG V-cycle, Sec. 5) on the decoupled pressure block and a
+ *     full-system block ILU(0) stage;
+ *   - the multi-color Gauss-Seidel smoother PGS-MC of Alg. 4.3 on the groups
+ *     of Alg. 4.2 (VerticesGrouping);
+ *   - the adaptive SETUP of Sec. 3.2: the preconditioner of the previous
+ *     Newton system is reused while that solve needed at most mu iterations
+ *     and the size is unchanged;
+ *   - restarted GMRES(m) of Sec. 5 as flexible GMRES(m).
+ *
+ * Conventions for every entry point:
+ *   - return value: MSP_OK (0), a negative error code, or a positive warning;
+ *     no entry point throws, aborts or prints;
+ *   - array arguments are DEVICE pointers on the device that was current when
+ *     the context was created, unless the comment says "host";
+ *   - all work is ordered on the context's stream; every entry point is
+ *     synchronous with the host on return;
+ *   - a context is used by one host thread at a time (not re-entrant); many
+ *     contexts may run concurrently on different streams.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSP_OK 0
+#define MSP_ERR_ARG (-1)       /* null pointer, n < 1, b outside 1..16, p outside [0,b), nnzb < n */
+#define MSP_ERR_PATTERN (-2)   /* row_ptr not monotone, column out of range, unsorted or duplicate
+                                  column, or a block row without its diagonal block */
+#define MSP_ERR_SINGULAR (-3)  /* singular diagonal block (decoupling or BILU pivot), zero AMG
+                                  diagonal, or singular coarsest-level block */
+#define MSP_ERR_NONFINITE (-4) /* NaN or Inf in the matrix values or the right-hand side */
+#define MSP_ERR_NOMEM (-5)     /* device or host allocation failed */
+#define MSP_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define MSP_ERR_NO_DEVICE (-7) /* no usable GPU */
+#define MSP_ERR_STATE (-8)     /* solve or inspection before a successful setup */
+#define MSP_ERR_COARSE (-9)    /* coarsening stalled above the dense coarsest-level limit */
+#define MSP_NOT_CONVERGED 1    /* max_iter reached; x holds the last iterate, info is filled */
+
+#define MSP_MAX_LEVELS 25
+#define MSP_MAX_BLOCK 16
+
+/* Solver options.  msp_default_options() fills the paper's settings
+ * (Sec. 5: GMRES(30), MaxIt 1000, coarsest space of at most 10000 unknowns)
+ * with mu = 0 (standard MSP, every system rebuilds, Sec. 3.2). */
+typedef struct {
+    int mu;           /* adaptive-setup threshold It^(i-1) <= mu => reuse (Sec. 3.2) */
+    int restart;      /* m of FGMRES(m), 1..200 */
+    int max_iter;     /* total Arnoldi steps over all restarts */
+    int max_coarse;   /* the coarsest AMG level has at most this many rows */
+    int precond_fp32; /* 0: FP64 preconditioner; 1: AMG hierarchy, GS, BILU and the
+                         pressure-column residual stored and applied in FP32 (FGMRES,
+                         decoupling weights and the coarsest solve stay FP64) */
+    int bilu_order;   /* 0: block ILU(0) in natural block order (default);
+                         1: in the multi-color order of the block adjacency graph */
+    void *stream;     /* hipStream_t for all work; NULL = the default stream */
+    /* Optional device allocator (e.g. a framework caching allocator); both NULL =
+     * hipMalloc/hipFree.  dev_alloc returns NULL on failure. */
+    void *(*dev_alloc)(size_t bytes, void *user);
+    void (*dev_free)(void *ptr, void *user);
+    void *alloc_user;
+} msp_options;
+
+typedef struct {
+    int status;               /* return code of the call that filled it */
+    int iterations;           /* Arnoldi steps of the last solve (Iter, Tables 2/4/6) */
+    int restarts;             /* restart cycles of the last solve */
+    int rebuilt;              /* 1 if the last setup regenerated the preconditioner */
+    int setup_calls;          /* number of rebuilds so far (SetupCalls, Tables 2/4/6) */
+    int solves;               /* number of solves so far */
+    int n_levels;             /* AMG levels including the coarsest */
+    int level_rows[MSP_MAX_LEVELS];
+    int n_colors[MSP_MAX_LEVELS]; /* PGS-MC groups per level (0 on the coarsest) */
+    int bilu_levels_fwd;      /* dependency levels of the BILU forward solve */
+    int bilu_levels_bwd;
+    double rel_true_residual; /* ||b - A x|| / ||b|| after the last solve (FP64) */
+    double setup_ms;          /* host wall time of the last setup */
+    double rebuild_ms;        /* ... of which preconditioner regeneration */
+    double solve_ms;          /* host wall time of the last solve */
+} msp_info;
+
+/* Fill *opt with the defaults listed above.  Returns MSP_ERR_ARG on NULL. */
+int msp_default_options(msp_options *opt);
+
+/* Create a context on the current device.  *ctx receives an opaque handle
+ * owned by the caller until msp_destroy.  opt may be NULL (defaults).
+ * Errors: MSP_ERR_ARG (ctx NULL, bad option values), MSP_ERR_NO_DEVICE,
+ * MSP_ERR_NOMEM. */
+int msp_create(struct msp_ctx **ctx, const msp_options *opt);
+
+/* Ingest one Newton-step Jacobian A^(i) (Sec. 3.2) and decide, by the
+ * adaptive rule, whether to regenerate the preconditioner:
+ *   regenerate iff no preconditioner exists yet, or (n, b, p) differ from the
+ *   last regeneration, or the last solve took more than mu iterations;
+ *   otherwise B^(i-1) is kept whole (decoupling weights, AMG hierarchy, BILU
+ *   factors).  The current matrix is always ingested: FGMRES and the residual
+ *   steps of Alg. 3.1 use A^(i).
+ * Arguments (device pointers, read only, may be overwritten by the caller as
+ * soon as the call returns):
+ *   n_block_rows  n >= 1 block rows (cells);
+ *   block_size    b in 1..16 (n_c+1 in the paper);
+ *   pressure_index p in [0, b): the pressure unknown inside each block;
+ *   row_ptr       int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnzb;
+ *   col_ind       int32[nnzb], strictly ascending inside each block row, every
+ *                 block row holding its diagonal block;
+ *   vals          double[nnzb*b*b], block k row-major at vals[k*b*b].
+ * Errors: MSP_ERR_ARG, MSP_ERR_PATTERN, MSP_ERR_NONFINITE, MSP_ERR_SINGULAR,
+ * MSP_ERR_COARSE, MSP_ERR_NOMEM, MSP_ERR_HIP.  After an error the context
+ * holds no preconditioner and the next setup regenerates it. */
+int msp_setup(struct msp_ctx *ctx, int n_block_rows, int block_size, int pressure_index,
+              const int *row_ptr, const int *col_ind, const double *vals, long long nnzb);
+
+/* Solve A x = rhs by FGMRES(restart) preconditioned with B, to
+ * ||rhs - A x||_2 <= rtol ||rhs||_2 (true FP64 residual).
+ *   rhs  double[n*b], device, read only;
+ *   x    double[n*b], device: initial guess on entry, solution on return;
+ *   rtol > 0;
+ *   info may be NULL (host).
+ * rhs = 0 gives x = 0 after 0 iterations.  Returns MSP_OK,
+ * MSP_NOT_CONVERGED (x = last iterate), MSP_ERR_STATE (no setup),
+ * MSP_ERR_NONFINITE (rhs), MSP_ERR_ARG, MSP_ERR_HIP. */
+int msp_solve(struct msp_ctx *ctx, const double *rhs, double *x, double rtol, msp_info *info);
+
+/* Statistics of the last setup/solve (host pointer). */
+int msp_get_info(struct msp_ctx *ctx, msp_info *info);
+
+/* Upper bound of the device memory a context needs for a system of this
+ * shape (used by admission control).  bytes: host pointer. */
+int msp_footprint(int n_block_rows, long long nnzb, int block_size, const msp_options *opt,
+                  size_t *bytes);
+
+/* Release every resource of the context (NULL is accepted). */
+int msp_destroy(struct msp_ctx *ctx);
+
+/* Static description of a status code (never NULL). */
+const char *msp_status_string(int status);
+
+typedef struct msp_ctx msp_ctx;
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSP_H */

@@ -1,0 +1,76 @@
+/*
+ * msp_stages.h -- per-step entry points of libmsp.  Each runs exactly one step
+ * of the hot path on the context's current matrix / preconditioner so that it
+ * can be checked and timed on its own.  Same conventions as msp.h (device
+ * pointers unless "host", synchronous on return, negative = error).
+ * All of them return MSP_ERR_STATE before a successful msp_setup.
+ */
+#ifndef MSP_STAGES_H
+#define MSP_STAGES_H
+
+#include "msp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* y = A x, the block SpMV of every FGMRES iteration (Sec. 5), FP64.
+ * x, y: double[n*b], must not alias. */
+int msp_stage_spmv(msp_ctx *ctx, const double *x, double *y);
+
+/* z = B v, one application of the two-stage preconditioner of eq. (MSP) /
+ * Alg. 3.1 (pressure stage then BILU stage, initial w = 0), in the context's
+ * preconditioner precision.  v, z: double[n*b], must not alias. */
+int msp_stage_precond(msp_ctx *ctx, const double *v, double *z);
+
+/* e = V-cycle(f) on the decoupled pressure matrix (level 0 of the UA-AMG
+ * hierarchy, Sec. 5) with the PGS-MC smoother of Alg. 4.3.  f, e: double[n]
+ * in natural cell order (converted to the preconditioner precision inside). */
+int msp_stage_vcycle(msp_ctx *ctx, const double *f, double *e);
+
+/* One multi-color Gauss-Seidel sweep (Alg. 4.3) on AMG level `level`
+ * (0 <= level < n_levels-1): colors 1..g if forward != 0, else g..1.
+ * f: double[n_level] read; x: double[n_level] updated in place; natural order
+ * of that level. */
+int msp_stage_smooth(msp_ctx *ctx, int level, const double *f, double *x, int forward);
+
+/* z = (LU)^{-1} r with the block ILU(0) factors (the R stage of eq. MSP).
+ * r, z: double[n*b]. */
+int msp_stage_bilu(msp_ctx *ctx, const double *r, double *z);
+
+/* Shape of AMG level `level` (host outputs, any may be NULL): rows, stored
+ * entries, number of PGS-MC groups (0 on the coarsest), rows of the next
+ * level (0 on the coarsest). */
+int msp_stage_level_info(msp_ctx *ctx, int level, int *n, long long *nnz, int *ncolors,
+                         int *n_next);
+
+/* Copy AMG level `level` to HOST arrays in natural order (any may be NULL):
+ * row_ptr int32[n+1], col_ind int32[nnz] (ascending per row), val
+ * double[nnz] (FP64 setup values), color int32[n] (1..g; not on the
+ * coarsest), agg int32[n] (row of the next level; not on the coarsest). */
+int msp_stage_get_level(msp_ctx *ctx, int level, int *row_ptr, int *col_ind, double *val,
+                        int *color, int *agg);
+
+/* FP32 copy of level `level`'s values (HOST float[nnz], natural order);
+ * MSP_ERR_STATE unless precond_fp32. */
+int msp_stage_get_level_f32(msp_ctx *ctx, int level, float *val);
+
+/* Decoupling weights w_c (row p of the inverse diagonal block), HOST
+ * double[n*b], cell-major. */
+int msp_stage_get_omega(msp_ctx *ctx, double *omega);
+
+/* Block ILU(0) factors in natural BSR order of the pattern used at the last
+ * regeneration: F double[nnzb*b*b] (strictly lower blocks L, unit diagonal
+ * implied; upper blocks U; diagonal slots hold the factored pivot block) and
+ * Dinv double[n*b*b] (inverted pivot blocks); HOST pointers, either may be
+ * NULL. */
+int msp_stage_get_bilu(msp_ctx *ctx, double *F, double *Dinv);
+
+/* FP32 copies of the BILU factors (HOST, same layout); precond_fp32 only. */
+int msp_stage_get_bilu_f32(msp_ctx *ctx, float *F, float *Dinv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSP_STAGES_H */

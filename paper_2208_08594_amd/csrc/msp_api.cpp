@@ -1,0 +1,1216 @@
+// libmsp C-ABI: context, adaptive setup, two-stage preconditioner apply and
+// the FGMRES driver.  Device work is in msp_kernels.hip; host graph work in
+// msp_host.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <type_traits>
+#include <vector>
+
+#include "msp.h"
+#include "msp_host.h"
+#include "msp_kernels.h"
+#include "msp_stages.h"
+
+namespace {
+
+using namespace msp;
+
+struct MspError {
+    int code;
+};
+
+[[noreturn]] void fail(int code) { throw MspError{code}; }
+
+#define HIPCHK(expr)                                 \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) {                      \
+            (void)hipGetLastError();                 \
+            fail(e_ == hipErrorOutOfMemory ? MSP_ERR_NOMEM : MSP_ERR_HIP); \
+        }                                            \
+    } while (0)
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// A device sliced-ELL matrix (pattern on the device + the host layout).
+struct DevSell {
+    SellLayout lay;
+    int4 *slices = nullptr;
+    int *col = nullptr;
+    int *src = nullptr;
+    SellView view(int seg) const
+    {
+        SellView v;
+        v.slices = slices;
+        v.col = col;
+        v.slice_begin = lay.seg_slice[seg];
+        v.slice_end = lay.seg_slice[seg + 1];
+        return v;
+    }
+    SellView all() const
+    {
+        SellView v;
+        v.slices = slices;
+        v.col = col;
+        v.slice_begin = 0;
+        v.slice_end = (int)lay.slice_row0.size();
+        return v;
+    }
+    int nseg() const { return (int)lay.seg_slice.size() - 1; }
+};
+
+struct Level {
+    int n = 0, g = 0, nc = 0;
+    Csr A;                      // natural order, FP64 setup values
+    std::vector<int> color, agg;
+    std::vector<int> perm, iperm;  // natural -> position, position -> natural
+    std::vector<int> seg_row;
+    DevSell S;                  // off-diagonal entries in position space
+    double *val64 = nullptr, *diag64 = nullptr;
+    float *val32 = nullptr, *diag32 = nullptr;
+    int *perm_d = nullptr, *iperm_d = nullptr;
+    int *agg_pos = nullptr, *mem_ptr = nullptr, *mem = nullptr;
+    void *f = nullptr, *x = nullptr, *r = nullptr;  // work vectors in the precond precision
+};
+
+struct BiluData {
+    std::vector<int> ord;  // elimination order
+    std::vector<int> fwd_rows, fwd_ptr, bwd_rows, bwd_ptr;
+    std::vector<int> rp, ci;  // pattern at regeneration
+    DevSell L, U;
+    int *fwd_rows_d = nullptr, *bwd_rows_d = nullptr;
+    int *dsrc = nullptr;  // per U slice-lane: block row (for the pivot inverses)
+    double *F = nullptr, *Dinv = nullptr;  // natural layout FP64
+    double *L64 = nullptr, *U64 = nullptr, *D64 = nullptr;
+    float *L32 = nullptr, *U32 = nullptr, *D32 = nullptr;
+};
+
+}  // namespace
+
+struct msp_ctx {
+    msp_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // allocation lists by lifetime
+    std::vector<void *> allocA, allocB, allocW;
+    // current matrix
+    int n = 0, b = 0, p = 0;
+    long long nnzb = 0;
+    std::vector<int> rp, ci, diag_pos;
+    DevSell SA;
+    int *rp_d = nullptr, *diag_d = nullptr;
+    double *valA = nullptr;
+    float *pcol32 = nullptr;
+    bool haveA = false;
+    // preconditioner
+    bool hasB = false;
+    int Bn = 0, Bb = 0, Bp = 0;
+    long long Bnnzb = 0;
+    double *omega = nullptr;
+    std::vector<Level> lev;
+    int nL = 0;
+    double *cinv = nullptr;
+    BiluData bilu;
+    void *e_nat = nullptr, *ybuf = nullptr;
+    // krylov workspace
+    long long wsN = 0;
+    int wsm = 0;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hbuf = nullptr,
+           *ydev = nullptr, *tmpN = nullptr, *tmpN2 = nullptr;
+    double *hhost = nullptr;  // pinned
+    int *flag = nullptr, *flag_host = nullptr;
+    // adaptive state and statistics
+    int it_prev = -1, setup_calls = 0, solves = 0;
+    msp_info info{};
+
+    void *dalloc(size_t bytes, std::vector<void *> &list)
+    {
+        if (bytes == 0) bytes = 16;
+        void *p_ = nullptr;
+        if (opt.dev_alloc) {
+            p_ = opt.dev_alloc(bytes, opt.alloc_user);
+            if (!p_) fail(MSP_ERR_NOMEM);
+        } else {
+            hipError_t e = hipMalloc(&p_, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(MSP_ERR_NOMEM);
+            }
+        }
+        list.push_back(p_);
+        return p_;
+    }
+    void release(std::vector<void *> &list)
+    {
+        if (!list.empty()) (void)hipStreamSynchronize(stream);
+        for (void *p_ : list) {
+            if (opt.dev_free)
+                opt.dev_free(p_, opt.alloc_user);
+            else
+                (void)hipFree(p_);
+        }
+        list.clear();
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &h, std::vector<void *> &list)
+    {
+        T *d = (T *)dalloc(sizeof(T) * std::max<size_t>(h.size(), 1), list);
+        if (!h.empty())
+            HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice,
+                                  stream));
+        return d;
+    }
+    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+    int read_flag()
+    {
+        HIPCHK(hipMemcpyAsync(flag_host, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        return *flag_host;
+    }
+    void clear_flag() { HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), stream)); }
+    bool fp32() const { return opt.precond_fp32 != 0; }
+};
+
+namespace {
+
+void upload_sell(msp_ctx *c, DevSell &S, std::vector<void *> &list)
+{
+    std::vector<int4> sl(S.lay.slice_row0.size());
+    for (size_t s = 0; s < sl.size(); ++s)
+        sl[s] = make_int4(S.lay.slice_row0[s], S.lay.slice_rows[s], S.lay.slice_width[s],
+                          S.lay.slice_off[s]);
+    S.slices = c->upload(sl, list);
+    S.col = c->upload(S.lay.col, list);
+    S.src = c->upload(S.lay.src, list);
+}
+
+// --------------------------------------------------------------------------
+// matrix ingest
+// --------------------------------------------------------------------------
+void build_layout_A(msp_ctx *c)
+{
+    c->release(c->allocA);
+    const int n = c->n;
+    std::vector<int> seg_row = {0, n};
+    std::vector<int> src(c->ci.size());
+    std::iota(src.begin(), src.end(), 0);
+    build_sell(n, seg_row, c->rp, c->ci, src, c->SA.lay);
+    upload_sell(c, c->SA, c->allocA);
+    const long long E = (long long)c->b * c->b;
+    c->valA = (double *)c->dalloc(sizeof(double) * c->SA.lay.slot_lanes * E, c->allocA);
+    c->pcol32 = c->fp32()
+                    ? (float *)c->dalloc(sizeof(float) * c->SA.lay.slot_lanes * c->b, c->allocA)
+                    : nullptr;
+    c->rp_d = c->upload(c->rp, c->allocA);
+    c->diag_d = c->upload(c->diag_pos, c->allocA);
+}
+
+// --------------------------------------------------------------------------
+// preconditioner regeneration
+// --------------------------------------------------------------------------
+void release_B(msp_ctx *c)
+{
+    c->release(c->allocB);
+    c->lev.clear();
+    c->bilu = BiluData();
+    c->hasB = false;
+    c->omega = nullptr;
+    c->cinv = nullptr;
+    c->e_nat = c->ybuf = nullptr;
+}
+
+template <typename T>
+void *alloc_vec(msp_ctx *c, long long n)
+{
+    return c->dalloc(sizeof(T) * (size_t)std::max<long long>(n, 1), c->allocB);
+}
+
+void build_level_device(msp_ctx *c, int l, const Hierarchy &H)
+{
+    Level &L = c->lev[l];
+    const bool last = (l == (int)H.A.size() - 1);
+    const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
+    L.f = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
+    L.x = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
+    if (last) {
+        L.perm.resize(L.n);
+        std::iota(L.perm.begin(), L.perm.end(), 0);
+        L.iperm = L.perm;
+        L.perm_d = c->upload(L.perm, c->allocB);
+        L.iperm_d = L.perm_d;
+        return;
+    }
+    L.r = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
+    // positions: color 1 rows ascending, then color 2, ... (PGS-MC groups)
+    L.perm.assign(L.n, 0);
+    L.iperm.clear();
+    L.iperm.reserve(L.n);
+    L.seg_row.assign(L.g + 1, 0);
+    {
+        std::vector<int> cnt(L.g + 2, 0);
+        for (int i = 0; i < L.n; ++i) ++cnt[L.color[i]];
+        for (int g = 1; g <= L.g; ++g) L.seg_row[g] = L.seg_row[g - 1] + cnt[g];
+        std::vector<int> f(L.seg_row.begin(), L.seg_row.end() - 1);
+        L.iperm.assign(L.n, 0);
+        for (int i = 0; i < L.n; ++i) {
+            int t = f[L.color[i] - 1]++;
+            L.perm[i] = t;
+            L.iperm[t] = i;
+        }
+    }
+    std::vector<int> ent_ptr(L.n + 1, 0), ent_col, ent_src;
+    std::vector<double> diag(L.n, 0.0);
+    ent_col.reserve(L.A.ci.size());
+    ent_src.reserve(L.A.ci.size());
+    for (int t = 0; t < L.n; ++t) {
+        int i = L.iperm[t];
+        for (int k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k) {
+            int j = L.A.ci[k];
+            if (j == i) {
+                diag[t] = L.A.val[k];
+            } else {
+                ent_col.push_back(L.perm[j]);
+                ent_src.push_back(k);
+            }
+        }
+        ent_ptr[t + 1] = (int)ent_col.size();
+    }
+    build_sell(L.n, L.seg_row, ent_ptr, ent_col, ent_src, L.S.lay);
+    upload_sell(c, L.S, c->allocB);
+    const long long sl = L.S.lay.slot_lanes;
+    std::vector<double> v64(sl, 0.0);
+    for (long long q = 0; q < sl; ++q)
+        if (L.S.lay.src[q] >= 0) v64[q] = L.A.val[L.S.lay.src[q]];
+    if (c->fp32()) {
+        std::vector<float> v32(sl), d32(L.n);
+        for (long long q = 0; q < sl; ++q) v32[q] = (float)v64[q];
+        for (int t = 0; t < L.n; ++t) d32[t] = (float)diag[t];
+        L.val32 = c->upload(v32, c->allocB);
+        L.diag32 = c->upload(d32, c->allocB);
+    } else {
+        L.val64 = c->upload(v64, c->allocB);
+        L.diag64 = c->upload(diag, c->allocB);
+    }
+    L.perm_d = c->upload(L.perm, c->allocB);
+    L.iperm_d = c->upload(L.iperm, c->allocB);
+}
+
+void link_levels(msp_ctx *c)
+{
+    for (size_t l = 0; l + 1 < c->lev.size(); ++l) {
+        Level &L = c->lev[l];
+        const Level &C = c->lev[l + 1];
+        std::vector<int> agg_pos(L.n);
+        for (int t = 0; t < L.n; ++t) agg_pos[t] = C.perm[L.agg[L.iperm[t]]];
+        // members of each coarse position, natural fine index ascending
+        std::vector<int> mptr(C.n + 1, 0), mem(L.n);
+        for (int i = 0; i < L.n; ++i) ++mptr[C.perm[L.agg[i]] + 1];
+        for (int J = 0; J < C.n; ++J) mptr[J + 1] += mptr[J];
+        std::vector<int> f(mptr.begin(), mptr.end() - 1);
+        for (int i = 0; i < L.n; ++i) mem[f[C.perm[L.agg[i]]]++] = L.perm[i];
+        L.agg_pos = c->upload(agg_pos, c->allocB);
+        L.mem_ptr = c->upload(mptr, c->allocB);
+        L.mem = c->upload(mem, c->allocB);
+    }
+}
+
+void build_coarse(msp_ctx *c)
+{
+    Level &L = c->lev.back();
+    const int m = L.n;
+    c->nL = m;
+    c->cinv = (double *)c->dalloc(sizeof(double) * (size_t)m * m, c->allocB);
+    std::vector<void *> tmp;
+    int *rp = c->upload(L.A.rp, tmp);
+    int *ci = c->upload(L.A.ci, tmp);
+    double *val = c->upload(L.A.val, tmp);
+    double *work = (double *)c->dalloc(sizeof(double) * ((size_t)2 * 64 * m + 64 * 64), tmp);
+    HIPCHK(launch_fill((long long)m * m, 0.0, c->cinv, c->stream));
+    HIPCHK(launch_dense_scatter(m, rp, ci, val, c->cinv, c->stream));
+    c->clear_flag();
+    HIPCHK(dense_inverse(m, c->cinv, work, c->flag, c->stream));
+    int bad = c->read_flag();
+    c->release(tmp);
+    if (bad) fail(MSP_ERR_SINGULAR);
+}
+
+void build_bilu(msp_ctx *c, const double *vals)
+{
+    BiluData &D = c->bilu;
+    const int n = c->n, b = c->b;
+    const long long E = (long long)b * b;
+    D.rp = c->rp;
+    D.ci = c->ci;
+    D.ord.resize(n);
+    if (c->opt.bilu_order == 1) {
+        Adjacency G = build_adjacency(n, c->rp.data(), c->ci.data());
+        std::vector<int> color;
+        int g = vertices_grouping(G, color);
+        int t = 0;
+        for (int col = 1; col <= g; ++col)
+            for (int i = 0; i < n; ++i)
+                if (color[i] == col) D.ord[t++] = i;
+    } else {
+        std::iota(D.ord.begin(), D.ord.end(), 0);
+    }
+    std::vector<int> pos(n);
+    for (int t = 0; t < n; ++t) pos[D.ord[t]] = t;
+    triangular_levels(n, c->rp.data(), c->ci.data(), D.ord, true, D.fwd_rows, D.fwd_ptr);
+    triangular_levels(n, c->rp.data(), c->ci.data(), D.ord, false, D.bwd_rows, D.bwd_ptr);
+    // factorisation tasks per block row: lower entries in elimination order and
+    // their update pairs (F_ij -= F_ik F_kj for stored j after k, (k,j) stored)
+    std::vector<int> lt_ptr(n + 1, 0), lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
+    std::vector<int> low;
+    for (int i = 0; i < n; ++i) {
+        low.clear();
+        for (int q = c->rp[i]; q < c->rp[i + 1]; ++q)
+            if (pos[c->ci[q]] < pos[i]) low.push_back(q);
+        std::sort(low.begin(), low.end(),
+                  [&](int a, int bq) { return pos[c->ci[a]] < pos[c->ci[bq]]; });
+        for (int kk : low) {
+            int k = c->ci[kk];
+            lt_kk.push_back(kk);
+            lt_k.push_back(k);
+            lt_pp.push_back((int)pr_jj.size());
+            for (int jj = c->rp[i]; jj < c->rp[i + 1]; ++jj) {
+                int j = c->ci[jj];
+                if (pos[j] <= pos[k]) continue;
+                auto b0 = c->ci.begin() + c->rp[k], b1 = c->ci.begin() + c->rp[k + 1];
+                auto it = std::lower_bound(b0, b1, j);
+                if (it != b1 && *it == j) {
+                    pr_jj.push_back(jj);
+                    pr_kj.push_back((int)(it - c->ci.begin()));
+                }
+            }
+        }
+        lt_ptr[i + 1] = (int)lt_kk.size();
+    }
+    lt_pp.push_back((int)pr_jj.size());
+    std::vector<void *> tmp;
+    BiluTasks T;
+    T.lt_ptr = c->upload(lt_ptr, tmp);
+    T.lt_kk = c->upload(lt_kk, tmp);
+    T.lt_k = c->upload(lt_k, tmp);
+    T.lt_pp = c->upload(lt_pp, tmp);
+    T.pr_jj = c->upload(pr_jj, tmp);
+    T.pr_kj = c->upload(pr_kj, tmp);
+    T.diag_pos = c->diag_d;
+    int *rows_d = c->upload(D.fwd_rows, tmp);
+    D.F = (double *)c->dalloc(sizeof(double) * (size_t)(c->nnzb * E), c->allocB);
+    D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
+    HIPCHK(hipMemcpyAsync(D.F, vals, sizeof(double) * (size_t)(c->nnzb * E),
+                          hipMemcpyDeviceToDevice, c->stream));
+    c->clear_flag();
+    for (size_t lv = 0; lv + 1 < D.fwd_ptr.size(); ++lv) {
+        T.rows = rows_d + D.fwd_ptr[lv];
+        T.nrows = D.fwd_ptr[lv + 1] - D.fwd_ptr[lv];
+        HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag, c->stream));
+    }
+    int bad = c->read_flag();
+    c->release(tmp);
+    if (bad) fail(MSP_ERR_SINGULAR);
+    // sliced layouts of the lower (forward levels) and upper (backward levels) parts
+    auto make = [&](const std::vector<int> &rows, const std::vector<int> &lptr, bool lower,
+                    DevSell &S) {
+        std::vector<int> ent_ptr(n + 1, 0), ent_col, ent_src;
+        std::vector<int> tmpk;
+        for (int t = 0; t < n; ++t) {
+            int i = rows[t];
+            tmpk.clear();
+            for (int q = c->rp[i]; q < c->rp[i + 1]; ++q) {
+                int j = c->ci[q];
+                if (lower ? pos[j] < pos[i] : pos[j] > pos[i]) tmpk.push_back(q);
+            }
+            std::sort(tmpk.begin(), tmpk.end(),
+                      [&](int a, int bq) { return pos[c->ci[a]] < pos[c->ci[bq]]; });
+            for (int q : tmpk) {
+                ent_col.push_back(c->ci[q]);
+                ent_src.push_back(q);
+            }
+            ent_ptr[t + 1] = (int)ent_col.size();
+        }
+        build_sell(n, lptr, ent_ptr, ent_col, ent_src, S.lay);
+        upload_sell(c, S, c->allocB);
+    };
+    make(D.fwd_rows, D.fwd_ptr, true, D.L);
+    make(D.bwd_rows, D.bwd_ptr, false, D.U);
+    D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
+    D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
+    std::vector<int> dsrc(D.U.lay.slice_row0.size() * 64, -1);
+    for (size_t s = 0; s < D.U.lay.slice_row0.size(); ++s)
+        for (int l = 0; l < D.U.lay.slice_rows[s]; ++l)
+            dsrc[s * 64 + l] = D.bwd_rows[D.U.lay.slice_row0[s] + l];
+    D.dsrc = c->upload(dsrc, c->allocB);
+    const long long dsl = (long long)dsrc.size();
+    if (c->fp32()) {
+        D.L32 = (float *)c->dalloc(sizeof(float) * D.L.lay.slot_lanes * E, c->allocB);
+        D.U32 = (float *)c->dalloc(sizeof(float) * D.U.lay.slot_lanes * E, c->allocB);
+        D.D32 = (float *)c->dalloc(sizeof(float) * dsl * E, c->allocB);
+        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, nullptr, D.L32, c->stream));
+        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, nullptr, D.U32, c->stream));
+        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, nullptr, D.D32, c->stream));
+    } else {
+        D.L64 = (double *)c->dalloc(sizeof(double) * D.L.lay.slot_lanes * E, c->allocB);
+        D.U64 = (double *)c->dalloc(sizeof(double) * D.U.lay.slot_lanes * E, c->allocB);
+        D.D64 = (double *)c->dalloc(sizeof(double) * dsl * E, c->allocB);
+        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, D.L64, nullptr, c->stream));
+        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, D.U64, nullptr, c->stream));
+        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, D.D64, nullptr, c->stream));
+    }
+}
+
+void rebuild_B(msp_ctx *c, const double *vals)
+{
+    release_B(c);
+    const int n = c->n, b = c->b;
+    // decoupling and pressure extraction (device), pressure matrix to the host
+    c->omega = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
+    std::vector<void *> tmp;
+    double *ap = (double *)c->dalloc(sizeof(double) * (size_t)c->nnzb, tmp);
+    c->clear_flag();
+    HIPCHK(launch_decouple(b, c->p, n, c->rp_d, c->diag_d, vals, c->omega, ap, c->flag,
+                           c->stream));
+    Csr A0;
+    A0.n = n;
+    A0.rp = c->rp;
+    A0.ci = c->ci;
+    A0.val.resize(c->nnzb);
+    HIPCHK(hipMemcpyAsync(A0.val.data(), ap, sizeof(double) * c->nnzb, hipMemcpyDeviceToHost,
+                          c->stream));
+    int bad = c->read_flag();
+    c->release(tmp);
+    if (bad) fail(MSP_ERR_SINGULAR);
+    // UA-AMG hierarchy on the host (greedy grouping and matching)
+    Hierarchy H;
+    int st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H);
+    if (st == -3) fail(MSP_ERR_SINGULAR);
+    if (st == -9) fail(MSP_ERR_COARSE);
+    c->lev.resize(H.A.size());
+    for (size_t l = 0; l < H.A.size(); ++l) {
+        Level &L = c->lev[l];
+        L.A = std::move(H.A[l]);
+        L.n = L.A.n;
+        if (l + 1 < c->lev.size()) {
+            L.color = std::move(H.color[l]);
+            L.agg = std::move(H.agg[l]);
+            L.g = H.ncolors[l];
+        }
+    }
+    for (size_t l = 0; l + 1 < c->lev.size(); ++l) c->lev[l].nc = c->lev[l + 1].A.n;
+    for (size_t l = 0; l < c->lev.size(); ++l) build_level_device(c, (int)l, H);
+    link_levels(c);
+    build_coarse(c);
+    build_bilu(c, vals);
+    const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
+    c->e_nat = c->dalloc(tsz * n, c->allocB);
+    c->ybuf = c->dalloc(tsz * (size_t)n * b, c->allocB);
+    c->sync();
+    c->Bn = n;
+    c->Bb = b;
+    c->Bp = c->p;
+    c->Bnnzb = c->nnzb;
+    c->hasB = true;
+    c->setup_calls++;
+}
+
+// --------------------------------------------------------------------------
+// preconditioner apply (Alg. 3.1, reduced form)
+// --------------------------------------------------------------------------
+template <typename T>
+const T *lev_val(const Level &L);
+template <>
+const double *lev_val<double>(const Level &L) { return L.val64; }
+template <>
+const float *lev_val<float>(const Level &L) { return L.val32; }
+template <typename T>
+const T *lev_diag(const Level &L);
+template <>
+const double *lev_diag<double>(const Level &L) { return L.diag64; }
+template <>
+const float *lev_diag<float>(const Level &L) { return L.diag32; }
+
+template <typename T>
+void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero)
+{
+    T *f = (T *)L.f, *x = (T *)L.x;
+    const T *val = lev_val<T>(L);
+    const T *diag = lev_diag<T>(L);
+    if (forward) {
+        int g0 = 0;
+        if (from_zero) {
+            HIPCHK(launch_gs_first<T>(L.S.all(), L.n, diag, f, x, L.seg_row[0], L.seg_row[1],
+                                      c->stream));
+            g0 = 1;
+        }
+        for (int g = g0; g < L.g; ++g)
+            HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
+    } else {
+        for (int g = L.g - 1; g >= 0; --g)
+            HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
+    }
+}
+
+template <typename T>
+void vcycle(msp_ctx *c, int l)
+{
+    Level &L = c->lev[l];
+    if (l == (int)c->lev.size() - 1) {
+        HIPCHK(launch_coarse_gemv<T>(L.n, c->cinv, (const T *)L.f, (T *)L.x, c->stream));
+        return;
+    }
+    Level &C = c->lev[l + 1];
+    smooth<T>(c, L, true, true);
+    HIPCHK(launch_residual<T>(L.S.all(), lev_val<T>(L), lev_diag<T>(L), (const T *)L.f,
+                              (const T *)L.x, (T *)L.r, c->stream));
+    HIPCHK(launch_restrict<T>(C.n, L.mem_ptr, L.mem, (const T *)L.r, (T *)C.f, c->stream));
+    vcycle<T>(c, l + 1);
+    HIPCHK(launch_prolong<T>(L.n, L.agg_pos, (const T *)C.x, (T *)L.x, c->stream));
+    smooth<T>(c, L, false, false);
+}
+
+template <typename T>
+void bilu_solve(msp_ctx *c, T *y)
+{
+    BiluData &D = c->bilu;
+    const T *Lv, *Uv, *Dv;
+    if (std::is_same<T, float>::value) {
+        Lv = (const T *)D.L32; Uv = (const T *)D.U32; Dv = (const T *)D.D32;
+    } else {
+        Lv = (const T *)D.L64; Uv = (const T *)D.U64; Dv = (const T *)D.D64;
+    }
+    for (int s = 0; s < D.L.nseg(); ++s)
+        HIPCHK(launch_bilu_fwd<T>(c->b, D.L.view(s), D.fwd_rows_d, Lv, y, c->stream));
+    for (int s = 0; s < D.U.nseg(); ++s)
+        HIPCHK(launch_bilu_bwd<T>(c->b, D.U.view(s), D.bwd_rows_d, Uv, Dv, y, c->stream));
+}
+
+template <typename T>
+void apply_T(msp_ctx *c, const double *v, double *z)
+{
+    Level &L0 = c->lev[0];
+    HIPCHK(launch_decouple_restrict<T>(c->b, c->n, L0.iperm_d, c->omega, v, (T *)L0.f, c->stream));
+    vcycle<T>(c, 0);
+    HIPCHK(launch_unpermute<T>(c->n, L0.perm_d, (const T *)L0.x, (T *)c->e_nat, c->stream));
+    HIPCHK(launch_pcol_residual<T>(c->b, c->p, c->SA.all(), c->valA, c->pcol32, v,
+                                   (const T *)c->e_nat, (T *)c->ybuf, c->stream));
+    bilu_solve<T>(c, (T *)c->ybuf);
+    HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, (const T *)c->e_nat, z,
+                            c->stream));
+}
+
+void apply(msp_ctx *c, const double *v, double *z)
+{
+    if (c->fp32())
+        apply_T<float>(c, v, z);
+    else
+        apply_T<double>(c, v, z);
+}
+
+void spmv(msp_ctx *c, const double *x, const double *sub, double *y)
+{
+    HIPCHK(launch_spmv(c->b, c->SA.all(), c->valA, x, sub, y, c->stream));
+}
+
+// --------------------------------------------------------------------------
+// FGMRES
+// --------------------------------------------------------------------------
+void ensure_workspace(msp_ctx *c)
+{
+    const long long N = (long long)c->n * c->b;
+    const int m = c->opt.restart;
+    if (c->wsN == N && c->wsm == m) return;
+    c->release(c->allocW);
+    c->V = (double *)c->dalloc(sizeof(double) * (size_t)N * (m + 1), c->allocW);
+    c->Z = (double *)c->dalloc(sizeof(double) * (size_t)N * m, c->allocW);
+    c->w = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
+    c->tmpN = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
+    c->tmpN2 = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
+    c->partial = (double *)c->dalloc(sizeof(double) * (size_t)kDotBlocks * (m + 2), c->allocW);
+    c->hbuf = (double *)c->dalloc(sizeof(double) * (size_t)(2 * (m + 2) + 2), c->allocW);
+    c->ydev = (double *)c->dalloc(sizeof(double) * (size_t)(m + 1), c->allocW);
+    c->wsN = N;
+    c->wsm = m;
+}
+
+// sum_i x_i^2 on the device, returned to the host
+double device_norm2(msp_ctx *c, const double *x, long long N)
+{
+    HIPCHK(launch_dot_multi(N, 1, x, N, x, c->partial, c->stream));
+    HIPCHK(launch_reduce_partials(1, c->partial, c->hbuf, 0, c->stream));
+    HIPCHK(hipMemcpyAsync(c->hhost, c->hbuf, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return c->hhost[0];
+}
+
+int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, int &restarts,
+           double &relres)
+{
+    const long long N = (long long)c->n * c->b;
+    const int m = c->opt.restart;
+    ensure_workspace(c);
+    iters = 0;
+    restarts = 0;
+    relres = 0.0;
+    double bn2 = device_norm2(c, rhs, N);
+    if (!std::isfinite(bn2)) return MSP_ERR_NONFINITE;
+    const double bnorm = std::sqrt(bn2);
+    if (bnorm == 0.0) {
+        HIPCHK(launch_fill(N, 0.0, x, c->stream));
+        c->sync();
+        return MSP_OK;
+    }
+    const double tol = rtol * bnorm;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    spmv(c, x, rhs, c->w);
+    double beta = std::sqrt(device_norm2(c, c->w, N));
+    if (!std::isfinite(beta)) return MSP_ERR_NONFINITE;
+    int status = MSP_OK;
+    double *h1 = c->hbuf, *h2 = c->hbuf + (m + 1), *hn = c->hbuf + 2 * (m + 1);
+    while (beta > tol) {
+        if (iters >= c->opt.max_iter) {
+            status = MSP_NOT_CONVERGED;
+            break;
+        }
+        HIPCHK(launch_scale(N, c->w, beta, c->V, c->stream));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = c->V + (size_t)j * N;
+            double *zj = c->Z + (size_t)j * N;
+            apply(c, vj, zj);
+            spmv(c, zj, nullptr, c->w);
+            // classical Gram-Schmidt, twice
+            HIPCHK(launch_dot_multi(N, j + 1, c->V, N, c->w, c->partial, c->stream));
+            HIPCHK(launch_reduce_partials(j + 1, c->partial, h1, 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, j + 1, c->V, N, h1, c->w, c->stream));
+            HIPCHK(launch_dot_multi(N, j + 1, c->V, N, c->w, c->partial, c->stream));
+            HIPCHK(launch_reduce_partials(j + 1, c->partial, h2, 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, j + 1, c->V, N, h2, c->w, c->stream));
+            HIPCHK(launch_dot_multi(N, 1, c->w, N, c->w, c->partial, c->stream));
+            HIPCHK(launch_reduce_partials(1, c->partial, hn, 0, c->stream));
+            HIPCHK(hipMemcpyAsync(c->hhost, c->hbuf, sizeof(double) * (2 * (m + 1) + 1),
+                                  hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            const double *hh1 = c->hhost, *hh2 = c->hhost + (m + 1);
+            const double hnorm = std::sqrt(c->hhost[2 * (m + 1)]);
+            if (!std::isfinite(hnorm)) return MSP_ERR_NONFINITE;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh1[i] + hh2[i];
+            H[(size_t)(j + 1) * m + j] = hnorm;
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+            }
+            double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
+            double d = std::hypot(a, bq);
+            cs[j] = a / d;
+            sn[j] = bq / d;
+            H[(size_t)j * m + j] = d;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            k = j + 1;
+            if (hnorm == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c->opt.max_iter) break;
+            HIPCHK(launch_scale(N, c->w, hnorm, c->V + (size_t)(j + 1) * N, c->stream));
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int q = i + 1; q < k; ++q) acc -= H[(size_t)i * m + q] * y[q];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        std::memcpy(c->hhost + 2 * (m + 2), y.data(), sizeof(double) * k);
+        HIPCHK(hipMemcpyAsync(c->ydev, c->hhost + 2 * (m + 2), sizeof(double) * k,
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_update_x(N, k, c->Z, N, c->ydev, x, c->stream));
+        spmv(c, x, rhs, c->w);
+        beta = std::sqrt(device_norm2(c, c->w, N));
+        ++restarts;
+    }
+    relres = beta / bnorm;
+    return status;
+}
+
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const MspError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return MSP_ERR_NOMEM;
+    } catch (...) {
+        return MSP_ERR_HIP;
+    }
+}
+
+bool valid_options(const msp_options &o)
+{
+    return o.mu >= 0 && o.restart >= 1 && o.restart <= 200 && o.max_iter >= 1 &&
+           o.max_coarse >= 1 && (o.precond_fp32 == 0 || o.precond_fp32 == 1) &&
+           (o.bilu_order == 0 || o.bilu_order == 1) &&
+           ((o.dev_alloc == nullptr) == (o.dev_free == nullptr));
+}
+
+// copy a device sliced layout back to natural block order (host)
+template <typename T>
+void ungather(msp_ctx *c, const DevSell &S, const T *dev, long long E, T *out)
+{
+    const long long sl = S.lay.slot_lanes;
+    std::vector<T> h((size_t)(sl * E));
+    HIPCHK(hipMemcpyAsync(h.data(), dev, sizeof(T) * sl * E, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    for (long long q = 0; q < sl; ++q) {
+        int s = S.lay.src[q];
+        if (s < 0) continue;
+        for (long long e = 0; e < E; ++e)
+            out[(long long)s * E + e] = h[(q >> 6) * 64 * E + e * 64 + (q & 63)];
+    }
+}
+
+template <typename T>
+void stage_vcycle_T(msp_ctx *c, const double *f, double *e)
+{
+    Level &L0 = c->lev[0];
+    // natural -> positions in the preconditioner precision
+    T *tmp = (T *)c->ybuf;  // n*b >= n entries
+    HIPCHK(launch_from_double<T>(c->n, f, tmp, c->stream));
+    HIPCHK(launch_unpermute<T>(c->n, L0.iperm_d, tmp, (T *)L0.f, c->stream));
+    vcycle<T>(c, 0);
+    HIPCHK(launch_unpermute<T>(c->n, L0.perm_d, (const T *)L0.x, tmp, c->stream));
+    HIPCHK(launch_to_double<T>(c->n, tmp, e, c->stream));
+}
+
+template <typename T>
+void stage_smooth_T(msp_ctx *c, int level, const double *f, double *x, int forward)
+{
+    Level &L = c->lev[level];
+    T *tmp = (T *)c->ybuf;
+    HIPCHK(launch_from_double<T>(L.n, f, tmp, c->stream));
+    HIPCHK(launch_unpermute<T>(L.n, L.iperm_d, tmp, (T *)L.f, c->stream));
+    HIPCHK(launch_from_double<T>(L.n, x, tmp, c->stream));
+    HIPCHK(launch_unpermute<T>(L.n, L.iperm_d, tmp, (T *)L.x, c->stream));
+    smooth<T>(c, L, forward != 0, false);
+    HIPCHK(launch_unpermute<T>(L.n, L.perm_d, (const T *)L.x, tmp, c->stream));
+    HIPCHK(launch_to_double<T>(L.n, tmp, x, c->stream));
+}
+
+template <typename T>
+void stage_bilu_T(msp_ctx *c, const double *r, double *z)
+{
+    const long long N = (long long)c->n * c->b;
+    HIPCHK(launch_from_double<T>(N, r, (T *)c->ybuf, c->stream));
+    bilu_solve<T>(c, (T *)c->ybuf);
+    HIPCHK(launch_to_double<T>(N, (const T *)c->ybuf, z, c->stream));
+}
+
+}  // namespace
+
+// ==========================================================================
+// C-ABI
+// ==========================================================================
+extern "C" {
+
+int msp_default_options(msp_options *opt)
+{
+    if (!opt) return MSP_ERR_ARG;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->mu = 0;
+    opt->restart = 30;
+    opt->max_iter = 1000;
+    opt->max_coarse = 10000;
+    opt->precond_fp32 = 0;
+    opt->bilu_order = 0;
+    return MSP_OK;
+}
+
+int msp_create(msp_ctx **ctx, const msp_options *opt)
+{
+    if (!ctx) return MSP_ERR_ARG;
+    *ctx = nullptr;
+    msp_options o;
+    msp_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_options(o)) return MSP_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return MSP_ERR_NO_DEVICE;
+    }
+    msp_ctx *c = new (std::nothrow) msp_ctx();
+    if (!c) return MSP_ERR_NOMEM;
+    c->opt = o;
+    int st = guarded([&]() {
+        HIPCHK(hipGetDevice(&c->device));
+        c->stream = (hipStream_t)o.stream;
+        HIPCHK(hipHostMalloc((void **)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int), hipHostMallocDefault));
+        c->flag = (int *)c->dalloc(sizeof(int) * 4, c->allocW);
+        c->wsN = -1;
+        return MSP_OK;
+    });
+    if (st != MSP_OK) {
+        msp_destroy(c);
+        return st;
+    }
+    // the workspace list owns only the flag so far; keep it across workspace resizes
+    c->allocW.clear();
+    *ctx = c;
+    return MSP_OK;
+}
+
+int msp_destroy(msp_ctx *c)
+{
+    if (!c) return MSP_OK;
+    int st = guarded([&]() {
+        c->release(c->allocA);
+        c->release(c->allocB);
+        c->release(c->allocW);
+        if (c->flag) {
+            if (c->opt.dev_free)
+                c->opt.dev_free(c->flag, c->opt.alloc_user);
+            else
+                (void)hipFree(c->flag);
+        }
+        if (c->hhost) (void)hipHostFree(c->hhost);
+        if (c->flag_host) (void)hipHostFree(c->flag_host);
+        return MSP_OK;
+    });
+    delete c;
+    return st;
+}
+
+int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *col_ind,
+              const double *vals, long long nnzb)
+{
+    if (!c || !row_ptr || !col_ind || !vals) return MSP_ERR_ARG;
+    if (n < 1 || b < 1 || b > 8 || p < 0 || p >= b || nnzb < n) return MSP_ERR_ARG;
+    if (nnzb * b * b >= (1LL << 31) * 8LL || nnzb >= (1LL << 31) - 1) return MSP_ERR_ARG;
+    const double t0 = now_ms();
+    int st = guarded([&]() {
+        c->haveA = false;
+        std::vector<int> rp(n + 1), ci(nnzb);
+        HIPCHK(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
+                              c->stream));
+        c->sync();
+        if (rp[0] != 0 || (long long)rp[n] != nnzb) fail(MSP_ERR_PATTERN);
+        HIPCHK(hipMemcpyAsync(ci.data(), col_ind, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
+                              c->stream));
+        c->sync();
+        if (check_pattern(n, rp.data(), ci.data(), nnzb) != 0) fail(MSP_ERR_PATTERN);
+        const bool layout_changed = !c->haveA || n != c->n || b != c->b || p != c->p ||
+                                    nnzb != c->nnzb || rp != c->rp || ci != c->ci;
+        if (layout_changed) {
+            c->n = n;
+            c->b = b;
+            c->p = p;
+            c->nnzb = nnzb;
+            c->rp.swap(rp);
+            c->ci.swap(ci);
+            c->diag_pos.assign(n, -1);
+            for (int i = 0; i < n; ++i)
+                for (int k = c->rp[i]; k < c->rp[i + 1]; ++k)
+                    if (c->ci[k] == i) c->diag_pos[i] = k;
+            build_layout_A(c);
+        }
+        c->clear_flag();
+        HIPCHK(launch_ingest_bsr(b, p, c->SA.lay.slot_lanes, c->SA.src, vals, c->valA, c->pcol32,
+                                 c->flag, c->stream));
+        if (c->read_flag()) fail(MSP_ERR_NONFINITE);
+        c->haveA = true;
+        // adaptive SETUP (Sec. 3.2)
+        const bool rebuild = !c->hasB || c->Bn != n || c->Bb != b || c->Bp != p ||
+                             c->it_prev < 0 || c->it_prev > c->opt.mu;
+        c->info.rebuilt = rebuild ? 1 : 0;
+        c->info.rebuild_ms = 0.0;
+        if (rebuild) {
+            const double t1 = now_ms();
+            rebuild_B(c, vals);
+            c->info.rebuild_ms = now_ms() - t1;
+        }
+        return MSP_OK;
+    });
+    if (st != MSP_OK) {
+        try {
+            release_B(c);
+        } catch (...) {
+        }
+    }
+    c->info.status = st;
+    c->info.setup_ms = now_ms() - t0;
+    c->info.setup_calls = c->setup_calls;
+    c->info.n_levels = (int)c->lev.size();
+    for (int l = 0; l < MSP_MAX_LEVELS; ++l) {
+        c->info.level_rows[l] = l < (int)c->lev.size() ? c->lev[l].n : 0;
+        c->info.n_colors[l] = l < (int)c->lev.size() ? c->lev[l].g : 0;
+    }
+    c->info.bilu_levels_fwd = c->hasB ? (int)c->bilu.fwd_ptr.size() - 1 : 0;
+    c->info.bilu_levels_bwd = c->hasB ? (int)c->bilu.bwd_ptr.size() - 1 : 0;
+    return st;
+}
+
+int msp_solve(msp_ctx *c, const double *rhs, double *x, double rtol, msp_info *info)
+{
+    if (!c || !rhs || !x || !(rtol > 0.0)) return MSP_ERR_ARG;
+    if (!c->hasB || !c->haveA) return MSP_ERR_STATE;
+    const double t0 = now_ms();
+    int iters = 0, restarts = 0;
+    double relres = 0.0;
+    int st = guarded([&]() { return fgmres(c, rhs, x, rtol, iters, restarts, relres); });
+    c->info.status = st;
+    c->info.iterations = iters;
+    c->info.restarts = restarts;
+    c->info.rel_true_residual = relres;
+    c->info.solve_ms = now_ms() - t0;
+    c->solves++;
+    c->info.solves = c->solves;
+    c->it_prev = iters;
+    if (info) *info = c->info;
+    return st;
+}
+
+int msp_get_info(msp_ctx *c, msp_info *info)
+{
+    if (!c || !info) return MSP_ERR_ARG;
+    *info = c->info;
+    return MSP_OK;
+}
+
+int msp_footprint(int n, long long nnzb, int b, const msp_options *opt, size_t *bytes)
+{
+    if (!bytes || n < 1 || b < 1 || b > 8 || nnzb < n) return MSP_ERR_ARG;
+    msp_options o;
+    msp_default_options(&o);
+    if (opt) o = *opt;
+    const double E = (double)b * b;
+    const double slots = (double)nnzb * 1.15 + 64.0 * 64;  // slice padding bound
+    const double ts = o.precond_fp32 ? 4.0 : 8.0;
+    double A = slots * (E * 8 + 8) + (double)n * 8 + (o.precond_fp32 ? slots * b * 4 : 0);
+    double amg = 2.0 * ((double)nnzb * 1.15 * (8 + ts + 8)) + 8.0 * n * (3 * ts + 16);
+    double coarse = 8.0 * (double)o.max_coarse * o.max_coarse * 1.0;
+    double bilu = (double)nnzb * E * 8 + (double)n * E * 8 + 2 * slots * (E * ts + 8) +
+                  (double)n * (E * ts + 24);
+    double vecs = (double)n * b * (8 + 2 * ts) + (double)n * 8 * b;
+    double krylov = 8.0 * (double)n * b * (2.0 * o.restart + 4) + 8.0 * kDotBlocks * (o.restart + 2);
+    double setup_tmp = 8.0 * nnzb + 8.0 * (2 * 64.0 * o.max_coarse);
+    *bytes = (size_t)(A + amg + coarse + bilu + vecs + krylov + setup_tmp + (1 << 20));
+    return MSP_OK;
+}
+
+const char *msp_status_string(int s)
+{
+    switch (s) {
+    case MSP_OK: return "ok";
+    case MSP_ERR_ARG: return "invalid argument";
+    case MSP_ERR_PATTERN: return "invalid sparsity pattern";
+    case MSP_ERR_SINGULAR: return "singular block, pivot or diagonal";
+    case MSP_ERR_NONFINITE: return "non-finite value";
+    case MSP_ERR_NOMEM: return "out of memory";
+    case MSP_ERR_HIP: return "HIP runtime error";
+    case MSP_ERR_NO_DEVICE: return "no GPU device";
+    case MSP_ERR_STATE: return "no preconditioner: call msp_setup first";
+    case MSP_ERR_COARSE: return "coarsest level exceeds the dense limit";
+    case MSP_NOT_CONVERGED: return "not converged within max_iter";
+    default: return "unknown status";
+    }
+}
+
+// ---------------------------- stage entry points --------------------------
+int msp_stage_spmv(msp_ctx *c, const double *x, double *y)
+{
+    if (!c || !x || !y) return MSP_ERR_ARG;
+    if (!c->haveA) return MSP_ERR_STATE;
+    return guarded([&]() {
+        spmv(c, x, nullptr, y);
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+int msp_stage_precond(msp_ctx *c, const double *v, double *z)
+{
+    if (!c || !v || !z) return MSP_ERR_ARG;
+    if (!c->hasB || !c->haveA) return MSP_ERR_STATE;
+    return guarded([&]() {
+        apply(c, v, z);
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+
+int msp_stage_vcycle(msp_ctx *c, const double *f, double *e)
+{
+    if (!c || !f || !e) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    return guarded([&]() {
+        if (c->fp32())
+            stage_vcycle_T<float>(c, f, e);
+        else
+            stage_vcycle_T<double>(c, f, e);
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+
+int msp_stage_smooth(msp_ctx *c, int level, const double *f, double *x, int forward)
+{
+    if (!c || !f || !x) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    if (level < 0 || level >= (int)c->lev.size() - 1) return MSP_ERR_ARG;
+    return guarded([&]() {
+        if (c->fp32())
+            stage_smooth_T<float>(c, level, f, x, forward);
+        else
+            stage_smooth_T<double>(c, level, f, x, forward);
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+
+int msp_stage_bilu(msp_ctx *c, const double *r, double *z)
+{
+    if (!c || !r || !z) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    return guarded([&]() {
+        if (c->fp32())
+            stage_bilu_T<float>(c, r, z);
+        else
+            stage_bilu_T<double>(c, r, z);
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+int msp_stage_level_info(msp_ctx *c, int level, int *n, long long *nnz, int *ncolors,
+                         int *n_next)
+{
+    if (!c) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    if (level < 0 || level >= (int)c->lev.size()) return MSP_ERR_ARG;
+    const Level &L = c->lev[level];
+    if (n) *n = L.n;
+    if (nnz) *nnz = L.A.nnz();
+    if (ncolors) *ncolors = L.g;
+    if (n_next) *n_next = level + 1 < (int)c->lev.size() ? c->lev[level + 1].n : 0;
+    return MSP_OK;
+}
+
+int msp_stage_get_level(msp_ctx *c, int level, int *row_ptr, int *col_ind, double *val,
+                        int *color, int *agg)
+{
+    if (!c) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    if (level < 0 || level >= (int)c->lev.size()) return MSP_ERR_ARG;
+    const Level &L = c->lev[level];
+    const bool last = level == (int)c->lev.size() - 1;
+    if (row_ptr) std::memcpy(row_ptr, L.A.rp.data(), sizeof(int) * (L.n + 1));
+    if (col_ind) std::memcpy(col_ind, L.A.ci.data(), sizeof(int) * L.A.ci.size());
+    if (val) std::memcpy(val, L.A.val.data(), sizeof(double) * L.A.val.size());
+    if (!last) {
+        if (color) std::memcpy(color, L.color.data(), sizeof(int) * L.n);
+        if (agg) std::memcpy(agg, L.agg.data(), sizeof(int) * L.n);
+    }
+    return MSP_OK;
+}
+
+int msp_stage_get_level_f32(msp_ctx *c, int level, float *val)
+{
+    if (!c || !val) return MSP_ERR_ARG;
+    if (!c->hasB || !c->fp32()) return MSP_ERR_STATE;
+    if (level < 0 || level >= (int)c->lev.size() - 1) return MSP_ERR_ARG;
+    return guarded([&]() {
+        const Level &L = c->lev[level];
+        // off-diagonal entries from the device layout, diagonal from the device array
+        ungather<float>(c, L.S, L.val32, 1, val);
+        std::vector<float> d(L.n);
+        HIPCHK(hipMemcpyAsync(d.data(), L.diag32, sizeof(float) * L.n, hipMemcpyDeviceToHost,
+                              c->stream));
+        c->sync();
+        for (int t = 0; t < L.n; ++t) {
+            int i = L.iperm[t];
+            for (int k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k)
+                if (L.A.ci[k] == i) val[k] = d[t];
+        }
+        return MSP_OK;
+    });
+}
+
+int msp_stage_get_omega(msp_ctx *c, double *omega)
+{
+    if (!c || !omega) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    return guarded([&]() {
+        HIPCHK(hipMemcpyAsync(omega, c->omega, sizeof(double) * (size_t)c->Bn * c->Bb,
+                              hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+int msp_stage_get_bilu(msp_ctx *c, double *F, double *Dinv)
+{
+    if (!c) return MSP_ERR_ARG;
+    if (!c->hasB) return MSP_ERR_STATE;
+    return guarded([&]() {
+        const long long E = (long long)c->Bb * c->Bb;
+        if (F)
+            HIPCHK(hipMemcpyAsync(F, c->bilu.F, sizeof(double) * c->Bnnzb * E,
+                                  hipMemcpyDeviceToHost, c->stream));
+        if (Dinv)
+            HIPCHK(hipMemcpyAsync(Dinv, c->bilu.Dinv, sizeof(double) * (size_t)c->Bn * E,
+                                  hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+int msp_stage_get_bilu_f32(msp_ctx *c, float *F, float *Dinv)
+{
+    if (!c) return MSP_ERR_ARG;
+    if (!c->hasB || !c->fp32()) return MSP_ERR_STATE;
+    return guarded([&]() {
+        const long long E = (long long)c->Bb * c->Bb;
+        BiluData &D = c->bilu;
+        if (F) {
+            // diagonal slots are not stored in the FP32 layouts; fill them from FP64 F
+            std::vector<double> F64((size_t)(c->Bnnzb * E));
+            HIPCHK(hipMemcpyAsync(F64.data(), D.F, sizeof(double) * c->Bnnzb * E,
+                                  hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            for (long long q = 0; q < c->Bnnzb * E; ++q) F[q] = (float)F64[q];
+            ungather<float>(c, D.L, D.L32, E, F);
+            ungather<float>(c, D.U, D.U32, E, F);
+        }
+        if (Dinv) {
+            const long long dsl = (long long)D.U.lay.slice_row0.size() * 64;
+            std::vector<float> h((size_t)(dsl * E));
+            HIPCHK(hipMemcpyAsync(h.data(), D.D32, sizeof(float) * dsl * E, hipMemcpyDeviceToHost,
+                                  c->stream));
+            c->sync();
+            for (size_t s = 0; s < D.U.lay.slice_row0.size(); ++s)
+                for (int l = 0; l < D.U.lay.slice_rows[s]; ++l) {
+                    int i = D.bwd_rows[D.U.lay.slice_row0[s] + l];
+                    for (long long e = 0; e < E; ++e)
+                        Dinv[(long long)i * E + e] = h[s * 64 * E + e * 64 + l];
+                }
+        }
+        return MSP_OK;
+    });
+}
+
+}  // extern "C"

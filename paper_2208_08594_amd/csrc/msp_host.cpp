@@ -1,0 +1,324 @@
+// Host-side setup of libmsp (see msp_host.h).  Compiled with -ffp-contract=off:
+// the aggregation decisions and Galerkin sums must round exactly as written.
+#include "msp_host.h"
+
+#include <algorithm>
+#include <numeric>
+#include <queue>
+
+namespace msp {
+
+int check_pattern(int n, const int *rp, const int *ci, long long nnz)
+{
+    if (rp[0] != 0 || (long long)rp[n] != nnz) return -2;
+    for (int i = 0; i < n; ++i) {
+        int a = rp[i], b = rp[i + 1];
+        if (b <= a) return -2;
+        bool diag = false;
+        for (int k = a; k < b; ++k) {
+            int j = ci[k];
+            if (j < 0 || j >= n) return -2;
+            if (k > a && j <= ci[k - 1]) return -2;
+            diag |= (j == i);
+        }
+        if (!diag) return -2;
+    }
+    return 0;
+}
+
+Adjacency build_adjacency(int n, const int *rp, const int *ci)
+{
+    // count both directions of every off-diagonal entry, then sort + dedupe
+    std::vector<int> cnt(n + 1, 0);
+    for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] != i) { ++cnt[i + 1]; ++cnt[ci[k] + 1]; }
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int> buf(cnt[n]);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            int j = ci[k];
+            if (j == i) continue;
+            buf[fill[i]++] = j;
+            buf[fill[j]++] = i;
+        }
+    Adjacency G;
+    G.n = n;
+    G.ptr.assign(n + 1, 0);
+    G.nbr.reserve(buf.size());
+    for (int i = 0; i < n; ++i) {
+        auto b0 = buf.begin() + cnt[i], b1 = buf.begin() + cnt[i + 1];
+        std::sort(b0, b1);
+        auto e = std::unique(b0, b1);
+        G.nbr.insert(G.nbr.end(), b0, e);
+        G.ptr[i + 1] = (int)G.nbr.size();
+    }
+    return G;
+}
+
+int vertices_grouping(const Adjacency &G, std::vector<int> &color)
+{
+    const int n = G.n;
+    color.assign(n, 0);
+    // Static priority: larger |S_i| first, smaller index on ties (Alg. 4.1 picks
+    // any vertex of maximal |S_i|; the lowest index makes the choice unique).
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        int da = G.degree(a), db = G.degree(b);
+        return da != db ? da > db : a < b;
+    });
+    struct Cand {
+        int deg, v;
+    };
+    auto lower_priority = [](const Cand &a, const Cand &b) {
+        return a.deg != b.deg ? a.deg < b.deg : a.v > b.v;
+    };
+    std::vector<unsigned char> open(n), queued(n);
+    int left = n, g = 0;
+    while (left > 0) {
+        ++g;  // one call of VerticesSplitting builds group g
+        int avail = 0;
+        for (int i = 0; i < n; ++i) {
+            open[i] = color[i] == 0;  // V: undetermined vertices
+            queued[i] = 0;
+            avail += open[i];
+        }
+        std::priority_queue<Cand, std::vector<Cand>, decltype(lower_priority)> hat(lower_priority);
+        size_t cursor = 0;
+        while (avail > 0) {
+            int v = -1;
+            while (!hat.empty()) {  // second-ring candidates W^ that are still in V
+                int t = hat.top().v;
+                hat.pop();
+                if (open[t]) { v = t; break; }
+            }
+            if (v < 0) {
+                while (!open[order[cursor]]) ++cursor;
+                v = order[cursor];
+            }
+            color[v] = g;  // v joins W
+            open[v] = 0;
+            --avail;
+            --left;
+            for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // S_v leaves V (W-bar)
+                int u = G.nbr[q];
+                if (open[u]) { open[u] = 0; --avail; }
+            }
+            for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // second ring enters W^
+                int u = G.nbr[q];
+                for (int t = G.ptr[u]; t < G.ptr[u + 1]; ++t) {
+                    int w = G.nbr[t];
+                    if (open[w] && !queued[w]) {
+                        queued[w] = 1;
+                        hat.push({G.degree(w), w});
+                    }
+                }
+            }
+        }
+    }
+    return g;
+}
+
+static inline double entry(const Csr &A, int i, int j)
+{
+    auto b = A.ci.begin() + A.rp[i], e = A.ci.begin() + A.rp[i + 1];
+    auto it = std::lower_bound(b, e, j);
+    return (it != e && *it == j) ? A.val[it - A.ci.begin()] : 0.0;
+}
+
+int pairwise_pass(const Csr &A, std::vector<int> &agg)
+{
+    const int n = A.n;
+    Adjacency G = build_adjacency(n, A.rp.data(), A.ci.data());
+    // strength s_ij = -(a_ij + a_ji)/2 on the symmetrised neighbours
+    std::vector<double> s(G.nbr.size());
+    std::vector<double> smax(n, 0.0);
+    std::vector<unsigned char> eligible(n, 0);
+    for (int i = 0; i < n; ++i) {
+        bool coupled = false;
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] != i && A.val[k] != 0.0) coupled = true;
+        double mx = 0.0;
+        bool any = false;
+        for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
+            int j = G.nbr[q];
+            s[q] = -(entry(A, i, j) + entry(A, j, i)) / 2.0;
+            if (!any || s[q] > mx) mx = s[q];
+            any = true;
+        }
+        smax[i] = mx;
+        eligible[i] = coupled && any && mx > 0.0;
+    }
+    agg.assign(n, -1);
+    int nc = 0;
+    for (int i = 0; i < n; ++i) {
+        if (agg[i] >= 0) continue;
+        int best = -1;
+        double bs = 0.0;
+        if (eligible[i]) {
+            const double thr = 0.25 * smax[i];
+            for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
+                int j = G.nbr[q];
+                if (agg[j] >= 0 || !eligible[j]) continue;
+                if (s[q] >= thr && (best < 0 || s[q] > bs)) { best = j; bs = s[q]; }
+            }
+        }
+        agg[i] = nc;
+        if (best >= 0) agg[best] = nc;
+        ++nc;
+    }
+    return nc;
+}
+
+Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc)
+{
+    const int n = A.n;
+    std::vector<int> mptr(nc + 1, 0), mem(n);
+    for (int i = 0; i < n; ++i) ++mptr[agg[i] + 1];
+    for (int I = 0; I < nc; ++I) mptr[I + 1] += mptr[I];
+    {
+        std::vector<int> f(mptr.begin(), mptr.end() - 1);
+        for (int i = 0; i < n; ++i) mem[f[agg[i]]++] = i;  // ascending fine index
+    }
+    Csr C;
+    C.n = nc;
+    C.rp.assign(nc + 1, 0);
+    C.ci.reserve(A.ci.size());
+    C.val.reserve(A.ci.size());
+    std::vector<int> slot(nc, -1), cols;
+    std::vector<double> vals;
+    std::vector<int> idx;
+    for (int I = 0; I < nc; ++I) {
+        cols.clear();
+        vals.clear();
+        for (int m = mptr[I]; m < mptr[I + 1]; ++m) {
+            int i = mem[m];
+            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                int J = agg[A.ci[k]];
+                if (slot[J] < 0) {
+                    slot[J] = (int)cols.size();
+                    cols.push_back(J);
+                    vals.push_back(A.val[k]);
+                } else {
+                    vals[slot[J]] = vals[slot[J]] + A.val[k];
+                }
+            }
+        }
+        idx.resize(cols.size());
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+        for (int q : idx) {
+            C.ci.push_back(cols[q]);
+            C.val.push_back(vals[q]);
+            slot[cols[q]] = -1;
+        }
+        C.rp[I + 1] = (int)C.ci.size();
+    }
+    return C;
+}
+
+int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H)
+{
+    H = Hierarchy();
+    H.A.push_back(std::move(A0));
+    for (int l = 0;; ++l) {
+        const Csr &cur = H.A[l];
+        bool last = cur.n <= max_coarse || l == max_levels - 1 ||
+                    (l > 0 && (double)cur.n > 0.9 * (double)H.A[l - 1].n);
+        if (last) break;
+        std::vector<int> color;
+        Adjacency G = build_adjacency(cur.n, cur.rp.data(), cur.ci.data());
+        int g = vertices_grouping(G, color);
+        std::vector<int> a1, a2;
+        int nc1 = pairwise_pass(cur, a1);
+        Csr M1 = galerkin(cur, a1, nc1);
+        int nc2 = pairwise_pass(M1, a2);
+        Csr Cn = galerkin(M1, a2, nc2);
+        std::vector<int> agg(cur.n);
+        for (int i = 0; i < cur.n; ++i) agg[i] = a2[a1[i]];
+        H.color.push_back(std::move(color));
+        H.agg.push_back(std::move(agg));
+        H.ncolors.push_back(g);
+        H.A.push_back(std::move(Cn));
+    }
+    for (size_t l = 0; l + 1 < H.A.size(); ++l) {
+        const Csr &A = H.A[l];
+        for (int i = 0; i < A.n; ++i) {
+            double d = entry(A, i, i);
+            if (d == 0.0) return -3;
+        }
+    }
+    if (H.A.back().n > max_dense) return -9;
+    return 0;
+}
+
+void triangular_levels(int n, const int *rp, const int *ci, const std::vector<int> &ord,
+                       bool lower, std::vector<int> &rows_by_level, std::vector<int> &level_ptr)
+{
+    std::vector<int> pos(n), lev(n, 0);
+    for (int t = 0; t < n; ++t) pos[ord[t]] = t;
+    int maxlev = 0;
+    for (int s = 0; s < n; ++s) {
+        int t = lower ? s : n - 1 - s;
+        int i = ord[t];
+        int l = 0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            int j = ci[k];
+            bool dep = lower ? pos[j] < t : pos[j] > t;
+            if (dep) l = std::max(l, lev[j] + 1);
+        }
+        lev[i] = l;
+        maxlev = std::max(maxlev, l);
+    }
+    level_ptr.assign(maxlev + 2, 0);
+    for (int i = 0; i < n; ++i) ++level_ptr[lev[i] + 1];
+    for (int l = 0; l <= maxlev; ++l) level_ptr[l + 1] += level_ptr[l];
+    rows_by_level.assign(n, 0);
+    std::vector<int> f(level_ptr.begin(), level_ptr.end() - 1);
+    for (int s = 0; s < n; ++s) {
+        int i = ord[lower ? s : n - 1 - s];
+        rows_by_level[f[lev[i]]++] = i;
+    }
+}
+
+void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
+                const std::vector<int> &ent_col, const std::vector<int> &ent_src, SellLayout &L)
+{
+    L = SellLayout();
+    L.nrows = nrows;
+    const int nseg = (int)seg_row.size() - 1;
+    L.seg_slice.assign(nseg + 1, 0);
+    int off = 0;
+    for (int s = 0; s < nseg; ++s) {
+        L.seg_slice[s] = (int)L.slice_row0.size();
+        for (int r0 = seg_row[s]; r0 < seg_row[s + 1]; r0 += 64) {
+            int rows = std::min(64, seg_row[s + 1] - r0);
+            int w = 0;
+            for (int t = r0; t < r0 + rows; ++t) w = std::max(w, ent_ptr[t + 1] - ent_ptr[t]);
+            L.slice_row0.push_back(r0);
+            L.slice_rows.push_back(rows);
+            L.slice_width.push_back(w);
+            L.slice_off.push_back(off);
+            off += w * 64;
+        }
+    }
+    L.seg_slice[nseg] = (int)L.slice_row0.size();
+    L.slot_lanes = off;
+    L.col.assign(off, -1);
+    L.src.assign(off, -1);
+    for (size_t s = 0; s < L.slice_row0.size(); ++s) {
+        for (int l = 0; l < L.slice_rows[s]; ++l) {
+            int t = L.slice_row0[s] + l;
+            for (int k = ent_ptr[t]; k < ent_ptr[t + 1]; ++k) {
+                int slot = k - ent_ptr[t];
+                long q = (long)L.slice_off[s] + slot * 64 + l;
+                L.col[q] = ent_col[k];
+                L.src[q] = ent_src[k];
+            }
+        }
+    }
+}
+
+}  // namespace msp

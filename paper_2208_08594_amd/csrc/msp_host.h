@@ -1,0 +1,77 @@
+// Host-side setup of libmsp: pattern checks, the adjacency-graph grouping of
+// Alg. 4.1/4.2, pairwise aggregation, Galerkin products, block-ILU(0)
+// dependency levels and the sliced-ELL device layout.  Plain C++, no HIP.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace msp {
+
+// Scalar CSR matrix (one AMG level).
+struct Csr {
+    int n = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> val;
+    long long nnz() const { return rp.empty() ? 0 : rp[n]; }
+};
+
+// Returns 0, or -2 (pattern error) for a BSR/CSR pattern that is not
+// monotone / in range / strictly ascending per row / holding every diagonal.
+int check_pattern(int n, const int *rp, const int *ci, long long nnz);
+
+// Symmetrised off-diagonal adjacency (Sec. 4.1 with A and A^T together),
+// sorted neighbour lists.
+struct Adjacency {
+    int n = 0;
+    std::vector<int> ptr, nbr;
+    int degree(int i) const { return ptr[i + 1] - ptr[i]; }
+};
+Adjacency build_adjacency(int n, const int *rp, const int *ci);
+
+// Alg. 4.2 (VerticesGrouping) around Alg. 4.1 (VerticesSplitting): color[i]
+// in 1..g, returns g.  Largest static degree first, lowest index on ties,
+// second-ring candidates before the rest.
+int vertices_grouping(const Adjacency &G, std::vector<int> &color);
+
+// One pairwise-matching pass; agg[i] in [0, nc), returns nc.
+int pairwise_pass(const Csr &A, std::vector<int> &agg);
+
+// Galerkin product P^T A P for a piecewise-constant P given by agg; entries
+// summed in (fine row, fine column) ascending order, structural pattern.
+Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc);
+
+// AMG hierarchy (Sec. 5): levels[0] = A0, ..., levels.back() = coarsest;
+// colors/aggs for every non-coarsest level.  Returns 0 or a negative code
+// (-3: zero diagonal on a smoothed level, -9: coarsest level too large).
+struct Hierarchy {
+    std::vector<Csr> A;
+    std::vector<std::vector<int>> color, agg;
+    std::vector<int> ncolors;
+};
+int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H);
+
+// Dependency levels of a block triangular solve restricted to the stored
+// pattern: lower = true gives level(i) = 1 + max level(k) over stored k < i
+// in the order `ord` (ord[t] = block row at position t of the elimination
+// order); upper = reverse.  Returns the positions sorted by level (stable) and
+// the level boundaries.
+void triangular_levels(int n, const int *rp, const int *ci, const std::vector<int> &ord,
+                       bool lower, std::vector<int> &rows_by_level, std::vector<int> &level_ptr);
+
+// Sliced ELL with 64-row slices that never straddle a segment boundary.
+struct SellLayout {
+    int nrows = 0;                    // positions
+    std::vector<int> seg_slice;       // nseg+1 slice boundaries
+    std::vector<int> slice_row0, slice_rows, slice_width, slice_off;  // off in slot-lanes
+    long long slot_lanes = 0;         // sum of width*64
+    std::vector<int> col;             // [slot_lanes], -1 = padding
+    std::vector<int> src;             // [slot_lanes], source entry id or -1
+};
+// seg_row: segment boundaries over positions (size nseg+1); per position t its
+// entries ent_ptr[t]..ent_ptr[t+1] with columns ent_col and source ids ent_src.
+void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
+                const std::vector<int> &ent_col, const std::vector<int> &ent_src,
+                SellLayout &L);
+
+}  // namespace msp

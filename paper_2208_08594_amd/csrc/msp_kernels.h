@@ -1,0 +1,128 @@
+// Launchers of the libmsp HIP kernels (gfx950, wave64).  Every launcher
+// enqueues on `st` and returns hipSuccess or the launch error.  Matrices in
+// the sliced-ELL layout: slices of 64 rows; slice s = {row0, rows, width, off}
+// (off in slot-lanes, a multiple of 64); entry e of slot k of lane l lives at
+// val[((off/64) + k) * 64 * E + e * 64 + l], column index at col[off + k*64 + l].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace msp {
+
+struct SellView {
+    const int4 *slices = nullptr;  // {row0, rows, width, off}
+    const int *col = nullptr;
+    int slice_begin = 0, slice_end = 0;
+};
+
+// ---- ingest / layout ----------------------------------------------------
+// Copy BSR blocks (row-major, b*b) into the sliced layout: dst entry (q, e) =
+// vals[src[q]*b*b + e] (0 where src < 0).  Sets *bad to 1 if a value is not
+// finite.  If dst32 != nullptr also writes the FP32 pressure column
+// (E = b: entry r = (float)block[r][p]).
+hipError_t launch_ingest_bsr(int b, int p, long long slot_lanes, const int *src,
+                             const double *vals, double *dst, float *dst32_pcol, int *bad,
+                             hipStream_t st);
+// Generic block gather into a sliced layout of E = b*b entries, converting
+// to float when dst32 != nullptr (RNE) else copying to dst64.
+hipError_t launch_gather_blocks(int b, long long slot_lanes, const int *src, const double *blocks,
+                                double *dst64, float *dst32, hipStream_t st);
+hipError_t launch_check_finite(const double *x, long long n, int *bad, hipStream_t st);
+hipError_t launch_round_f32(const double *x, float *y, long long n, hipStream_t st);
+
+// ---- decoupling (ABF) ----------------------------------------------------
+// omega[c*b..] = row p of D_c^{-1}; ap[k] = sum_r omega_c[r] * A_k[r][p] for
+// the blocks of row c.  Fixed evaluation order without contraction.
+hipError_t launch_decouple(int b, int p, int n, const int *rp, const int *diag_pos,
+                           const double *vals, double *omega, double *ap, int *bad,
+                           hipStream_t st);
+
+// ---- block ILU(0) factorisation ----------------------------------------
+struct BiluTasks {
+    const int *rows = nullptr;     // block rows of this level
+    int nrows = 0;
+    const int *lt_ptr = nullptr;   // per block row: lower tasks [lt_ptr[i], lt_ptr[i+1])
+    const int *lt_kk = nullptr;    // BSR slot of F_ik
+    const int *lt_k = nullptr;     // k
+    const int *lt_pp = nullptr;    // first update pair of the task (size ntasks+1)
+    const int *pr_jj = nullptr;    // slot of F_ij
+    const int *pr_kj = nullptr;    // slot of F_kj
+    const int *diag_pos = nullptr;
+};
+hipError_t launch_bilu_factor_level(int b, const BiluTasks &t, double *F, double *Dinv, int *bad,
+                                    hipStream_t st);
+
+// ---- SpMV -----------------------------------------------------------------
+// y[row] = A x (or sub - A x when sub != nullptr), FP64, natural rows.
+hipError_t launch_spmv(int b, const SellView &A, const double *val, const double *x,
+                       const double *sub, double *y, hipStream_t st);
+
+// ---- preconditioner pieces (T = float or double) ------------------------
+template <typename T>
+hipError_t launch_decouple_restrict(int b, int n, const int *iperm0, const double *omega,
+                                    const double *v, T *g, hipStream_t st);
+template <typename T>
+hipError_t launch_gs_first(const SellView &seg0, int npos, const T *diag, const T *f, T *x,
+                           int seg0_begin, int seg0_end, hipStream_t st);
+template <typename T>
+hipError_t launch_gs_color(const SellView &seg, const T *val, const T *diag, const T *f, T *x,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_residual(const SellView &all, const T *val, const T *diag, const T *f,
+                           const T *x, T *r, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *r, T *fc,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse_gemv(int n, const double *inv, const T *f, T *x, hipStream_t st);
+template <typename T>
+hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hipStream_t st);
+// r_c[k] = v_c[k] - sum_d A_cd[k][p] e_d; pcol64: FP64 A (E = b*b, entry k*b+p);
+// pcol32: FP32 pressure columns (E = b).
+template <typename T>
+hipError_t launch_pcol_residual(int b, int p, const SellView &A, const double *val64,
+                                const float *pcol32, const double *v, const T *e, T *r,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_bilu_fwd(int b, const SellView &L, const int *rows, const T *Lval, T *y,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *Uval,
+                           const T *Dval, T *z, hipStream_t st);
+template <typename T>
+hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, double *z, hipStream_t st);
+template <typename T>
+hipError_t launch_to_double(long long n, const T *x, double *y, hipStream_t st);
+template <typename T>
+hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st);
+
+// ---- Krylov (FP64) --------------------------------------------------------
+constexpr int kDotBlocks = 1024;
+// partial[blk * nv + i] = sum over the block's chunk of V_i . w  (V_i = V + i*ldv)
+hipError_t launch_dot_multi(long long N, int nv, const double *V, long long ldv, const double *w,
+                            double *partial, hipStream_t st);
+// out[i] = sum_blk partial[blk*nv + i] (+ out[i] if accumulate)
+hipError_t launch_reduce_partials(int nv, const double *partial, double *out, int accumulate,
+                                  hipStream_t st);
+// w -= sum_i h[i] V_i
+hipError_t launch_axpy_multi(long long N, int nv, const double *V, long long ldv,
+                             const double *h, double *w, hipStream_t st);
+// y = x / s
+hipError_t launch_scale(long long N, const double *x, double s, double *y, hipStream_t st);
+// x += sum_i y[i] Z_i
+hipError_t launch_update_x(long long N, int k, const double *Z, long long ldz, const double *y,
+                           double *x, hipStream_t st);
+hipError_t launch_fill(long long N, double v, double *x, hipStream_t st);
+
+// ---- dense coarsest level ---------------------------------------------------
+hipError_t launch_dense_scatter(int n, const int *rp, const int *ci, const double *val, double *M,
+                                hipStream_t st);
+// In-place inverse of the n x n row-major matrix M by block Gauss-Jordan with
+// partial pivoting inside each diagonal block.  work >= (2*n*64 + 64*64) doubles.
+hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t st);
+
+}  // namespace msp

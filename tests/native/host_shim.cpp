@@ -1,0 +1,63 @@
+// Test-only C shim over the library's host setup code (msp_host.cpp), so the
+// CPU suite can compare its grouping, matching and Galerkin products with the
+// oracle without a GPU.
+#include <cstring>
+#include <vector>
+
+#include "msp_host.h"
+
+extern "C" {
+
+int shim_color(int n, const int *rp, const int *ci, int *color)
+{
+    msp::Adjacency G = msp::build_adjacency(n, rp, ci);
+    std::vector<int> c;
+    int g = msp::vertices_grouping(G, c);
+    std::memcpy(color, c.data(), sizeof(int) * n);
+    return g;
+}
+
+static msp::Csr make(int n, const int *rp, const int *ci, const double *val)
+{
+    msp::Csr A;
+    A.n = n;
+    A.rp.assign(rp, rp + n + 1);
+    A.ci.assign(ci, ci + rp[n]);
+    A.val.assign(val, val + rp[n]);
+    return A;
+}
+
+int shim_pair(int n, const int *rp, const int *ci, const double *val, int *agg)
+{
+    std::vector<int> a;
+    int nc = msp::pairwise_pass(make(n, rp, ci, val), a);
+    std::memcpy(agg, a.data(), sizeof(int) * n);
+    return nc;
+}
+
+long long shim_galerkin(int n, const int *rp, const int *ci, const double *val, const int *agg,
+                        int nc, int *crp, int *cci, double *cval)
+{
+    std::vector<int> a(agg, agg + n);
+    msp::Csr C = msp::galerkin(make(n, rp, ci, val), a, nc);
+    std::memcpy(crp, C.rp.data(), sizeof(int) * (nc + 1));
+    std::memcpy(cci, C.ci.data(), sizeof(int) * C.ci.size());
+    std::memcpy(cval, C.val.data(), sizeof(double) * C.val.size());
+    return (long long)C.ci.size();
+}
+
+int shim_pattern(int n, const int *rp, const int *ci, long long nnz)
+{
+    return msp::check_pattern(n, rp, ci, nnz);
+}
+
+// levels of a triangular solve in natural order; returns the number of levels
+int shim_levels(int n, const int *rp, const int *ci, int lower, int *rows_by_level)
+{
+    std::vector<int> ord(n), rows, ptr;
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    msp::triangular_levels(n, rp, ci, ord, lower != 0, rows, ptr);
+    std::memcpy(rows_by_level, rows.data(), sizeof(int) * n);
+    return (int)ptr.size() - 1;
+}
+}

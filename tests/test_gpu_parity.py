@@ -1,0 +1,341 @@
+"""GPU parity: every step of the HIP path (through the libmsp C-ABI) against the
+CPU oracle on the same seeded inputs.
+
+Bars:
+  * integer work (groups, aggregates, sparsity patterns) and the FP64 setup
+    values that decide it (decoupled pressure matrix, Galerkin products):
+    bit-exact;
+  * FP64 kernels: relative error <= 1e-12 (SpMV, GS sweep, BILU factors and
+    solve, preconditioner without the coarsest solve); the coarsest level is
+    an explicit inverse on the GPU and LU factors in the oracle, so stages
+    that include it are held to kappa(A_L) * 1e-15 (at most 1e-10 here);
+  * FGMRES: the same iteration count +-1 and both true residuals <= rtol;
+  * FP32 preconditioner: stored values equal RNE(FP64), bit for bit, and the
+    apply agrees with the oracle's FP32 apply to 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2208_08594_amd import msp, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def solvers(sys, max_coarse=10000, fp32=False, mu=0):
+    announce(sys.name, f"n={sys.n} b={sys.b} max_coarse={max_coarse} fp32={fp32} mu={mu}")
+    g = msp.Solver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu)
+    g.setup(sys)
+    o = O.OracleSolver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu)
+    o.setup(sys)
+    return g, o
+
+
+CASES = [
+    ("cfg0", lambda: synth.config(0), 10000),
+    ("cfg0-mc64", lambda: synth.config(0), 64),
+    ("grid20x18x9b3", lambda: synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4"), 200),
+    ("grid13x11x7b7", lambda: synth.lognormal_grid(13, 11, 7, 7, 8, 1.0, 0.1, "lateral4"), 100),
+    ("grid33x17x5b2", lambda: synth.lognormal_grid(33, 17, 5, 2, 9, 1.5, 1.0, "corners2"), 150),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    name, mk, mc = request.param
+    sys = mk()
+    g, o = solvers(sys, mc)
+    yield sys, g, o
+    g.close()
+    o.close()
+
+
+# --------------------------------------------------------------------------
+# setup: bit-exact integer work and the values that decide it
+# --------------------------------------------------------------------------
+def test_hierarchy_bit_exact(case):
+    sys, g, o = case
+    assert g.nlevels == o.nlevels
+    for l in range(o.nlevels):
+        a, b = g.level(l), o.level(l)
+        assert a["n"] == b["n"]
+        assert np.array_equal(a["row_ptr"], b["row_ptr"])
+        assert np.array_equal(a["col_ind"], b["col_ind"])
+        assert np.array_equal(a["val"], b["val"]), f"level {l} values"
+        if l < o.nlevels - 1:
+            assert a["ncolors"] == b["ncolors"]
+            assert np.array_equal(a["color"], b["color"])
+            assert np.array_equal(a["agg"], b["agg"])
+
+
+def test_decoupling_weights_exact(case):
+    sys, g, o = case
+    assert np.array_equal(g.omega(), o.omega())
+
+
+def test_bilu_factors(case):
+    sys, g, o = case
+    Fg, Dg = g.bilu()
+    Fo, Do = o.bilu()
+    assert relerr(Fg, Fo) <= 1e-12 and relerr(Dg, Do) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# kernels
+# --------------------------------------------------------------------------
+def test_spmv(case):
+    sys, g, o = case
+    x = np.random.default_rng(1).uniform(-1, 1, sys.N)
+    yg = to_np(g.spmv(x))
+    yo = o.spmv(x)
+    # row-scaled bound: |err| <= 1e-13 * (|A| |x|)_row
+    absA = np.abs(sys.vals)
+    scale = np.zeros(sys.N)
+    for c in range(sys.n):
+        for k in range(sys.row_ptr[c], sys.row_ptr[c + 1]):
+            d = sys.col_ind[k]
+            scale[c * sys.b:(c + 1) * sys.b] += absA[k] @ np.abs(x[d * sys.b:(d + 1) * sys.b])
+    assert np.all(np.abs(yg - yo) <= 1e-13 * scale + 1e-300)
+
+
+def test_gs_sweeps(case):
+    sys, g, o = case
+    rng = np.random.default_rng(2)
+    for l in range(o.nlevels - 1):
+        L = o.level(l)
+        f = rng.uniform(-1, 1, L["n"])
+        x0 = rng.uniform(-1, 1, L["n"])
+        for fwd in (True, False):
+            xo = O.gs_sweep(L["row_ptr"], L["col_ind"], L["val"], L["color"], L["ncolors"], f, x0, fwd)
+            xg = to_np(g.smooth(l, f, x0, fwd))
+            assert relerr(xg, xo) <= 1e-12, (l, fwd)
+
+
+def test_bilu_solve(case):
+    sys, g, o = case
+    r = np.random.default_rng(3).uniform(-1, 1, sys.N)
+    assert relerr(to_np(g.bilu_apply(r)), o.bilu_apply(r)) <= 1e-12
+
+
+def _coarse_tol(o):
+    Lc = o.level(o.nlevels - 1)
+    m = Lc["n"]
+    A = np.zeros((m, m))
+    for i in range(m):
+        A[i, Lc["col_ind"][Lc["row_ptr"][i]:Lc["row_ptr"][i + 1]]] = \
+            Lc["val"][Lc["row_ptr"][i]:Lc["row_ptr"][i + 1]]
+    kappa = np.linalg.cond(A)
+    return max(1e-12, min(1e-10, kappa * 1e-15))
+
+
+def test_vcycle(case):
+    sys, g, o = case
+    f = np.random.default_rng(4).uniform(-1, 1, sys.n)
+    assert relerr(to_np(g.vcycle(f)), o.vcycle(f)) <= _coarse_tol(o)
+
+
+def test_preconditioner_apply(case):
+    sys, g, o = case
+    v = np.random.default_rng(5).uniform(-1, 1, sys.N)
+    assert relerr(to_np(g.apply(v)), o.apply(v)) <= _coarse_tol(o)
+
+
+def test_fgmres_solve(case):
+    sys, g, o = case
+    xg, ig = g.solve(sys.rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-6)
+    assert ig["status"] == 0 and st == 0
+    assert abs(ig["iterations"] - it) <= 1, (ig["iterations"], it)
+    assert ig["rel_true_residual"] <= 1e-6 and rr <= 1e-6
+    xg = to_np(xg)
+    A = sys.to_dense() if sys.N <= 8000 else None
+    if A is not None:
+        assert np.linalg.norm(sys.rhs - A @ xg) / np.linalg.norm(sys.rhs) <= 1e-6
+    assert relerr(xg, xo) <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# FP32 preconditioner
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mc", [10000, 64])
+def test_fp32_storage_is_rne_of_fp64(mc):
+    sys = synth.config(0)
+    g, o = solvers(sys, mc, fp32=True)
+    for l in range(o.nlevels - 1):
+        v32 = g.level_f32(l)
+        assert np.array_equal(v32, o.level(l)["val"].astype(np.float32))
+    F64, D64 = g.bilu(False)
+    F32, D32 = g.bilu(True)
+    assert np.array_equal(F32, F64.astype(np.float32)) and np.array_equal(D32, D64.astype(np.float32))
+    v = np.random.default_rng(6).uniform(-1, 1, sys.N)
+    assert relerr(to_np(g.apply(v)), o.apply(v)) <= 1e-5
+    xg, ig = g.solve(sys.rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-6)
+    assert abs(ig["iterations"] - it) <= 1 and ig["rel_true_residual"] <= 1e-6
+
+
+def test_fp32_vs_fp64_same_final_residual():
+    sys = synth.lognormal_grid(24, 24, 12, 4, 3, 1.5, 0.1, "lateral4")
+    announce(sys.name, "fp32 vs fp64")
+    g64 = msp.Solver(max_coarse=500)
+    g32 = msp.Solver(max_coarse=500, precond_fp32=True)
+    g64.setup(sys)
+    g32.setup(sys)
+    x64, i64 = g64.solve(sys.rhs, rtol=1e-6)
+    x32, i32 = g32.solve(sys.rhs, rtol=1e-6)
+    assert abs(i64["iterations"] - i32["iterations"]) <= 1
+    assert i32["rel_true_residual"] <= 1e-6 and i64["rel_true_residual"] <= 1e-6
+    assert relerr(to_np(x32), to_np(x64)) <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# shapes: block sizes, ragged slices, degenerate sizes, nonsymmetric patterns
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [1, 2, 3, 5, 6, 8])
+def test_block_sizes(b):
+    sys = synth.lognormal_grid(11, 7, 5, b, 20 + b, 1.0, 1.0, "corners2")
+    g, o = solvers(sys, 40)
+    x = np.random.default_rng(b).uniform(-1, 1, sys.N)
+    assert relerr(to_np(g.spmv(x)), o.spmv(x)) <= 1e-13
+    assert relerr(to_np(g.apply(x)), o.apply(x)) <= _coarse_tol(o)
+    xg, ig = g.solve(sys.rhs, rtol=1e-8)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-8)
+    assert abs(ig["iterations"] - it) <= 1 and ig["rel_true_residual"] <= 1e-8
+
+
+def test_single_cell_and_tiny():
+    for shape in [(1, 1, 1), (2, 1, 1), (3, 2, 1)]:
+        sys = synth.lognormal_grid(*shape, 3, 1, 1.0, 1.0, "none")
+        g, o = solvers(sys, 10000)
+        xg, ig = g.solve(sys.rhs, rtol=1e-10)
+        xo, it, rr, st = o.solve(sys.rhs, 1e-10)
+        assert ig["iterations"] == it and ig["rel_true_residual"] <= 1e-10
+
+
+def test_nonsymmetric_random_pattern():
+    n, b = 300, 3
+    rp, ci, vals = synth.random_bsr(n, b, 0.02, 7)
+    rhs = np.random.default_rng(8).uniform(-1, 1, n * b)
+    announce("random_bsr", n, b)
+    g = msp.Solver(max_coarse=30)
+    o = O.OracleSolver(max_coarse=30)
+    g.setup(n=n, b=b, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    o.setup(n=n, b=b, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    for l in range(o.nlevels):
+        assert np.array_equal(g.level(l)["val"], o.level(l)["val"])
+        if l < o.nlevels - 1:
+            assert np.array_equal(g.level(l)["color"], o.level(l)["color"])
+    v = np.random.default_rng(9).uniform(-1, 1, n * b)
+    assert relerr(to_np(g.apply(v)), o.apply(v)) <= _coarse_tol(o)
+    xg, ig = g.solve(rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(rhs, 1e-6)
+    assert abs(ig["iterations"] - it) <= 1
+
+
+# --------------------------------------------------------------------------
+# adaptive setup and error handling
+# --------------------------------------------------------------------------
+def test_adaptive_setup_matches_oracle():
+    sys = synth.lognormal_grid(14, 12, 6, 3, 9, 1.0, 1.0, "corners2")
+    seq = [sys] + [synth.newton_step(sys, t, 77) for t in range(1, 5)]
+    for mu in (0, 3, 1000):
+        announce("adaptive mu", mu)
+        g = msp.Solver(mu=mu, max_coarse=60)
+        o = O.OracleSolver(mu=mu, max_coarse=60)
+        for A in seq:
+            rg = g.setup(A)
+            ro = o.setup(A)
+            assert rg == ro
+            xg, ig = g.solve(A.rhs, rtol=1e-6)
+            xo, it, rr, st = o.solve(A.rhs, 1e-6)
+            assert abs(ig["iterations"] - it) <= 1 and ig["rel_true_residual"] <= 1e-6
+            if abs(ig["iterations"] - it) == 1:
+                break  # the rebuild decisions may now legitimately differ
+        assert g.info()["setup_calls"] >= 1
+
+
+def test_errors_and_edge_cases():
+    sys = synth.config(0)
+    announce("errors")
+    g = msp.Solver()
+    with pytest.raises(msp.MspError) as e:
+        g.solve(sys.rhs)
+    assert e.value.code == -8
+    bad = sys.vals.copy()
+    bad[10, 1, 1] = np.nan
+    with pytest.raises(msp.MspError) as e:
+        g.setup(n=sys.n, b=sys.b, p=0, row_ptr=sys.row_ptr, col_ind=sys.col_ind, vals=bad)
+    assert e.value.code == -4
+    ci = sys.col_ind.copy()
+    ci[0], ci[1] = ci[1], ci[0]
+    with pytest.raises(msp.MspError) as e:
+        g.setup(n=sys.n, b=sys.b, p=0, row_ptr=sys.row_ptr, col_ind=ci, vals=sys.vals)
+    assert e.value.code == -2
+    sing = sys.vals.copy()
+    sing[sys.diag_pos[17]] = 0.0
+    with pytest.raises(msp.MspError) as e:
+        g.setup(n=sys.n, b=sys.b, p=0, row_ptr=sys.row_ptr, col_ind=sys.col_ind, vals=sing)
+    assert e.value.code == -3
+    with pytest.raises(msp.MspError) as e:
+        g.solve(sys.rhs)
+    assert e.value.code == -8
+    g.setup(sys)
+    x = torch.ones(sys.N, dtype=torch.float64, device="cuda")
+    x, info = g.solve(np.zeros(sys.N), x)
+    assert info["iterations"] == 0 and torch.count_nonzero(x).item() == 0
+    rhs_bad = sys.rhs.copy()
+    rhs_bad[3] = np.inf
+    with pytest.raises(msp.MspError) as e:
+        g.solve(rhs_bad)
+    assert e.value.code == -4
+    g2 = msp.Solver(max_iter=2, max_coarse=64)
+    g2.setup(sys)
+    x, info = g2.solve(sys.rhs, rtol=1e-14)
+    assert info["status"] == 1 and info["iterations"] == 2
+
+
+def test_deterministic_bitwise():
+    sys = synth.config(0)
+    announce("determinism")
+    g = msp.Solver(max_coarse=64)
+    g.setup(sys)
+    x1, _ = g.solve(sys.rhs)
+    x2, _ = g.solve(sys.rhs)
+    assert torch.equal(x1, x2)
+
+
+# --------------------------------------------------------------------------
+# the benchmark workload at full size: 64x64x32 cells, block size 4
+# --------------------------------------------------------------------------
+def test_full_size_benchmark_workload():
+    sys = synth.config(1)
+    g, o = solvers(sys, 10000)
+    info = g.info()
+    assert info["n_levels"] == o.nlevels
+    for l in range(o.nlevels):
+        a, b = g.level(l), o.level(l)
+        assert np.array_equal(a["col_ind"], b["col_ind"]) and np.array_equal(a["val"], b["val"])
+        if l < o.nlevels - 1:
+            assert np.array_equal(a["color"], b["color"]) and np.array_equal(a["agg"], b["agg"])
+    assert o.level(0)["ncolors"] == 2
+    x = np.random.default_rng(11).uniform(-1, 1, sys.N)
+    assert relerr(to_np(g.spmv(x)), o.spmv(x)) <= 1e-14
+    xg, ig = g.solve(sys.rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-6)
+    announce("cfg1 iterations gpu/oracle", ig["iterations"], it)
+    assert abs(ig["iterations"] - it) <= 1 and ig["rel_true_residual"] <= 1e-6

@@ -1,0 +1,212 @@
+"""CPU checks of libmsp: the C-ABI loads and exports every declared symbol, the
+ctypes structs match the C layout, host-only entry points behave, and the
+library's host setup code (grouping, matching, Galerkin) agrees bit for bit
+with the oracle.  No GPU work is launched here."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_08594_amd import msp, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "include")
+CSRC = os.path.join(ROOT, "paper_2208_08594_amd", "csrc")
+
+
+def header_functions():
+    names = set()
+    for h in ("msp.h", "msp_stages.h"):
+        txt = open(os.path.join(INC, h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?(?:int|char\s*\*|const char \*)\s*\**\s*(msp_\w+)\s*\(",
+                             txt, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = msp.lib()
+    declared = header_functions()
+    assert len(declared) >= 19
+    assert declared == set(msp.SIGNATURES), declared ^ set(msp.SIGNATURES)
+    for name in declared:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", msp.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert declared <= exported
+
+
+def test_struct_layout_matches_c():
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "msp.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(msp_options), offsetof(msp_options, stream),
+         offsetof(msp_options, alloc_user), sizeof(msp_info),
+         offsetof(msp_info, rel_true_residual), offsetof(msp_info, solve_ms));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        cpath = os.path.join(d, "t.c")
+        open(cpath, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", INC, cpath, "-o", exe])
+        vals = list(map(int, subprocess.check_output([exe]).split()))
+    got = [C.sizeof(msp.MspOptions), msp.MspOptions.stream.offset, msp.MspOptions.alloc_user.offset,
+           C.sizeof(msp.MspInfo), msp.MspInfo.rel_true_residual.offset, msp.MspInfo.solve_ms.offset]
+    assert vals == got
+
+
+def test_status_strings_and_defaults():
+    for code in list(msp.STATUS) + [12345]:
+        assert isinstance(msp.status_string(code), str) and msp.status_string(code)
+    opt = msp.MspOptions()
+    assert msp.lib().msp_default_options(C.byref(opt)) == 0
+    assert (opt.mu, opt.restart, opt.max_iter, opt.max_coarse, opt.precond_fp32) == (0, 30, 1000, 10000, 0)
+    assert msp.lib().msp_default_options(None) == -1
+
+
+def test_host_argument_errors_need_no_gpu():
+    L = msp.lib()
+    assert L.msp_create(None, None) == -1
+    assert L.msp_destroy(None) == 0
+    assert L.msp_setup(None, 1, 1, 0, None, None, None, 1) == -1
+    assert L.msp_solve(None, None, None, 1e-6, None) == -1
+    out = C.c_size_t()
+    assert L.msp_footprint(0, 1, 4, None, C.byref(out)) == -1
+    assert L.msp_footprint(10, 5, 4, None, C.byref(out)) == -1
+    assert L.msp_footprint(10, 10, 9, None, C.byref(out)) == -1
+    bad = msp.MspOptions()
+    L.msp_default_options(C.byref(bad))
+    bad.restart = 0
+    h = C.c_void_p()
+    assert L.msp_create(C.byref(h), C.byref(bad)) == -1
+
+
+def test_footprint_scales_with_size():
+    small = msp.footprint(1000, 6400, 4)
+    big = msp.footprint(1048576, 7274496, 7)
+    big32 = msp.footprint(1048576, 7274496, 7, precond_fp32=True)
+    assert 0 < small < big and big32 < big
+    # the dominant pieces are at least the matrix and the Krylov basis
+    assert big > 7274496 * 49 * 8 + 61 * 7340032 * 8
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert msp.lib().msp_create(C.byref(h), None) == -7
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(msp, "_LIB", None)
+    monkeypatch.setattr(msp, "LIB_PATH", "/nonexistent/libmsp.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        msp.lib()
+
+
+# --------------------------------------------------------------------------
+# the library's host setup code against the oracle (bit for bit)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def shim():
+    d = tempfile.mkdtemp()
+    so = os.path.join(d, "libshim.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+                           f"-I{CSRC}", os.path.join(ROOT, "tests", "native", "host_shim.cpp"),
+                           os.path.join(CSRC, "msp_host.cpp"), "-o", so])
+    L = C.CDLL(so)
+    i32 = np.ctypeslib.ndpointer(np.int32, flags="C")
+    f64 = np.ctypeslib.ndpointer(np.float64, flags="C")
+    L.shim_color.argtypes = [C.c_int, i32, i32, i32]
+    L.shim_pair.argtypes = [C.c_int, i32, i32, f64, i32]
+    L.shim_galerkin.argtypes = [C.c_int, i32, i32, f64, i32, C.c_int, i32, i32, f64]
+    L.shim_galerkin.restype = C.c_longlong
+    L.shim_pattern.argtypes = [C.c_int, i32, i32, C.c_longlong]
+    L.shim_levels.argtypes = [C.c_int, i32, i32, C.c_int, i32]
+    return L
+
+
+def _lib_color(shim, rp, ci):
+    col = np.zeros(len(rp) - 1, dtype=np.int32)
+    g = shim.shim_color(len(rp) - 1, rp, ci, col)
+    return col, g
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_library_grouping_matches_oracle(shim, seed):
+    rng = np.random.default_rng(seed)
+    n = 50 + 30 * seed
+    P = rng.random((n, n)) < 0.05
+    np.fill_diagonal(P, True)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(P.sum(1))
+    ci = np.nonzero(P)[1].astype(np.int32)
+    c_lib, g_lib = _lib_color(shim, rp, ci)
+    c_or, g_or = O.color(rp, ci)
+    assert g_lib == g_or and np.array_equal(c_lib, c_or)
+
+
+def test_library_hierarchy_steps_match_oracle(shim):
+    for sys, mc in [(synth.config(0), 64), (synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1,
+                                                                  "lateral4"), 200)]:
+        s = O.OracleSolver(max_coarse=mc)
+        s.setup(sys)
+        assert s.nlevels >= 3
+        for l in range(s.nlevels - 1):
+            L = s.level(l)
+            rp, ci, val = L["row_ptr"], L["col_ind"], L["val"]
+            n = L["n"]
+            col, g = _lib_color(shim, rp, ci)
+            assert g == L["ncolors"] and np.array_equal(col, L["color"])
+            a1 = np.zeros(n, dtype=np.int32)
+            nc1 = shim.shim_pair(n, rp, ci, val, a1)
+            crp = np.zeros(nc1 + 1, dtype=np.int32)
+            cci = np.zeros(len(ci), dtype=np.int32)
+            cv = np.zeros(len(ci))
+            m = shim.shim_galerkin(n, rp, ci, val, a1, nc1, crp, cci, cv)
+            a2 = np.zeros(nc1, dtype=np.int32)
+            nc2 = shim.shim_pair(nc1, crp, cci[:m].copy(), cv[:m].copy(), a2)
+            drp = np.zeros(nc2 + 1, dtype=np.int32)
+            dci = np.zeros(m, dtype=np.int32)
+            dv = np.zeros(m)
+            m2 = shim.shim_galerkin(nc1, crp, cci[:m].copy(), cv[:m].copy(), a2, nc2, drp, dci, dv)
+            assert np.array_equal(a2[a1], L["agg"])
+            nxt = s.level(l + 1)
+            assert np.array_equal(drp, nxt["row_ptr"]) and np.array_equal(dci[:m2], nxt["col_ind"])
+            assert np.array_equal(dv[:m2], nxt["val"])  # same summation order: exact
+
+
+def test_library_pattern_check(shim):
+    rp, ci, _ = synth.poisson_csr((4, 3, 2))
+    assert shim.shim_pattern(len(rp) - 1, rp, ci, len(ci)) == 0
+    bad = ci.copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    assert shim.shim_pattern(len(rp) - 1, rp, bad, len(ci)) == -2
+    for v in (-1, len(rp) - 1):
+        bad = ci.copy()
+        bad[2] = v
+        assert shim.shim_pattern(len(rp) - 1, rp, bad, len(ci)) == -2
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 4), (64, 64, 32), (60, 220, 85)])
+def test_bilu_levels_are_hyperplanes(shim, shape):
+    nx, ny, nz = shape
+    rp, ci, _ = synth.poisson_csr(shape)
+    n = len(rp) - 1
+    rows = np.zeros(n, dtype=np.int32)
+    nlev = shim.shim_levels(n, rp, ci, 1, rows)
+    assert nlev == nx + ny + nz - 2
+    nlev_b = shim.shim_levels(n, rp, ci, 0, rows)
+    assert nlev_b == nx + ny + nz - 2
