@@ -69,6 +69,24 @@ int msp_stage_get_bilu(msp_ctx *ctx, double *F, double *Dinv);
 /* FP32 copies of the BILU factors (HOST, same layout); precond_fp32 only. */
 int msp_stage_get_bilu_f32(msp_ctx *ctx, float *F, float *Dinv);
 
+/* Stage ids for msp_stage_repeat. */
+#define MSP_STAGE_SPMV 0    /* out = A in (double[n*b]) */
+#define MSP_STAGE_GS0 1     /* one forward PGS-MC sweep on AMG level 0 (all colors) on the
+                               library's level-0 work vectors; in/out unused */
+#define MSP_STAGE_PRECOND 2 /* out = B in (double[n*b]) */
+#define MSP_STAGE_BILU 3    /* block ILU(0) forward + backward solve on the library's
+                               work vector; in/out unused */
+#define MSP_STAGE_VCYCLE 4  /* level-0 V-cycle on the library's work vectors; in/out unused */
+#define MSP_STAGE_COARSE 5  /* coarsest-level solve on the library's work vectors */
+
+/* Enqueue `reps` (>= 1) back-to-back executions of one stage on the context's
+ * stream with no host synchronisation between them, then synchronise.  Meant
+ * for timing with events recorded on the same stream around the call.
+ * in/out: device double arrays as listed above (may be NULL where unused).
+ * Errors: MSP_ERR_ARG (unknown stage, reps < 1, missing array),
+ * MSP_ERR_STATE. */
+int msp_stage_repeat(msp_ctx *ctx, int stage, int reps, const double *in, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1213,4 +1213,46 @@ int msp_stage_get_bilu_f32(msp_ctx *c, float *F, float *Dinv)
     });
 }
 
+int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *out)
+{
+    if (!c || reps < 1 || stage < 0 || stage > 5) return MSP_ERR_ARG;
+    if ((stage == MSP_STAGE_SPMV || stage == MSP_STAGE_PRECOND) && (!in || !out))
+        return MSP_ERR_ARG;
+    if (!c->haveA || (stage != MSP_STAGE_SPMV && !c->hasB)) return MSP_ERR_STATE;
+    if (stage == MSP_STAGE_GS0 && c->lev.size() < 2) return MSP_ERR_STATE;
+    return guarded([&]() {
+        const bool f32 = c->fp32();
+        for (int r = 0; r < reps; ++r) {
+            switch (stage) {
+            case MSP_STAGE_SPMV: spmv(c, in, nullptr, out); break;
+            case MSP_STAGE_GS0:
+                if (f32) smooth<float>(c, c->lev[0], true, false);
+                else smooth<double>(c, c->lev[0], true, false);
+                break;
+            case MSP_STAGE_PRECOND: apply(c, in, out); break;
+            case MSP_STAGE_BILU:
+                if (f32) bilu_solve<float>(c, (float *)c->ybuf);
+                else bilu_solve<double>(c, (double *)c->ybuf);
+                break;
+            case MSP_STAGE_VCYCLE:
+                if (f32) vcycle<float>(c, 0);
+                else vcycle<double>(c, 0);
+                break;
+            case MSP_STAGE_COARSE: {
+                Level &L = c->lev.back();
+                if (f32)
+                    HIPCHK(launch_coarse_gemv<float>(L.n, c->cinv, (const float *)L.f,
+                                                     (float *)L.x, c->stream));
+                else
+                    HIPCHK(launch_coarse_gemv<double>(L.n, c->cinv, (const double *)L.f,
+                                                      (double *)L.x, c->stream));
+                break;
+            }
+            }
+        }
+        c->sync();
+        return MSP_OK;
+    });
+}
+
 }  // extern "C"

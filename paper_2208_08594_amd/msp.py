@@ -76,7 +76,9 @@ SIGNATURES = {
     "msp_stage_get_omega": ([_vp, _vp], _i),
     "msp_stage_get_bilu": ([_vp, _vp, _vp], _i),
     "msp_stage_get_bilu_f32": ([_vp, _vp, _vp], _i),
+    "msp_stage_repeat": ([_vp, _i, _i, _vp, _vp], _i),
 }
+STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE = range(6)
 
 _LIB = None
 _LOCK = threading.Lock()
@@ -234,7 +236,7 @@ class Solver:
         t = self.torch
         rhs = self._dev(rhs, t.float64)
         if x is None:
-            x = t.zeros(self.n * self.b, dtype=t.float64, device=self.device)
+            x = t.zeros_like(rhs)
         info = MspInfo()
         with t.cuda.device(self.device):
             code = self._lib.msp_solve(self.h, _ptr(rhs), _ptr(x), float(rtol), C.byref(info))
@@ -277,6 +279,13 @@ class Solver:
             _check(self._lib.msp_stage_smooth(self.h, int(level), _ptr(f), _ptr(x),
                                               1 if forward else 0), "smooth")
         return x
+
+    def repeat(self, stage, reps, inp=None, out=None):
+        """msp_stage_repeat: reps back-to-back launches of one stage (for timing)."""
+        p = lambda t: None if t is None else _ptr(t)
+        with self.torch.cuda.device(self.device):
+            _check(self._lib.msp_stage_repeat(self.h, int(stage), int(reps), p(inp), p(out)),
+                   "repeat")
 
     @property
     def nlevels(self):
