@@ -101,7 +101,8 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
         log(f"{'fp32' if precond_fp32 else 'fp64'} step {k}: {times[-1]:.2f} ms, "
             f"{info['iterations']} it, relres {info['rel_true_residual']:.2e}, "
             f"setup {info['setup_ms']:.2f} ms (rebuild {info['rebuild_ms']:.2f}), "
-            f"solve {info['solve_ms']:.2f} ms")
+            f"solve {info['solve_ms']:.2f} ms; phases "
+            + " ".join(f"{v:.1f}" for v in info["phase_ms"][:7]))
     torch.cuda.synchronize()
     total_ms = (time.perf_counter() - t0) * 1e3
     return solver, x.clone(), times, total_ms, infos, stream
@@ -113,7 +114,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
-    ap.add_argument("--bilu-order", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--bilu-order", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
@@ -206,6 +207,9 @@ def main():
                    "bilu_order": "natural" if args.bilu_order == 0 else "multicolor"},
         "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
         "setup_ms": setup_ms, "solve_ms": solve_ms, "iterations": last["iterations"],
+        "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "hierarchy_host",
+                                    "level_upload", "coarse_inverse", "bilu"],
+                                   [round(v, 3) for v in last["phase_ms"][:7]])),
         "rel_true_residual": last["rel_true_residual"],
         "levels": last["level_rows"], "colors": last["n_colors"],
         "bilu_levels": [last["bilu_levels_fwd"], last["bilu_levels_bwd"]],

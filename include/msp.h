@@ -37,7 +37,7 @@ extern "C" {
 #endif
 
 #define MSP_OK 0
-#define MSP_ERR_ARG (-1)       /* null pointer, n < 1, b outside 1..16, p outside [0,b), nnzb < n */
+#define MSP_ERR_ARG (-1)       /* null pointer, n < 1, b outside 1..8, p outside [0,b), nnzb < n */
 #define MSP_ERR_PATTERN (-2)   /* row_ptr not monotone, column out of range, unsorted or duplicate
                                   column, or a block row without its diagonal block */
 #define MSP_ERR_SINGULAR (-3)  /* singular diagonal block (decoupling or BILU pivot), zero AMG
@@ -51,11 +51,12 @@ extern "C" {
 #define MSP_NOT_CONVERGED 1    /* max_iter reached; x holds the last iterate, info is filled */
 
 #define MSP_MAX_LEVELS 25
-#define MSP_MAX_BLOCK 16
+#define MSP_MAX_BLOCK 8
 
 /* Solver options.  msp_default_options() fills the paper's settings
  * (Sec. 5: GMRES(30), MaxIt 1000, coarsest space of at most 10000 unknowns)
- * with mu = 0 (standard MSP, every system rebuilds, Sec. 3.2). */
+ * with mu = 0 (standard MSP, every system rebuilds, Sec. 3.2), an FP64
+ * preconditioner and the multi-color block ILU(0) order. */
 typedef struct {
     int mu;           /* adaptive-setup threshold It^(i-1) <= mu => reuse (Sec. 3.2) */
     int restart;      /* m of FGMRES(m), 1..200 */
@@ -64,8 +65,10 @@ typedef struct {
     int precond_fp32; /* 0: FP64 preconditioner; 1: AMG hierarchy, GS, BILU and the
                          pressure-column residual stored and applied in FP32 (FGMRES,
                          decoupling weights and the coarsest solve stay FP64) */
-    int bilu_order;   /* 0: block ILU(0) in natural block order (default);
-                         1: in the multi-color order of the block adjacency graph */
+    int bilu_order;   /* elimination order of the block ILU(0) stage:
+                         1 (default): the groups of Alg. 4.2 on the block adjacency graph
+                         one after another (two dependency levels on a 7-point grid);
+                         0: natural block order (nx+ny+nz-2 levels on a 7-point grid) */
     void *stream;     /* hipStream_t for all work; NULL = the default stream */
     /* Optional device allocator (e.g. a framework caching allocator); both NULL =
      * hipMalloc/hipFree.  dev_alloc returns NULL on failure. */
@@ -90,6 +93,12 @@ typedef struct {
     double setup_ms;          /* host wall time of the last setup */
     double rebuild_ms;        /* ... of which preconditioner regeneration */
     double solve_ms;          /* host wall time of the last solve */
+    /* host wall time of the phases of the last setup (ms):
+     * [0] pattern copy and check, [1] value ingest, [2] decoupling,
+     * [3] AMG hierarchy on the host, [4] level layouts and upload,
+     * [5] coarsest-level inverse, [6] block ILU(0) factorisation and layouts,
+     * [7] unused */
+    double phase_ms[8];
 } msp_info;
 
 /* Fill *opt with the defaults listed above.  Returns MSP_ERR_ARG on NULL. */
@@ -111,7 +120,7 @@ int msp_create(struct msp_ctx **ctx, const msp_options *opt);
  * Arguments (device pointers, read only, may be overwritten by the caller as
  * soon as the call returns):
  *   n_block_rows  n >= 1 block rows (cells);
- *   block_size    b in 1..16 (n_c+1 in the paper);
+ *   block_size    b in 1..MSP_MAX_BLOCK (n_c+1 in the paper);
  *   pressure_index p in [0, b): the pressure unknown inside each block;
  *   row_ptr       int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnzb;
  *   col_ind       int32[nnzb], strictly ascending inside each block row, every

@@ -598,30 +598,66 @@ static void block_mul(int b, const double *A, const double *B, double *C)
 }
 
 /* ------------------------------------------------------------------------ */
-/* O7  Block ILU(0) of the whole system (the relaxation R of eq. MSP), in    */
-/*     natural block order, IKJ form: for each block row i and each stored   */
-/*     k < i (ascending): F_ik <- F_ik F_kk^{-1}; F_ij <- F_ij - F_ik F_kj    */
-/*     for stored j > k with (k,j) stored.  Pivot blocks are kept inverted.   */
+/* O7  Block ILU(0) of the whole system (the relaxation R of eq. MSP), IKJ   */
+/*     form in a given elimination order ord (ord[t] = block row eliminated   */
+/*     t-th; natural order is ord[t] = t): for each block row i in that order */
+/*     and each stored k eliminated before i (in elimination order):          */
+/*     F_ik <- F_ik F_kk^{-1}; F_ij <- F_ij - F_ik F_kj for stored j          */
+/*     eliminated after k with (k,j) stored.  Pivot blocks are kept inverted. */
 /* ------------------------------------------------------------------------ */
-int or_bilu0_factor(int n, int b, const int *rp, const int *ci, const double *A, double *F,
-                    double *Dinv)
+/* entries of block row i whose column is eliminated before (lower != 0) or  */
+/* after (lower == 0) row i, in elimination order; returns their count       */
+static int ordered_entries(const int *rp, const int *ci, const int *pos, int i, int lower,
+                           int *out)
+{
+    int m = 0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+        int j = ci[q];
+        if (lower ? pos[j] < pos[i] : pos[j] > pos[i]) {
+            int a = m++;
+            while (a > 0 && pos[ci[out[a - 1]]] > pos[j]) {
+                out[a] = out[a - 1];
+                --a;
+            }
+            out[a] = q;
+        }
+    }
+    return m;
+}
+
+static int max_row_len(int n, const int *rp)
+{
+    int w = 1;
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] - rp[i] > w)
+            w = rp[i + 1] - rp[i];
+    return w;
+}
+
+int or_bilu0_factor_ordered(int n, int b, const int *rp, const int *ci, const double *A,
+                            const int *ord, double *F, double *Dinv)
 {
     const int bb = b * b;
     long nnzb = rp[n];
     memcpy(F, A, sizeof(double) * (size_t)(nnzb * bb));
+    int *pos = (int *)malloc(sizeof(int) * (size_t)n);
+    int *low = (int *)malloc(sizeof(int) * (size_t)max_row_len(n, rp));
+    if (!pos || !low) { free(pos); free(low); return OR_ERR_NOMEM; }
+    for (int t = 0; t < n; ++t)
+        pos[ord[t]] = t;
     double tmp[OR_MAXB * OR_MAXB], prod[OR_MAXB * OR_MAXB];
-    for (int i = 0; i < n; ++i) {
-        int kd = -1;
-        for (int kk = rp[i]; kk < rp[i + 1]; ++kk) {
-            int k = ci[kk];
-            if (k == i)
-                kd = kk;
-            if (k >= i)
-                continue;
+    int st = OR_OK;
+    for (int t = 0; t < n && st == OR_OK; ++t) {
+        int i = ord[t];
+        int m = ordered_entries(rp, ci, pos, i, 1, low);
+        for (int a = 0; a < m; ++a) {
+            int kk = low[a], k = ci[kk];
             block_mul(b, F + (long)kk * bb, Dinv + (long)k * bb, tmp);
             memcpy(F + (long)kk * bb, tmp, sizeof(double) * (size_t)bb);
-            for (int jj = kk + 1; jj < rp[i + 1]; ++jj) {
+            for (int jj = rp[i]; jj < rp[i + 1]; ++jj) {
                 int j = ci[jj];
+                if (pos[j] <= pos[k])
+                    continue;
                 int kj = find_col(rp, ci, k, j);
                 if (kj < 0)
                     continue;
@@ -631,13 +667,46 @@ int or_bilu0_factor(int n, int b, const int *rp, const int *ci, const double *A,
                     Fij[q] = Fij[q] - prod[q];
             }
         }
+        int kd = find_col(rp, ci, i, i);
         if (kd < 0)
-            return OR_ERR_PATTERN;
-        int st = block_inverse(b, F + (long)kd * bb, Dinv + (long)i * bb);
-        if (st != OR_OK)
-            return st;
+            st = OR_ERR_PATTERN;
+        else
+            st = block_inverse(b, F + (long)kd * bb, Dinv + (long)i * bb);
     }
-    return OR_OK;
+    free(pos);
+    free(low);
+    return st;
+}
+
+int or_bilu0_factor(int n, int b, const int *rp, const int *ci, const double *A, double *F,
+                    double *Dinv)
+{
+    int *ord = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!ord)
+        return OR_ERR_NOMEM;
+    for (int t = 0; t < n; ++t)
+        ord[t] = t;
+    int st = or_bilu0_factor_ordered(n, b, rp, ci, A, ord, F, Dinv);
+    free(ord);
+    return st;
+}
+
+/* Multi-color elimination order of the block adjacency graph: the groups of */
+/* Alg. 4.2 one after another, ascending index inside a group.               */
+int or_multicolor_order(int n, const int *rp, const int *ci, int *ord)
+{
+    int *col = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!col)
+        return OR_ERR_NOMEM;
+    int g = or_color(n, rp, ci, col);
+    if (g < 0) { free(col); return g; }
+    int t = 0;
+    for (int l = 1; l <= g; ++l)
+        for (int i = 0; i < n; ++i)
+            if (col[i] == l)
+                ord[t++] = i;
+    free(col);
+    return g;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -656,10 +725,22 @@ int or_bilu0_factor(int n, int b, const int *rp, const int *ci, const double *A,
 #undef SFX
 
 /* Exported double-precision stage functions (pins and per-kernel parity). */
+void or_bilu0_solve_ordered(int n, int b, const int *rp, const int *ci, const double *F,
+                            const double *Dinv, const int *ord, const double *r, double *z)
+{
+    bilu0_solve_f64(n, b, rp, ci, F, Dinv, ord, r, z);
+}
+
 void or_bilu0_solve(int n, int b, const int *rp, const int *ci, const double *F,
                     const double *Dinv, const double *r, double *z)
 {
-    bilu0_solve_f64(n, b, rp, ci, F, Dinv, r, z);
+    int *ord = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!ord)
+        return;
+    for (int t = 0; t < n; ++t)
+        ord[t] = t;
+    bilu0_solve_f64(n, b, rp, ci, F, Dinv, ord, r, z);
+    free(ord);
 }
 
 void or_gs_sweep(int n, const int *rp, const int *ci, const double *val, const int *color, int g,
@@ -690,7 +771,7 @@ typedef struct {
 
 typedef struct {
     /* options */
-    int mu, restart, max_iter, max_coarse, precond_fp32;
+    int mu, restart, max_iter, max_coarse, precond_fp32, bilu_order;
     /* current matrix (used by the Krylov SpMV and the pressure-column residual) */
     int n, b, p;
     long nnzb;
@@ -706,14 +787,15 @@ typedef struct {
     double *coarse_dense, *LU;
     int *piv;
     int have_lu;
-    int *Brp, *Bci;
+    int *Brp, *Bci, *Bord;
     double *F, *Dinv;
     float *F32, *Dinv32;
     /* adaptive state */
     int it_prev, setup_calls, solves;
 } or_ctx;
 
-or_ctx *or_create(int mu, int restart, int max_iter, int max_coarse, int precond_fp32)
+or_ctx *or_create(int mu, int restart, int max_iter, int max_coarse, int precond_fp32,
+                  int bilu_order)
 {
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     if (!c)
@@ -723,6 +805,7 @@ or_ctx *or_create(int mu, int restart, int max_iter, int max_coarse, int precond
     c->max_iter = max_iter;
     c->max_coarse = max_coarse;
     c->precond_fp32 = precond_fp32;
+    c->bilu_order = bilu_order;
     c->it_prev = -1;
     return c;
 }
@@ -737,9 +820,9 @@ static void free_B(or_ctx *c)
     memset(c->lev, 0, sizeof(c->lev));
     c->nlev = 0;
     free(c->coarse_dense); free(c->LU); free(c->piv);
-    free(c->Brp); free(c->Bci); free(c->F); free(c->Dinv); free(c->F32); free(c->Dinv32);
+    free(c->Brp); free(c->Bci); free(c->Bord); free(c->F); free(c->Dinv); free(c->F32); free(c->Dinv32);
     c->omega = NULL; c->coarse_dense = NULL; c->LU = NULL; c->piv = NULL;
-    c->Brp = NULL; c->Bci = NULL; c->F = NULL; c->Dinv = NULL; c->F32 = NULL; c->Dinv32 = NULL;
+    c->Brp = NULL; c->Bci = NULL; c->Bord = NULL; c->F = NULL; c->Dinv = NULL; c->F32 = NULL; c->Dinv32 = NULL;
     c->have_lu = 0;
     c->has_B = 0;
 }
@@ -903,7 +986,18 @@ int or_setup(or_ctx *c, int n, int b, int p, const int *rp, const int *ci, const
         return OR_ERR_NOMEM;
     memcpy(c->Brp, rp, sizeof(int) * ((size_t)n + 1));
     memcpy(c->Bci, ci, sizeof(int) * (size_t)nnzb);
-    st = or_bilu0_factor(n, b, rp, ci, vals, c->F, c->Dinv);
+    c->Bord = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!c->Bord)
+        return OR_ERR_NOMEM;
+    if (c->bilu_order == 1) {
+        st = or_multicolor_order(n, rp, ci, c->Bord);
+        if (st < 0)
+            return st;
+    } else {
+        for (int t = 0; t < n; ++t)
+            c->Bord[t] = t;
+    }
+    st = or_bilu0_factor_ordered(n, b, rp, ci, vals, c->Bord, c->F, c->Dinv);
     if (st != OR_OK)
         return st;
     if (c->precond_fp32) {
@@ -1027,7 +1121,7 @@ int or_bilu_apply(or_ctx *c, const double *r, double *z)
 {
     if (!c->has_B)
         return OR_ERR_STATE;
-    bilu0_solve_f64(c->Bn, c->Bb, c->Brp, c->Bci, c->F, c->Dinv, r, z);
+    bilu0_solve_f64(c->Bn, c->Bb, c->Brp, c->Bci, c->F, c->Dinv, c->Bord, r, z);
     return OR_OK;
 }
 

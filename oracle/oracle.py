@@ -66,11 +66,16 @@ def lib():
     L.or_bilu0_factor.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p]
     L.or_bilu0_solve.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p, f64p]
     L.or_bilu0_solve.restype = None
+    L.or_bilu0_factor_ordered.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, i32p, f64p, f64p]
+    L.or_bilu0_solve_ordered.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, i32p, f64p,
+                                         f64p]
+    L.or_bilu0_solve_ordered.restype = None
+    L.or_multicolor_order.argtypes = [C.c_int, i32p, i32p, i32p]
     L.or_gs_sweep.argtypes = [C.c_int, i32p, i32p, f64p, i32p, C.c_int, f64p, f64p, C.c_int]
     L.or_gs_sweep.restype = None
     L.or_lu_solve.argtypes = [C.c_int, f64p, i32p, f64p, f64p]
     L.or_lu_solve.restype = None
-    L.or_create.argtypes = [C.c_int] * 5
+    L.or_create.argtypes = [C.c_int] * 6
     L.or_create.restype = vp
     L.or_destroy.argtypes = [vp]
     L.or_destroy.restype = None
@@ -158,18 +163,35 @@ def galerkin(rp, ci, val, agg, nc):
     return crp, cci[:nnz].copy(), cval[:nnz].copy()
 
 
-def bilu0_factor(n, b, rp, ci, vals):
+def multicolor_order(rp, ci):
+    """Elimination order: the groups of Alg. 4.2 one after another."""
+    n = len(rp) - 1
+    ord_ = np.zeros(n, dtype=np.int32)
+    _check(lib().or_multicolor_order(n, _i32(rp), _i32(ci), ord_), "multicolor_order")
+    return ord_
+
+
+def bilu0_factor(n, b, rp, ci, vals, order=None):
+    """Block ILU(0) in natural order, or in the elimination order `order`."""
     F = np.zeros(len(ci) * b * b)
     D = np.zeros(n * b * b)
-    _check(lib().or_bilu0_factor(n, b, _i32(rp), _i32(ci), _f64(vals).reshape(-1), F, D),
-           "bilu0_factor")
+    if order is None:
+        st = lib().or_bilu0_factor(n, b, _i32(rp), _i32(ci), _f64(vals).reshape(-1), F, D)
+    else:
+        st = lib().or_bilu0_factor_ordered(n, b, _i32(rp), _i32(ci), _f64(vals).reshape(-1),
+                                           _i32(order), F, D)
+    _check(st, "bilu0_factor")
     return F.reshape(-1, b, b), D.reshape(n, b, b)
 
 
-def bilu0_solve(n, b, rp, ci, F, D, r):
+def bilu0_solve(n, b, rp, ci, F, D, r, order=None):
     z = np.zeros(n * b)
-    lib().or_bilu0_solve(n, b, _i32(rp), _i32(ci), _f64(F).reshape(-1), _f64(D).reshape(-1),
-                         _f64(r), z)
+    if order is None:
+        lib().or_bilu0_solve(n, b, _i32(rp), _i32(ci), _f64(F).reshape(-1), _f64(D).reshape(-1),
+                             _f64(r), z)
+    else:
+        lib().or_bilu0_solve_ordered(n, b, _i32(rp), _i32(ci), _f64(F).reshape(-1),
+                                     _f64(D).reshape(-1), _i32(order), _f64(r), z)
     return z
 
 
@@ -196,10 +218,11 @@ def lu_solve(lu, piv, f):
 # Solver context: adaptive setup + FGMRES (a Newton sequence of systems)
 # --------------------------------------------------------------------------
 class OracleSolver:
-    def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False):
+    def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
+                 bilu_order=1):
         self._lib = lib()
         self.h = self._lib.or_create(int(mu), int(restart), int(max_iter), int(max_coarse),
-                                     1 if precond_fp32 else 0)
+                                     1 if precond_fp32 else 0, int(bilu_order))
         if not self.h:
             raise MemoryError("or_create")
         self.n = self.b = self.p = None

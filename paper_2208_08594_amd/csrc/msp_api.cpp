@@ -334,7 +334,7 @@ void build_coarse(msp_ctx *c)
     int *rp = c->upload(L.A.rp, tmp);
     int *ci = c->upload(L.A.ci, tmp);
     double *val = c->upload(L.A.val, tmp);
-    double *work = (double *)c->dalloc(sizeof(double) * ((size_t)2 * 64 * m + 64 * 64), tmp);
+    double *work = (double *)c->dalloc(sizeof(double) * dense_inverse_work(m), tmp);
     HIPCHK(launch_fill((long long)m * m, 0.0, c->cinv, c->stream));
     HIPCHK(launch_dense_scatter(m, rp, ci, val, c->cinv, c->stream));
     c->clear_flag();
@@ -473,6 +473,12 @@ void rebuild_B(msp_ctx *c, const double *vals)
 {
     release_B(c);
     const int n = c->n, b = c->b;
+    double tp = now_ms();
+    auto phase = [&](int i) {
+        double t = now_ms();
+        c->info.phase_ms[i] += t - tp;
+        tp = t;
+    };
     // decoupling and pressure extraction (device), pressure matrix to the host
     c->omega = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
     std::vector<void *> tmp;
@@ -490,11 +496,13 @@ void rebuild_B(msp_ctx *c, const double *vals)
     int bad = c->read_flag();
     c->release(tmp);
     if (bad) fail(MSP_ERR_SINGULAR);
+    phase(2);
     // UA-AMG hierarchy on the host (greedy grouping and matching)
     Hierarchy H;
     int st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H);
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
+    phase(3);
     c->lev.resize(H.A.size());
     for (size_t l = 0; l < H.A.size(); ++l) {
         Level &L = c->lev[l];
@@ -509,8 +517,13 @@ void rebuild_B(msp_ctx *c, const double *vals)
     for (size_t l = 0; l + 1 < c->lev.size(); ++l) c->lev[l].nc = c->lev[l + 1].A.n;
     for (size_t l = 0; l < c->lev.size(); ++l) build_level_device(c, (int)l, H);
     link_levels(c);
+    c->sync();
+    phase(4);
     build_coarse(c);
+    phase(5);
     build_bilu(c, vals);
+    c->sync();
+    phase(6);
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
     c->e_nat = c->dalloc(tsz * n, c->allocB);
     c->ybuf = c->dalloc(tsz * (size_t)n * b, c->allocB);
@@ -832,7 +845,7 @@ int msp_default_options(msp_options *opt)
     opt->max_iter = 1000;
     opt->max_coarse = 10000;
     opt->precond_fp32 = 0;
-    opt->bilu_order = 0;
+    opt->bilu_order = 1;
     return MSP_OK;
 }
 
@@ -910,6 +923,7 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
                               c->stream));
         c->sync();
         if (check_pattern(n, rp.data(), ci.data(), nnzb) != 0) fail(MSP_ERR_PATTERN);
+        for (double &ph : c->info.phase_ms) ph = 0.0;
         const bool layout_changed = !c->haveA || n != c->n || b != c->b || p != c->p ||
                                     nnzb != c->nnzb || rp != c->rp || ci != c->ci;
         if (layout_changed) {
@@ -925,10 +939,13 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
                     if (c->ci[k] == i) c->diag_pos[i] = k;
             build_layout_A(c);
         }
+        const double ti = now_ms();
+        c->info.phase_ms[0] = ti - t0;
         c->clear_flag();
         HIPCHK(launch_ingest_bsr(b, p, c->SA.lay.slot_lanes, c->SA.src, vals, c->valA, c->pcol32,
                                  c->flag, c->stream));
         if (c->read_flag()) fail(MSP_ERR_NONFINITE);
+        c->info.phase_ms[1] = now_ms() - ti;
         c->haveA = true;
         // adaptive SETUP (Sec. 3.2)
         const bool rebuild = !c->hasB || c->Bn != n || c->Bb != b || c->Bp != p ||
@@ -1004,7 +1021,7 @@ int msp_footprint(int n, long long nnzb, int b, const msp_options *opt, size_t *
                   (double)n * (E * ts + 24);
     double vecs = (double)n * b * (8 + 2 * ts) + (double)n * 8 * b;
     double krylov = 8.0 * (double)n * b * (2.0 * o.restart + 4) + 8.0 * kDotBlocks * (o.restart + 2);
-    double setup_tmp = 8.0 * nnzb + 8.0 * (2 * 64.0 * o.max_coarse);
+    double setup_tmp = 8.0 * nnzb + 8.0 * (3 * 128.0 * o.max_coarse + 128.0 * 128.0);
     *bytes = (size_t)(A + amg + coarse + bilu + vecs + krylov + setup_tmp + (1 << 20));
     return MSP_OK;
 }

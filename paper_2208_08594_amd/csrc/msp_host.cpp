@@ -69,13 +69,15 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         int da = G.degree(a), db = G.degree(b);
         return da != db ? da > db : a < b;
     });
-    struct Cand {
-        int deg, v;
+    // candidate key: larger degree first, then smaller index (max-heap on the key)
+    auto key = [&](int v) -> unsigned long long {
+        return ((unsigned long long)(unsigned)G.degree(v) << 32) | (unsigned)(0x7fffffff - v);
     };
-    auto lower_priority = [](const Cand &a, const Cand &b) {
-        return a.deg != b.deg ? a.deg < b.deg : a.v > b.v;
-    };
-    std::vector<unsigned char> open(n), queued(n);
+    // open: still in V; queued: already a second-ring candidate of this group;
+    // scanned: neighbourhood already enumerated for this group.  A vertex never
+    // re-enters V inside a group, so enumerating a neighbourhood a second time
+    // cannot add a candidate: each neighbourhood is scanned at most once per group.
+    std::vector<unsigned char> open(n), queued(n), scanned(n);
     int left = n, g = 0;
     while (left > 0) {
         ++g;  // one call of VerticesSplitting builds group g
@@ -83,14 +85,15 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         for (int i = 0; i < n; ++i) {
             open[i] = color[i] == 0;  // V: undetermined vertices
             queued[i] = 0;
+            scanned[i] = 0;
             avail += open[i];
         }
-        std::priority_queue<Cand, std::vector<Cand>, decltype(lower_priority)> hat(lower_priority);
+        std::priority_queue<unsigned long long> hat;
         size_t cursor = 0;
         while (avail > 0) {
             int v = -1;
             while (!hat.empty()) {  // second-ring candidates W^ that are still in V
-                int t = hat.top().v;
+                int t = 0x7fffffff - (int)(hat.top() & 0xffffffffULL);
                 hat.pop();
                 if (open[t]) { v = t; break; }
             }
@@ -108,11 +111,13 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             }
             for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // second ring enters W^
                 int u = G.nbr[q];
+                if (scanned[u]) continue;
+                scanned[u] = 1;
                 for (int t = G.ptr[u]; t < G.ptr[u + 1]; ++t) {
                     int w = G.nbr[t];
                     if (open[w] && !queued[w]) {
                         queued[w] = 1;
-                        hat.push({G.degree(w), w});
+                        hat.push(key(w));
                     }
                 }
             }
@@ -131,23 +136,47 @@ static inline double entry(const Csr &A, int i, int j)
 int pairwise_pass(const Csr &A, std::vector<int> &agg)
 {
     const int n = A.n;
-    Adjacency G = build_adjacency(n, A.rp.data(), A.ci.data());
-    // strength s_ij = -(a_ij + a_ji)/2 on the symmetrised neighbours
-    std::vector<double> s(G.nbr.size());
+    // transpose with values: AT row j lists (i, a_ij) for stored (i, j), i ascending
+    std::vector<int> tp(n + 1, 0), ti(A.ci.size());
+    std::vector<double> tv(A.ci.size());
+    for (size_t k = 0; k < A.ci.size(); ++k) ++tp[A.ci[k] + 1];
+    for (int j = 0; j < n; ++j) tp[j + 1] += tp[j];
+    {
+        std::vector<int> f(tp.begin(), tp.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                int q = f[A.ci[k]]++;
+                ti[q] = i;
+                tv[q] = A.val[k];
+            }
+    }
+    // symmetrised neighbours of i = merge of row i of A and row i of A^T
+    // (both ascending), with s_ij = -(a_ij + a_ji)/2
+    std::vector<int> nptr(n + 1, 0), nbr;
+    std::vector<double> s;
+    nbr.reserve(2 * A.ci.size());
+    s.reserve(2 * A.ci.size());
     std::vector<double> smax(n, 0.0);
     std::vector<unsigned char> eligible(n, 0);
     for (int i = 0; i < n; ++i) {
-        bool coupled = false;
-        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-            if (A.ci[k] != i && A.val[k] != 0.0) coupled = true;
+        int a = A.rp[i], ae = A.rp[i + 1], t = tp[i], te = tp[i + 1];
+        bool coupled = false, any = false;
         double mx = 0.0;
-        bool any = false;
-        for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
-            int j = G.nbr[q];
-            s[q] = -(entry(A, i, j) + entry(A, j, i)) / 2.0;
-            if (!any || s[q] > mx) mx = s[q];
+        while (a < ae || t < te) {
+            int ja = a < ae ? A.ci[a] : n, jt = t < te ? ti[t] : n;
+            int j = ja < jt ? ja : jt;
+            double aij = 0.0, aji = 0.0;
+            if (ja == j) { aij = A.val[a]; ++a; }
+            if (jt == j) { aji = tv[t]; ++t; }
+            if (j == i) continue;
+            if (ja == j && aij != 0.0) coupled = true;
+            double sij = -(aij + aji) / 2.0;
+            nbr.push_back(j);
+            s.push_back(sij);
+            if (!any || sij > mx) mx = sij;
             any = true;
         }
+        nptr[i + 1] = (int)nbr.size();
         smax[i] = mx;
         eligible[i] = coupled && any && mx > 0.0;
     }
@@ -159,8 +188,8 @@ int pairwise_pass(const Csr &A, std::vector<int> &agg)
         double bs = 0.0;
         if (eligible[i]) {
             const double thr = 0.25 * smax[i];
-            for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
-                int j = G.nbr[q];
+            for (int q = nptr[i]; q < nptr[i + 1]; ++q) {
+                int j = nbr[q];
                 if (agg[j] >= 0 || !eligible[j]) continue;
                 if (s[q] >= thr && (best < 0 || s[q] > bs)) { best = j; bs = s[q]; }
             }

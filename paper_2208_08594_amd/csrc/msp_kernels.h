@@ -121,8 +121,13 @@ hipError_t launch_fill(long long N, double v, double *x, hipStream_t st);
 // ---- dense coarsest level ---------------------------------------------------
 hipError_t launch_dense_scatter(int n, const int *rp, const int *ci, const double *val, double *M,
                                 hipStream_t st);
-// In-place inverse of the n x n row-major matrix M by block Gauss-Jordan with
-// partial pivoting inside each diagonal block.  work >= (2*n*64 + 64*64) doubles.
+// C = alpha A B + beta C, row-major FP64 (matrix-core tiles).
+hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
+                        double *C, int ldc, double alpha, double beta, hipStream_t st);
+// In-place inverse of the n x n row-major matrix M by block Gauss-Jordan over
+// 128-wide panels with partial pivoting inside each diagonal block.
+// work must hold dense_inverse_work(n) doubles.
+size_t dense_inverse_work(int n);
 hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t st);
 
 }  // namespace msp

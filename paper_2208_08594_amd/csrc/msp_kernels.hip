@@ -760,167 +760,248 @@ __global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, const int *__
     for (int k = rp[i]; k < rp[i + 1]; ++k) M[(long long)i * n + ci[k]] = val[k];
 }
 
-constexpr int kNB = 64;
+constexpr int kNB = 128;  // Gauss-Jordan panel width
 
-// Invert the kb x kb diagonal block at (K, K) by Gauss-Jordan with partial
-// pivoting inside the block.  One work-group.
-__global__ __launch_bounds__(kThreads) void k_gj_diag(int n, int K, int kb,
-                                                      const double *__restrict__ M,
-                                                      double *__restrict__ Dblk, int *bad)
+// Inverse of the kb x kb diagonal block at (K, K) by Gauss-Jordan elimination
+// with partial pivoting inside the block.  One 1024-thread work-group keeps the
+// block A and the growing inverse X in registers: thread (tr, tc) owns rows
+// tr + 32a and columns tc + 32b (a, b < 4).  Pivoting is implicit: column k
+// is eliminated with the unused row p_k of largest magnitude (lowest index on
+// ties) and no rows move, so at the end row k of A^-1 is row p_k of X.
+// Per step the pivot column and the scaled pivot row go through LDS (double
+// buffered), three barriers per step.  Dblk has leading dimension kNB.
+__global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
+                                                  const double *__restrict__ M,
+                                                  double *__restrict__ Dblk, int *bad)
 {
-    __shared__ double A[kNB][kNB + 1];
-    __shared__ double X[kNB][kNB + 1];
-    __shared__ double fac[kNB];
-    __shared__ int piv_s;
+    __shared__ double colk[2][kNB];
+    __shared__ double prowA[2][kNB], prowX[2][kNB];
+    __shared__ unsigned char used[kNB];
+    __shared__ int invp[kNB];
+    __shared__ int piv_s[2];
     const int tid = threadIdx.x;
-    for (int q = tid; q < kNB * kNB; q += kThreads) {
-        int r = q / kNB, c = q % kNB;
-        A[r][c] = (r < kb && c < kb) ? M[(long long)(K + r) * n + K + c] : (r == c ? 1.0 : 0.0);
-        X[r][c] = (r == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        if (tid < 64) {
-            double a = (tid >= k && tid < kb) ? fabs(A[tid][k]) : -1.0;
-            int idx = tid;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                double a2 = __shfl_xor(a, o, 64);
-                int i2 = __shfl_xor(idx, o, 64);
-                if (a2 > a || (a2 == a && i2 < idx)) { a = a2; idx = i2; }
-            }
-            if (tid == 0) {
-                piv_s = idx;
-                if (!(a > 0.0)) atomicOr(bad, 1);
-            }
-        }
-        __syncthreads();
-        const int pv = piv_s;
-        if (pv != k) {
-            for (int c = tid; c < kNB; c += kThreads) {
-                double t = A[k][c]; A[k][c] = A[pv][c]; A[pv][c] = t;
-                t = X[k][c]; X[k][c] = X[pv][c]; X[pv][c] = t;
-            }
-        }
-        __syncthreads();
-        const double d = A[k][k];
-        __syncthreads();
-        for (int c = tid; c < kNB; c += kThreads) {
-            A[k][c] = A[k][c] / d;
-            X[k][c] = X[k][c] / d;
-        }
-        __syncthreads();
-        for (int r = tid; r < kNB; r += kThreads) fac[r] = (r == k) ? 0.0 : A[r][k];
-        __syncthreads();
-        for (int q = tid; q < kNB * kNB; q += kThreads) {
-            int r = q / kNB, c = q % kNB;
-            if (r != k) {
-                A[r][c] -= fac[r] * A[k][c];
-                X[r][c] -= fac[r] * X[k][c];
-            }
-        }
-        __syncthreads();
-    }
-    // undo nothing: row swaps of A were applied to X as well, so X = A^{-1}
-    for (int q = tid; q < kNB * kNB; q += kThreads) {
-        int r = q / kNB, c = q % kNB;
-        Dblk[q] = X[r][c];
-    }
-}
-
-// Trow[t][j] = sum_u Dblk[t][u] M[K+u][j] for j outside the block, Dblk[t][j-K] inside.
-__global__ __launch_bounds__(kThreads) void k_gj_trow(int n, int K, int kb,
-                                                      const double *__restrict__ M,
-                                                      const double *__restrict__ Dblk,
-                                                      double *__restrict__ Trow)
-{
-    __shared__ double Ds[kNB][kNB + 1];
-    for (int q = threadIdx.x; q < kNB * kNB; q += kThreads) Ds[q / kNB][q % kNB] = Dblk[q];
-    __syncthreads();
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= n) return;
-    if (j >= K && j < K + kb) {
-        for (int t = 0; t < kb; ++t) Trow[(long long)t * n + j] = Ds[t][j - K];
-        return;
-    }
-    double col[kNB];
-#pragma unroll
-    for (int u = 0; u < kNB; ++u) col[u] = u < kb ? M[(long long)(K + u) * n + j] : 0.0;
-    for (int t = 0; t < kb; ++t) {
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kNB; ++u) acc += Ds[t][u] * col[u];
-        Trow[(long long)t * n + j] = acc;
-    }
-}
-
-// Ccol[i][t] = M[i][K+t]
-__global__ __launch_bounds__(kThreads) void k_gj_ccol(int n, int K, int kb,
-                                                      const double *__restrict__ M,
-                                                      double *__restrict__ Ccol)
-{
-    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= (long long)n * kNB) return;
-    int i = (int)(q / kNB), t = (int)(q % kNB);
-    Ccol[q] = t < kb ? M[(long long)i * n + K + t] : 0.0;
-}
-
-// M[i][j] = (j in block ? 0 : M[i][j]) - sum_t Ccol[i][t] Trow[t][j]  (i outside block)
-// M[i][j] = Trow[i-K][j]                                              (i inside block)
-__global__ __launch_bounds__(kThreads) void k_gj_update(int n, int K, int kb,
-                                                        const double *__restrict__ Ccol,
-                                                        const double *__restrict__ Trow,
-                                                        double *__restrict__ M)
-{
-    __shared__ double Cs[64][kNB + 1];
-    __shared__ double Ts[kNB][64 + 1];
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    const int tid = threadIdx.x;
-    for (int q = tid; q < 64 * kNB; q += kThreads) {
-        int r = q / kNB, t = q % kNB;
-        int i = i0 + r;
-        Cs[r][t] = (i < n) ? Ccol[(long long)i * kNB + t] : 0.0;
-    }
-    for (int q = tid; q < kNB * 64; q += kThreads) {
-        int t = q / 64, c = q % 64;
-        int j = j0 + c;
-        Ts[t][c] = (j < n && t < kb) ? Trow[(long long)t * n + j] : 0.0;
-    }
-    __syncthreads();
-    const int ty = tid / 16, tx = tid % 16;
-    double acc[4][4];
+    const int tr = tid >> 5, tc = tid & 31;
+    double A[4][4], X[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    for (int t = 0; t < kb; ++t) {
-        double cv[4], tv[4];
+        for (int b = 0; b < 4; ++b) {
+            const int r = tr + 32 * a, c = tc + 32 * b;
+            A[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * n + K + c] : (r == c ? 1.0 : 0.0);
+            X[a][b] = (r == c) ? 1.0 : 0.0;
+        }
+    if (tid < kNB) used[tid] = 0;
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        const int buf = k & 1;
+        if (tc == (k & 31)) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) cv[a] = Cs[ty * 4 + a][t];
+            for (int b = 0; b < 4; ++b)
+                if (b == (k >> 5))
 #pragma unroll
-        for (int c = 0; c < 4; ++c) tv[c] = Ts[t][tx * 4 + c];
+                    for (int a = 0; a < 4; ++a) colk[buf][tr + 32 * a] = A[a][b];
+        }
+        __syncthreads();
+        if (tid < 64) {
+            double best = -1.0;
+            int idx = kNB;
+            for (int r = tid; r < kb; r += 64) {
+                double v = used[r] ? -1.0 : fabs(colk[buf][r]);
+                if (v > best) { best = v; idx = r; }
+            }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int o = 32; o > 0; o >>= 1) {
+                double b2 = __shfl_xor(best, o, 64);
+                int i2 = __shfl_xor(idx, o, 64);
+                if (b2 > best || (b2 == best && i2 < idx)) { best = b2; idx = i2; }
+            }
+            if (tid == 0) {
+                piv_s[buf] = idx;
+                used[idx] = 1;
+                invp[idx] = k;
+                if (!(best > 0.0)) atomicOr(bad, 1);
+            }
+        }
+        __syncthreads();
+        const int p = piv_s[buf];
+        if (tr == (p & 31)) {
+            const double d = colk[buf][p];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[a][c] += cv[a] * tv[c];
-    }
+            for (int a = 0; a < 4; ++a)
+                if (a == (p >> 5))
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ty * 4 + a;
-        if (i >= n) continue;
+                    for (int b = 0; b < 4; ++b) {
+                        prowA[buf][tc + 32 * b] = A[a][b] / d;
+                        prowX[buf][tc + 32 * b] = X[a][b] / d;
+                    }
+        }
+        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int j = j0 + tx * 4 + c;
-            if (j >= n) continue;
-            double *m = M + (long long)i * n + j;
-            if (i >= K && i < K + kb) {
-                *m = Ts[i - K][tx * 4 + c];
-            } else {
-                double base = (j >= K && j < K + kb) ? 0.0 : *m;
-                *m = base - acc[a][c];
+        for (int a = 0; a < 4; ++a) {
+            const int r = tr + 32 * a;
+            const double f = colk[buf][r];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = tc + 32 * b;
+                if (r == p) {
+                    A[a][b] = prowA[buf][c];
+                    X[a][b] = prowX[buf][c];
+                } else {
+                    A[a][b] -= f * prowA[buf][c];
+                    X[a][b] -= f * prowX[buf][c];
+                }
             }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = tr + 32 * a, c = tc + 32 * b;
+            if (r < kb && c < kb) Dblk[invp[r] * kNB + c] = X[a][b];
+        }
+    // zero the padding so the following products see an exact kb x kb block
+    for (int q = tid; q < kNB * kNB; q += 1024) {
+        int r = q / kNB, c = q % kNB;
+        if (r >= kb || c >= kb) Dblk[q] = 0.0;
+    }
+}
+
+// Ccol[i][t] = M[i][K+t] for rows outside the block (0 inside), ld kNB;
+// Mrow[t][j] = M[K+t][j], ld n.
+__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int K, int kb,
+                                                         const double *__restrict__ M,
+                                                         double *__restrict__ Ccol,
+                                                         double *__restrict__ Mrow)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long nc = (long long)n * kNB;
+    if (q < nc) {
+        int i = (int)(q / kNB), t = (int)(q % kNB);
+        bool inblk = i >= K && i < K + kb;
+        Ccol[q] = (t < kb && !inblk) ? M[(long long)i * n + K + t] : 0.0;
+    } else if (q < nc + (long long)kb * n) {
+        long long r = q - nc;
+        int t = (int)(r / n), j = (int)(r % n);
+        Mrow[r] = M[(long long)(K + t) * n + j];
+    }
+}
+
+// Trow[t][K+u] = Dblk[t][u]; M[i][K+u] = 0 for rows outside the block.
+__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int K, int kb,
+                                                     const double *__restrict__ Dblk,
+                                                     double *__restrict__ Trow,
+                                                     double *__restrict__ M)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const long long nt = (long long)kb * kb;
+    if (q < nt) {
+        int t = (int)(q / kb), u = (int)(q % kb);
+        Trow[(long long)t * n + K + u] = Dblk[t * kNB + u];
+    } else if (q < nt + (long long)n * kb) {
+        long long r = q - nt;
+        int i = (int)(r / kb), u = (int)(r % kb);
+        if (i < K || i >= K + kb) M[(long long)i * n + K + u] = 0.0;
+    }
+}
+
+// M[K+t][j] = Trow[t][j]
+__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int K, int kb,
+                                                        const double *__restrict__ Trow,
+                                                        double *__restrict__ M)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q < (long long)kb * n) M[(long long)K * n + q] = Trow[q];
+}
+
+// C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  Each
+// 256-thread work-group owns a 128x128 tile of C; each wave a 64x64 quadrant
+// of 4x4 v_mfma_f64_16x16x4 blocks (64 accumulators per lane).  A and B are
+// staged through LDS in k-chunks of 32, double buffered: the next chunk is
+// fetched into registers while the current one is multiplied.
+// Lane layout of the 16x16x4 FP64 MFMA: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (the output rows of
+// one lane are interleaved by 4, unlike the FP32 variant).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kGT = 128, kGK = 32;
+
+__global__ __launch_bounds__(kThreads) void k_dgemm(int Mr, int Nc, int Kd,
+                                                    const double *__restrict__ A, int lda,
+                                                    const double *__restrict__ B, int ldb,
+                                                    double *__restrict__ C, int ldc, double alpha,
+                                                    double beta)
+{
+    __shared__ double As[2][kGT][kGK + 1];
+    __shared__ double Bs[2][kGK][kGT + 1];
+    const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // each thread moves 16 A values (rows tid/32*... ) and 16 B values per chunk
+    double ra[16], rb[16];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = tid + u * kThreads;  // 0..4095
+            const int r = q >> 5, c = q & 31;  // A chunk: 128 x 32
+            const int i = i0 + r, k = k0 + c;
+            ra[u] = (i < Mr && k < Kd) ? A[(long long)i * lda + k] : 0.0;
+            const int rb_ = q >> 7, cb = q & 127;  // B chunk: 32 x 128
+            const int kb = k0 + rb_, j = j0 + cb;
+            rb[u] = (kb < Kd && j < Nc) ? B[(long long)kb * ldb + j] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = tid + u * kThreads;
+            As[buf][q >> 5][q & 31] = ra[u];
+            Bs[buf][q >> 7][q & 127] = rb[u];
+        }
+    };
+    const int nchunk = (Kd + kGK - 1) / kGK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) fetch((ch + 1) * kGK);
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 4) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[buf][wr + a * 16 + li][kk + lk];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk + lk][wc + b * 16 + li];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + a * 16 + lk + 4 * r;
+                const int j = j0 + wc + b * 16 + li;
+                if (i < Mr && j < Nc) {
+                    double *c = C + (long long)i * ldc + j;
+                    const double v = alpha * acc[a][b][r];
+                    *c = (beta != 0.0) ? v + beta * *c : v;
+                }
+            }
 }
 
 }  // namespace
@@ -1220,19 +1301,35 @@ hipError_t launch_dense_scatter(int n, const int *rp, const int *ci, const doubl
     return hipGetLastError();
 }
 
+hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
+                        double *C, int ldc, double alpha, double beta, hipStream_t st)
+{
+    dim3 grid((unsigned)((Nc + kGT - 1) / kGT), (unsigned)((Mr + kGT - 1) / kGT));
+    k_dgemm<<<grid, kThreads, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
+    return hipGetLastError();
+}
+
+size_t dense_inverse_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
+
 hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t st)
 {
-    double *Trow = work;
-    double *Ccol = work + (long long)kNB * n;
-    double *Dblk = work + 2LL * kNB * n;
+    double *Ccol = work;                       // n x kNB
+    double *Mrow = work + (long long)kNB * n;  // kNB x n
+    double *Trow = Mrow + (long long)kNB * n;  // kNB x n
+    double *Dblk = Trow + (long long)kNB * n;  // kNB x kNB
     for (int K = 0; K < n; K += kNB) {
         const int kb = n - K < kNB ? n - K : kNB;
-        k_gj_diag<<<1, kThreads, 0, st>>>(n, K, kb, M, Dblk, bad);
-        k_gj_trow<<<blocks_for(n), kThreads, 0, st>>>(n, K, kb, M, Dblk, Trow);
-        k_gj_ccol<<<blocks_for((long long)n * kNB), kThreads, 0, st>>>(n, K, kb, M, Ccol);
-        dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-        k_gj_update<<<grid, kThreads, 0, st>>>(n, K, kb, Ccol, Trow, M);
-        hipError_t e = hipGetLastError();
+        k_gj_diag<<<1, 1024, 0, st>>>(n, K, kb, M, Dblk, bad);
+        k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
+            n, K, kb, M, Ccol, Mrow);
+        hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);
+        if (e != hipSuccess) return e;
+        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
+            n, K, kb, Dblk, Trow, M);
+        e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, n, -1.0, 1.0, st);
+        if (e != hipSuccess) return e;
+        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, K, kb, Trow, M);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

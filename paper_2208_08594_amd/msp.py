@@ -40,7 +40,8 @@ class MspInfo(C.Structure):
                 ("n_levels", C.c_int), ("level_rows", C.c_int * MAX_LEVELS),
                 ("n_colors", C.c_int * MAX_LEVELS), ("bilu_levels_fwd", C.c_int),
                 ("bilu_levels_bwd", C.c_int), ("rel_true_residual", C.c_double),
-                ("setup_ms", C.c_double), ("rebuild_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("rebuild_ms", C.c_double), ("solve_ms", C.c_double),
+                ("phase_ms", C.c_double * 8)]
 
     def as_dict(self):
         nl = self.n_levels
@@ -50,7 +51,8 @@ class MspInfo(C.Structure):
                     n_colors=list(self.n_colors[:nl]), bilu_levels_fwd=self.bilu_levels_fwd,
                     bilu_levels_bwd=self.bilu_levels_bwd,
                     rel_true_residual=self.rel_true_residual, setup_ms=self.setup_ms,
-                    rebuild_ms=self.rebuild_ms, solve_ms=self.solve_ms)
+                    rebuild_ms=self.rebuild_ms, solve_ms=self.solve_ms,
+                    phase_ms=list(self.phase_ms))
 
 
 # every exported symbol and its signature (checked by the CPU tests against the headers)
@@ -161,7 +163,7 @@ class Solver:
     """
 
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
-                 bilu_order=0, stream=None, device=None, torch_allocator=True):
+                 bilu_order=1, stream=None, device=None, torch_allocator=True):
         import torch
         self.torch = torch
         dev = torch.device("cuda") if device is None else torch.device(device)

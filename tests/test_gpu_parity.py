@@ -37,29 +37,34 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def solvers(sys, max_coarse=10000, fp32=False, mu=0):
-    announce(sys.name, f"n={sys.n} b={sys.b} max_coarse={max_coarse} fp32={fp32} mu={mu}")
-    g = msp.Solver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu)
+def solvers(sys, max_coarse=10000, fp32=False, mu=0, bilu_order=0):
+    announce(sys.name, f"n={sys.n} b={sys.b} max_coarse={max_coarse} fp32={fp32} mu={mu} "
+                       f"bilu_order={bilu_order}")
+    g = msp.Solver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu, bilu_order=bilu_order)
     g.setup(sys)
-    o = O.OracleSolver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu)
+    o = O.OracleSolver(max_coarse=max_coarse, precond_fp32=fp32, mu=mu, bilu_order=bilu_order)
     o.setup(sys)
     return g, o
 
 
 CASES = [
-    ("cfg0", lambda: synth.config(0), 10000),
-    ("cfg0-mc64", lambda: synth.config(0), 64),
-    ("grid20x18x9b3", lambda: synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4"), 200),
-    ("grid13x11x7b7", lambda: synth.lognormal_grid(13, 11, 7, 7, 8, 1.0, 0.1, "lateral4"), 100),
-    ("grid33x17x5b2", lambda: synth.lognormal_grid(33, 17, 5, 2, 9, 1.5, 1.0, "corners2"), 150),
+    ("cfg0", lambda: synth.config(0), 10000, 0),
+    ("cfg0-mc64", lambda: synth.config(0), 64, 0),
+    ("cfg0-mc64-mcbilu", lambda: synth.config(0), 64, 1),
+    ("grid20x18x9b3", lambda: synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4"), 200, 0),
+    ("grid13x11x7b7-mcbilu", lambda: synth.lognormal_grid(13, 11, 7, 7, 8, 1.0, 0.1, "lateral4"),
+     100, 1),
+    ("grid33x17x5b2", lambda: synth.lognormal_grid(33, 17, 5, 2, 9, 1.5, 1.0, "corners2"), 150, 0),
+    ("grid40x40x12b4-mcbilu", lambda: synth.lognormal_grid(40, 40, 12, 4, 10, 1.5, 0.1,
+                                                           "lateral4"), 10000, 1),
 ]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
 def case(request):
-    name, mk, mc = request.param
+    name, mk, mc, bo = request.param
     sys = mk()
-    g, o = solvers(sys, mc)
+    g, o = solvers(sys, mc, bilu_order=bo)
     yield sys, g, o
     g.close()
     o.close()
@@ -322,9 +327,10 @@ def test_deterministic_bitwise():
 # --------------------------------------------------------------------------
 # the benchmark workload at full size: 64x64x32 cells, block size 4
 # --------------------------------------------------------------------------
-def test_full_size_benchmark_workload():
+@pytest.mark.parametrize("bilu_order", [1, 0])
+def test_full_size_benchmark_workload(bilu_order):
     sys = synth.config(1)
-    g, o = solvers(sys, 10000)
+    g, o = solvers(sys, 10000, bilu_order=bilu_order)
     info = g.info()
     assert info["n_levels"] == o.nlevels
     for l in range(o.nlevels):

@@ -51,7 +51,7 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(msp_options), offsetof(msp_options, stream),
          offsetof(msp_options, alloc_user), sizeof(msp_info),
-         offsetof(msp_info, rel_true_residual), offsetof(msp_info, solve_ms));
+         offsetof(msp_info, rel_true_residual), offsetof(msp_info, phase_ms));
   return 0;
 }
 '''
@@ -62,7 +62,7 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", INC, cpath, "-o", exe])
         vals = list(map(int, subprocess.check_output([exe]).split()))
     got = [C.sizeof(msp.MspOptions), msp.MspOptions.stream.offset, msp.MspOptions.alloc_user.offset,
-           C.sizeof(msp.MspInfo), msp.MspInfo.rel_true_residual.offset, msp.MspInfo.solve_ms.offset]
+           C.sizeof(msp.MspInfo), msp.MspInfo.rel_true_residual.offset, msp.MspInfo.phase_ms.offset]
     assert vals == got
 
 

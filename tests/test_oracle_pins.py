@@ -360,7 +360,7 @@ def test_bilu0_exact_on_block_tridiagonal_one_iteration():
     F, D = O.bilu0_factor(sys.n, sys.b, sys.row_ptr, sys.col_ind, sys.vals)
     L, U = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, F, D, sys.n, sys.b)
     np.testing.assert_allclose(L @ U, sys.to_dense(), rtol=1e-12, atol=1e-10)
-    s = O.OracleSolver(max_coarse=8)
+    s = O.OracleSolver(max_coarse=8, bilu_order=0)
     s.setup(sys)
     x, it, rr, st = s.solve(sys.rhs, 1e-10)
     assert it == 1 and rr <= 1e-10
@@ -377,7 +377,7 @@ def _dense_operator(fn, n):
 def test_reduced_apply_equals_literal_alg31(max_coarse):
     sys = synth.lognormal_grid(3, 3, 2, 3, 7, 1.0, 1.0, [0])
     n, b, p, N = sys.n, sys.b, sys.p, sys.N
-    s = O.OracleSolver(max_coarse=max_coarse)
+    s = O.OracleSolver(max_coarse=max_coarse, bilu_order=0)
     s.setup(sys)
     A = sys.to_dense()
     W = np.zeros((N, N))
@@ -634,3 +634,39 @@ def test_validation_errors():
     rp2 = np.array([0, 1, 2], dtype=np.int32)
     ci2 = np.array([1, 0], dtype=np.int32)
     assert O.validate(2, 1, 0, rp2, ci2, np.ones((2, 1, 1))) == -2
+
+
+@pytest.mark.parametrize("b", [1, 3])
+def test_bilu0_multicolor_order_defining_property(b):
+    """Block ILU(0) in the multi-color elimination order is ILU(0) of the
+    symmetrically permuted matrix: (L U)_ij = (P A P^T)_ij on its pattern."""
+    sys = synth.lognormal_grid(6, 5, 4, b, 31, 1.0, 1.0, "corners2")
+    n = sys.n
+    order = O.multicolor_order(sys.row_ptr, sys.col_ind)
+    col, g = O.color(sys.row_ptr, sys.col_ind)
+    assert g == 2 and np.all(np.diff(col[order]) >= 0)
+    F, D = O.bilu0_factor(n, b, sys.row_ptr, sys.col_ind, sys.vals, order=order)
+    pos = np.argsort(order)
+    L = np.eye(n * b)
+    U = np.zeros((n * b, n * b))
+    for i in range(n):
+        for k in range(sys.row_ptr[i], sys.row_ptr[i + 1]):
+            j = sys.col_ind[k]
+            pi, pj = pos[i], pos[j]
+            blk = (slice(pi * b, (pi + 1) * b), slice(pj * b, (pj + 1) * b))
+            if pj < pi:
+                L[blk] = F[k]
+            elif pj > pi:
+                U[blk] = F[k]
+        U[pos[i] * b:(pos[i] + 1) * b, pos[i] * b:(pos[i] + 1) * b] = np.linalg.inv(D[i])
+    perm = (order[:, None] * b + np.arange(b)[None, :]).reshape(-1)
+    PAPt = sys.to_dense()[np.ix_(perm, perm)]
+    LU = L @ U
+    for i in range(n):
+        for k in range(sys.row_ptr[i], sys.row_ptr[i + 1]):
+            pi, pj = pos[i], pos[sys.col_ind[k]]
+            blk = (slice(pi * b, (pi + 1) * b), slice(pj * b, (pj + 1) * b))
+            np.testing.assert_allclose(LU[blk], PAPt[blk], rtol=1e-11, atol=1e-11)
+    r = np.random.default_rng(1).uniform(-1, 1, n * b)
+    z = O.bilu0_solve(n, b, sys.row_ptr, sys.col_ind, F, D, r, order=order)
+    np.testing.assert_allclose(LU @ z[perm], r[perm], rtol=1e-10, atol=1e-12)
