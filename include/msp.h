@@ -69,6 +69,10 @@ typedef struct {
                          1 (default): the groups of Alg. 4.2 on the block adjacency graph
                          one after another (two dependency levels on a 7-point grid);
                          0: natural block order (nx+ny+nz-2 levels on a 7-point grid) */
+    int use_graphs;   /* 1 (default): the preconditioner apply is captured once per
+                         regeneration into a HIP graph and replayed every iteration
+                         (input/output staged through two context-owned vectors);
+                         0: every kernel is launched eagerly */
     void *stream;     /* hipStream_t for all work; NULL = the default stream */
     /* Optional device allocator (e.g. a framework caching allocator); both NULL =
      * hipMalloc/hipFree.  dev_alloc returns NULL on failure. */

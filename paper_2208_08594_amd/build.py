@@ -38,7 +38,8 @@ def build(verbose: bool = False) -> str:
         _run(["hipcc", *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = OUT + f".tmp{os.getpid()}"
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-pthread"],
+         verbose)
     os.replace(tmp, OUT)
     return OUT
 

@@ -7,7 +7,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
+#include <thread>
 #include <numeric>
 #include <type_traits>
 #include <vector>
@@ -118,10 +120,14 @@ struct msp_ctx {
     long long Bnnzb = 0;
     double *omega = nullptr;
     std::vector<Level> lev;
-    int nL = 0;
+    int nL = 0, ldL = 0;
     double *cinv = nullptr;
     BiluData bilu;
     void *e_nat = nullptr, *ybuf = nullptr;
+    // captured preconditioner apply (valid for the current B and A layout)
+    double *vin = nullptr, *zout = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t apply_exec = nullptr;
     // krylov workspace
     long long wsN = 0;
     int wsm = 0;
@@ -197,8 +203,11 @@ void upload_sell(msp_ctx *c, DevSell &S, std::vector<void *> &list)
 // --------------------------------------------------------------------------
 // matrix ingest
 // --------------------------------------------------------------------------
+void drop_graph(msp_ctx *c);
+
 void build_layout_A(msp_ctx *c)
 {
+    drop_graph(c);
     c->release(c->allocA);
     const int n = c->n;
     std::vector<int> seg_row = {0, n};
@@ -218,8 +227,18 @@ void build_layout_A(msp_ctx *c)
 // --------------------------------------------------------------------------
 // preconditioner regeneration
 // --------------------------------------------------------------------------
+void drop_graph(msp_ctx *c)
+{
+    if (c->apply_exec) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->apply_exec);
+        c->apply_exec = nullptr;
+    }
+}
+
 void release_B(msp_ctx *c)
 {
+    drop_graph(c);
     c->release(c->allocB);
     c->lev.clear();
     c->bilu = BiluData();
@@ -329,26 +348,32 @@ void build_coarse(msp_ctx *c)
     Level &L = c->lev.back();
     const int m = L.n;
     c->nL = m;
-    c->cinv = (double *)c->dalloc(sizeof(double) * (size_t)m * m, c->allocB);
+    c->ldL = (m + 15) & ~15;  // rows 128-byte aligned for the streaming GEMV
+    c->cinv = (double *)c->dalloc(sizeof(double) * (size_t)m * c->ldL, c->allocB);
     std::vector<void *> tmp;
     int *rp = c->upload(L.A.rp, tmp);
     int *ci = c->upload(L.A.ci, tmp);
     double *val = c->upload(L.A.val, tmp);
     double *work = (double *)c->dalloc(sizeof(double) * dense_inverse_work(m), tmp);
-    HIPCHK(launch_fill((long long)m * m, 0.0, c->cinv, c->stream));
-    HIPCHK(launch_dense_scatter(m, rp, ci, val, c->cinv, c->stream));
+    HIPCHK(launch_fill((long long)m * c->ldL, 0.0, c->cinv, c->stream));
+    HIPCHK(launch_dense_scatter(m, c->ldL, rp, ci, val, c->cinv, c->stream));
     c->clear_flag();
-    HIPCHK(dense_inverse(m, c->cinv, work, c->flag, c->stream));
+    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream));
     int bad = c->read_flag();
     c->release(tmp);
     if (bad) fail(MSP_ERR_SINGULAR);
 }
 
-void build_bilu(msp_ctx *c, const double *vals)
+// Host-only part of the block ILU(0) setup: elimination order, dependency
+// levels, factorisation tasks and the sliced layouts of L and U.  Touches no
+// device state, so it can run on a second host thread.
+struct BiluPlan {
+    std::vector<int> lt_ptr, lt_kk, lt_k, lt_pp, pr_jj, pr_kj, dsrc;
+};
+
+void bilu_plan(const msp_ctx *c, BiluData &D, BiluPlan &P)
 {
-    BiluData &D = c->bilu;
-    const int n = c->n, b = c->b;
-    const long long E = (long long)b * b;
+    const int n = c->n;
     D.rp = c->rp;
     D.ci = c->ci;
     D.ord.resize(n);
@@ -356,10 +381,10 @@ void build_bilu(msp_ctx *c, const double *vals)
         Adjacency G = build_adjacency(n, c->rp.data(), c->ci.data());
         std::vector<int> color;
         int g = vertices_grouping(G, color);
-        int t = 0;
-        for (int col = 1; col <= g; ++col)
-            for (int i = 0; i < n; ++i)
-                if (color[i] == col) D.ord[t++] = i;
+        std::vector<int> start(g + 2, 0);
+        for (int i = 0; i < n; ++i) ++start[color[i] + 1];
+        for (int l = 1; l <= g; ++l) start[l + 1] += start[l];
+        for (int i = 0; i < n; ++i) D.ord[start[color[i]]++] = i;
     } else {
         std::iota(D.ord.begin(), D.ord.end(), 0);
     }
@@ -369,7 +394,7 @@ void build_bilu(msp_ctx *c, const double *vals)
     triangular_levels(n, c->rp.data(), c->ci.data(), D.ord, false, D.bwd_rows, D.bwd_ptr);
     // factorisation tasks per block row: lower entries in elimination order and
     // their update pairs (F_ij -= F_ik F_kj for stored j after k, (k,j) stored)
-    std::vector<int> lt_ptr(n + 1, 0), lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
+    P.lt_ptr.assign(n + 1, 0);
     std::vector<int> low;
     for (int i = 0; i < n; ++i) {
         low.clear();
@@ -379,49 +404,26 @@ void build_bilu(msp_ctx *c, const double *vals)
                   [&](int a, int bq) { return pos[c->ci[a]] < pos[c->ci[bq]]; });
         for (int kk : low) {
             int k = c->ci[kk];
-            lt_kk.push_back(kk);
-            lt_k.push_back(k);
-            lt_pp.push_back((int)pr_jj.size());
+            P.lt_kk.push_back(kk);
+            P.lt_k.push_back(k);
+            P.lt_pp.push_back((int)P.pr_jj.size());
             for (int jj = c->rp[i]; jj < c->rp[i + 1]; ++jj) {
                 int j = c->ci[jj];
                 if (pos[j] <= pos[k]) continue;
                 auto b0 = c->ci.begin() + c->rp[k], b1 = c->ci.begin() + c->rp[k + 1];
                 auto it = std::lower_bound(b0, b1, j);
                 if (it != b1 && *it == j) {
-                    pr_jj.push_back(jj);
-                    pr_kj.push_back((int)(it - c->ci.begin()));
+                    P.pr_jj.push_back(jj);
+                    P.pr_kj.push_back((int)(it - c->ci.begin()));
                 }
             }
         }
-        lt_ptr[i + 1] = (int)lt_kk.size();
+        P.lt_ptr[i + 1] = (int)P.lt_kk.size();
     }
-    lt_pp.push_back((int)pr_jj.size());
-    std::vector<void *> tmp;
-    BiluTasks T;
-    T.lt_ptr = c->upload(lt_ptr, tmp);
-    T.lt_kk = c->upload(lt_kk, tmp);
-    T.lt_k = c->upload(lt_k, tmp);
-    T.lt_pp = c->upload(lt_pp, tmp);
-    T.pr_jj = c->upload(pr_jj, tmp);
-    T.pr_kj = c->upload(pr_kj, tmp);
-    T.diag_pos = c->diag_d;
-    int *rows_d = c->upload(D.fwd_rows, tmp);
-    D.F = (double *)c->dalloc(sizeof(double) * (size_t)(c->nnzb * E), c->allocB);
-    D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
-    HIPCHK(hipMemcpyAsync(D.F, vals, sizeof(double) * (size_t)(c->nnzb * E),
-                          hipMemcpyDeviceToDevice, c->stream));
-    c->clear_flag();
-    for (size_t lv = 0; lv + 1 < D.fwd_ptr.size(); ++lv) {
-        T.rows = rows_d + D.fwd_ptr[lv];
-        T.nrows = D.fwd_ptr[lv + 1] - D.fwd_ptr[lv];
-        HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag, c->stream));
-    }
-    int bad = c->read_flag();
-    c->release(tmp);
-    if (bad) fail(MSP_ERR_SINGULAR);
+    P.lt_pp.push_back((int)P.pr_jj.size());
     // sliced layouts of the lower (forward levels) and upper (backward levels) parts
     auto make = [&](const std::vector<int> &rows, const std::vector<int> &lptr, bool lower,
-                    DevSell &S) {
+                    SellLayout &lay) {
         std::vector<int> ent_ptr(n + 1, 0), ent_col, ent_src;
         std::vector<int> tmpk;
         for (int t = 0; t < n; ++t) {
@@ -439,19 +441,51 @@ void build_bilu(msp_ctx *c, const double *vals)
             }
             ent_ptr[t + 1] = (int)ent_col.size();
         }
-        build_sell(n, lptr, ent_ptr, ent_col, ent_src, S.lay);
-        upload_sell(c, S, c->allocB);
+        build_sell(n, lptr, ent_ptr, ent_col, ent_src, lay);
     };
-    make(D.fwd_rows, D.fwd_ptr, true, D.L);
-    make(D.bwd_rows, D.bwd_ptr, false, D.U);
-    D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
-    D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
-    std::vector<int> dsrc(D.U.lay.slice_row0.size() * 64, -1);
+    make(D.fwd_rows, D.fwd_ptr, true, D.L.lay);
+    make(D.bwd_rows, D.bwd_ptr, false, D.U.lay);
+    P.dsrc.assign(D.U.lay.slice_row0.size() * 64, -1);
     for (size_t s = 0; s < D.U.lay.slice_row0.size(); ++s)
         for (int l = 0; l < D.U.lay.slice_rows[s]; ++l)
-            dsrc[s * 64 + l] = D.bwd_rows[D.U.lay.slice_row0[s] + l];
-    D.dsrc = c->upload(dsrc, c->allocB);
-    const long long dsl = (long long)dsrc.size();
+            P.dsrc[s * 64 + l] = D.bwd_rows[D.U.lay.slice_row0[s] + l];
+}
+
+// Device part: factorise level by level and lay the factors out.
+void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P)
+{
+    BiluData &D = c->bilu;
+    const int n = c->n, b = c->b;
+    const long long E = (long long)b * b;
+    std::vector<void *> tmp;
+    BiluTasks T;
+    T.lt_ptr = c->upload(P.lt_ptr, tmp);
+    T.lt_kk = c->upload(P.lt_kk, tmp);
+    T.lt_k = c->upload(P.lt_k, tmp);
+    T.lt_pp = c->upload(P.lt_pp, tmp);
+    T.pr_jj = c->upload(P.pr_jj, tmp);
+    T.pr_kj = c->upload(P.pr_kj, tmp);
+    T.diag_pos = c->diag_d;
+    int *rows_d = c->upload(D.fwd_rows, tmp);
+    D.F = (double *)c->dalloc(sizeof(double) * (size_t)(c->nnzb * E), c->allocB);
+    D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
+    HIPCHK(hipMemcpyAsync(D.F, vals, sizeof(double) * (size_t)(c->nnzb * E),
+                          hipMemcpyDeviceToDevice, c->stream));
+    c->clear_flag();
+    for (size_t lv = 0; lv + 1 < D.fwd_ptr.size(); ++lv) {
+        T.rows = rows_d + D.fwd_ptr[lv];
+        T.nrows = D.fwd_ptr[lv + 1] - D.fwd_ptr[lv];
+        HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag, c->stream));
+    }
+    int bad = c->read_flag();
+    c->release(tmp);
+    if (bad) fail(MSP_ERR_SINGULAR);
+    upload_sell(c, D.L, c->allocB);
+    upload_sell(c, D.U, c->allocB);
+    D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
+    D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
+    D.dsrc = c->upload(P.dsrc, c->allocB);
+    const long long dsl = (long long)P.dsrc.size();
     if (c->fp32()) {
         D.L32 = (float *)c->dalloc(sizeof(float) * D.L.lay.slot_lanes * E, c->allocB);
         D.U32 = (float *)c->dalloc(sizeof(float) * D.U.lay.slot_lanes * E, c->allocB);
@@ -497,9 +531,27 @@ void rebuild_B(msp_ctx *c, const double *vals)
     c->release(tmp);
     if (bad) fail(MSP_ERR_SINGULAR);
     phase(2);
-    // UA-AMG hierarchy on the host (greedy grouping and matching)
+    // UA-AMG hierarchy on the host (greedy grouping and matching), with the
+    // host part of the block ILU(0) setup on a second thread
     Hierarchy H;
-    int st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H);
+    BiluPlan plan;
+    std::exception_ptr plan_err;
+    std::thread planner([&]() {
+        try {
+            bilu_plan(c, c->bilu, plan);
+        } catch (...) {
+            plan_err = std::current_exception();
+        }
+    });
+    int st = 0;
+    try {
+        st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H);
+    } catch (...) {
+        planner.join();
+        throw;
+    }
+    planner.join();
+    if (plan_err) std::rethrow_exception(plan_err);
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
     phase(3);
@@ -521,12 +573,14 @@ void rebuild_B(msp_ctx *c, const double *vals)
     phase(4);
     build_coarse(c);
     phase(5);
-    build_bilu(c, vals);
+    bilu_device(c, vals, plan);
     c->sync();
     phase(6);
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
     c->e_nat = c->dalloc(tsz * n, c->allocB);
     c->ybuf = c->dalloc(tsz * (size_t)n * b, c->allocB);
+    c->vin = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
+    c->zout = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
     c->sync();
     c->Bn = n;
     c->Bb = b;
@@ -578,7 +632,7 @@ void vcycle(msp_ctx *c, int l)
 {
     Level &L = c->lev[l];
     if (l == (int)c->lev.size() - 1) {
-        HIPCHK(launch_coarse_gemv<T>(L.n, c->cinv, (const T *)L.f, (T *)L.x, c->stream));
+        HIPCHK(launch_coarse_gemv<T>(L.n, c->ldL, c->cinv, (const T *)L.f, (T *)L.x, c->stream));
         return;
     }
     Level &C = c->lev[l + 1];
@@ -621,12 +675,53 @@ void apply_T(msp_ctx *c, const double *v, double *z)
                             c->stream));
 }
 
-void apply(msp_ctx *c, const double *v, double *z)
+void apply_eager(msp_ctx *c, const double *v, double *z)
 {
     if (c->fp32())
         apply_T<float>(c, v, z);
     else
         apply_T<double>(c, v, z);
+}
+
+// Capture the whole preconditioner apply (vin -> zout) into a HIP graph on a
+// private capture stream; nothing runs during capture.  The graph holds only
+// kernel nodes.
+void capture_apply(msp_ctx *c)
+{
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    try {
+        apply_eager(c, c->vin, c->zout);
+    } catch (...) {
+        c->stream = user;
+        (void)hipStreamEndCapture(c->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    c->stream = user;
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&c->apply_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->apply_exec = nullptr;
+        HIPCHK(e);
+    }
+}
+
+void apply(msp_ctx *c, const double *v, double *z)
+{
+    if (!c->opt.use_graphs) {
+        apply_eager(c, v, z);
+        return;
+    }
+    if (!c->apply_exec) capture_apply(c);
+    const size_t bytes = sizeof(double) * (size_t)c->n * c->b;
+    HIPCHK(hipMemcpyAsync(c->vin, v, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipGraphLaunch(c->apply_exec, c->stream));
+    HIPCHK(hipMemcpyAsync(z, c->zout, bytes, hipMemcpyDeviceToDevice, c->stream));
 }
 
 void spmv(msp_ctx *c, const double *x, const double *sub, double *y)
@@ -773,7 +868,7 @@ bool valid_options(const msp_options &o)
 {
     return o.mu >= 0 && o.restart >= 1 && o.restart <= 200 && o.max_iter >= 1 &&
            o.max_coarse >= 1 && (o.precond_fp32 == 0 || o.precond_fp32 == 1) &&
-           (o.bilu_order == 0 || o.bilu_order == 1) &&
+           (o.bilu_order == 0 || o.bilu_order == 1) && (o.use_graphs == 0 || o.use_graphs == 1) &&
            ((o.dev_alloc == nullptr) == (o.dev_free == nullptr));
 }
 
@@ -846,6 +941,7 @@ int msp_default_options(msp_options *opt)
     opt->max_coarse = 10000;
     opt->precond_fp32 = 0;
     opt->bilu_order = 1;
+    opt->use_graphs = 1;
     return MSP_OK;
 }
 
@@ -888,6 +984,8 @@ int msp_destroy(msp_ctx *c)
 {
     if (!c) return MSP_OK;
     int st = guarded([&]() {
+        drop_graph(c);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         c->release(c->allocA);
         c->release(c->allocB);
         c->release(c->allocW);
@@ -1258,10 +1356,10 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
             case MSP_STAGE_COARSE: {
                 Level &L = c->lev.back();
                 if (f32)
-                    HIPCHK(launch_coarse_gemv<float>(L.n, c->cinv, (const float *)L.f,
+                    HIPCHK(launch_coarse_gemv<float>(L.n, c->ldL, c->cinv, (const float *)L.f,
                                                      (float *)L.x, c->stream));
                 else
-                    HIPCHK(launch_coarse_gemv<double>(L.n, c->cinv, (const double *)L.f,
+                    HIPCHK(launch_coarse_gemv<double>(L.n, c->ldL, c->cinv, (const double *)L.f,
                                                       (double *)L.x, c->stream));
                 break;
             }

@@ -77,8 +77,9 @@ hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *
                            hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st);
+// x = Ainv f with the row-major n x n inverse of leading dimension ld (even)
 template <typename T>
-hipError_t launch_coarse_gemv(int n, const double *inv, const T *f, T *x, hipStream_t st);
+hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st);
 template <typename T>
 hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hipStream_t st);
 // r_c[k] = v_c[k] - sum_d A_cd[k][p] e_d; pcol64: FP64 A (E = b*b, entry k*b+p);
@@ -119,15 +120,15 @@ hipError_t launch_update_x(long long N, int k, const double *Z, long long ldz, c
 hipError_t launch_fill(long long N, double v, double *x, hipStream_t st);
 
 // ---- dense coarsest level ---------------------------------------------------
-hipError_t launch_dense_scatter(int n, const int *rp, const int *ci, const double *val, double *M,
-                                hipStream_t st);
+hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, const double *val,
+                                double *M, hipStream_t st);
 // C = alpha A B + beta C, row-major FP64 (matrix-core tiles).
 hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
                         double *C, int ldc, double alpha, double beta, hipStream_t st);
-// In-place inverse of the n x n row-major matrix M by block Gauss-Jordan over
-// 128-wide panels with partial pivoting inside each diagonal block.
-// work must hold dense_inverse_work(n) doubles.
+// In-place inverse of the n x n row-major matrix M (leading dimension ld) by
+// block Gauss-Jordan over 128-wide panels with partial pivoting inside each
+// diagonal block.  work must hold dense_inverse_work(n) doubles.
 size_t dense_inverse_work(int n);
-hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t st);
+hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st);
 
 }  // namespace msp

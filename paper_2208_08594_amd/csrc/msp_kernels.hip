@@ -465,18 +465,26 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int n, const int *__restri
     x[t] += xc[agg_pos[t]];
 }
 
-// x = Ainv f on the coarsest level, FP64 arithmetic, one wave per row.
+// x = Ainv f on the coarsest level, FP64 arithmetic, one wave per row; rows
+// are 16-byte aligned (ld even) so each lane streams pairs of doubles.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, const double *__restrict__ inv,
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, int ld,
+                                                          const double *__restrict__ inv,
                                                           const T *__restrict__ f,
                                                           T *__restrict__ x)
 {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
     const int lane = threadIdx.x & 63;
-    const double *a = inv + (long long)row * n;
+    const double2 *a = reinterpret_cast<const double2 *>(inv + (long long)row * ld);
+    const int n2 = n >> 1;
     double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += a[j] * (double)f[j];
+#pragma unroll 4
+    for (int j2 = lane; j2 < n2; j2 += 64) {
+        const double2 v = a[j2];
+        acc += v.x * (double)f[2 * j2] + v.y * (double)f[2 * j2 + 1];
+    }
+    if ((n & 1) && lane == 0) acc += inv[(long long)row * ld + n - 1] * (double)f[n - 1];
     acc = wave_sum(acc);
     if (lane == 0) x[row] = (T)acc;
 }
@@ -750,14 +758,15 @@ __global__ __launch_bounds__(kThreads) void k_fill(long long N, double v, double
 // ---------------------------------------------------------------------------
 // dense coarsest level: scatter + block Gauss-Jordan inverse
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, const int *__restrict__ rp,
+__global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, int ld,
+                                                            const int *__restrict__ rp,
                                                             const int *__restrict__ ci,
                                                             const double *__restrict__ val,
                                                             double *__restrict__ M)
 {
     int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) M[(long long)i * n + ci[k]] = val[k];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) M[(long long)i * ld + ci[k]] = val[k];
 }
 
 constexpr int kNB = 128;  // Gauss-Jordan panel width
@@ -770,16 +779,14 @@ constexpr int kNB = 128;  // Gauss-Jordan panel width
 // ties) and no rows move, so at the end row k of A^-1 is row p_k of X.
 // Per step the pivot column and the scaled pivot row go through LDS (double
 // buffered), three barriers per step.  Dblk has leading dimension kNB.
-__global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
+__global__ __launch_bounds__(1024) void k_gj_diag(int ld, int K, int kb,
                                                   const double *__restrict__ M,
                                                   double *__restrict__ Dblk, int *bad)
 {
     __shared__ double colk[2][kNB];
     __shared__ double prowA[2][kNB], prowX[2][kNB];
-    __shared__ unsigned char used[kNB];
     __shared__ int invp[kNB];
-    __shared__ int piv_s[2];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int tr = tid >> 5, tc = tid & 31;
     double A[4][4], X[4][4];
 #pragma unroll
@@ -787,52 +794,47 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int r = tr + 32 * a, c = tc + 32 * b;
-            A[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * n + K + c] : (r == c ? 1.0 : 0.0);
+            A[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * ld + K + c] : (r == c ? 1.0 : 0.0);
             X[a][b] = (r == c) ? 1.0 : 0.0;
         }
-    if (tid < kNB) used[tid] = 0;
+    // pivot rows already used, as a bit mask per lane pair (rows lane and lane+64)
+    bool used0 = false, used1 = false;
+    if (tc == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) colk[0][tr + 32 * a] = A[a][0];
+    }
     __syncthreads();
     for (int k = 0; k < kb; ++k) {
         const int buf = k & 1;
-        if (tc == (k & 31)) {
+        // every wave finds the pivot: largest unused |a_rk|, lowest row on ties
+        double v0 = (lane < kb && !used0) ? fabs(colk[buf][lane]) : -1.0;
+        double v1 = (lane + 64 < kb && !used1) ? fabs(colk[buf][lane + 64]) : -1.0;
+        double best = v0;
+        int idx = lane;
+        if (v1 > best) { best = v1; idx = lane + 64; }
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b == (k >> 5))
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) colk[buf][tr + 32 * a] = A[a][b];
+        for (int o = 32; o > 0; o >>= 1) {
+            double b2 = __shfl_xor(best, o, 64);
+            int i2 = __shfl_xor(idx, o, 64);
+            if (b2 > best || (b2 == best && i2 < idx)) { best = b2; idx = i2; }
         }
-        __syncthreads();
-        if (tid < 64) {
-            double best = -1.0;
-            int idx = kNB;
-            for (int r = tid; r < kb; r += 64) {
-                double v = used[r] ? -1.0 : fabs(colk[buf][r]);
-                if (v > best) { best = v; idx = r; }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                double b2 = __shfl_xor(best, o, 64);
-                int i2 = __shfl_xor(idx, o, 64);
-                if (b2 > best || (b2 == best && i2 < idx)) { best = b2; idx = i2; }
-            }
-            if (tid == 0) {
-                piv_s[buf] = idx;
-                used[idx] = 1;
-                invp[idx] = k;
-                if (!(best > 0.0)) atomicOr(bad, 1);
-            }
+        const int p = idx;
+        if (lane == (p & 63)) {
+            if (p < 64) used0 = true; else used1 = true;
         }
-        __syncthreads();
-        const int p = piv_s[buf];
+        if (tid == 0) {
+            invp[p] = k;
+            if (!(best > 0.0)) atomicOr(bad, 1);
+        }
         if (tr == (p & 31)) {
-            const double d = colk[buf][p];
+            const double rd = 1.0 / colk[buf][p];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
                 if (a == (p >> 5))
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        prowA[buf][tc + 32 * b] = A[a][b] / d;
-                        prowX[buf][tc + 32 * b] = X[a][b] / d;
+                        prowA[buf][tc + 32 * b] = A[a][b] * rd;
+                        prowX[buf][tc + 32 * b] = X[a][b] * rd;
                     }
         }
         __syncthreads();
@@ -852,8 +854,16 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
                 }
             }
         }
+        // publish the next pivot column into the other buffer
+        if (k + 1 < kb && tc == ((k + 1) & 31)) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b == ((k + 1) >> 5))
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) colk[buf ^ 1][tr + 32 * a] = A[a][b];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -861,7 +871,6 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
             const int r = tr + 32 * a, c = tc + 32 * b;
             if (r < kb && c < kb) Dblk[invp[r] * kNB + c] = X[a][b];
         }
-    // zero the padding so the following products see an exact kb x kb block
     for (int q = tid; q < kNB * kNB; q += 1024) {
         int r = q / kNB, c = q % kNB;
         if (r >= kb || c >= kb) Dblk[q] = 0.0;
@@ -870,7 +879,7 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int n, int K, int kb,
 
 // Ccol[i][t] = M[i][K+t] for rows outside the block (0 inside), ld kNB;
 // Mrow[t][j] = M[K+t][j], ld n.
-__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int K, int kb,
+__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int ld, int K, int kb,
                                                          const double *__restrict__ M,
                                                          double *__restrict__ Ccol,
                                                          double *__restrict__ Mrow)
@@ -880,16 +889,16 @@ __global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int K, int kb,
     if (q < nc) {
         int i = (int)(q / kNB), t = (int)(q % kNB);
         bool inblk = i >= K && i < K + kb;
-        Ccol[q] = (t < kb && !inblk) ? M[(long long)i * n + K + t] : 0.0;
+        Ccol[q] = (t < kb && !inblk) ? M[(long long)i * ld + K + t] : 0.0;
     } else if (q < nc + (long long)kb * n) {
         long long r = q - nc;
         int t = (int)(r / n), j = (int)(r % n);
-        Mrow[r] = M[(long long)(K + t) * n + j];
+        Mrow[r] = M[(long long)(K + t) * ld + j];
     }
 }
 
 // Trow[t][K+u] = Dblk[t][u]; M[i][K+u] = 0 for rows outside the block.
-__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int K, int kb,
+__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int K, int kb,
                                                      const double *__restrict__ Dblk,
                                                      double *__restrict__ Trow,
                                                      double *__restrict__ M)
@@ -902,17 +911,19 @@ __global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int K, int kb,
     } else if (q < nt + (long long)n * kb) {
         long long r = q - nt;
         int i = (int)(r / kb), u = (int)(r % kb);
-        if (i < K || i >= K + kb) M[(long long)i * n + K + u] = 0.0;
+        if (i < K || i >= K + kb) M[(long long)i * ld + K + u] = 0.0;
     }
 }
 
 // M[K+t][j] = Trow[t][j]
-__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int K, int kb,
+__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int ld, int K, int kb,
                                                         const double *__restrict__ Trow,
                                                         double *__restrict__ M)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (q < (long long)kb * n) M[(long long)K * n + q] = Trow[q];
+    if (q >= (long long)kb * n) return;
+    const int t = (int)(q / n), j = (int)(q % n);
+    M[(long long)(K + t) * ld + j] = Trow[q];
 }
 
 // C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  Each
@@ -924,45 +935,49 @@ __global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int K, int kb,
 // lane j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (the output rows of
 // one lane are interleaved by 4, unlike the FP32 variant).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kGT = 128, kGK = 32;
+constexpr int kGT = 128, kGK = 16, kGThreads = 512;
 
-__global__ __launch_bounds__(kThreads) void k_dgemm(int Mr, int Nc, int Kd,
-                                                    const double *__restrict__ A, int lda,
-                                                    const double *__restrict__ B, int ldb,
-                                                    double *__restrict__ C, int ldc, double alpha,
-                                                    double beta)
+// two work-groups per CU (68 KB of LDS each, <= 128 registers per lane) so one
+// work-group's C read-modify-write overlaps the other's matrix-core work
+__global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dgemm(int Mr, int Nc, int Kd,
+                                                     const double *__restrict__ A, int lda,
+                                                     const double *__restrict__ B, int ldb,
+                                                     double *__restrict__ C, int ldc,
+                                                     double alpha, double beta)
 {
     __shared__ double As[2][kGT][kGK + 1];
     __shared__ double Bs[2][kGK][kGT + 1];
     const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;  // 2 x 4 waves of 64 x 32
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 acc[4][4];
+    dbl4 acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // each thread moves 16 A values (rows tid/32*... ) and 16 B values per chunk
-    double ra[16], rb[16];
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // per-thread fetch slots: A rows r0 + 32u (column ac), B rows bk0 + 4u (column bj)
+    const int ac = tid & 15, r0 = tid >> 4, bk0 = tid >> 7;
+    const int bj = j0 + (tid & 127);
+    const bool bj_ok = bj < Nc;
+    const double *pa = A + (long long)(i0 + r0) * lda + ac;
+    const double *pb = B + (bj_ok ? bj : 0);
+    const int arows = Mr - i0 - r0;  // row r0 + 32u valid iff 32u < arows
+    double ra[4], rb[4];
     auto fetch = [&](int k0) {
+        const bool ak_ok = k0 + ac < Kd;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = tid + u * kThreads;  // 0..4095
-            const int r = q >> 5, c = q & 31;  // A chunk: 128 x 32
-            const int i = i0 + r, k = k0 + c;
-            ra[u] = (i < Mr && k < Kd) ? A[(long long)i * lda + k] : 0.0;
-            const int rb_ = q >> 7, cb = q & 127;  // B chunk: 32 x 128
-            const int kb = k0 + rb_, j = j0 + cb;
-            rb[u] = (kb < Kd && j < Nc) ? B[(long long)kb * ldb + j] : 0.0;
+        for (int u = 0; u < 4; ++u) {
+            ra[u] = (32 * u < arows && ak_ok) ? pa[(long long)(32 * u) * lda + k0] : 0.0;
+            const int kk = k0 + bk0 + 4 * u;
+            rb[u] = (bj_ok && kk < Kd) ? pb[(long long)kk * ldb] : 0.0;
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = tid + u * kThreads;
-            As[buf][q >> 5][q & 31] = ra[u];
-            Bs[buf][q >> 7][q & 127] = rb[u];
+        for (int u = 0; u < 4; ++u) {
+            As[buf][r0 + 32 * u][ac] = ra[u];
+            Bs[buf][bk0 + 4 * u][tid & 127] = rb[u];
         }
     };
     const int nchunk = (Kd + kGK - 1) / kGK;
@@ -974,15 +989,15 @@ __global__ __launch_bounds__(kThreads) void k_dgemm(int Mr, int Nc, int Kd,
         if (ch + 1 < nchunk) fetch((ch + 1) * kGK);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 4) {
-            double av[4], bv[4];
+            double av[4], bv[2];
 #pragma unroll
             for (int a = 0; a < 4; ++a) av[a] = As[buf][wr + a * 16 + li][kk + lk];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk + lk][wc + b * 16 + li];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + lk][wc + b * 16 + li];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < 2; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
@@ -991,17 +1006,18 @@ __global__ __launch_bounds__(kThreads) void k_dgemm(int Mr, int Nc, int Kd,
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + wr + a * 16 + lk + 4 * r;
+            if (i >= Mr) continue;
+            double *crow = C + (long long)i * ldc + j0 + wc + li;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wr + a * 16 + lk + 4 * r;
-                const int j = j0 + wc + b * 16 + li;
-                if (i < Mr && j < Nc) {
-                    double *c = C + (long long)i * ldc + j;
-                    const double v = alpha * acc[a][b][r];
-                    *c = (beta != 0.0) ? v + beta * *c : v;
-                }
+            for (int b = 0; b < 2; ++b) {
+                if (j0 + wc + b * 16 + li >= Nc) continue;
+                double *c = crow + b * 16;
+                const double v = alpha * acc[a][b][r];
+                *c = (beta != 0.0) ? v + beta * *c : v;
             }
+        }
 }
 
 }  // namespace
@@ -1137,9 +1153,9 @@ hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStrea
 }
 
 template <typename T>
-hipError_t launch_coarse_gemv(int n, const double *inv, const T *f, T *x, hipStream_t st)
+hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st)
 {
-    k_coarse_gemv<T><<<(unsigned)((n + 3) / 4), kThreads, 0, st>>>(n, inv, f, x);
+    k_coarse_gemv<T><<<(unsigned)((n + 3) / 4), kThreads, 0, st>>>(n, ld, inv, f, x);
     return hipGetLastError();
 }
 
@@ -1228,7 +1244,7 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
     template hipError_t launch_restrict<T>(int, const int *, const int *, const T *, T *,      \
                                            hipStream_t);                                       \
     template hipError_t launch_prolong<T>(int, const int *, const T *, T *, hipStream_t);      \
-    template hipError_t launch_coarse_gemv<T>(int, const double *, const T *, T *,             \
+    template hipError_t launch_coarse_gemv<T>(int, int, const double *, const T *, T *,        \
                                               hipStream_t);                                    \
     template hipError_t launch_unpermute<T>(int, const int *, const T *, T *, hipStream_t);    \
     template hipError_t launch_pcol_residual<T>(int, int, const SellView &, const double *,    \
@@ -1294,10 +1310,10 @@ hipError_t launch_fill(long long N, double v, double *x, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_dense_scatter(int n, const int *rp, const int *ci, const double *val, double *M,
-                                hipStream_t st)
+hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, const double *val,
+                                double *M, hipStream_t st)
 {
-    k_dense_scatter<<<blocks_for(n), kThreads, 0, st>>>(n, rp, ci, val, M);
+    k_dense_scatter<<<blocks_for(n), kThreads, 0, st>>>(n, ld, rp, ci, val, M);
     return hipGetLastError();
 }
 
@@ -1305,13 +1321,13 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
                         double *C, int ldc, double alpha, double beta, hipStream_t st)
 {
     dim3 grid((unsigned)((Nc + kGT - 1) / kGT), (unsigned)((Mr + kGT - 1) / kGT));
-    k_dgemm<<<grid, kThreads, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
+    k_dgemm<<<grid, kGThreads, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
     return hipGetLastError();
 }
 
 size_t dense_inverse_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
 
-hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t st)
+hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st)
 {
     double *Ccol = work;                       // n x kNB
     double *Mrow = work + (long long)kNB * n;  // kNB x n
@@ -1319,16 +1335,16 @@ hipError_t dense_inverse(int n, double *M, double *work, int *bad, hipStream_t s
     double *Dblk = Trow + (long long)kNB * n;  // kNB x kNB
     for (int K = 0; K < n; K += kNB) {
         const int kb = n - K < kNB ? n - K : kNB;
-        k_gj_diag<<<1, 1024, 0, st>>>(n, K, kb, M, Dblk, bad);
+        k_gj_diag<<<1, 1024, 0, st>>>(ld, K, kb, M, Dblk, bad);
         k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
-            n, K, kb, M, Ccol, Mrow);
+            n, ld, K, kb, M, Ccol, Mrow);
         hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);
         if (e != hipSuccess) return e;
         k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
-            n, K, kb, Dblk, Trow, M);
-        e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, n, -1.0, 1.0, st);
+            n, ld, K, kb, Dblk, Trow, M);
+        e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, ld, -1.0, 1.0, st);
         if (e != hipSuccess) return e;
-        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, K, kb, Trow, M);
+        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, ld, K, kb, Trow, M);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -30,7 +30,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class MspOptions(C.Structure):
     _fields_ = [("mu", C.c_int), ("restart", C.c_int), ("max_iter", C.c_int),
                 ("max_coarse", C.c_int), ("precond_fp32", C.c_int), ("bilu_order", C.c_int),
-                ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("use_graphs", C.c_int), ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_user", C.c_void_p)]
 
 
@@ -163,7 +163,7 @@ class Solver:
     """
 
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
-                 bilu_order=1, stream=None, device=None, torch_allocator=True):
+                 bilu_order=1, stream=None, device=None, torch_allocator=True, use_graphs=True):
         import torch
         self.torch = torch
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -177,6 +177,7 @@ class Solver:
         opt.mu, opt.restart, opt.max_iter, opt.max_coarse = mu, restart, max_iter, max_coarse
         opt.precond_fp32 = 1 if precond_fp32 else 0
         opt.bilu_order = int(bilu_order)
+        opt.use_graphs = 1 if use_graphs else 0
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         self._alloc = None
         if torch_allocator:
