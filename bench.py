@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 METRIC = "CPR-FGMRES time-to-1e-6 + SpMV/GS HBM GB/s; FP32-vs-FP64 precond; p50/p99"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+KERNEL_SRC = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gj_update_traffic.md")
 WORKLOADS = {
     "cfg0": (0, "10x10x10 cells, b=4, lognormal sigma=1, 2 wells (4,000 unknowns)"),
     "cfg1": (1, "64x64x32 cells, b=4, lognormal sigma=1.5, kz/kh=0.1, 4 wells (524,288 unknowns)"),
@@ -117,7 +120,13 @@ def main():
     ap.add_argument("--bilu-order", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (PMC byte calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver path is single-GPU (see DESIGN.md for how "
               "it would shard); run with --gpus 1", file=sys.stderr)
@@ -164,6 +173,7 @@ def main():
     t_vc = stage_ms(solver, stream, msp.STAGE_VCYCLE, 10)
     t_pre = stage_ms(solver, stream, msp.STAGE_PRECOND, 10, xin, yout)
     t_coarse = stage_ms(solver, stream, msp.STAGE_COARSE, 20)
+    t_upd = stage_ms(solver, stream, msp.STAGE_GJ_UPDATE, 10)
     b_spmv = spmv_bytes(sys_)
     lev0_nnz = int(solver.level(0)["row_ptr"][-1])
     b_gs = gs_sweep_bytes(lev0_nnz, sys_.n, 8)
@@ -188,10 +198,24 @@ def main():
                 "precond_apply_us": stage_ms(s32, stream, msp.STAGE_PRECOND, 10, xin, yout) * 1e3}
         s32.close()
 
-    roofline = {"kernel": "bsr_spmv (k_spmv<4>)", "bound": "hbm",
-                "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": b_spmv, "avg_launch_us": t_spmv * 1e3}
+    # dominant kernel of a step: the rank-128 update of the coarsest-level
+    # Gauss-Jordan inverse (FP64 matrix cores); algorithmic work 2 n_L^2 128 flops
+    upd_flops = 2.0 * nL * nL * 128
+    achieved = upd_flops / (t_upd * 1e-3) / 1e12
+    roofline = {"kernel": "k_dgemm (rank-128 update of the coarsest-level inverse, "
+                          f"n_L={nL})", "bound": "mfma",
+                "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": stored_traffic(),
+                "flops_per_launch": upd_flops, "avg_launch_us": t_upd * 1e3,
+                "algorithmic_bytes_per_launch": 2 * nL * ((nL + 15) // 16 * 16) * 8
+                + 2 * nL * 128 * 8}
+    roofline_spmv = {"kernel": f"k_spmv<{sys_.b}>", "bound": "hbm",
+                     "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS, "bytes_per_launch": b_spmv,
+                     "avg_launch_us": t_spmv * 1e3}
+    serving = None
+    if not args.no_serving:
+        serving = serving_sample()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -221,9 +245,65 @@ def main():
                      "precond_apply": t_pre * 1e3, "coarse_solve": t_coarse * 1e3},
         "fp32_precond": fp32,
         "roofline": roofline,
+        "roofline_spmv": roofline_spmv,
+        "coarse_gemv_gbs": gbs(b_coarse, t_coarse),
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, only if it was taken on the current kernel source."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].rsplit(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256[:16]") != source_hash():
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy():
+    import torch
+    a = torch.rand(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 8, "reps": 3}))
+
+
+def serving_sample():
+    """A short continuous-batching run (reported beside the main metric)."""
+    from paper_2208_08594_amd import serve
+    log("serving sample: 16 requests, sides 16..32, 4 slots, mu=10")
+    cal = serve.make_requests(2, rate=0.0, steps=4, sides=[16, 24, 32])
+    t = time.perf_counter()
+    serve.Server(slots=1, mu=10).run(cal)
+    per_req = (time.perf_counter() - t) / len(cal)
+    rate = 0.7 * 4 / per_req
+    reqs = serve.make_requests(16, rate=rate, steps=4, sides=[16, 24, 32])
+    res = serve.Server(slots=4, mu=10).run(reqs)
+    res.update({"arrival_rate_per_s": rate, "slots": 4, "mu": 10,
+                "sample": "16 requests x 4 Newton steps, cubes 16^3..32^3, b 3..7"})
+    res.pop("errors", None)
+    return res
 
 
 def cpu_baseline(sys_):

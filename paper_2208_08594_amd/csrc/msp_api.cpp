@@ -126,6 +126,7 @@ struct msp_ctx {
     void *e_nat = nullptr, *ybuf = nullptr;
     // captured preconditioner apply (valid for the current B and A layout)
     double *vin = nullptr, *zout = nullptr;
+    double *tC = nullptr, *tA = nullptr, *tB = nullptr;  // timing-stage scratch (with B)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t apply_exec = nullptr;
     // krylov workspace
@@ -246,6 +247,7 @@ void release_B(msp_ctx *c)
     c->omega = nullptr;
     c->cinv = nullptr;
     c->e_nat = c->ybuf = nullptr;
+    c->tC = c->tA = c->tB = nullptr;
 }
 
 template <typename T>
@@ -1330,13 +1332,33 @@ int msp_stage_get_bilu_f32(msp_ctx *c, float *F, float *Dinv)
 
 int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *out)
 {
-    if (!c || reps < 1 || stage < 0 || stage > 5) return MSP_ERR_ARG;
+    if (!c || reps < 1 || stage < 0 || stage > 6) return MSP_ERR_ARG;
     if ((stage == MSP_STAGE_SPMV || stage == MSP_STAGE_PRECOND) && (!in || !out))
         return MSP_ERR_ARG;
     if (!c->haveA || (stage != MSP_STAGE_SPMV && !c->hasB)) return MSP_ERR_STATE;
     if (stage == MSP_STAGE_GS0 && c->lev.size() < 2) return MSP_ERR_STATE;
     return guarded([&]() {
         const bool f32 = c->fp32();
+        if (stage == MSP_STAGE_GJ_UPDATE) {
+            // scratch operands of the coarsest size (made on first use, kept with
+            // B): C = copy of the inverse, A (n x 128) and B (128 x n) constant
+            const int m = c->nL, ld = c->ldL;
+            if (!c->tC) {
+                c->tC = (double *)c->dalloc(sizeof(double) * (size_t)m * ld, c->allocB);
+                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)m * 128, c->allocB);
+                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)128 * m, c->allocB);
+                HIPCHK(hipMemcpyAsync(c->tC, c->cinv, sizeof(double) * (size_t)m * ld,
+                                      hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(launch_fill((long long)m * 128, 1e-3, c->tA, c->stream));
+                HIPCHK(launch_fill((long long)m * 128, 1e-3, c->tB, c->stream));
+                c->sync();
+            }
+            for (int r = 0; r < reps; ++r)
+                HIPCHK(launch_dgemm(m, m, 128, c->tA, 128, c->tB, m, c->tC, ld, -1.0, 1.0,
+                                    c->stream));
+            c->sync();
+            return MSP_OK;
+        }
         for (int r = 0; r < reps; ++r) {
             switch (stage) {
             case MSP_STAGE_SPMV: spmv(c, in, nullptr, out); break;

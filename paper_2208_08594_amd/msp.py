@@ -80,7 +80,8 @@ SIGNATURES = {
     "msp_stage_get_bilu_f32": ([_vp, _vp, _vp], _i),
     "msp_stage_repeat": ([_vp, _i, _i, _vp, _vp], _i),
 }
-STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE = range(6)
+STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE, STAGE_GJ_UPDATE = \
+    range(7)
 
 _LIB = None
 _LOCK = threading.Lock()
