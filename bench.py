@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gj_update_traffic.md")
+GJ_PANEL = 256  # Gauss-Jordan panel width of the coarsest-level inverse
 WORKLOADS = {
     "cfg0": (0, "10x10x10 cells, b=4, lognormal sigma=1, 2 wells (4,000 unknowns)"),
     "cfg1": (1, "64x64x32 cells, b=4, lognormal sigma=1.5, kz/kh=0.1, 4 wells (524,288 unknowns)"),
@@ -198,17 +199,17 @@ def main():
                 "precond_apply_us": stage_ms(s32, stream, msp.STAGE_PRECOND, 10, xin, yout) * 1e3}
         s32.close()
 
-    # dominant kernel of a step: the rank-128 update of the coarsest-level
-    # Gauss-Jordan inverse (FP64 matrix cores); algorithmic work 2 n_L^2 128 flops
-    upd_flops = 2.0 * nL * nL * 128
+    # dominant kernel of a step: the rank-256 update of the coarsest-level
+    # Gauss-Jordan inverse (FP64 matrix cores); algorithmic work 2 n_L^2 256 flops
+    upd_flops = 2.0 * nL * nL * GJ_PANEL
     achieved = upd_flops / (t_upd * 1e-3) / 1e12
-    roofline = {"kernel": "k_dgemm (rank-128 update of the coarsest-level inverse, "
+    roofline = {"kernel": f"k_dgemm (rank-{GJ_PANEL} update of the coarsest-level inverse, "
                           f"n_L={nL})", "bound": "mfma",
                 "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": stored_traffic(),
                 "flops_per_launch": upd_flops, "avg_launch_us": t_upd * 1e3,
                 "algorithmic_bytes_per_launch": 2 * nL * ((nL + 15) // 16 * 16) * 8
-                + 2 * nL * 128 * 8}
+                + 2 * nL * GJ_PANEL * 8}
     roofline_spmv = {"kernel": f"k_spmv<{sys_.b}>", "bound": "hbm",
                      "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS, "bytes_per_launch": b_spmv,
@@ -231,8 +232,9 @@ def main():
                    "bilu_order": "natural" if args.bilu_order == 0 else "multicolor"},
         "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
         "setup_ms": setup_ms, "solve_ms": solve_ms, "iterations": last["iterations"],
-        "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "hierarchy_host",
-                                    "level_upload", "coarse_inverse", "bilu"],
+        "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "aggregation_host",
+                                    "groups_and_levels", "coarse_inverse_wait",
+                                    "bilu"],
                                    [round(v, 3) for v in last["phase_ms"][:7]])),
         "rel_true_residual": last["rel_true_residual"],
         "levels": last["level_rows"], "colors": last["n_colors"],

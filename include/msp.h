@@ -99,8 +99,12 @@ typedef struct {
     double solve_ms;          /* host wall time of the last solve */
     /* host wall time of the phases of the last setup (ms):
      * [0] pattern copy and check, [1] value ingest, [2] decoupling,
-     * [3] AMG hierarchy on the host, [4] level layouts and upload,
-     * [5] coarsest-level inverse, [6] block ILU(0) factorisation and layouts,
+     * [3] aggregation chain on the host (pairwise passes and Galerkin
+     *     products) up to queueing the coarsest-level inverse,
+     * [4] grouping of the smoothed levels and level layouts and uploads
+     *     (while the coarsest inverse runs on the device),
+     * [6] block ILU(0) factorisation and layouts (likewise overlapped),
+     * [5] what remains of the coarsest-level inverse after [4] and [6],
      * [7] unused */
     double phase_ms[8];
 } msp_info;

@@ -78,7 +78,7 @@ int msp_stage_get_bilu_f32(msp_ctx *ctx, float *F, float *Dinv);
                                work vector; in/out unused */
 #define MSP_STAGE_VCYCLE 4  /* level-0 V-cycle on the library's work vectors; in/out unused */
 #define MSP_STAGE_COARSE 5  /* coarsest-level solve on the library's work vectors */
-#define MSP_STAGE_GJ_UPDATE 6 /* one rank-128 update C -= A B of the coarsest-level
+#define MSP_STAGE_GJ_UPDATE 6 /* one rank-256 update C -= A B of the coarsest-level
                                  Gauss-Jordan inverse (n_L x n_L, FP64 matrix cores) on
                                  scratch copies; in/out unused */
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <future>
 #include <new>
 #include <thread>
 #include <numeric>
@@ -128,6 +129,13 @@ struct msp_ctx {
     double *vin = nullptr, *zout = nullptr;
     double *tC = nullptr, *tA = nullptr, *tB = nullptr;  // timing-stage scratch (with B)
     hipStream_t cap_stream = nullptr;
+    // second stream of the setup: level uploads and the block ILU(0)
+    // factorisation run on it while the coarsest inverse runs on `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    hipStream_t copy_stream = nullptr;  // stream of upload(); null = `stream`
+    // look-ahead stream and events of the coarsest-level inverse
+    GjLookAhead gj{};
     hipGraphExec_t apply_exec = nullptr;
     // krylov workspace
     long long wsN = 0;
@@ -159,7 +167,11 @@ struct msp_ctx {
     }
     void release(std::vector<void *> &list)
     {
-        if (!list.empty()) (void)hipStreamSynchronize(stream);
+        if (!list.empty()) {
+            (void)hipStreamSynchronize(stream);
+            if (side) (void)hipStreamSynchronize(side);
+            if (gj.aux) (void)hipStreamSynchronize(gj.aux);
+        }
         for (void *p_ : list) {
             if (opt.dev_free)
                 opt.dev_free(p_, opt.alloc_user);
@@ -174,17 +186,22 @@ struct msp_ctx {
         T *d = (T *)dalloc(sizeof(T) * std::max<size_t>(h.size(), 1), list);
         if (!h.empty())
             HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice,
-                                  stream));
+                                  copy_stream ? copy_stream : stream));
         return d;
     }
     void sync() { HIPCHK(hipStreamSynchronize(stream)); }
-    int read_flag()
+    // flag[0] is written by work on `stream`, flag[1] by work on `side`
+    int read_flag(int i = 0)
     {
-        HIPCHK(hipMemcpyAsync(flag_host, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
-        sync();
-        return *flag_host;
+        hipStream_t s_ = i == 0 ? stream : side;
+        HIPCHK(hipMemcpyAsync(flag_host + i, flag + i, sizeof(int), hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+        return flag_host[i];
     }
-    void clear_flag() { HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), stream)); }
+    void clear_flag(int i = 0)
+    {
+        HIPCHK(hipMemsetAsync(flag + i, 0, sizeof(int), i == 0 ? stream : side));
+    }
     bool fp32() const { return opt.precond_fp32 != 0; }
 };
 
@@ -345,25 +362,30 @@ void link_levels(msp_ctx *c)
     }
 }
 
-void build_coarse(msp_ctx *c)
+// Queues the coarsest-level inverse on `stream` and returns without waiting;
+// flag[0] is set on a singular pivot block.  The upload and work buffers go
+// to `tmp`, which the caller releases after the stream has drained.
+void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
 {
-    Level &L = c->lev.back();
-    const int m = L.n;
+    const int m = A.n;
     c->nL = m;
     c->ldL = (m + 15) & ~15;  // rows 128-byte aligned for the streaming GEMV
     c->cinv = (double *)c->dalloc(sizeof(double) * (size_t)m * c->ldL, c->allocB);
-    std::vector<void *> tmp;
-    int *rp = c->upload(L.A.rp, tmp);
-    int *ci = c->upload(L.A.ci, tmp);
-    double *val = c->upload(L.A.val, tmp);
+    int *rp = c->upload(A.rp, tmp);
+    int *ci = c->upload(A.ci, tmp);
+    double *val = c->upload(A.val, tmp);
     double *work = (double *)c->dalloc(sizeof(double) * dense_inverse_work(m), tmp);
     HIPCHK(launch_fill((long long)m * c->ldL, 0.0, c->cinv, c->stream));
     HIPCHK(launch_dense_scatter(m, c->ldL, rp, ci, val, c->cinv, c->stream));
-    c->clear_flag();
-    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream));
-    int bad = c->read_flag();
-    c->release(tmp);
-    if (bad) fail(MSP_ERR_SINGULAR);
+    if (!c->gj.aux) {
+        HIPCHK(hipStreamCreateWithFlags(&c->gj.aux, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(hipEventCreateWithFlags(&c->gj.ev_block[i], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->gj.ev_inv[i], hipEventDisableTiming));
+        }
+    }
+    c->clear_flag(0);
+    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream, &c->gj));
 }
 
 // Host-only part of the block ILU(0) setup: elimination order, dependency
@@ -373,16 +395,15 @@ struct BiluPlan {
     std::vector<int> lt_ptr, lt_kk, lt_k, lt_pp, pr_jj, pr_kj, dsrc;
 };
 
-void bilu_plan(const msp_ctx *c, BiluData &D, BiluPlan &P)
+// color/g: the Alg. 4.2 groups of the block pattern (used for the
+// multi-color elimination order).
+void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData &D, BiluPlan &P)
 {
     const int n = c->n;
     D.rp = c->rp;
     D.ci = c->ci;
     D.ord.resize(n);
     if (c->opt.bilu_order == 1) {
-        Adjacency G = build_adjacency(n, c->rp.data(), c->ci.data());
-        std::vector<int> color;
-        int g = vertices_grouping(G, color);
         std::vector<int> start(g + 2, 0);
         for (int i = 0; i < n; ++i) ++start[color[i] + 1];
         for (int l = 1; l <= g; ++l) start[l + 1] += start[l];
@@ -453,13 +474,15 @@ void bilu_plan(const msp_ctx *c, BiluData &D, BiluPlan &P)
             P.dsrc[s * 64 + l] = D.bwd_rows[D.U.lay.slice_row0[s] + l];
 }
 
-// Device part: factorise level by level and lay the factors out.
-void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P)
+// Device part: factorise level by level and lay the factors out, on the side
+// stream (flag[1] is set on a singular pivot block).  The task arrays go to
+// `tmp`, released by the caller after the side stream has drained.
+void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P, std::vector<void *> &tmp)
 {
+    const hipStream_t st = c->side;
     BiluData &D = c->bilu;
     const int n = c->n, b = c->b;
     const long long E = (long long)b * b;
-    std::vector<void *> tmp;
     BiluTasks T;
     T.lt_ptr = c->upload(P.lt_ptr, tmp);
     T.lt_kk = c->upload(P.lt_kk, tmp);
@@ -472,16 +495,13 @@ void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P)
     D.F = (double *)c->dalloc(sizeof(double) * (size_t)(c->nnzb * E), c->allocB);
     D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
     HIPCHK(hipMemcpyAsync(D.F, vals, sizeof(double) * (size_t)(c->nnzb * E),
-                          hipMemcpyDeviceToDevice, c->stream));
-    c->clear_flag();
+                          hipMemcpyDeviceToDevice, st));
+    c->clear_flag(1);
     for (size_t lv = 0; lv + 1 < D.fwd_ptr.size(); ++lv) {
         T.rows = rows_d + D.fwd_ptr[lv];
         T.nrows = D.fwd_ptr[lv + 1] - D.fwd_ptr[lv];
-        HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag, c->stream));
+        HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag + 1, st));
     }
-    int bad = c->read_flag();
-    c->release(tmp);
-    if (bad) fail(MSP_ERR_SINGULAR);
     upload_sell(c, D.L, c->allocB);
     upload_sell(c, D.U, c->allocB);
     D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
@@ -492,18 +512,32 @@ void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P)
         D.L32 = (float *)c->dalloc(sizeof(float) * D.L.lay.slot_lanes * E, c->allocB);
         D.U32 = (float *)c->dalloc(sizeof(float) * D.U.lay.slot_lanes * E, c->allocB);
         D.D32 = (float *)c->dalloc(sizeof(float) * dsl * E, c->allocB);
-        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, nullptr, D.L32, c->stream));
-        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, nullptr, D.U32, c->stream));
-        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, nullptr, D.D32, c->stream));
+        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, nullptr, D.L32, st));
+        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, nullptr, D.U32, st));
+        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, nullptr, D.D32, st));
     } else {
         D.L64 = (double *)c->dalloc(sizeof(double) * D.L.lay.slot_lanes * E, c->allocB);
         D.U64 = (double *)c->dalloc(sizeof(double) * D.U.lay.slot_lanes * E, c->allocB);
         D.D64 = (double *)c->dalloc(sizeof(double) * dsl * E, c->allocB);
-        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, D.L64, nullptr, c->stream));
-        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, D.U64, nullptr, c->stream));
-        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, D.D64, nullptr, c->stream));
+        HIPCHK(launch_gather_blocks(b, D.L.lay.slot_lanes, D.L.src, D.F, D.L64, nullptr, st));
+        HIPCHK(launch_gather_blocks(b, D.U.lay.slot_lanes, D.U.src, D.F, D.U64, nullptr, st));
+        HIPCHK(launch_gather_blocks(b, dsl, D.dsrc, D.Dinv, D.D64, nullptr, st));
     }
 }
+
+// Scope guards for the setup: temporary device buffers are released (after
+// both setup streams drained) and uploads return to `stream` on every exit.
+struct ReleaseScope {
+    msp_ctx *c;
+    std::vector<void *> &list;
+    ReleaseScope(msp_ctx *c_, std::vector<void *> &l_) : c(c_), list(l_) {}
+    ~ReleaseScope() { c->release(list); }
+};
+struct CopyStreamScope {
+    msp_ctx *c;
+    CopyStreamScope(msp_ctx *c_, hipStream_t s_) : c(c_) { c->copy_stream = s_; }
+    ~CopyStreamScope() { c->copy_stream = nullptr; }
+};
 
 void rebuild_B(msp_ctx *c, const double *vals)
 {
@@ -518,6 +552,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     // decoupling and pressure extraction (device), pressure matrix to the host
     c->omega = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
     std::vector<void *> tmp;
+    ReleaseScope release_tmp(c, tmp);
     double *ap = (double *)c->dalloc(sizeof(double) * (size_t)c->nnzb, tmp);
     c->clear_flag();
     HIPCHK(launch_decouple(b, c->p, n, c->rp_d, c->diag_d, vals, c->omega, ap, c->flag,
@@ -529,55 +564,81 @@ void rebuild_B(msp_ctx *c, const double *vals)
     A0.val.resize(c->nnzb);
     HIPCHK(hipMemcpyAsync(A0.val.data(), ap, sizeof(double) * c->nnzb, hipMemcpyDeviceToHost,
                           c->stream));
-    int bad = c->read_flag();
-    c->release(tmp);
-    if (bad) fail(MSP_ERR_SINGULAR);
+    if (c->read_flag()) fail(MSP_ERR_SINGULAR);
     phase(2);
-    // UA-AMG hierarchy on the host (greedy grouping and matching), with the
-    // host part of the block ILU(0) setup on a second thread
-    Hierarchy H;
+    // Host setup after the decoupling.  The aggregation chain (pairwise passes
+    // and Galerkin products, level by level) is the critical path; the Alg.
+    // 4.2 groups of the block pattern (level 0, shared with the multi-color
+    // block ILU(0) order) and the host part of the block ILU(0) setup run on
+    // worker threads beside it.  Once the coarsest level is known its inverse
+    // is queued on `stream`; the groups of the other levels, the level layouts
+    // and uploads, and the block ILU(0) factorisation (on the side stream)
+    // then overlap that inverse.
+    if (!c->side) HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->ev_main) HIPCHK(hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming));
+    if (!c->ev_side) HIPCHK(hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(c->ev_main, c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_main, 0));
+    struct Groups {
+        std::vector<int> color;
+        int g = 0;
+    };
+    std::shared_future<Groups> groups0 = std::async(std::launch::async, [c]() {
+        Groups G;
+        Adjacency adj = build_adjacency(c->n, c->rp.data(), c->ci.data());
+        G.g = vertices_grouping(adj, G.color);
+        return G;
+    }).share();
     BiluPlan plan;
-    std::exception_ptr plan_err;
-    std::thread planner([&]() {
-        try {
-            bilu_plan(c, c->bilu, plan);
-        } catch (...) {
-            plan_err = std::current_exception();
-        }
+    std::future<void> planned = std::async(std::launch::async, [c, &plan, groups0]() {
+        const Groups &G = groups0.get();
+        bilu_plan(c, G.color, G.g, c->bilu, plan);
     });
-    int st = 0;
-    try {
-        st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H);
-    } catch (...) {
-        planner.join();
-        throw;
-    }
-    planner.join();
-    if (plan_err) std::rethrow_exception(plan_err);
+    Hierarchy H;
+    int st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false);
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
+    const int nlev = (int)H.A.size();
+    std::vector<std::future<Groups>> groups(nlev);
+    for (int l = 1; l + 1 < nlev; ++l)
+        groups[l] = std::async(std::launch::async, [&H, l]() {
+            Groups G;
+            const Csr &A = H.A[l];
+            Adjacency adj = build_adjacency(A.n, A.rp.data(), A.ci.data());
+            G.g = vertices_grouping(adj, G.color);
+            return G;
+        });
+    launch_coarse(c, H.A.back(), tmp);
     phase(3);
-    c->lev.resize(H.A.size());
-    for (size_t l = 0; l < H.A.size(); ++l) {
+    c->lev.resize(nlev);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        Groups G = l == 0 ? groups0.get() : groups[l].get();
+        c->lev[l].color = std::move(G.color);
+        c->lev[l].g = G.g;
+    }
+    for (int l = 0; l < nlev; ++l) {
         Level &L = c->lev[l];
         L.A = std::move(H.A[l]);
         L.n = L.A.n;
-        if (l + 1 < c->lev.size()) {
-            L.color = std::move(H.color[l]);
-            L.agg = std::move(H.agg[l]);
-            L.g = H.ncolors[l];
-        }
+        if (l + 1 < nlev) L.agg = std::move(H.agg[l]);
     }
-    for (size_t l = 0; l + 1 < c->lev.size(); ++l) c->lev[l].nc = c->lev[l + 1].A.n;
-    for (size_t l = 0; l < c->lev.size(); ++l) build_level_device(c, (int)l, H);
-    link_levels(c);
-    c->sync();
-    phase(4);
-    build_coarse(c);
-    phase(5);
-    bilu_device(c, vals, plan);
-    c->sync();
+    for (int l = 0; l + 1 < nlev; ++l) c->lev[l].nc = c->lev[l + 1].A.n;
+    {
+        CopyStreamScope on_side(c, c->side);
+        for (int l = 0; l < nlev; ++l) build_level_device(c, l, H);
+        link_levels(c);
+        phase(4);
+        planned.get();
+        bilu_device(c, vals, plan, tmp);
+    }
+    HIPCHK(hipEventRecord(c->ev_side, c->side));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
+    const int bad_bilu = c->read_flag(1);
     phase(6);
+    const int bad_coarse = c->read_flag(0);
+    c->release(tmp);
+    if (bad_coarse || bad_bilu) fail(MSP_ERR_SINGULAR);
+    phase(5);
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
     c->e_nat = c->dalloc(tsz * n, c->allocB);
     c->ybuf = c->dalloc(tsz * (size_t)n * b, c->allocB);
@@ -967,7 +1028,7 @@ int msp_create(msp_ctx **ctx, const msp_options *opt)
         HIPCHK(hipGetDevice(&c->device));
         c->stream = (hipStream_t)o.stream;
         HIPCHK(hipHostMalloc((void **)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault));
         c->flag = (int *)c->dalloc(sizeof(int) * 4, c->allocW);
         c->wsN = -1;
         return MSP_OK;
@@ -988,6 +1049,14 @@ int msp_destroy(msp_ctx *c)
     int st = guarded([&]() {
         drop_graph(c);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->gj.aux) (void)hipStreamDestroy(c->gj.aux);
+        for (int i = 0; i < 2; ++i) {
+            if (c->gj.ev_block[i]) (void)hipEventDestroy(c->gj.ev_block[i]);
+            if (c->gj.ev_inv[i]) (void)hipEventDestroy(c->gj.ev_inv[i]);
+        }
+        if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+        if (c->ev_side) (void)hipEventDestroy(c->ev_side);
         c->release(c->allocA);
         c->release(c->allocB);
         c->release(c->allocW);
@@ -1121,7 +1190,7 @@ int msp_footprint(int n, long long nnzb, int b, const msp_options *opt, size_t *
                   (double)n * (E * ts + 24);
     double vecs = (double)n * b * (8 + 2 * ts) + (double)n * 8 * b;
     double krylov = 8.0 * (double)n * b * (2.0 * o.restart + 4) + 8.0 * kDotBlocks * (o.restart + 2);
-    double setup_tmp = 8.0 * nnzb + 8.0 * (3 * 128.0 * o.max_coarse + 128.0 * 128.0);
+    double setup_tmp = 8.0 * nnzb + 8.0 * (double)dense_inverse_work(o.max_coarse);
     *bytes = (size_t)(A + amg + coarse + bilu + vecs + krylov + setup_tmp + (1 << 20));
     return MSP_OK;
 }
@@ -1341,20 +1410,22 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
         const bool f32 = c->fp32();
         if (stage == MSP_STAGE_GJ_UPDATE) {
             // scratch operands of the coarsest size (made on first use, kept with
-            // B): C = copy of the inverse, A (n x 128) and B (128 x n) constant
+            // B): C = copy of the inverse, A (n x P) and B (P x n) constant, P
+            // the Gauss-Jordan panel width
             const int m = c->nL, ld = c->ldL;
+            constexpr int P = kGJPanel;
             if (!c->tC) {
                 c->tC = (double *)c->dalloc(sizeof(double) * (size_t)m * ld, c->allocB);
-                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)m * 128, c->allocB);
-                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)128 * m, c->allocB);
+                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)m * P, c->allocB);
+                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)P * m, c->allocB);
                 HIPCHK(hipMemcpyAsync(c->tC, c->cinv, sizeof(double) * (size_t)m * ld,
                                       hipMemcpyDeviceToDevice, c->stream));
-                HIPCHK(launch_fill((long long)m * 128, 1e-3, c->tA, c->stream));
-                HIPCHK(launch_fill((long long)m * 128, 1e-3, c->tB, c->stream));
+                HIPCHK(launch_fill((long long)m * P, 1e-3, c->tA, c->stream));
+                HIPCHK(launch_fill((long long)m * P, 1e-3, c->tB, c->stream));
                 c->sync();
             }
             for (int r = 0; r < reps; ++r)
-                HIPCHK(launch_dgemm(m, m, 128, c->tA, 128, c->tB, m, c->tC, ld, -1.0, 1.0,
+                HIPCHK(launch_dgemm(m, m, P, c->tA, P, c->tB, m, c->tC, ld, -1.0, 1.0,
                                     c->stream));
             c->sync();
             return MSP_OK;

@@ -248,7 +248,14 @@ Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc)
     return C;
 }
 
-int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H)
+int color_level(const Csr &A, std::vector<int> &color)
+{
+    Adjacency G = build_adjacency(A.n, A.rp.data(), A.ci.data());
+    return vertices_grouping(G, color);
+}
+
+int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
+                    bool with_colors)
 {
     H = Hierarchy();
     H.A.push_back(std::move(A0));
@@ -257,9 +264,11 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         bool last = cur.n <= max_coarse || l == max_levels - 1 ||
                     (l > 0 && (double)cur.n > 0.9 * (double)H.A[l - 1].n);
         if (last) break;
-        std::vector<int> color;
-        Adjacency G = build_adjacency(cur.n, cur.rp.data(), cur.ci.data());
-        int g = vertices_grouping(G, color);
+        if (with_colors) {
+            std::vector<int> color;
+            H.ncolors.push_back(color_level(cur, color));
+            H.color.push_back(std::move(color));
+        }
         std::vector<int> a1, a2;
         int nc1 = pairwise_pass(cur, a1);
         Csr M1 = galerkin(cur, a1, nc1);
@@ -267,9 +276,7 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         Csr Cn = galerkin(M1, a2, nc2);
         std::vector<int> agg(cur.n);
         for (int i = 0; i < cur.n; ++i) agg[i] = a2[a1[i]];
-        H.color.push_back(std::move(color));
         H.agg.push_back(std::move(agg));
-        H.ncolors.push_back(g);
         H.A.push_back(std::move(Cn));
     }
     for (size_t l = 0; l + 1 < H.A.size(); ++l) {

@@ -49,7 +49,12 @@ struct Hierarchy {
     std::vector<std::vector<int>> color, agg;
     std::vector<int> ncolors;
 };
-int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H);
+// with_colors = false leaves color/ncolors empty (the groups can then be
+// computed per level with color_level, e.g. on other threads).
+int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
+                    bool with_colors = true);
+// groups of Alg. 4.2 on one level: fills color, returns g
+int color_level(const Csr &A, std::vector<int> &color);
 
 // Dependency levels of a block triangular solve restricted to the stored
 // pattern: lower = true gives level(i) = 1 + max level(k) over stored k < i

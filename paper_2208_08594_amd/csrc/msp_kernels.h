@@ -126,9 +126,20 @@ hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, con
 hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
                         double *C, int ldc, double alpha, double beta, hipStream_t st);
 // In-place inverse of the n x n row-major matrix M (leading dimension ld) by
-// block Gauss-Jordan over 128-wide panels with partial pivoting inside each
-// diagonal block.  work must hold dense_inverse_work(n) doubles.
+// block Gauss-Jordan over kGJPanel-wide panels.  Each diagonal block is
+// inverted by an inner Gauss-Jordan pass over 128-wide panels with partial
+// pivoting inside each 128 x 128 diagonal block; *bad is set on a zero pivot.
+// With `la`, the inverse of the next diagonal block (formed apart from the
+// step's update) runs on la->aux while the full rank-kGJPanel update runs on
+// st (look-ahead); the events order the two streams.  Without it everything
+// runs on st.  work must hold dense_inverse_work(n) doubles.
+constexpr int kGJPanel = 256;
+struct GjLookAhead {
+    hipStream_t aux;
+    hipEvent_t ev_block[2], ev_inv[2];
+};
 size_t dense_inverse_work(int n);
-hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st);
+hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st,
+                         const GjLookAhead *la);
 
 }  // namespace msp

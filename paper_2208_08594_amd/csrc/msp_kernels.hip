@@ -877,17 +877,19 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int ld, int K, int kb,
     }
 }
 
-// Ccol[i][t] = M[i][K+t] for rows outside the block (0 inside), ld kNB;
+// Panel steps of a Gauss-Jordan pass with panel width P (block (K, K) of
+// size kb <= P).
+// Ccol[i][t] = M[i][K+t] for rows outside the block (0 inside), ld P;
 // Mrow[t][j] = M[K+t][j], ld n.
-__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int ld, int K, int kb,
+__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int ld, int P, int K, int kb,
                                                          const double *__restrict__ M,
                                                          double *__restrict__ Ccol,
                                                          double *__restrict__ Mrow)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    const long long nc = (long long)n * kNB;
+    const long long nc = (long long)n * P;
     if (q < nc) {
-        int i = (int)(q / kNB), t = (int)(q % kNB);
+        int i = (int)(q / P), t = (int)(q % P);
         bool inblk = i >= K && i < K + kb;
         Ccol[q] = (t < kb && !inblk) ? M[(long long)i * ld + K + t] : 0.0;
     } else if (q < nc + (long long)kb * n) {
@@ -897,8 +899,9 @@ __global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int ld, int K, i
     }
 }
 
-// Trow[t][K+u] = Dblk[t][u]; M[i][K+u] = 0 for rows outside the block.
-__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int K, int kb,
+// Trow[t][K+u] = Dblk[t][u] (Dblk with ld P); M[i][K+u] = 0 for rows outside
+// the block.
+__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int P, int K, int kb,
                                                      const double *__restrict__ Dblk,
                                                      double *__restrict__ Trow,
                                                      double *__restrict__ M)
@@ -907,12 +910,23 @@ __global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int K, int k
     const long long nt = (long long)kb * kb;
     if (q < nt) {
         int t = (int)(q / kb), u = (int)(q % kb);
-        Trow[(long long)t * n + K + u] = Dblk[t * kNB + u];
+        Trow[(long long)t * n + K + u] = Dblk[(long long)t * P + u];
     } else if (q < nt + (long long)n * kb) {
         long long r = q - nt;
         int i = (int)(r / kb), u = (int)(r % kb);
         if (i < K || i >= K + kb) M[(long long)i * ld + K + u] = 0.0;
     }
+}
+
+// B[r][c] = A[r][c] for r, c < kb (B with ld ldb)
+__global__ __launch_bounds__(kThreads) void k_copy_block(int kb, const double *__restrict__ A,
+                                                         int lda, double *__restrict__ B,
+                                                         int ldb)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long long)kb * kb) return;
+    const int r = (int)(q / kb), c = (int)(q % kb);
+    B[(long long)r * ldb + c] = A[(long long)r * lda + c];
 }
 
 // M[K+t][j] = Trow[t][j]
@@ -1325,9 +1339,12 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
     return hipGetLastError();
 }
 
-size_t dense_inverse_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
+namespace {
 
-hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st)
+// Gauss-Jordan inverse of an n x n matrix (ld ld) in place with 128-wide
+// panels; each diagonal block is inverted by k_gj_diag (pivoting inside the
+// block).  work: 3 kNB n + kNB kNB doubles.
+hipError_t gj_inverse_128(int n, int ld, double *M, double *work, int *bad, hipStream_t st)
 {
     double *Ccol = work;                       // n x kNB
     double *Mrow = work + (long long)kNB * n;  // kNB x n
@@ -1337,16 +1354,87 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
         const int kb = n - K < kNB ? n - K : kNB;
         k_gj_diag<<<1, 1024, 0, st>>>(ld, K, kb, M, Dblk, bad);
         k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
-            n, ld, K, kb, M, Ccol, Mrow);
+            n, ld, kNB, K, kb, M, Ccol, Mrow);
         hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);
         if (e != hipSuccess) return e;
         k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
-            n, ld, K, kb, Dblk, Trow, M);
+            n, ld, kNB, K, kb, Dblk, Trow, M);
         e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, ld, -1.0, 1.0, st);
         if (e != hipSuccess) return e;
         k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, ld, K, kb, Trow, M);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+size_t gj128_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
+
+}  // namespace
+
+size_t dense_inverse_work(int n)
+{
+    return (size_t)3 * kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+}
+
+hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st,
+                         const GjLookAhead *la)
+{
+    constexpr int P = kGJPanel;
+    double *Ccol = work;                                // n x P
+    double *Mrow = Ccol + (long long)P * n;             // P x n
+    double *Trow = Mrow + (long long)P * n;             // P x n
+    double *Nblk[2] = {Trow + (long long)P * n,         // P x P, two buffers
+                       Trow + (long long)P * n + (long long)P * P};
+    double *iwork = Nblk[1] + (long long)P * P;         // inner inverse
+    const hipStream_t aux = la ? la->aux : st;
+    hipError_t e;
+    // block 0: copy out and invert on the side stream
+    {
+        const int kb0 = n < P ? n : P;
+        k_copy_block<<<blocks_for((long long)kb0 * kb0), kThreads, 0, st>>>(kb0, M, ld, Nblk[0],
+                                                                           P);
+        if (la) {
+            if ((e = hipEventRecord(la->ev_block[0], st)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(aux, la->ev_block[0], 0)) != hipSuccess) return e;
+        }
+        if ((e = gj_inverse_128(kb0, P, Nblk[0], iwork, bad, aux)) != hipSuccess) return e;
+        if (la && (e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
+    }
+    for (int K = 0, s = 0; K < n; K += P, ++s) {
+        const int kb = n - K < P ? n - K : P;
+        const double *D = Nblk[s & 1];
+        if (la && (e = hipStreamWaitEvent(st, la->ev_inv[s & 1], 0)) != hipSuccess) return e;
+        k_gj_extract<<<blocks_for((long long)n * P + (long long)kb * n), kThreads, 0, st>>>(
+            n, ld, P, K, kb, M, Ccol, Mrow);
+        if ((e = launch_dgemm(kb, n, kb, D, P, Mrow, n, Trow, n, 1.0, 0.0, st)) != hipSuccess)
+            return e;
+        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
+            n, ld, P, K, kb, D, Trow, M);
+        // look-ahead: the next diagonal block after this step's update,
+        // computed apart and inverted on the side stream while the full
+        // update runs here
+        const int Kn = K + P;
+        if (Kn < n) {
+            const int kb2 = n - Kn < P ? n - Kn : P;
+            double *Nn = Nblk[(s + 1) & 1];
+            k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, st>>>(
+                kb2, M + (long long)Kn * ld + Kn, ld, Nn, P);
+            if ((e = launch_dgemm(kb2, kb2, kb, Ccol + (long long)Kn * P, P, Trow + Kn, n, Nn, P,
+                                  -1.0, 1.0, st)) != hipSuccess)
+                return e;
+            if (la) {
+                if ((e = hipEventRecord(la->ev_block[(s + 1) & 1], st)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(aux, la->ev_block[(s + 1) & 1], 0)) != hipSuccess)
+                    return e;
+            }
+            if ((e = gj_inverse_128(kb2, P, Nn, iwork, bad, aux)) != hipSuccess) return e;
+            if (la && (e = hipEventRecord(la->ev_inv[(s + 1) & 1], aux)) != hipSuccess) return e;
+        }
+        if ((e = launch_dgemm(n, n, kb, Ccol, P, Trow, n, M, ld, -1.0, 1.0, st)) != hipSuccess)
+            return e;
+        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, ld, K, kb, Trow, M);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
