@@ -171,6 +171,7 @@ struct msp_ctx {
             (void)hipStreamSynchronize(stream);
             if (side) (void)hipStreamSynchronize(side);
             if (gj.aux) (void)hipStreamSynchronize(gj.aux);
+            if (gj.main) (void)hipStreamSynchronize(gj.main);
         }
         for (void *p_ : list) {
             if (opt.dev_free)
@@ -362,6 +363,51 @@ void link_levels(msp_ctx *c)
     }
 }
 
+// Streams of the coarsest-level inverse: the update stream gets all compute
+// units but kGjAuxCUs, the diagonal-block stream those few, so the short
+// kernels of the diagonal chain never queue for slots behind the large
+// update GEMMs.  Where a compute-unit mask cannot be set both streams are
+// plain (same results, less overlap).
+constexpr int kGjAuxCUs = 8;
+void make_gj_streams(msp_ctx *c)
+{
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, c->device));
+    const int ncu = prop.multiProcessorCount;
+    bool masked = false;
+    if (ncu > 4 * kGjAuxCUs) {
+        const int words = (ncu + 31) / 32;
+        std::vector<uint32_t> mmain(words, 0), maux(words, 0);
+        for (int cu = 0; cu < ncu; ++cu) {
+            if (cu < kGjAuxCUs)
+                maux[cu / 32] |= 1u << (cu % 32);
+            else
+                mmain[cu / 32] |= 1u << (cu % 32);
+        }
+        hipStream_t a = nullptr, m = nullptr;
+        if (hipExtStreamCreateWithCUMask(&m, (uint32_t)words, mmain.data()) == hipSuccess &&
+            hipExtStreamCreateWithCUMask(&a, (uint32_t)words, maux.data()) == hipSuccess) {
+            c->gj.main = m;
+            c->gj.aux = a;
+            masked = true;
+        } else {
+            (void)hipGetLastError();
+            if (m) (void)hipStreamDestroy(m);
+            if (a) (void)hipStreamDestroy(a);
+        }
+    }
+    if (!masked) {
+        HIPCHK(hipStreamCreateWithFlags(&c->gj.main, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&c->gj.aux, hipStreamNonBlocking));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->gj.ev_start, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->gj.ev_done, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipEventCreateWithFlags(&c->gj.ev_block[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->gj.ev_inv[i], hipEventDisableTiming));
+    }
+}
+
 // Queues the coarsest-level inverse on `stream` and returns without waiting;
 // flag[0] is set on a singular pivot block.  The upload and work buffers go
 // to `tmp`, which the caller releases after the stream has drained.
@@ -377,15 +423,32 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
     double *work = (double *)c->dalloc(sizeof(double) * dense_inverse_work(m), tmp);
     HIPCHK(launch_fill((long long)m * c->ldL, 0.0, c->cinv, c->stream));
     HIPCHK(launch_dense_scatter(m, c->ldL, rp, ci, val, c->cinv, c->stream));
-    if (!c->gj.aux) {
-        HIPCHK(hipStreamCreateWithFlags(&c->gj.aux, hipStreamNonBlocking));
-        for (int i = 0; i < 2; ++i) {
-            HIPCHK(hipEventCreateWithFlags(&c->gj.ev_block[i], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&c->gj.ev_inv[i], hipEventDisableTiming));
+    if (!c->gj.aux) make_gj_streams(c);
+    // fill window of each panel step: a row first takes part in the step of
+    // the panel holding its first stored column, a column in that of its
+    // first stored row
+    const int steps = (m + kGJPanel - 1) / kGJPanel;
+    std::vector<int> rows_end(steps, 0), cols_end(steps, 0);
+    {
+        std::vector<int> first_row(m, m);
+        for (int i = 0; i < m; ++i) {
+            const int s0 = A.ci[A.rp[i]] / kGJPanel;  // columns ascending
+            rows_end[s0] = std::max(rows_end[s0], i + 1);
+            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                first_row[A.ci[k]] = std::min(first_row[A.ci[k]], i);
+        }
+        for (int j = 0; j < m; ++j) {
+            const int s0 = first_row[j] / kGJPanel;
+            cols_end[s0] = std::max(cols_end[s0], j + 1);
+        }
+        for (int s = 1; s < steps; ++s) {
+            rows_end[s] = std::max(rows_end[s], rows_end[s - 1]);
+            cols_end[s] = std::max(cols_end[s], cols_end[s - 1]);
         }
     }
     c->clear_flag(0);
-    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream, &c->gj));
+    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream, &c->gj, rows_end.data(),
+                         cols_end.data()));
 }
 
 // Host-only part of the block ILU(0) setup: elimination order, dependency
@@ -1051,6 +1114,9 @@ int msp_destroy(msp_ctx *c)
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->side) (void)hipStreamDestroy(c->side);
         if (c->gj.aux) (void)hipStreamDestroy(c->gj.aux);
+        if (c->gj.main) (void)hipStreamDestroy(c->gj.main);
+        if (c->gj.ev_start) (void)hipEventDestroy(c->gj.ev_start);
+        if (c->gj.ev_done) (void)hipEventDestroy(c->gj.ev_done);
         for (int i = 0; i < 2; ++i) {
             if (c->gj.ev_block[i]) (void)hipEventDestroy(c->gj.ev_block[i]);
             if (c->gj.ev_inv[i]) (void)hipEventDestroy(c->gj.ev_inv[i]);

@@ -3,10 +3,42 @@
 #include "msp_host.h"
 
 #include <algorithm>
+#include <memory>
 #include <numeric>
 #include <queue>
+#include <thread>
 
 namespace msp {
+
+namespace {
+
+// Runs f(lo, hi, t) over nparts contiguous, ordered chunks of [0, n) on
+// worker threads (chunk t on thread t); results that each chunk keeps apart
+// and the caller joins in chunk order are identical to a sequential pass.
+template <class F>
+void for_chunks(int n, int nparts, F f)
+{
+    if (nparts <= 1 || n < 2 * nparts) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nparts - 1);
+    for (int t = 1; t < nparts; ++t)
+        th.emplace_back([&, t]() { f((int)((long long)n * t / nparts), (int)((long long)n * (t + 1) / nparts), t); });
+    f(0, (int)((long long)n / nparts), 0);
+    for (auto &x : th) x.join();
+}
+
+int host_parts(int n)
+{
+    // worth splitting only for large levels; a few threads are enough
+    unsigned hc = std::thread::hardware_concurrency();
+    int p = (int)std::min(hc ? hc : 1u, 8u);
+    return n >= 16384 ? p : 1;
+}
+
+}  // namespace
 
 int check_pattern(int n, const int *rp, const int *ci, long long nnz)
 {
@@ -136,49 +168,97 @@ static inline double entry(const Csr &A, int i, int j)
 int pairwise_pass(const Csr &A, std::vector<int> &agg)
 {
     const int n = A.n;
-    // transpose with values: AT row j lists (i, a_ij) for stored (i, j), i ascending
-    std::vector<int> tp(n + 1, 0), ti(A.ci.size());
-    std::vector<double> tv(A.ci.size());
-    for (size_t k = 0; k < A.ci.size(); ++k) ++tp[A.ci[k] + 1];
-    for (int j = 0; j < n; ++j) tp[j + 1] += tp[j];
+    const int parts = host_parts(n);
+    // transpose with values: AT row j lists (i, a_ij) for stored (i, j), i
+    // ascending.  For a structurally symmetric pattern row j of A^T has the
+    // columns of row j of A, so only the values are gathered (through the
+    // mirror position of each entry, in parallel); otherwise a counting sort.
+    std::vector<int> tp;
+    std::unique_ptr<int[]> ti_own;
+    const int *ti = A.ci.data();
+    std::unique_ptr<double[]> tv(new double[A.ci.size() + 1]);
+    bool symmetric = true;
     {
+        std::vector<unsigned char> miss(parts, 0);
+        for_chunks(n, parts, [&](int lo, int hi, int t) {
+            for (int i = lo; i < hi && !miss[t]; ++i)
+                for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                    const int j = A.ci[k];
+                    auto b = A.ci.begin() + A.rp[j], e = A.ci.begin() + A.rp[j + 1];
+                    auto it = std::lower_bound(b, e, i);
+                    if (it == e || *it != i) {
+                        miss[t] = 1;
+                        break;
+                    }
+                    tv[k] = A.val[it - A.ci.begin()];
+                }
+        });
+        for (unsigned char m : miss) symmetric = symmetric && !m;
+    }
+    if (symmetric) {
+        tp = A.rp;
+    } else {
+        tp.assign(n + 1, 0);
+        ti_own.reset(new int[A.ci.size() + 1]);
+        for (size_t k = 0; k < A.ci.size(); ++k) ++tp[A.ci[k] + 1];
+        for (int j = 0; j < n; ++j) tp[j + 1] += tp[j];
         std::vector<int> f(tp.begin(), tp.end() - 1);
         for (int i = 0; i < n; ++i)
             for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
                 int q = f[A.ci[k]]++;
-                ti[q] = i;
+                ti_own[q] = i;
                 tv[q] = A.val[k];
             }
+        ti = ti_own.get();
     }
     // symmetrised neighbours of i = merge of row i of A and row i of A^T
-    // (both ascending), with s_ij = -(a_ij + a_ji)/2
-    std::vector<int> nptr(n + 1, 0), nbr;
-    std::vector<double> s;
-    nbr.reserve(2 * A.ci.size());
-    s.reserve(2 * A.ci.size());
+    // (both ascending), with s_ij = -(a_ij + a_ji)/2, built per row chunk.
+    // A chunk writes from the bound offset rp[lo] + tp[lo] (a row has at most
+    // rowlen(A) + rowlen(A^T) neighbours) into memory allocated here; the
+    // chunks are then packed in order.
     std::vector<double> smax(n, 0.0);
     std::vector<unsigned char> eligible(n, 0);
-    for (int i = 0; i < n; ++i) {
-        int a = A.rp[i], ae = A.rp[i + 1], t = tp[i], te = tp[i + 1];
-        bool coupled = false, any = false;
-        double mx = 0.0;
-        while (a < ae || t < te) {
-            int ja = a < ae ? A.ci[a] : n, jt = t < te ? ti[t] : n;
-            int j = ja < jt ? ja : jt;
-            double aij = 0.0, aji = 0.0;
-            if (ja == j) { aij = A.val[a]; ++a; }
-            if (jt == j) { aji = tv[t]; ++t; }
-            if (j == i) continue;
-            if (ja == j && aij != 0.0) coupled = true;
-            double sij = -(aij + aji) / 2.0;
-            nbr.push_back(j);
-            s.push_back(sij);
-            if (!any || sij > mx) mx = sij;
-            any = true;
+    const size_t bound = (size_t)A.rp[n] + (size_t)tp[n];
+    std::unique_ptr<int[]> nbr(new int[bound + 1]);
+    std::unique_ptr<double[]> s(new double[bound + 1]);
+    std::vector<int> cnt(n, 0), chunk_lo(parts + 1, n);
+    for_chunks(n, parts, [&](int lo, int hi, int t) {
+        chunk_lo[t] = lo;
+        size_t o = (size_t)A.rp[lo] + (size_t)tp[lo];
+        for (int i = lo; i < hi; ++i) {
+            int a = A.rp[i], ae = A.rp[i + 1], q = tp[i], te = tp[i + 1];
+            bool coupled = false, any = false;
+            double mx = 0.0;
+            const size_t before = o;
+            while (a < ae || q < te) {
+                int ja = a < ae ? A.ci[a] : n, jt = q < te ? ti[q] : n;
+                int j = ja < jt ? ja : jt;
+                double aij = 0.0, aji = 0.0;
+                if (ja == j) { aij = A.val[a]; ++a; }
+                if (jt == j) { aji = tv[q]; ++q; }
+                if (j == i) continue;
+                if (ja == j && aij != 0.0) coupled = true;
+                double sij = -(aij + aji) / 2.0;
+                nbr[o] = j;
+                s[o] = sij;
+                ++o;
+                if (!any || sij > mx) mx = sij;
+                any = true;
+            }
+            cnt[i] = (int)(o - before);
+            smax[i] = mx;
+            eligible[i] = coupled && any && mx > 0.0;
         }
-        nptr[i + 1] = (int)nbr.size();
-        smax[i] = mx;
-        eligible[i] = coupled && any && mx > 0.0;
+    });
+    std::vector<int> nptr(n + 1, 0);
+    for (int i = 0; i < n; ++i) nptr[i + 1] = nptr[i] + cnt[i];
+    for (int t = 0; t < parts && chunk_lo[t] < n; ++t) {
+        const int lo = chunk_lo[t], hi = chunk_lo[t + 1];
+        const size_t from = (size_t)A.rp[lo] + (size_t)tp[lo], len = nptr[hi] - nptr[lo];
+        if (from != (size_t)nptr[lo] && len) {
+            std::copy(nbr.get() + from, nbr.get() + from + len, nbr.get() + nptr[lo]);
+            std::copy(s.get() + from, s.get() + from + len, s.get() + nptr[lo]);
+        }
     }
     agg.assign(n, -1);
     int nc = 0;
@@ -211,40 +291,67 @@ Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc)
         std::vector<int> f(mptr.begin(), mptr.end() - 1);
         for (int i = 0; i < n; ++i) mem[f[agg[i]]++] = i;  // ascending fine index
     }
+    // Coarse rows in ordered chunks, each with its own accumulator.  Row I has
+    // at most as many entries as its member rows hold together, so a chunk
+    // writes from that bound offset into memory allocated here; the chunks
+    // are then packed in order.
+    const int parts = host_parts(n);
+    std::vector<long long> bnd(nc + 1, 0);
+    for (int I = 0; I < nc; ++I) {
+        long long w = 0;
+        for (int m = mptr[I]; m < mptr[I + 1]; ++m) w += A.rp[mem[m] + 1] - A.rp[mem[m]];
+        bnd[I + 1] = bnd[I] + w;
+    }
     Csr C;
     C.n = nc;
-    C.rp.assign(nc + 1, 0);
-    C.ci.reserve(A.ci.size());
-    C.val.reserve(A.ci.size());
-    std::vector<int> slot(nc, -1), cols;
-    std::vector<double> vals;
-    std::vector<int> idx;
-    for (int I = 0; I < nc; ++I) {
-        cols.clear();
-        vals.clear();
-        for (int m = mptr[I]; m < mptr[I + 1]; ++m) {
-            int i = mem[m];
-            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-                int J = agg[A.ci[k]];
-                if (slot[J] < 0) {
-                    slot[J] = (int)cols.size();
-                    cols.push_back(J);
-                    vals.push_back(A.val[k]);
-                } else {
-                    vals[slot[J]] = vals[slot[J]] + A.val[k];
+    C.ci.resize(bnd[nc]);
+    C.val.resize(bnd[nc]);
+    std::vector<int> rowlen(nc, 0), chunk_lo(parts + 1, nc);
+    for_chunks(nc, parts, [&](int lo, int hi, int t) {
+        chunk_lo[t] = lo;
+        std::vector<int> slot(nc, -1), cols, idx;
+        std::vector<double> vals;
+        long long o = bnd[lo];
+        for (int I = lo; I < hi; ++I) {
+            cols.clear();
+            vals.clear();
+            for (int m = mptr[I]; m < mptr[I + 1]; ++m) {
+                int i = mem[m];
+                for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                    int J = agg[A.ci[k]];
+                    if (slot[J] < 0) {
+                        slot[J] = (int)cols.size();
+                        cols.push_back(J);
+                        vals.push_back(A.val[k]);
+                    } else {
+                        vals[slot[J]] = vals[slot[J]] + A.val[k];
+                    }
                 }
             }
+            idx.resize(cols.size());
+            std::iota(idx.begin(), idx.end(), 0);
+            std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+            for (int q : idx) {
+                C.ci[o] = cols[q];
+                C.val[o] = vals[q];
+                ++o;
+                slot[cols[q]] = -1;
+            }
+            rowlen[I] = (int)cols.size();
         }
-        idx.resize(cols.size());
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cols[a] < cols[b]; });
-        for (int q : idx) {
-            C.ci.push_back(cols[q]);
-            C.val.push_back(vals[q]);
-            slot[cols[q]] = -1;
+    });
+    C.rp.assign(nc + 1, 0);
+    for (int I = 0; I < nc; ++I) C.rp[I + 1] = C.rp[I] + rowlen[I];
+    for (int t = 0; t < parts && chunk_lo[t] < nc; ++t) {
+        const int lo = chunk_lo[t], hi = chunk_lo[t + 1];
+        const long long from = bnd[lo], len = C.rp[hi] - C.rp[lo];
+        if (from != C.rp[lo] && len) {
+            std::copy(C.ci.begin() + from, C.ci.begin() + from + len, C.ci.begin() + C.rp[lo]);
+            std::copy(C.val.begin() + from, C.val.begin() + from + len, C.val.begin() + C.rp[lo]);
         }
-        C.rp[I + 1] = (int)C.ci.size();
     }
+    C.ci.resize(C.rp[nc]);
+    C.val.resize(C.rp[nc]);
     return C;
 }
 

@@ -131,15 +131,23 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // pivoting inside each 128 x 128 diagonal block; *bad is set on a zero pivot.
 // With `la`, the inverse of the next diagonal block (formed apart from the
 // step's update) runs on la->aux while the full rank-kGJPanel update runs on
-// st (look-ahead); the events order the two streams.  Without it everything
-// runs on st.  work must hold dense_inverse_work(n) doubles.
+// la->main (look-ahead); events order the streams, and st waits for the whole
+// inverse.  The two streams are meant to own disjoint sets of compute units,
+// so the latency-bound diagonal chain never waits for slots behind the
+// update.  Without `la` everything runs on st.  rows_end/cols_end (host
+// arrays, one entry per panel step s, or null for the full matrix) bound the
+// window [0, rows_end[s]) x [0, cols_end[s]) that step s changes: with
+// rows_end[s] = 1 + the last row whose first stored column lies before the end
+// of panel s (cols_end likewise by columns), entries outside the window are
+// still those of the original sparse matrix.  work must hold
+// dense_inverse_work(n) doubles.
 constexpr int kGJPanel = 256;
 struct GjLookAhead {
-    hipStream_t aux;
-    hipEvent_t ev_block[2], ev_inv[2];
+    hipStream_t main, aux;
+    hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2];
 };
 size_t dense_inverse_work(int n);
 hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st,
-                         const GjLookAhead *la);
+                         const GjLookAhead *la, const int *rows_end, const int *cols_end);
 
 }  // namespace msp

@@ -6,6 +6,8 @@
 // way.  Reductions use a fixed tree, so results are identical run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "msp_kernels.h"
 
 namespace msp {
@@ -878,30 +880,33 @@ __global__ __launch_bounds__(1024) void k_gj_diag(int ld, int K, int kb,
 }
 
 // Panel steps of a Gauss-Jordan pass with panel width P (block (K, K) of
-// size kb <= P).
-// Ccol[i][t] = M[i][K+t] for rows outside the block (0 inside), ld P;
-// Mrow[t][j] = M[K+t][j], ld n.
-__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int ld, int P, int K, int kb,
+// size kb <= P) restricted to rows [0, nr) and columns [0, ncol) of the n x n
+// matrix: outside that window the step changes nothing (entries there are
+// still those of the original matrix, zero in the panel rows and columns).
+// Ccol[i][t] = M[i][K+t] for rows i < nr outside the block (0 inside), ld P;
+// Mrow[t][j] = M[K+t][j] for j < ncol, ld n.
+__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int nr, int ncol, int ld, int P,
+                                                         int K, int kb,
                                                          const double *__restrict__ M,
                                                          double *__restrict__ Ccol,
                                                          double *__restrict__ Mrow)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    const long long nc = (long long)n * P;
+    const long long nc = (long long)nr * P;
     if (q < nc) {
         int i = (int)(q / P), t = (int)(q % P);
         bool inblk = i >= K && i < K + kb;
         Ccol[q] = (t < kb && !inblk) ? M[(long long)i * ld + K + t] : 0.0;
-    } else if (q < nc + (long long)kb * n) {
+    } else if (q < nc + (long long)kb * ncol) {
         long long r = q - nc;
-        int t = (int)(r / n), j = (int)(r % n);
-        Mrow[r] = M[(long long)(K + t) * ld + j];
+        int t = (int)(r / ncol), j = (int)(r % ncol);
+        Mrow[(long long)t * n + j] = M[(long long)(K + t) * ld + j];
     }
 }
 
-// Trow[t][K+u] = Dblk[t][u] (Dblk with ld P); M[i][K+u] = 0 for rows outside
-// the block.
-__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int P, int K, int kb,
+// Trow[t][K+u] = Dblk[t][u] (Dblk with ld P, Trow with ld n); M[i][K+u] = 0
+// for rows i < nr outside the block.
+__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int nr, int ld, int P, int K, int kb,
                                                      const double *__restrict__ Dblk,
                                                      double *__restrict__ Trow,
                                                      double *__restrict__ M)
@@ -911,7 +916,7 @@ __global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int ld, int P, int K
     if (q < nt) {
         int t = (int)(q / kb), u = (int)(q % kb);
         Trow[(long long)t * n + K + u] = Dblk[(long long)t * P + u];
-    } else if (q < nt + (long long)n * kb) {
+    } else if (q < nt + (long long)nr * kb) {
         long long r = q - nt;
         int i = (int)(r / kb), u = (int)(r % kb);
         if (i < K || i >= K + kb) M[(long long)i * ld + K + u] = 0.0;
@@ -929,15 +934,15 @@ __global__ __launch_bounds__(kThreads) void k_copy_block(int kb, const double *_
     B[(long long)r * ldb + c] = A[(long long)r * lda + c];
 }
 
-// M[K+t][j] = Trow[t][j]
-__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int ld, int K, int kb,
+// M[K+t][j] = Trow[t][j] for j < ncol (Trow with ld n)
+__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int ncol, int ld, int K, int kb,
                                                         const double *__restrict__ Trow,
                                                         double *__restrict__ M)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= (long long)kb * n) return;
-    const int t = (int)(q / n), j = (int)(q % n);
-    M[(long long)(K + t) * ld + j] = Trow[q];
+    if (q >= (long long)kb * ncol) return;
+    const int t = (int)(q / ncol), j = (int)(q % ncol);
+    M[(long long)(K + t) * ld + j] = Trow[(long long)t * n + j];
 }
 
 // C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  Each
@@ -1354,14 +1359,14 @@ hipError_t gj_inverse_128(int n, int ld, double *M, double *work, int *bad, hipS
         const int kb = n - K < kNB ? n - K : kNB;
         k_gj_diag<<<1, 1024, 0, st>>>(ld, K, kb, M, Dblk, bad);
         k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
-            n, ld, kNB, K, kb, M, Ccol, Mrow);
+            n, n, n, ld, kNB, K, kb, M, Ccol, Mrow);
         hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);
         if (e != hipSuccess) return e;
         k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
-            n, ld, kNB, K, kb, Dblk, Trow, M);
+            n, n, ld, kNB, K, kb, Dblk, Trow, M);
         e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, ld, -1.0, 1.0, st);
         if (e != hipSuccess) return e;
-        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, ld, K, kb, Trow, M);
+        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, n, ld, K, kb, Trow, M);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1377,9 +1382,16 @@ size_t dense_inverse_work(int n)
     return (size_t)3 * kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
 }
 
-hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st,
-                         const GjLookAhead *la)
+hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t caller,
+                         const GjLookAhead *la, const int *rows_end, const int *cols_end)
 {
+    hipError_t e;
+    hipStream_t st = caller;
+    if (la) {
+        st = la->main;
+        if ((e = hipEventRecord(la->ev_start, caller)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, la->ev_start, 0)) != hipSuccess) return e;
+    }
     constexpr int P = kGJPanel;
     double *Ccol = work;                                // n x P
     double *Mrow = Ccol + (long long)P * n;             // P x n
@@ -1388,7 +1400,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
                        Trow + (long long)P * n + (long long)P * P};
     double *iwork = Nblk[1] + (long long)P * P;         // inner inverse
     const hipStream_t aux = la ? la->aux : st;
-    hipError_t e;
     // block 0: copy out and invert on the side stream
     {
         const int kb0 = n < P ? n : P;
@@ -1403,14 +1414,18 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
     }
     for (int K = 0, s = 0; K < n; K += P, ++s) {
         const int kb = n - K < P ? n - K : P;
+        // window of this step (the look-ahead block included)
+        const int cover = n - K < 2 * P ? n : K + 2 * P;
+        const int nr = rows_end ? std::max(rows_end[s], cover) : n;
+        const int ncol = cols_end ? std::max(cols_end[s], cover) : n;
         const double *D = Nblk[s & 1];
         if (la && (e = hipStreamWaitEvent(st, la->ev_inv[s & 1], 0)) != hipSuccess) return e;
-        k_gj_extract<<<blocks_for((long long)n * P + (long long)kb * n), kThreads, 0, st>>>(
-            n, ld, P, K, kb, M, Ccol, Mrow);
-        if ((e = launch_dgemm(kb, n, kb, D, P, Mrow, n, Trow, n, 1.0, 0.0, st)) != hipSuccess)
+        k_gj_extract<<<blocks_for((long long)nr * P + (long long)kb * ncol), kThreads, 0, st>>>(
+            n, nr, ncol, ld, P, K, kb, M, Ccol, Mrow);
+        if ((e = launch_dgemm(kb, ncol, kb, D, P, Mrow, n, Trow, n, 1.0, 0.0, st)) != hipSuccess)
             return e;
-        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
-            n, ld, P, K, kb, D, Trow, M);
+        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)nr * kb), kThreads, 0, st>>>(
+            n, nr, ld, P, K, kb, D, Trow, M);
         // look-ahead: the next diagonal block after this step's update,
         // computed apart and inverted on the side stream while the full
         // update runs here
@@ -1431,10 +1446,16 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
             if ((e = gj_inverse_128(kb2, P, Nn, iwork, bad, aux)) != hipSuccess) return e;
             if (la && (e = hipEventRecord(la->ev_inv[(s + 1) & 1], aux)) != hipSuccess) return e;
         }
-        if ((e = launch_dgemm(n, n, kb, Ccol, P, Trow, n, M, ld, -1.0, 1.0, st)) != hipSuccess)
+        if ((e = launch_dgemm(nr, ncol, kb, Ccol, P, Trow, n, M, ld, -1.0, 1.0, st)) !=
+            hipSuccess)
             return e;
-        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, ld, K, kb, Trow, M);
+        k_gj_putrow<<<blocks_for((long long)kb * ncol), kThreads, 0, st>>>(n, ncol, ld, K, kb,
+                                                                         Trow, M);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (la) {
+        if ((e = hipEventRecord(la->ev_done, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(caller, la->ev_done, 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

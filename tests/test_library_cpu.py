@@ -188,6 +188,48 @@ def test_library_hierarchy_steps_match_oracle(shim):
             assert np.array_equal(dv[:m2], nxt["val"])  # same summation order: exact
 
 
+def _sparse_nonsymmetric(n, per_row, seed):
+    """Random CSR with a diagonal and `per_row` off-diagonal entries per row
+    (pattern not symmetric), negative off-diagonals and a dominant diagonal."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        c = np.unique(np.concatenate([[i], rng.integers(0, n, per_row)]))
+        rows.append(c)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(c) for c in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    val = -rng.uniform(0.0, 1.0, len(ci))
+    r = np.repeat(np.arange(n), np.diff(rp))
+    val[ci == r] = 2.0 * per_row
+    return rp, ci, val
+
+
+@pytest.mark.parametrize("case", ["grid_32k", "nonsymmetric_20k", "nonsymmetric_small"])
+def test_library_pair_and_galerkin_large(shim, case):
+    """Sizes that take the library's multi-threaded row-chunk paths (and the
+    counting-sort transpose of a nonsymmetric pattern) against the oracle."""
+    if case == "grid_32k":
+        rp, ci, val = synth.poisson_csr((40, 40, 20))
+        val = val * np.random.default_rng(3).uniform(0.5, 1.5, len(val))
+    elif case == "nonsymmetric_20k":
+        rp, ci, val = _sparse_nonsymmetric(20000, 5, 7)
+    else:
+        rp, ci, val = _sparse_nonsymmetric(300, 4, 8)
+    n = len(rp) - 1
+    a1 = np.zeros(n, dtype=np.int32)
+    nc1 = shim.shim_pair(n, rp, ci, val, a1)
+    o1, onc1 = O.npair_pass(rp, ci, val)
+    assert nc1 == onc1 and np.array_equal(a1, o1)
+    crp = np.zeros(nc1 + 1, dtype=np.int32)
+    cci = np.zeros(len(ci), dtype=np.int32)
+    cv = np.zeros(len(ci))
+    m = shim.shim_galerkin(n, rp, ci, val, a1, nc1, crp, cci, cv)
+    orp, oci, ov = O.galerkin(rp, ci, val, o1, onc1)
+    assert np.array_equal(crp, orp) and np.array_equal(cci[:m], oci)
+    assert np.array_equal(cv[:m], ov)
+
+
 def test_library_pattern_check(shim):
     rp, ci, _ = synth.poisson_csr((4, 3, 2))
     assert shim.shim_pattern(len(rp) - 1, rp, ci, len(ci)) == 0
