@@ -773,109 +773,223 @@ __global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, int ld,
 
 constexpr int kNB = 128;  // Gauss-Jordan panel width
 
-// Inverse of the kb x kb diagonal block at (K, K) by Gauss-Jordan elimination
-// with partial pivoting inside the block.  One 1024-thread work-group keeps the
-// block A and the growing inverse X in registers: thread (tr, tc) owns rows
-// tr + 32a and columns tc + 32b (a, b < 4).  Pivoting is implicit: column k
-// is eliminated with the unused row p_k of largest magnitude (lowest index on
-// ties) and no rows move, so at the end row k of A^-1 is row p_k of X.
-// Per step the pivot column and the scaled pivot row go through LDS (double
-// buffered), three barriers per step.  Dblk has leading dimension kNB.
-__global__ __launch_bounds__(1024) void k_gj_diag(int ld, int K, int kb,
-                                                  const double *__restrict__ M,
-                                                  double *__restrict__ Dblk, int *bad)
+// Largest 64-bit key over the wavefront: butterflies inside each row of 16
+// lanes by DPP moves, then the four row maxima read as scalars.
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long x)
 {
-    __shared__ double colk[2][kNB];
-    __shared__ double prowA[2][kNB], prowX[2][kNB];
-    __shared__ int invp[kNB];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int tr = tid >> 5, tc = tid & 31;
-    double A[4][4], X[4][4];
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, 0xf, 0xf, true);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b)
+{
+    return a > b ? a : b;
+}
+__device__ inline unsigned long long readlane_u64(unsigned long long x, int l)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long k)
+{
+    k = umax64(k, dpp_u64<0xB1>(k));   // quad_perm [1,0,3,2]
+    k = umax64(k, dpp_u64<0x4E>(k));   // quad_perm [2,3,0,1]
+    k = umax64(k, dpp_u64<0x141>(k));  // row_half_mirror
+    k = umax64(k, dpp_u64<0x140>(k));  // row_mirror
+    return umax64(umax64(readlane_u64(k, 0), readlane_u64(k, 16)),
+                  umax64(readlane_u64(k, 32), readlane_u64(k, 48)));
+}
+__device__ inline double readlane_f64(double x, int l)
+{
+    return __longlong_as_double((long long)readlane_u64((unsigned long long)__double_as_longlong(x), l));
+}
+
+// Pivot key of row r (< 128): |v| with its 8 lowest mantissa bits replaced by
+// 255 - r, so the largest key is the largest magnitude (to 2^-44 relative)
+// and the lowest row among equals; 0 marks a row already used.
+__device__ inline unsigned long long pivot_key(double v, int r)
+{
+    const unsigned long long m = (unsigned long long)__double_as_longlong(fabs(v));
+    return (m & ~255ull) | (unsigned long long)(255 - r);
+}
+
+constexpr int kDP = 16;  // column panel of the diagonal-block inverse
+
+// Inverse of the kb x kb diagonal block at (K, K) (kb <= 128, padded with the
+// identity) by blocked Gauss-Jordan elimination with partial pivoting inside
+// the block.  Pivoting is implicit: column k is eliminated with the unused row
+// p_k of largest magnitude and no rows move.  The elimination runs in place:
+// once column k is eliminated its slot holds column p_k of the growing
+// inverse X, so at the end S[i][k] = X[i][p_k] and A^-1[q][p_k] = S[p_q][k].
+// Per panel of 16 columns, wave 0 eliminates the panel alone (pivot search
+// by DPP max over packed keys, pivot row by lane reads), tracking the panel's
+// row transformation T = I + (Z - E_P) E_P^T; then all four waves apply it to
+// the other columns as one rank-16 update S += (Z - E_P) S[P, :] and store Z
+// in the panel's slots.  Thread (tr, tc) holds rows tr + 16a and columns
+// tc + 16b (a, b < 8).  Dblk has leading dimension kNB.
+__global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
+                                                 const double *__restrict__ M,
+                                                 double *__restrict__ Dblk, int *bad)
+{
+    __shared__ double Pn[kNB][kDP + 1];   // panel columns
+    __shared__ double Zm[kNB][kDP + 1];   // Z - E_P
+    __shared__ double Rp[kDP][kNB];       // pivot rows of the panel
+    __shared__ int rstep[kNB];            // panel step that chose row i, or -1
+    __shared__ int prow[kNB];             // pivot row of column k
+    __shared__ int invp[kNB];             // column whose pivot row is i
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tr = tid >> 4, tc = tid & 15;
+    double S[8][8];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int r = tr + 32 * a, c = tc + 32 * b;
-            A[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * ld + K + c] : (r == c ? 1.0 : 0.0);
-            X[a][b] = (r == c) ? 1.0 : 0.0;
+        for (int b = 0; b < 8; ++b) {
+            const int r = tr + 16 * a, c = tc + 16 * b;
+            S[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * ld + K + c] : (r == c ? 1.0 : 0.0);
         }
-    // pivot rows already used, as a bit mask per lane pair (rows lane and lane+64)
-    bool used0 = false, used1 = false;
-    if (tc == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) colk[0][tr + 32 * a] = A[a][0];
+    if (tid < kNB) {
+        prow[tid] = -1;
+        invp[tid] = -1;
     }
-    __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        const int buf = k & 1;
-        // every wave finds the pivot: largest unused |a_rk|, lowest row on ties
-        double v0 = (lane < kb && !used0) ? fabs(colk[buf][lane]) : -1.0;
-        double v1 = (lane + 64 < kb && !used1) ? fabs(colk[buf][lane + 64]) : -1.0;
-        double best = v0;
-        int idx = lane;
-        if (v1 > best) { best = v1; idx = lane + 64; }
+    bool used0 = false, used1 = false;  // wave 0: rows lane and lane + 64
+    for (int pnl = 0; pnl < kNB / kDP; ++pnl) {
+        // panel columns 16 pnl + tc are the slots b == pnl
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            double b2 = __shfl_xor(best, o, 64);
-            int i2 = __shfl_xor(idx, o, 64);
-            if (b2 > best || (b2 == best && i2 < idx)) { best = b2; idx = i2; }
-        }
-        const int p = idx;
-        if (lane == (p & 63)) {
-            if (p < 64) used0 = true; else used1 = true;
-        }
-        if (tid == 0) {
-            invp[p] = k;
-            if (!(best > 0.0)) atomicOr(bad, 1);
-        }
-        if (tr == (p & 31)) {
-            const double rd = 1.0 / colk[buf][p];
+        for (int a = 0; a < 8; ++a) {
+            double v = 0.0;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-                if (a == (p >> 5))
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        prowA[buf][tc + 32 * b] = A[a][b] * rd;
-                        prowX[buf][tc + 32 * b] = X[a][b] * rd;
-                    }
+            for (int b = 0; b < 8; ++b)
+                if (b == pnl) v = S[a][b];
+            Pn[tr + 16 * a][tc] = v;
         }
         __syncthreads();
+        if (wave == 0) {
+            double P0[kDP], P1[kDP], Z0[kDP], Z1[kDP];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = tr + 32 * a;
-            const double f = colk[buf][r];
+            for (int c = 0; c < kDP; ++c) {
+                P0[c] = Pn[lane][c];
+                P1[c] = Pn[lane + 64][c];
+                Z0[c] = 0.0;
+                Z1[c] = 0.0;
+            }
+            int step0 = -1, step1 = -1;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = tc + 32 * b;
-                if (r == p) {
-                    A[a][b] = prowA[buf][c];
-                    X[a][b] = prowX[buf][c];
+            for (int t = 0; t < kDP; ++t) {
+                const unsigned long long k0 = used0 ? 0ull : pivot_key(P0[t], lane);
+                const unsigned long long k1 = used1 ? 0ull : pivot_key(P1[t], lane + 64);
+                const unsigned long long kmax = wave_max_u64(umax64(k0, k1));
+                const int p = 255 - (int)(kmax & 255ull);
+                const int owner = p & 63;
+                const bool hi = p >= 64;
+                double pr[kDP], pz[kDP];
+#pragma unroll
+                for (int c = 0; c < kDP; ++c) {
+                    if (c >= t) pr[c] = readlane_f64(hi ? P1[c] : P0[c], owner);
+                    if (c < t) pz[c] = readlane_f64(hi ? Z1[c] : Z0[c], owner);
+                }
+                const double piv = pr[t];
+                if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(bad, 1);
+                const double rp = 1.0 / piv;
+#pragma unroll
+                for (int c = 0; c < kDP; ++c) {
+                    if (c > t) pr[c] *= rp;
+                    if (c < t) pz[c] *= rp;
+                }
+                pz[t] = rp;
+                // row lane
+                if (lane == p) {
+                    used0 = true;
+                    step0 = t;
+#pragma unroll
+                    for (int c = 0; c < kDP; ++c) {
+                        if (c > t) P0[c] = pr[c];
+                        if (c <= t) Z0[c] = pz[c];
+                    }
                 } else {
-                    A[a][b] -= f * prowA[buf][c];
-                    X[a][b] -= f * prowX[buf][c];
+                    const double f = P0[t];
+#pragma unroll
+                    for (int c = 0; c < kDP; ++c) {
+                        if (c > t) P0[c] -= f * pr[c];
+                        if (c <= t) Z0[c] -= f * pz[c];
+                    }
+                }
+                // row lane + 64
+                if (lane + 64 == p) {
+                    used1 = true;
+                    step1 = t;
+#pragma unroll
+                    for (int c = 0; c < kDP; ++c) {
+                        if (c > t) P1[c] = pr[c];
+                        if (c <= t) Z1[c] = pz[c];
+                    }
+                } else {
+                    const double f = P1[t];
+#pragma unroll
+                    for (int c = 0; c < kDP; ++c) {
+                        if (c > t) P1[c] -= f * pr[c];
+                        if (c <= t) Z1[c] -= f * pz[c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kDP; ++c) {
+                Zm[lane][c] = Z0[c] - (step0 == c ? 1.0 : 0.0);
+                Zm[lane + 64][c] = Z1[c] - (step1 == c ? 1.0 : 0.0);
+            }
+            rstep[lane] = step0;
+            rstep[lane + 64] = step1;
+            if (step0 >= 0) prow[kDP * pnl + step0] = lane;
+            if (step1 >= 0) prow[kDP * pnl + step1] = lane + 64;
+        }
+        __syncthreads();
+        // pivot rows (before this panel's transformation) to LDS
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int t = rstep[tr + 16 * a];
+            if (t >= 0)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) Rp[t][tc + 16 * b] = S[a][b];
+        }
+        __syncthreads();
+        // S += (Z - E_P) S[P, :] outside the panel; the panel slots take Z
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int i = tr + 16 * a;
+            double z[kDP];
+#pragma unroll
+            for (int t = 0; t < kDP; ++t) z[t] = Zm[i][t];
+            const double zpanel = z[tc] + (rstep[i] == tc ? 1.0 : 0.0);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b == pnl) {
+                    S[a][b] = zpanel;
+                } else {
+                    double acc = S[a][b];
+#pragma unroll
+                    for (int t = 0; t < kDP; ++t) acc += z[t] * Rp[t][tc + 16 * b];
+                    S[a][b] = acc;
                 }
             }
         }
-        // publish the next pivot column into the other buffer
-        if (k + 1 < kb && tc == ((k + 1) & 31)) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b == ((k + 1) >> 5))
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) colk[buf ^ 1][tr + 32 * a] = A[a][b];
-        }
         __syncthreads();
     }
+    if (tid < kNB && prow[tid] >= 0) invp[prow[tid]] = tid;
+    __syncthreads();
+    // S[i][c] = X[i][p_c] = A^-1[invp(i)][p_c]
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 8; ++a) {
+        const int q = invp[tr + 16 * a];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int r = tr + 32 * a, c = tc + 32 * b;
-            if (r < kb && c < kb) Dblk[invp[r] * kNB + c] = X[a][b];
+        for (int b = 0; b < 8; ++b) {
+            const int col = prow[tc + 16 * b];
+            if (q >= 0 && q < kb && col >= 0 && col < kb) Dblk[q * kNB + col] = S[a][b];
         }
-    for (int q = tid; q < kNB * kNB; q += 1024) {
-        int r = q / kNB, c = q % kNB;
-        if (r >= kb || c >= kb) Dblk[q] = 0.0;
+    }
+    for (int idx = tid; idx < kNB * kNB; idx += 256) {
+        const int r = idx / kNB, c = idx % kNB;
+        if (r >= kb || c >= kb) Dblk[idx] = 0.0;
     }
 }
 
@@ -1357,7 +1471,7 @@ hipError_t gj_inverse_128(int n, int ld, double *M, double *work, int *bad, hipS
     double *Dblk = Trow + (long long)kNB * n;  // kNB x kNB
     for (int K = 0; K < n; K += kNB) {
         const int kb = n - K < kNB ? n - K : kNB;
-        k_gj_diag<<<1, 1024, 0, st>>>(ld, K, kb, M, Dblk, bad);
+        k_gj_diag<<<1, 256, 0, st>>>(ld, K, kb, M, Dblk, bad);
         k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
             n, n, n, ld, kNB, K, kb, M, Ccol, Mrow);
         hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);

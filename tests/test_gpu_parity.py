@@ -252,6 +252,52 @@ def test_nonsymmetric_random_pattern():
     assert abs(ig["iterations"] - it) <= 1
 
 
+def _pivoting_matrix(n, seed):
+    """Scalar CSR: unit diagonal, one entry of 10 per row at a random
+    permutation position inside the row's aligned 128-row block, and weak
+    (<= 0.05) random couplings anywhere.  Elimination in natural order must
+    pivot inside each diagonal block; across blocks it needs none."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for q0 in range(0, n, 128):
+        m = min(128, n - q0)
+        perm = q0 + rng.permutation(m)
+        for i in range(q0, q0 + m):
+            ent = {i: 1.0}
+            j = int(perm[i - q0])
+            ent[j] = ent.get(j, 0.0) + 10.0
+            for jj in rng.integers(0, n, 4):
+                jj = int(jj)
+                ent[jj] = ent.get(jj, 0.0) + rng.uniform(-0.05, 0.05)
+            rows.append(sorted(ent.items()))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([j for r in rows for j, _ in r], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in r])
+    return rp, ci, val.reshape(-1, 1, 1)
+
+
+@pytest.mark.parametrize("n", [600, 129])
+def test_coarse_direct_solve_needs_pivoting(n):
+    """The whole matrix is the coarsest level (several 256-wide panels, ragged
+    last block), so the V-cycle is the direct solve alone, on a matrix whose
+    diagonal is 10x smaller than the largest entry of its row."""
+    rp, ci, vals = _pivoting_matrix(n, 11)
+    announce("pivoting", n)
+    g = msp.Solver(max_coarse=10000)
+    o = O.OracleSolver(max_coarse=10000)
+    g.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    o.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    assert o.nlevels == 1 and g.nlevels == 1
+    Lc = o.level(0)
+    offd = np.abs(Lc["val"][Lc["col_ind"] != np.repeat(np.arange(n), np.diff(Lc["row_ptr"]))])
+    assert offd.max() >= 9.0
+    f = np.random.default_rng(12).uniform(-1, 1, n)
+    assert relerr(to_np(g.vcycle(f)), o.vcycle(f)) <= _coarse_tol(o)
+    g.close()
+    o.close()
+
+
 # --------------------------------------------------------------------------
 # adaptive setup and error handling
 # --------------------------------------------------------------------------
