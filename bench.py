@@ -106,7 +106,7 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
             f"{info['iterations']} it, relres {info['rel_true_residual']:.2e}, "
             f"setup {info['setup_ms']:.2f} ms (rebuild {info['rebuild_ms']:.2f}), "
             f"solve {info['solve_ms']:.2f} ms; phases "
-            + " ".join(f"{v:.1f}" for v in info["phase_ms"][:7]))
+            + " ".join(f"{v:.1f}" for v in info["phase_ms"][:8]))
     torch.cuda.synchronize()
     total_ms = (time.perf_counter() - t0) * 1e3
     return solver, x.clone(), times, total_ms, infos, stream
@@ -233,9 +233,9 @@ def main():
         "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
         "setup_ms": setup_ms, "solve_ms": solve_ms, "iterations": last["iterations"],
         "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "aggregation_host",
-                                    "groups_and_levels", "coarse_inverse_wait",
-                                    "bilu"],
-                                   [round(v, 3) for v in last["phase_ms"][:7]])),
+                                    "level_layouts", "coarse_inverse_wait", "bilu",
+                                    "worker_wait"],
+                                   [round(v, 3) for v in last["phase_ms"][:8]])),
         "rel_true_residual": last["rel_true_residual"],
         "levels": last["level_rows"], "colors": last["n_colors"],
         "bilu_levels": [last["bilu_levels_fwd"], last["bilu_levels_bwd"]],

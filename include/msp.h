@@ -101,11 +101,12 @@ typedef struct {
      * [0] pattern copy and check, [1] value ingest, [2] decoupling,
      * [3] aggregation chain on the host (pairwise passes and Galerkin
      *     products) up to queueing the coarsest-level inverse,
-     * [4] grouping of the smoothed levels and level layouts and uploads
-     *     (while the coarsest inverse runs on the device),
+     * [7] waiting for the host worker threads (groups of the smoothed
+     *     levels, block ILU(0) plan) after the chain,
+     * [4] level layouts and uploads (while the coarsest inverse runs on the
+     *     device),
      * [6] block ILU(0) factorisation and layouts (likewise overlapped),
-     * [5] what remains of the coarsest-level inverse after [4] and [6],
-     * [7] unused */
+     * [5] what remains of the coarsest-level inverse after [4], [6], [7] */
     double phase_ms[8];
 } msp_info;
 

@@ -274,10 +274,72 @@ void *alloc_vec(msp_ctx *c, long long n)
     return c->dalloc(sizeof(T) * (size_t)std::max<long long>(n, 1), c->allocB);
 }
 
-void build_level_device(msp_ctx *c, int l, const Hierarchy &H)
+// Host layout of a smoothed level: positions (color 1 rows ascending, then
+// color 2, ... -- the PGS-MC groups), the sliced layout of the off-diagonal
+// entries in position space and the packed values in the preconditioner
+// precision.  Pure host work on plain arrays, so it runs on worker threads.
+struct LevelLayout {
+    std::vector<int> perm, iperm, seg_row;
+    SellLayout lay;
+    std::vector<double> v64, d64;
+    std::vector<float> v32, d32;
+};
+
+void level_layout(int n, const int *rp, const int *ci, const double *val,
+                  const std::vector<int> &color, int g, bool fp32, LevelLayout &O)
+{
+    O.perm.assign(n, 0);
+    O.iperm.assign(n, 0);
+    O.seg_row.assign(g + 1, 0);
+    {
+        std::vector<int> cnt(g + 2, 0);
+        for (int i = 0; i < n; ++i) ++cnt[color[i]];
+        for (int q = 1; q <= g; ++q) O.seg_row[q] = O.seg_row[q - 1] + cnt[q];
+        std::vector<int> f(O.seg_row.begin(), O.seg_row.end() - 1);
+        for (int i = 0; i < n; ++i) {
+            int t = f[color[i] - 1]++;
+            O.perm[i] = t;
+            O.iperm[t] = i;
+        }
+    }
+    std::vector<int> ent_ptr(n + 1, 0), ent_col, ent_src;
+    std::vector<double> diag(n, 0.0);
+    ent_col.reserve(rp[n]);
+    ent_src.reserve(rp[n]);
+    for (int t = 0; t < n; ++t) {
+        int i = O.iperm[t];
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            int j = ci[k];
+            if (j == i) {
+                diag[t] = val[k];
+            } else {
+                ent_col.push_back(O.perm[j]);
+                ent_src.push_back(k);
+            }
+        }
+        ent_ptr[t + 1] = (int)ent_col.size();
+    }
+    build_sell(n, O.seg_row, ent_ptr, ent_col, ent_src, O.lay);
+    const long long sl = O.lay.slot_lanes;
+    if (fp32) {
+        O.v32.assign(sl, 0.0f);
+        O.d32.resize(n);
+        for (long long q = 0; q < sl; ++q)
+            if (O.lay.src[q] >= 0) O.v32[q] = (float)val[O.lay.src[q]];
+        for (int t = 0; t < n; ++t) O.d32[t] = (float)diag[t];
+    } else {
+        O.v64.assign(sl, 0.0);
+        for (long long q = 0; q < sl; ++q)
+            if (O.lay.src[q] >= 0) O.v64[q] = val[O.lay.src[q]];
+        O.d64 = std::move(diag);
+    }
+}
+
+// Device arrays of level l (its layout computed by level_layout unless it is
+// the coarsest level, whose positions are the natural order).
+void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
 {
     Level &L = c->lev[l];
-    const bool last = (l == (int)H.A.size() - 1);
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
     L.f = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
     L.x = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
@@ -290,55 +352,17 @@ void build_level_device(msp_ctx *c, int l, const Hierarchy &H)
         return;
     }
     L.r = c->dalloc(tsz * std::max(L.n, 1), c->allocB);
-    // positions: color 1 rows ascending, then color 2, ... (PGS-MC groups)
-    L.perm.assign(L.n, 0);
-    L.iperm.clear();
-    L.iperm.reserve(L.n);
-    L.seg_row.assign(L.g + 1, 0);
-    {
-        std::vector<int> cnt(L.g + 2, 0);
-        for (int i = 0; i < L.n; ++i) ++cnt[L.color[i]];
-        for (int g = 1; g <= L.g; ++g) L.seg_row[g] = L.seg_row[g - 1] + cnt[g];
-        std::vector<int> f(L.seg_row.begin(), L.seg_row.end() - 1);
-        L.iperm.assign(L.n, 0);
-        for (int i = 0; i < L.n; ++i) {
-            int t = f[L.color[i] - 1]++;
-            L.perm[i] = t;
-            L.iperm[t] = i;
-        }
-    }
-    std::vector<int> ent_ptr(L.n + 1, 0), ent_col, ent_src;
-    std::vector<double> diag(L.n, 0.0);
-    ent_col.reserve(L.A.ci.size());
-    ent_src.reserve(L.A.ci.size());
-    for (int t = 0; t < L.n; ++t) {
-        int i = L.iperm[t];
-        for (int k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k) {
-            int j = L.A.ci[k];
-            if (j == i) {
-                diag[t] = L.A.val[k];
-            } else {
-                ent_col.push_back(L.perm[j]);
-                ent_src.push_back(k);
-            }
-        }
-        ent_ptr[t + 1] = (int)ent_col.size();
-    }
-    build_sell(L.n, L.seg_row, ent_ptr, ent_col, ent_src, L.S.lay);
+    L.perm = std::move(lay->perm);
+    L.iperm = std::move(lay->iperm);
+    L.seg_row = std::move(lay->seg_row);
+    L.S.lay = std::move(lay->lay);
     upload_sell(c, L.S, c->allocB);
-    const long long sl = L.S.lay.slot_lanes;
-    std::vector<double> v64(sl, 0.0);
-    for (long long q = 0; q < sl; ++q)
-        if (L.S.lay.src[q] >= 0) v64[q] = L.A.val[L.S.lay.src[q]];
     if (c->fp32()) {
-        std::vector<float> v32(sl), d32(L.n);
-        for (long long q = 0; q < sl; ++q) v32[q] = (float)v64[q];
-        for (int t = 0; t < L.n; ++t) d32[t] = (float)diag[t];
-        L.val32 = c->upload(v32, c->allocB);
-        L.diag32 = c->upload(d32, c->allocB);
+        L.val32 = c->upload(lay->v32, c->allocB);
+        L.diag32 = c->upload(lay->d32, c->allocB);
     } else {
-        L.val64 = c->upload(v64, c->allocB);
-        L.diag64 = c->upload(diag, c->allocB);
+        L.val64 = c->upload(lay->v64, c->allocB);
+        L.diag64 = c->upload(lay->d64, c->allocB);
     }
     L.perm_d = c->upload(L.perm, c->allocB);
     L.iperm_d = c->upload(L.iperm, c->allocB);
@@ -646,39 +670,74 @@ void rebuild_B(msp_ctx *c, const double *vals)
         std::vector<int> color;
         int g = 0;
     };
+    struct LevelWork {
+        Groups G;
+        LevelLayout lay;
+    };
+    const bool fp32 = c->fp32();
+    // H is declared before every future that reads its arrays, so those are
+    // joined first on every exit; the level arrays only move (never copy) as
+    // the level list grows.
+    Hierarchy H;
+    static_assert(std::is_nothrow_move_constructible<Csr>::value,
+                  "level arrays must move, not copy, when the level list grows");
+    const double *a0val = A0.val.data();
+    const bool level0_smoothed = n > c->opt.max_coarse;
     std::shared_future<Groups> groups0 = std::async(std::launch::async, [c]() {
         Groups G;
         Adjacency adj = build_adjacency(c->n, c->rp.data(), c->ci.data());
         G.g = vertices_grouping(adj, G.color);
         return G;
     }).share();
+    std::future<LevelLayout> layout0;
+    if (level0_smoothed)
+        layout0 = std::async(std::launch::async, [c, groups0, a0val, fp32]() {
+            const Groups &G = groups0.get();
+            LevelLayout O;
+            level_layout(c->n, c->rp.data(), c->ci.data(), a0val, G.color, G.g, fp32, O);
+            return O;
+        });
     BiluPlan plan;
     std::future<void> planned = std::async(std::launch::async, [c, &plan, groups0]() {
         const Groups &G = groups0.get();
         bilu_plan(c, G.color, G.g, c->bilu, plan);
     });
-    Hierarchy H;
-    int st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false);
+    // groups and layout of each coarser smoothed level start as soon as the
+    // chain has produced it
+    std::vector<std::future<LevelWork>> work(MSP_MAX_LEVELS);
+    int st = build_hierarchy(
+        std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
+        [&work, fp32](int l, int nl, const int *rp, const int *ci, const double *val) {
+            if (l == 0) return;  // level 0: the pattern's groups above
+            work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32]() {
+                LevelWork W;
+                Adjacency adj = build_adjacency(nl, rp, ci);
+                W.G.g = vertices_grouping(adj, W.G.color);
+                level_layout(nl, rp, ci, val, W.G.color, W.G.g, fp32, W.lay);
+                return W;
+            });
+        });
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
     const int nlev = (int)H.A.size();
-    std::vector<std::future<Groups>> groups(nlev);
-    for (int l = 1; l + 1 < nlev; ++l)
-        groups[l] = std::async(std::launch::async, [&H, l]() {
-            Groups G;
-            const Csr &A = H.A[l];
-            Adjacency adj = build_adjacency(A.n, A.rp.data(), A.ci.data());
-            G.g = vertices_grouping(adj, G.color);
-            return G;
-        });
     launch_coarse(c, H.A.back(), tmp);
     phase(3);
     c->lev.resize(nlev);
+    std::vector<LevelLayout> lays(nlev);
     for (int l = 0; l + 1 < nlev; ++l) {
-        Groups G = l == 0 ? groups0.get() : groups[l].get();
+        Groups G;
+        if (l == 0) {
+            G = groups0.get();
+            lays[0] = layout0.get();
+        } else {
+            LevelWork W = work[l].get();
+            G = std::move(W.G);
+            lays[l] = std::move(W.lay);
+        }
         c->lev[l].color = std::move(G.color);
         c->lev[l].g = G.g;
     }
+    phase(7);
     for (int l = 0; l < nlev; ++l) {
         Level &L = c->lev[l];
         L.A = std::move(H.A[l]);
@@ -688,10 +747,11 @@ void rebuild_B(msp_ctx *c, const double *vals)
     for (int l = 0; l + 1 < nlev; ++l) c->lev[l].nc = c->lev[l + 1].A.n;
     {
         CopyStreamScope on_side(c, c->side);
-        for (int l = 0; l < nlev; ++l) build_level_device(c, l, H);
+        for (int l = 0; l < nlev; ++l) build_level_device(c, l, l == nlev - 1, &lays[l]);
         link_levels(c);
         phase(4);
         planned.get();
+        phase(7);
         bilu_device(c, vals, plan, tmp);
     }
     HIPCHK(hipEventRecord(c->ev_side, c->side));

@@ -60,7 +60,38 @@ int check_pattern(int n, const int *rp, const int *ci, long long nnz)
 
 Adjacency build_adjacency(int n, const int *rp, const int *ci)
 {
-    // count both directions of every off-diagonal entry, then sort + dedupe
+    // A structurally symmetric pattern is its own symmetrisation: the
+    // neighbours of i are row i without the diagonal (already ascending).
+    {
+        const int parts = host_parts(n);
+        std::vector<unsigned char> miss(parts, 0);
+        for_chunks(n, parts, [&](int lo, int hi, int t) {
+            for (int i = lo; i < hi && !miss[t]; ++i)
+                for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                    const int j = ci[k];
+                    if (!std::binary_search(ci + rp[j], ci + rp[j + 1], i)) {
+                        miss[t] = 1;
+                        break;
+                    }
+                }
+        });
+        bool symmetric = true;
+        for (unsigned char m : miss) symmetric = symmetric && !m;
+        if (symmetric) {
+            Adjacency G;
+            G.n = n;
+            G.ptr.assign(n + 1, 0);
+            G.nbr.reserve((size_t)rp[n]);
+            for (int i = 0; i < n; ++i) {
+                for (int k = rp[i]; k < rp[i + 1]; ++k)
+                    if (ci[k] != i) G.nbr.push_back(ci[k]);
+                G.ptr[i + 1] = (int)G.nbr.size();
+            }
+            return G;
+        }
+    }
+    // otherwise count both directions of every off-diagonal entry, then sort
+    // and drop duplicates
     std::vector<int> cnt(n + 1, 0);
     for (int i = 0; i < n; ++i)
         for (int k = rp[i]; k < rp[i + 1]; ++k)
@@ -101,9 +132,29 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         int da = G.degree(a), db = G.degree(b);
         return da != db ? da > db : a < b;
     });
-    // candidate key: larger degree first, then smaller index (max-heap on the key)
-    auto key = [&](int v) -> unsigned long long {
-        return ((unsigned long long)(unsigned)G.degree(v) << 32) | (unsigned)(0x7fffffff - v);
+    // Candidates W^ are taken in the same priority, i.e. smallest position in
+    // `order` first: a two-level bit set over positions (words of 64
+    // positions and a summary bit per word) gives that position quickly.
+    std::vector<int> pos(n);
+    for (int q = 0; q < n; ++q) pos[order[q]] = q;
+    const int nw = (n + 63) / 64, ns = (nw + 63) / 64;
+    std::vector<unsigned long long> bits(nw, 0ull), summ(ns, 0ull);
+    int nqueued = 0;
+    auto hat_push = [&](int v) {
+        const int q = pos[v];
+        bits[q >> 6] |= 1ull << (q & 63);
+        summ[q >> 12] |= 1ull << ((q >> 6) & 63);
+        ++nqueued;
+    };
+    auto hat_pop = [&]() -> int {  // requires nqueued > 0
+        int s = 0;
+        while (summ[s] == 0ull) ++s;
+        const int w = (s << 6) + __builtin_ctzll(summ[s]);
+        const int b = __builtin_ctzll(bits[w]);
+        bits[w] &= bits[w] - 1;
+        if (bits[w] == 0ull) summ[s] &= ~(1ull << (w & 63));
+        --nqueued;
+        return order[(w << 6) + b];
     };
     // open: still in V; queued: already a second-ring candidate of this group;
     // scanned: neighbourhood already enumerated for this group.  A vertex never
@@ -120,13 +171,14 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             scanned[i] = 0;
             avail += open[i];
         }
-        std::priority_queue<unsigned long long> hat;
+        std::fill(bits.begin(), bits.end(), 0ull);
+        std::fill(summ.begin(), summ.end(), 0ull);
+        nqueued = 0;
         size_t cursor = 0;
         while (avail > 0) {
             int v = -1;
-            while (!hat.empty()) {  // second-ring candidates W^ that are still in V
-                int t = 0x7fffffff - (int)(hat.top() & 0xffffffffULL);
-                hat.pop();
+            while (nqueued > 0) {  // second-ring candidates W^ that are still in V
+                int t = hat_pop();
                 if (open[t]) { v = t; break; }
             }
             if (v < 0) {
@@ -149,7 +201,7 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
                     int w = G.nbr[t];
                     if (open[w] && !queued[w]) {
                         queued[w] = 1;
-                        hat.push(key(w));
+                        hat_push(w);
                     }
                 }
             }
@@ -362,7 +414,7 @@ int color_level(const Csr &A, std::vector<int> &color)
 }
 
 int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                    bool with_colors)
+                    bool with_colors, const LevelCallback &on_smoothed)
 {
     H = Hierarchy();
     H.A.push_back(std::move(A0));
@@ -371,6 +423,7 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         bool last = cur.n <= max_coarse || l == max_levels - 1 ||
                     (l > 0 && (double)cur.n > 0.9 * (double)H.A[l - 1].n);
         if (last) break;
+        if (on_smoothed) on_smoothed(l, cur.n, cur.rp.data(), cur.ci.data(), cur.val.data());
         if (with_colors) {
             std::vector<int> color;
             H.ncolors.push_back(color_level(cur, color));

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace msp {
@@ -50,9 +51,14 @@ struct Hierarchy {
     std::vector<int> ncolors;
 };
 // with_colors = false leaves color/ncolors empty (the groups can then be
-// computed per level with color_level, e.g. on other threads).
+// computed per level with color_level, e.g. on other threads); on_smoothed
+// (if set) is called with (l, n, row_ptr, col_ind, val) as soon as level l is
+// known to be a smoothed level.  The pointed-to arrays stay valid while H
+// lives; H.A grows meanwhile, so a callee must not keep a reference to the
+// Csr itself.
+using LevelCallback = std::function<void(int, int, const int *, const int *, const double *)>;
 int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                    bool with_colors = true);
+                    bool with_colors = true, const LevelCallback &on_smoothed = nullptr);
 // groups of Alg. 4.2 on one level: fills color, returns g
 int color_level(const Csr &A, std::vector<int> &color);
 

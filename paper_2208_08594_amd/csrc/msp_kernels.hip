@@ -1059,59 +1059,87 @@ __global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int ncol, int ld,
     M[(long long)(K + t) * ld + j] = Trow[(long long)t * n + j];
 }
 
-// C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  Each
-// 256-thread work-group owns a 128x128 tile of C; each wave a 64x64 quadrant
-// of 4x4 v_mfma_f64_16x16x4 blocks (64 accumulators per lane).  A and B are
-// staged through LDS in k-chunks of 32, double buffered: the next chunk is
-// fetched into registers while the current one is multiplied.
+// C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  A
+// work-group owns a TM x TN tile of C, its WM x WN waves a (TM/WM) x (TN/WN)
+// block each, made of 16x16 v_mfma_f64_16x16x4 blocks.  A and B are staged
+// through LDS in k-chunks of 16, double buffered: the next chunk is fetched
+// into registers while the current one is multiplied.
 // Lane layout of the 16x16x4 FP64 MFMA: A[i][k] in lane i + 16k, B[k][j] in
 // lane j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (the output rows of
 // one lane are interleaved by 4, unlike the FP32 variant).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kGT = 128, kGK = 16, kGThreads = 512;
+constexpr int kGK = 16;
 
-// two work-groups per CU (68 KB of LDS each, <= 128 registers per lane) so one
-// work-group's C read-modify-write overlaps the other's matrix-core work
-__global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dgemm(int Mr, int Nc, int Kd,
-                                                     const double *__restrict__ A, int lda,
-                                                     const double *__restrict__ B, int ldb,
-                                                     double *__restrict__ C, int ldc,
-                                                     double alpha, double beta)
+// Tile (ti, tj) of work-group `wg` (1-D grid) so that each XCD gets a compact
+// region: the grid's work-groups go round-robin to the 8 XCDs, so XCD x runs
+// a contiguous segment of a column-band order (bands of ceil(Tx/8) tile
+// columns, row-major inside a band), and the A row-blocks and B column-blocks
+// its concurrent tiles share stay in its L2.
+__device__ inline void xcd_tile(int wg, int Ty, int Tx, int &ti, int &tj)
 {
-    __shared__ double As[2][kGT][kGK + 1];
-    __shared__ double Bs[2][kGK][kGT + 1];
-    const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+    constexpr int kXcd = 8;
+    const int N = Ty * Tx;
+    const int q = N / kXcd, r = N % kXcd;
+    const int x = wg % kXcd, k = wg / kXcd;
+    const int g = x * q + (x < r ? x : r) + k;  // position in the band order
+    const int W = (Tx + kXcd - 1) / kXcd;
+    const int band = g / (W * Ty);
+    const int c0 = band * W;
+    const int w = Tx - c0 < W ? Tx - c0 : W;
+    const int gl = g - band * W * Ty;
+    ti = gl / w;
+    tj = c0 + gl % w;
+}
+
+template <int TM, int TN, int WM, int WN>
+__device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restrict__ A, int lda,
+                                  const double *__restrict__ B, int ldb, double *__restrict__ C,
+                                  int ldc, double alpha, double beta)
+{
+    constexpr int T = 64 * WM * WN;         // threads
+    constexpr int FM = TM / WM / 16, FN = TN / WN / 16;
+    constexpr int AR = T / kGK;             // A rows fetched per pass
+    constexpr int BK = T / TN;              // B k-rows fetched per pass
+    static_assert(TM % AR == 0 && kGK % BK == 0, "fetch mapping");
+    constexpr int AU = TM / AR, BU = kGK / BK;
+    __shared__ double As[2][TM][kGK + 1];
+    __shared__ double Bs[2][kGK][TN + 1];
+    int ti, tj;
+    xcd_tile(blockIdx.x, (Mr + TM - 1) / TM, (Nc + TN - 1) / TN, ti, tj);
+    const int i0 = ti * TM, j0 = tj * TN;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;  // 2 x 4 waves of 64 x 32
+    const int wr = (wave / WN) * (TM / WM), wc = (wave % WN) * (TN / WN);
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 acc[4][2];
+    dbl4 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // per-thread fetch slots: A rows r0 + 32u (column ac), B rows bk0 + 4u (column bj)
-    const int ac = tid & 15, r0 = tid >> 4, bk0 = tid >> 7;
-    const int bj = j0 + (tid & 127);
+        for (int b = 0; b < FN; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // per-thread fetch slots: A rows r0 + AR u (column ac), B k-rows bk0 + BK u
+    // (column bj)
+    const int ac = tid % kGK, r0 = tid / kGK, bk0 = tid / TN;
+    const int bj = j0 + tid % TN;
     const bool bj_ok = bj < Nc;
     const double *pa = A + (long long)(i0 + r0) * lda + ac;
     const double *pb = B + (bj_ok ? bj : 0);
-    const int arows = Mr - i0 - r0;  // row r0 + 32u valid iff 32u < arows
-    double ra[4], rb[4];
+    const int arows = Mr - i0 - r0;  // row r0 + AR u valid iff AR u < arows
+    double ra[AU], rb[BU];
     auto fetch = [&](int k0) {
         const bool ak_ok = k0 + ac < Kd;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ra[u] = (32 * u < arows && ak_ok) ? pa[(long long)(32 * u) * lda + k0] : 0.0;
-            const int kk = k0 + bk0 + 4 * u;
+        for (int u = 0; u < AU; ++u)
+            ra[u] = (AR * u < arows && ak_ok) ? pa[(long long)(AR * u) * lda + k0] : 0.0;
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+            const int kk = k0 + bk0 + BK * u;
             rb[u] = (bj_ok && kk < Kd) ? pb[(long long)kk * ldb] : 0.0;
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            As[buf][r0 + 32 * u][ac] = ra[u];
-            Bs[buf][bk0 + 4 * u][tid & 127] = rb[u];
-        }
+        for (int u = 0; u < AU; ++u) As[buf][r0 + AR * u][ac] = ra[u];
+#pragma unroll
+        for (int u = 0; u < BU; ++u) Bs[buf][bk0 + BK * u][tid % TN] = rb[u];
     };
     const int nchunk = (Kd + kGK - 1) / kGK;
     fetch(0);
@@ -1122,35 +1150,59 @@ __global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4, 4)
         if (ch + 1 < nchunk) fetch((ch + 1) * kGK);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 4) {
-            double av[4], bv[2];
+            double av[FM], bv[FN];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[buf][wr + a * 16 + li][kk + lk];
+            for (int a = 0; a < FM; ++a) av[a] = As[buf][wr + a * 16 + li][kk + lk];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + lk][wc + b * 16 + li];
+            for (int b = 0; b < FN; ++b) bv[b] = Bs[buf][kk + lk][wc + b * 16 + li];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < FN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = i0 + wr + a * 16 + lk + 4 * r;
             if (i >= Mr) continue;
             double *crow = C + (long long)i * ldc + j0 + wc + li;
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < FN; ++b) {
                 if (j0 + wc + b * 16 + li >= Nc) continue;
                 double *c = crow + b * 16;
                 const double v = alpha * acc[a][b][r];
                 *c = (beta != 0.0) ? v + beta * *c : v;
             }
         }
+}
+
+// Large products: 128x128 tiles, 8 waves of 64x32; two work-groups per CU (68
+// KB of LDS each, <= 128 registers per lane) so one work-group's C
+// read-modify-write overlaps the other's matrix-core work.
+constexpr int kGT = 128, kGThreads = 512;
+__global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dgemm(
+    int Mr, int Nc, int Kd, const double *__restrict__ A, int lda, const double *__restrict__ B,
+    int ldb, double *__restrict__ C, int ldc, double alpha, double beta)
+{
+    dgemm_tile<kGT, kGT, 2, 4>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
+}
+
+// Small products (too few 128x128 tiles to fill the chip): 64x64 tiles, 4
+// waves of 32x32, so four times as many work-groups share the work.
+constexpr int kGTs = 64, kGThreadsS = 256;
+constexpr long long kDgemmBigTiles = 512;  // two 128x128 tiles per compute unit
+__global__ __launch_bounds__(kGThreadsS) void k_dgemm_s(int Mr, int Nc, int Kd,
+                                                      const double *__restrict__ A, int lda,
+                                                      const double *__restrict__ B, int ldb,
+                                                      double *__restrict__ C, int ldc,
+                                                      double alpha, double beta)
+{
+    dgemm_tile<kGTs, kGTs, 2, 2>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
 }
 
 }  // namespace
@@ -1450,11 +1502,21 @@ hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, con
     return hipGetLastError();
 }
 
+
 hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
                         double *C, int ldc, double alpha, double beta, hipStream_t st)
 {
-    dim3 grid((unsigned)((Nc + kGT - 1) / kGT), (unsigned)((Mr + kGT - 1) / kGT));
-    k_dgemm<<<grid, kGThreads, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta);
+    if (Mr <= 0 || Nc <= 0) return hipSuccess;
+    const long long big_tiles = (long long)((Nc + kGT - 1) / kGT) * ((Mr + kGT - 1) / kGT);
+    if (big_tiles >= kDgemmBigTiles) {
+        k_dgemm<<<(unsigned)big_tiles, kGThreads, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc,
+                                                          alpha, beta);
+    } else {
+        const long long tiles =
+            (long long)((Nc + kGTs - 1) / kGTs) * ((Mr + kGTs - 1) / kGTs);
+        k_dgemm_s<<<(unsigned)tiles, kGThreadsS, 0, st>>>(Mr, Nc, Kd, A, lda, B, ldb, C, ldc,
+                                                         alpha, beta);
+    }
     return hipGetLastError();
 }
 
