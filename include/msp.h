@@ -56,7 +56,8 @@ extern "C" {
 /* Solver options.  msp_default_options() fills the paper's settings
  * (Sec. 5: GMRES(30), MaxIt 1000, coarsest space of at most 10000 unknowns)
  * with mu = 0 (standard MSP, every system rebuilds, Sec. 3.2), an FP64
- * preconditioner and the multi-color block ILU(0) order. */
+ * preconditioner, the multi-color block ILU(0) order, one PGS-MC sweep
+ * before and after each coarse correction, and block ILU(0) as R. */
 typedef struct {
     int mu;           /* adaptive-setup threshold It^(i-1) <= mu => reuse (Sec. 3.2) */
     int restart;      /* m of FGMRES(m), 1..200 */
@@ -79,6 +80,16 @@ typedef struct {
     void *(*dev_alloc)(size_t bytes, void *user);
     void (*dev_free)(void *ptr, void *user);
     void *alloc_user;
+    /* AMG smoother (Table 1 of Sec. 6 compares them): 0 (default) PGS-MC, the
+     * multi-color Gauss-Seidel of Alg. 4.3; 1 point Jacobi,
+     * x <- x + jacobi_weight D^-1 (f - A x) (the PJAC variant) */
+    int smoother;
+    int nu_pre;       /* smoothing sweeps before the coarse correction, 0..8 (default 1) */
+    int nu_post;      /* ... after it, 0..8 (default 1); Gauss-Seidel runs its colors
+                         forward before and backward after */
+    int full_smoother; /* relaxation operator R of the last stage (Sec. 3.1): 0 (default)
+                          block ILU(0), 1 block Jacobi (z_c = A_cc^-1 r_c) */
+    double jacobi_weight; /* weight of the Jacobi correction, (0, 2] (default 1) */
 } msp_options;
 
 typedef struct {

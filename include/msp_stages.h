@@ -28,14 +28,15 @@ int msp_stage_precond(msp_ctx *ctx, const double *v, double *z);
  * in natural cell order (converted to the preconditioner precision inside). */
 int msp_stage_vcycle(msp_ctx *ctx, const double *f, double *e);
 
-/* One multi-color Gauss-Seidel sweep (Alg. 4.3) on AMG level `level`
- * (0 <= level < n_levels-1): colors 1..g if forward != 0, else g..1.
- * f: double[n_level] read; x: double[n_level] updated in place; natural order
- * of that level. */
+/* One sweep of the configured AMG smoother on level `level`
+ * (0 <= level < n_levels-1): multi-color Gauss-Seidel (Alg. 4.3), colors
+ * 1..g if forward != 0, else g..1; or one weighted point-Jacobi sweep
+ * (forward ignored).  f: double[n_level] read; x: double[n_level] updated in
+ * place; natural order of that level. */
 int msp_stage_smooth(msp_ctx *ctx, int level, const double *f, double *x, int forward);
 
-/* z = (LU)^{-1} r with the block ILU(0) factors (the R stage of eq. MSP).
- * r, z: double[n*b]. */
+/* The R stage of eq. MSP on its own: z = (LU)^{-1} r with the block ILU(0)
+ * factors, or z_c = A_cc^{-1} r_c with block Jacobi.  r, z: double[n*b]. */
 int msp_stage_bilu(msp_ctx *ctx, const double *r, double *z);
 
 /* Shape of AMG level `level` (host outputs, any may be NULL): rows, stored
@@ -63,10 +64,12 @@ int msp_stage_get_omega(msp_ctx *ctx, double *omega);
  * regeneration: F double[nnzb*b*b] (strictly lower blocks L, unit diagonal
  * implied; upper blocks U; diagonal slots hold the factored pivot block) and
  * Dinv double[n*b*b] (inverted pivot blocks); HOST pointers, either may be
- * NULL. */
+ * NULL.  With block Jacobi as R, F is left untouched and Dinv receives the
+ * inverted diagonal blocks A_cc^{-1}. */
 int msp_stage_get_bilu(msp_ctx *ctx, double *F, double *Dinv);
 
-/* FP32 copies of the BILU factors (HOST, same layout); precond_fp32 only. */
+/* FP32 copies of the BILU factors (HOST, same layout; block Jacobi: Dinv
+ * only); precond_fp32 only. */
 int msp_stage_get_bilu_f32(msp_ctx *ctx, float *F, float *Dinv);
 
 /* Stage ids for msp_stage_repeat. */

@@ -743,6 +743,14 @@ void or_bilu0_solve(int n, int b, const int *rp, const int *ci, const double *F,
     free(ord);
 }
 
+/* One weighted point-Jacobi sweep x_out = x + w D^{-1} (f - A x): every row */
+/* reads only the incoming x.                                                 */
+int or_jacobi_sweep(int n, const int *rp, const int *ci, const double *val, double w,
+                    const double *f, const double *x, double *x_out)
+{
+    return jacobi_sweep_f64(n, rp, ci, val, w, f, x, x_out);
+}
+
 void or_gs_sweep(int n, const int *rp, const int *ci, const double *val, const int *color, int g,
                  const double *f, double *x, int forward)
 {
@@ -772,6 +780,10 @@ typedef struct {
 typedef struct {
     /* options */
     int mu, restart, max_iter, max_coarse, precond_fp32, bilu_order;
+    int smoother;          /* 0: PGS-MC (Alg. 4.3), 1: point Jacobi */
+    double jacobi_weight;  /* weight of the Jacobi correction */
+    int nu_pre, nu_post;   /* smoothing sweeps before / after the coarse correction */
+    int full_smoother;     /* R stage: 0 block ILU(0), 1 block Jacobi */
     /* current matrix (used by the Krylov SpMV and the pressure-column residual) */
     int n, b, p;
     long nnzb;
@@ -790,16 +802,24 @@ typedef struct {
     int *Brp, *Bci, *Bord;
     double *F, *Dinv;
     float *F32, *Dinv32;
+    double *Djac;  /* block Jacobi: inverses of the diagonal blocks A_cc */
+    float *Djac32;
     /* adaptive state */
     int it_prev, setup_calls, solves;
 } or_ctx;
 
 or_ctx *or_create(int mu, int restart, int max_iter, int max_coarse, int precond_fp32,
-                  int bilu_order)
+                  int bilu_order, int smoother, double jacobi_weight, int nu_pre, int nu_post,
+                  int full_smoother)
 {
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     if (!c)
         return NULL;
+    c->smoother = smoother;
+    c->jacobi_weight = jacobi_weight;
+    c->nu_pre = nu_pre;
+    c->nu_post = nu_post;
+    c->full_smoother = full_smoother;
     c->mu = mu;
     c->restart = restart;
     c->max_iter = max_iter;
@@ -821,8 +841,10 @@ static void free_B(or_ctx *c)
     c->nlev = 0;
     free(c->coarse_dense); free(c->LU); free(c->piv);
     free(c->Brp); free(c->Bci); free(c->Bord); free(c->F); free(c->Dinv); free(c->F32); free(c->Dinv32);
+    free(c->Djac); free(c->Djac32);
     c->omega = NULL; c->coarse_dense = NULL; c->LU = NULL; c->piv = NULL;
     c->Brp = NULL; c->Bci = NULL; c->Bord = NULL; c->F = NULL; c->Dinv = NULL; c->F32 = NULL; c->Dinv32 = NULL;
+    c->Djac = NULL; c->Djac32 = NULL;
     c->have_lu = 0;
     c->has_B = 0;
 }
@@ -997,9 +1019,23 @@ int or_setup(or_ctx *c, int n, int b, int p, const int *rp, const int *ci, const
         for (int t = 0; t < n; ++t)
             c->Bord[t] = t;
     }
-    st = or_bilu0_factor_ordered(n, b, rp, ci, vals, c->Bord, c->F, c->Dinv);
-    if (st != OR_OK)
-        return st;
+    if (c->full_smoother == 1) {
+        /* block Jacobi: the inverse of every diagonal block, as in the block */
+        /* ILU(0) pivot inversions                                           */
+        c->Djac = (double *)malloc(sizeof(double) * (size_t)n * b * b);
+        if (!c->Djac)
+            return OR_ERR_NOMEM;
+        for (int cc = 0; cc < n; ++cc) {
+            int kd = find_col(rp, ci, cc, cc);
+            st = block_inverse(b, vals + (long)kd * b * b, c->Djac + (long)cc * b * b);
+            if (st != OR_OK)
+                return st;
+        }
+    } else {
+        st = or_bilu0_factor_ordered(n, b, rp, ci, vals, c->Bord, c->F, c->Dinv);
+        if (st != OR_OK)
+            return st;
+    }
     if (c->precond_fp32) {
         /* O13: FP32 copies by IEEE round-to-nearest-even of the FP64 setup */
         for (int l = 0; l < c->nlev; ++l) {
@@ -1007,9 +1043,14 @@ int or_setup(or_ctx *c, int n, int b, int p, const int *rp, const int *ci, const
             L->val32 = round_f32(L->val, L->rp[L->n]);
             if (!L->val32) return OR_ERR_NOMEM;
         }
-        c->F32 = round_f32(c->F, nnzb * b * b);
-        c->Dinv32 = round_f32(c->Dinv, (long)n * b * b);
-        if (!c->F32 || !c->Dinv32) return OR_ERR_NOMEM;
+        if (c->full_smoother == 1) {
+            c->Djac32 = round_f32(c->Djac, (long)n * b * b);
+            if (!c->Djac32) return OR_ERR_NOMEM;
+        } else {
+            c->F32 = round_f32(c->F, nnzb * b * b);
+            c->Dinv32 = round_f32(c->Dinv, (long)n * b * b);
+            if (!c->F32 || !c->Dinv32) return OR_ERR_NOMEM;
+        }
     }
     c->Bn = n; c->Bb = b; c->Bp = p; c->Bnnzb = nnzb;
     c->has_B = 1;
@@ -1075,6 +1116,7 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #define APCOL(c, q, k) ((c)->A[(long)(q) * (c)->b * (c)->b + (long)(k) * (c)->b + (c)->p])
 #define BILU_F(c) ((c)->F)
 #define BILU_D(c) ((c)->Dinv)
+#define DJAC(c) ((c)->Djac)
 #include "oracle_cycle.inc"
 #undef REAL
 #undef SFX
@@ -1082,12 +1124,14 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #undef APCOL
 #undef BILU_F
 #undef BILU_D
+#undef DJAC
 #define REAL float
 #define SFX(name) name##_f32
 #define LEVVAL(L) ((L)->val32)
 #define APCOL(c, q, k) ((c)->A32[(long)(q) * (c)->b + (k)])
 #define BILU_F(c) ((c)->F32)
 #define BILU_D(c) ((c)->Dinv32)
+#define DJAC(c) ((c)->Djac32)
 #include "oracle_cycle.inc"
 #undef REAL
 #undef SFX
@@ -1095,6 +1139,7 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #undef APCOL
 #undef BILU_F
 #undef BILU_D
+#undef DJAC
 
 /* z = B v, the multiplicative two-stage preconditioner (Alg. 3.1, stages P  */
 /* then R, initial w = 0) in the reduced form                                  */
@@ -1117,11 +1162,16 @@ int or_vcycle(or_ctx *c, const double *f, double *x)
     return vcycle_f64(c, 0, f, x);
 }
 
+/* The R stage on its own (FP64): z = (LU)^{-1} r for block ILU(0), or       */
+/* z_c = A_cc^{-1} r_c for block Jacobi.                                       */
 int or_bilu_apply(or_ctx *c, const double *r, double *z)
 {
     if (!c->has_B)
         return OR_ERR_STATE;
-    bilu0_solve_f64(c->Bn, c->Bb, c->Brp, c->Bci, c->F, c->Dinv, c->Bord, r, z);
+    if (c->full_smoother == 1)
+        block_jacobi_f64(c->Bn, c->Bb, c->Djac, r, z);
+    else
+        bilu0_solve_f64(c->Bn, c->Bb, c->Brp, c->Bci, c->F, c->Dinv, c->Bord, r, z);
     return OR_OK;
 }
 
@@ -1276,8 +1326,11 @@ void or_get_omega(const or_ctx *c, double *out)
     memcpy(out, c->omega, sizeof(double) * (size_t)c->Bn * c->Bb);
 }
 
+/* R-stage data: block ILU(0) factors F and pivot inverses, or (block Jacobi) */
+/* no F and the diagonal-block inverses in Dinv.                              */
 void or_get_bilu(const or_ctx *c, double *F, double *Dinv)
 {
-    if (F) memcpy(F, c->F, sizeof(double) * (size_t)(c->Bnnzb * c->Bb * c->Bb));
-    if (Dinv) memcpy(Dinv, c->Dinv, sizeof(double) * (size_t)c->Bn * c->Bb * c->Bb);
+    if (F && c->F) memcpy(F, c->F, sizeof(double) * (size_t)(c->Bnnzb * c->Bb * c->Bb));
+    const double *D = c->full_smoother == 1 ? c->Djac : c->Dinv;
+    if (Dinv && D) memcpy(Dinv, D, sizeof(double) * (size_t)c->Bn * c->Bb * c->Bb);
 }

@@ -72,10 +72,11 @@ def lib():
     L.or_bilu0_solve_ordered.restype = None
     L.or_multicolor_order.argtypes = [C.c_int, i32p, i32p, i32p]
     L.or_gs_sweep.argtypes = [C.c_int, i32p, i32p, f64p, i32p, C.c_int, f64p, f64p, C.c_int]
+    L.or_jacobi_sweep.argtypes = [C.c_int, i32p, i32p, f64p, C.c_double, f64p, f64p, f64p]
     L.or_gs_sweep.restype = None
     L.or_lu_solve.argtypes = [C.c_int, f64p, i32p, f64p, f64p]
     L.or_lu_solve.restype = None
-    L.or_create.argtypes = [C.c_int] * 6
+    L.or_create.argtypes = [C.c_int] * 7 + [C.c_double, C.c_int, C.c_int, C.c_int]
     L.or_create.restype = vp
     L.or_destroy.argtypes = [vp]
     L.or_destroy.restype = None
@@ -202,6 +203,14 @@ def gs_sweep(rp, ci, val, color_, g, f, x, forward=True):
     return x
 
 
+def jacobi_sweep(rp, ci, val, w, f, x):
+    """One weighted point-Jacobi sweep: x + w D^-1 (f - A x)."""
+    out = np.zeros(len(rp) - 1)
+    _check(lib().or_jacobi_sweep(len(rp) - 1, _i32(rp), _i32(ci), _f64(val), float(w), _f64(f),
+                                 _f64(x), out), "jacobi")
+    return out
+
+
 def lu_factor(A):
     lu, piv = scipy.linalg.lu_factor(np.asarray(A, dtype=np.float64), check_finite=True)
     return np.ascontiguousarray(lu), np.ascontiguousarray(piv, dtype=np.int32)
@@ -218,11 +227,18 @@ def lu_solve(lu, piv, f):
 # Solver context: adaptive setup + FGMRES (a Newton sequence of systems)
 # --------------------------------------------------------------------------
 class OracleSolver:
+    """smoother: 0 = PGS-MC, 1 = weighted point Jacobi (jacobi_weight);
+    nu_pre/nu_post: sweeps around the coarse correction; full_smoother:
+    0 = block ILU(0), 1 = block Jacobi."""
+
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
-                 bilu_order=1):
+                 bilu_order=1, smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1,
+                 full_smoother=0):
         self._lib = lib()
         self.h = self._lib.or_create(int(mu), int(restart), int(max_iter), int(max_coarse),
-                                     1 if precond_fp32 else 0, int(bilu_order))
+                                     1 if precond_fp32 else 0, int(bilu_order), int(smoother),
+                                     float(jacobi_weight), int(nu_pre), int(nu_post),
+                                     int(full_smoother))
         if not self.h:
             raise MemoryError("or_create")
         self.n = self.b = self.p = None

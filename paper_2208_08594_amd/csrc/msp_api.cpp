@@ -612,6 +612,23 @@ void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P, std::vector<void *
     }
 }
 
+// Block Jacobi R stage: the inverse of every diagonal block (FP64, natural
+// block order) on the side stream, with its FP32 copy (flag[1] on a singular
+// block).
+void block_jacobi_device(msp_ctx *c, const double *vals)
+{
+    BiluData &D = c->bilu;
+    const int n = c->n, b = c->b;
+    const long long E = (long long)b * b;
+    D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
+    c->clear_flag(1);
+    HIPCHK(launch_block_inverse(b, n, c->diag_d, vals, D.Dinv, c->flag + 1, c->side));
+    if (c->fp32()) {
+        D.D32 = (float *)c->dalloc(sizeof(float) * (size_t)(n * E), c->allocB);
+        HIPCHK(launch_from_double<float>((long long)n * E, D.Dinv, D.D32, c->side));
+    }
+}
+
 // Scope guards for the setup: temporary device buffers are released (after
 // both setup streams drained) and uploads return to `stream` on every exit.
 struct ReleaseScope {
@@ -698,10 +715,12 @@ void rebuild_B(msp_ctx *c, const double *vals)
             return O;
         });
     BiluPlan plan;
-    std::future<void> planned = std::async(std::launch::async, [c, &plan, groups0]() {
-        const Groups &G = groups0.get();
-        bilu_plan(c, G.color, G.g, c->bilu, plan);
-    });
+    std::future<void> planned;
+    if (c->opt.full_smoother == 0)
+        planned = std::async(std::launch::async, [c, &plan, groups0]() {
+            const Groups &G = groups0.get();
+            bilu_plan(c, G.color, G.g, c->bilu, plan);
+        });
     // groups and layout of each coarser smoothed level start as soon as the
     // chain has produced it
     std::vector<std::future<LevelWork>> work(MSP_MAX_LEVELS);
@@ -750,9 +769,13 @@ void rebuild_B(msp_ctx *c, const double *vals)
         for (int l = 0; l < nlev; ++l) build_level_device(c, l, l == nlev - 1, &lays[l]);
         link_levels(c);
         phase(4);
-        planned.get();
-        phase(7);
-        bilu_device(c, vals, plan, tmp);
+        if (c->opt.full_smoother == 0) {
+            planned.get();
+            phase(7);
+            bilu_device(c, vals, plan, tmp);
+        } else {
+            block_jacobi_device(c, vals);
+        }
     }
     HIPCHK(hipEventRecord(c->ev_side, c->side));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
@@ -792,24 +815,46 @@ const double *lev_diag<double>(const Level &L) { return L.diag64; }
 template <>
 const float *lev_diag<float>(const Level &L) { return L.diag32; }
 
+// nu smoothing sweeps on level L (x in place; from_zero: x starts at 0).
+// PGS-MC runs colors 1..g (forward) or g..1 (backward) per sweep, Alg. 4.3;
+// point Jacobi is direction-free and uses L.r for its residual.
 template <typename T>
-void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero)
+void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero, int nu)
 {
     T *f = (T *)L.f, *x = (T *)L.x;
     const T *val = lev_val<T>(L);
     const T *diag = lev_diag<T>(L);
-    if (forward) {
-        int g0 = 0;
+    if (nu <= 0) {
+        if (from_zero) HIPCHK(launch_zero<T>(L.n, x, c->stream));
+        return;
+    }
+    if (c->opt.smoother == 1) {
+        const T w = (T)c->opt.jacobi_weight;
+        int s0 = 0;
         if (from_zero) {
-            HIPCHK(launch_gs_first<T>(L.S.all(), L.n, diag, f, x, L.seg_row[0], L.seg_row[1],
-                                      c->stream));
-            g0 = 1;
+            HIPCHK(launch_jacobi_first<T>(L.n, w, diag, f, x, c->stream));
+            s0 = 1;
         }
-        for (int g = g0; g < L.g; ++g)
-            HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
-    } else {
-        for (int g = L.g - 1; g >= 0; --g)
-            HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
+        for (int s = s0; s < nu; ++s) {
+            HIPCHK(launch_residual<T>(L.S.all(), val, diag, f, x, (T *)L.r, c->stream));
+            HIPCHK(launch_jacobi_update<T>(L.n, w, diag, (const T *)L.r, x, c->stream));
+        }
+        return;
+    }
+    for (int s = 0; s < nu; ++s) {
+        if (forward) {
+            int g0 = 0;
+            if (from_zero && s == 0) {
+                HIPCHK(launch_gs_first<T>(L.S.all(), L.n, diag, f, x, L.seg_row[0], L.seg_row[1],
+                                          c->stream));
+                g0 = 1;
+            }
+            for (int g = g0; g < L.g; ++g)
+                HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
+        } else {
+            for (int g = L.g - 1; g >= 0; --g)
+                HIPCHK(launch_gs_color<T>(L.S.view(g), val, diag, f, x, c->stream));
+        }
     }
 }
 
@@ -822,19 +867,25 @@ void vcycle(msp_ctx *c, int l)
         return;
     }
     Level &C = c->lev[l + 1];
-    smooth<T>(c, L, true, true);
+    smooth<T>(c, L, true, true, c->opt.nu_pre);
     HIPCHK(launch_residual<T>(L.S.all(), lev_val<T>(L), lev_diag<T>(L), (const T *)L.f,
                               (const T *)L.x, (T *)L.r, c->stream));
     HIPCHK(launch_restrict<T>(C.n, L.mem_ptr, L.mem, (const T *)L.r, (T *)C.f, c->stream));
     vcycle<T>(c, l + 1);
     HIPCHK(launch_prolong<T>(L.n, L.agg_pos, (const T *)C.x, (T *)L.x, c->stream));
-    smooth<T>(c, L, false, false);
+    smooth<T>(c, L, false, false, c->opt.nu_post);
 }
 
+// The R stage in place on y: block ILU(0) triangular solves, or block Jacobi.
 template <typename T>
 void bilu_solve(msp_ctx *c, T *y)
 {
     BiluData &D = c->bilu;
+    if (c->opt.full_smoother == 1) {
+        const T *Dj = std::is_same<T, float>::value ? (const T *)D.D32 : (const T *)D.Dinv;
+        HIPCHK(launch_block_jacobi<T>(c->b, c->n, Dj, y, c->stream));
+        return;
+    }
     const T *Lv, *Uv, *Dv;
     if (std::is_same<T, float>::value) {
         Lv = (const T *)D.L32; Uv = (const T *)D.U32; Dv = (const T *)D.D32;
@@ -1055,7 +1106,10 @@ bool valid_options(const msp_options &o)
     return o.mu >= 0 && o.restart >= 1 && o.restart <= 200 && o.max_iter >= 1 &&
            o.max_coarse >= 1 && (o.precond_fp32 == 0 || o.precond_fp32 == 1) &&
            (o.bilu_order == 0 || o.bilu_order == 1) && (o.use_graphs == 0 || o.use_graphs == 1) &&
-           ((o.dev_alloc == nullptr) == (o.dev_free == nullptr));
+           ((o.dev_alloc == nullptr) == (o.dev_free == nullptr)) &&
+           (o.smoother == 0 || o.smoother == 1) && o.nu_pre >= 0 && o.nu_pre <= 8 &&
+           o.nu_post >= 0 && o.nu_post <= 8 && (o.full_smoother == 0 || o.full_smoother == 1) &&
+           o.jacobi_weight > 0.0 && o.jacobi_weight <= 2.0;
 }
 
 // copy a device sliced layout back to natural block order (host)
@@ -1096,7 +1150,7 @@ void stage_smooth_T(msp_ctx *c, int level, const double *f, double *x, int forwa
     HIPCHK(launch_unpermute<T>(L.n, L.iperm_d, tmp, (T *)L.f, c->stream));
     HIPCHK(launch_from_double<T>(L.n, x, tmp, c->stream));
     HIPCHK(launch_unpermute<T>(L.n, L.iperm_d, tmp, (T *)L.x, c->stream));
-    smooth<T>(c, L, forward != 0, false);
+    smooth<T>(c, L, forward != 0, false, 1);
     HIPCHK(launch_unpermute<T>(L.n, L.perm_d, (const T *)L.x, tmp, c->stream));
     HIPCHK(launch_to_double<T>(L.n, tmp, x, c->stream));
 }
@@ -1128,6 +1182,11 @@ int msp_default_options(msp_options *opt)
     opt->precond_fp32 = 0;
     opt->bilu_order = 1;
     opt->use_graphs = 1;
+    opt->smoother = 0;
+    opt->nu_pre = 1;
+    opt->nu_post = 1;
+    opt->full_smoother = 0;
+    opt->jacobi_weight = 1.0;
     return MSP_OK;
 }
 
@@ -1268,8 +1327,8 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
         c->info.level_rows[l] = l < (int)c->lev.size() ? c->lev[l].n : 0;
         c->info.n_colors[l] = l < (int)c->lev.size() ? c->lev[l].g : 0;
     }
-    c->info.bilu_levels_fwd = c->hasB ? (int)c->bilu.fwd_ptr.size() - 1 : 0;
-    c->info.bilu_levels_bwd = c->hasB ? (int)c->bilu.bwd_ptr.size() - 1 : 0;
+    c->info.bilu_levels_fwd = c->hasB && !c->bilu.fwd_ptr.empty() ? (int)c->bilu.fwd_ptr.size() - 1 : 0;
+    c->info.bilu_levels_bwd = c->hasB && !c->bilu.bwd_ptr.empty() ? (int)c->bilu.bwd_ptr.size() - 1 : 0;
     return st;
 }
 
@@ -1480,7 +1539,7 @@ int msp_stage_get_bilu(msp_ctx *c, double *F, double *Dinv)
     if (!c->hasB) return MSP_ERR_STATE;
     return guarded([&]() {
         const long long E = (long long)c->Bb * c->Bb;
-        if (F)
+        if (F && c->bilu.F)
             HIPCHK(hipMemcpyAsync(F, c->bilu.F, sizeof(double) * c->Bnnzb * E,
                                   hipMemcpyDeviceToHost, c->stream));
         if (Dinv)
@@ -1498,6 +1557,13 @@ int msp_stage_get_bilu_f32(msp_ctx *c, float *F, float *Dinv)
     return guarded([&]() {
         const long long E = (long long)c->Bb * c->Bb;
         BiluData &D = c->bilu;
+        if (c->opt.full_smoother == 1) {  // block Jacobi: natural-order inverses only
+            if (Dinv)
+                HIPCHK(hipMemcpyAsync(Dinv, D.D32, sizeof(float) * (size_t)c->Bn * E,
+                                      hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            return MSP_OK;
+        }
         if (F) {
             // diagonal slots are not stored in the FP32 layouts; fill them from FP64 F
             std::vector<double> F64((size_t)(c->Bnnzb * E));
@@ -1560,8 +1626,8 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
             switch (stage) {
             case MSP_STAGE_SPMV: spmv(c, in, nullptr, out); break;
             case MSP_STAGE_GS0:
-                if (f32) smooth<float>(c, c->lev[0], true, false);
-                else smooth<double>(c, c->lev[0], true, false);
+                if (f32) smooth<float>(c, c->lev[0], true, false, 1);
+                else smooth<double>(c, c->lev[0], true, false, 1);
                 break;
             case MSP_STAGE_PRECOND: apply(c, in, out); break;
             case MSP_STAGE_BILU:

@@ -80,6 +80,21 @@ hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStrea
 // x = Ainv f with the row-major n x n inverse of leading dimension ld (even)
 template <typename T>
 hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st);
+// weighted point-Jacobi smoothing: x = w D^-1 f (first sweep from zero) and
+// x += w D^-1 r; launch_zero clears a level vector (kernel, graph-safe)
+template <typename T>
+hipError_t launch_jacobi_first(int n, T w, const T *diag, const T *f, T *x, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi_update(int n, T w, const T *diag, const T *r, T *x, hipStream_t st);
+template <typename T>
+hipError_t launch_zero(int n, T *x, hipStream_t st);
+// block Jacobi R stage: Dinv_c = A_cc^-1 (FP64, *bad set on a singular block)
+// and y_c <- Dinv_c y_c
+hipError_t launch_block_inverse(int b, int n, const int *diag_pos, const double *vals,
+                                double *Dinv, int *bad, hipStream_t st);
+template <typename T>
+hipError_t launch_block_jacobi(int b, int n, const T *Dinv, T *y, hipStream_t st);
+
 template <typename T>
 hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hipStream_t st);
 // r_c[k] = v_c[k] - sum_d A_cd[k][p] e_d; pcol64: FP64 A (E = b*b, entry k*b+p);

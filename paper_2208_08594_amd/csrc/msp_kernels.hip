@@ -268,6 +268,46 @@ __device__ bool invert_block(const double (&M)[B * B], double (&X)[B * B])
     return ok;
 }
 
+// Block-Jacobi full-system smoother (the alternative R stage): Dinv_c =
+// A_cc^-1 by the same partial-pivoting inversion as the block ILU(0) pivots,
+// and y_c <- Dinv_c y_c in place.
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_block_inverse(int n, const int *__restrict__ diag_pos,
+                                                            const double *__restrict__ vals,
+                                                            double *__restrict__ Dinv, int *bad)
+{
+    constexpr int E = B * B;
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= n) return;
+    double M[E], X[E];
+    const double *src = vals + (long long)diag_pos[c] * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) M[e] = src[e];
+    if (!invert_block<B>(M, X)) atomicOr(bad, 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) Dinv[(long long)c * E + e] = X[e];
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(kThreads) void k_block_jacobi(int n, const T *__restrict__ Dinv,
+                                                           T *__restrict__ y)
+{
+    constexpr int E = B * B;
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= n) return;
+    T v[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) v[s] = y[(long long)c * B + s];
+    const T *D = Dinv + (long long)c * E;
+#pragma unroll
+    for (int a = 0; a < B; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int s = 0; s < B; ++s) acc += D[a * B + s] * v[s];
+        y[(long long)c * B + a] = acc;
+    }
+}
+
 template <int B>
 __global__ __launch_bounds__(64) void k_bilu_factor(BiluTasks t, double *__restrict__ F,
                                                     double *__restrict__ Dinv, int *bad)
@@ -442,6 +482,37 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int4 *__restrict__ 
         if (c >= 0) sum += vb[k * 64] * x[c];
     }
     r[row] = f[row] - sum;
+}
+
+// Weighted point-Jacobi smoothing (the PJAC ablation of Sec. 6): the first
+// sweep from x = 0 is x = w D^-1 f; a later sweep is x += w D^-1 r with
+// r = f - A x from k_residual (all rows read the old x).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_jacobi_first(int n, T w, const T *__restrict__ diag,
+                                                           const T *__restrict__ f,
+                                                           T *__restrict__ x)
+{
+    int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    x[t] = w * (f[t] / diag[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_jacobi_update(int n, T w,
+                                                            const T *__restrict__ diag,
+                                                            const T *__restrict__ r,
+                                                            T *__restrict__ x)
+{
+    int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    x[t] = x[t] + w * (r[t] / diag[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero(int n, T *__restrict__ x)
+{
+    int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t < n) x[t] = T(0);
 }
 
 template <typename T>
@@ -1338,6 +1409,47 @@ hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStrea
 }
 
 template <typename T>
+hipError_t launch_jacobi_first(int n, T w, const T *diag, const T *f, T *x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_jacobi_first<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, diag, f, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi_update(int n, T w, const T *diag, const T *r, T *x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_jacobi_update<T><<<blocks_for(n), kThreads, 0, st>>>(n, w, diag, r, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero(int n, T *x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_zero<T><<<blocks_for(n), kThreads, 0, st>>>(n, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_inverse(int b, int n, const int *diag_pos, const double *vals,
+                                double *Dinv, int *bad, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_block_inverse<B><<<blocks_for(n), kThreads, 0, st>>>(n, diag_pos, vals,
+                                                                           Dinv, bad)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_block_jacobi(int b, int n, const T *Dinv, T *y, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_block_jacobi<B, T><<<blocks_for(n), kThreads, 0, st>>>(n, Dinv, y)));
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st)
 {
     k_coarse_gemv<T><<<(unsigned)((n + 3) / 4), kThreads, 0, st>>>(n, ld, inv, f, x);
@@ -1429,6 +1541,10 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
     template hipError_t launch_restrict<T>(int, const int *, const int *, const T *, T *,      \
                                            hipStream_t);                                       \
     template hipError_t launch_prolong<T>(int, const int *, const T *, T *, hipStream_t);      \
+    template hipError_t launch_jacobi_first<T>(int, T, const T *, const T *, T *, hipStream_t); \
+    template hipError_t launch_jacobi_update<T>(int, T, const T *, const T *, T *, hipStream_t); \
+    template hipError_t launch_zero<T>(int, T *, hipStream_t);                                 \
+    template hipError_t launch_block_jacobi<T>(int, int, const T *, T *, hipStream_t);         \
     template hipError_t launch_coarse_gemv<T>(int, int, const double *, const T *, T *,        \
                                               hipStream_t);                                    \
     template hipError_t launch_unpermute<T>(int, const int *, const T *, T *, hipStream_t);    \

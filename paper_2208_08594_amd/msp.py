@@ -31,7 +31,8 @@ class MspOptions(C.Structure):
     _fields_ = [("mu", C.c_int), ("restart", C.c_int), ("max_iter", C.c_int),
                 ("max_coarse", C.c_int), ("precond_fp32", C.c_int), ("bilu_order", C.c_int),
                 ("use_graphs", C.c_int), ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", C.c_void_p)]
+                ("alloc_user", C.c_void_p), ("smoother", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("full_smoother", C.c_int), ("jacobi_weight", C.c_double)]
 
 
 class MspInfo(C.Structure):
@@ -164,7 +165,8 @@ class Solver:
     """
 
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
-                 bilu_order=1, stream=None, device=None, torch_allocator=True, use_graphs=True):
+                 bilu_order=1, stream=None, device=None, torch_allocator=True, use_graphs=True,
+                 smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1, full_smoother=0):
         import torch
         self.torch = torch
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -179,6 +181,8 @@ class Solver:
         opt.precond_fp32 = 1 if precond_fp32 else 0
         opt.bilu_order = int(bilu_order)
         opt.use_graphs = 1 if use_graphs else 0
+        opt.smoother, opt.jacobi_weight = int(smoother), float(jacobi_weight)
+        opt.nu_pre, opt.nu_post, opt.full_smoother = int(nu_pre), int(nu_post), int(full_smoother)
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         self._alloc = None
         if torch_allocator:

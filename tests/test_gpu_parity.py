@@ -299,6 +299,79 @@ def test_coarse_direct_solve_needs_pivoting(n):
 
 
 # --------------------------------------------------------------------------
+# smoother options: point Jacobi (PJAC), sweep counts, block Jacobi as R
+# --------------------------------------------------------------------------
+OPTION_CASES = [
+    ("pjac-w1", dict(smoother=1, jacobi_weight=1.0), False),
+    ("pjac-w067-nu2", dict(smoother=1, jacobi_weight=2.0 / 3.0, nu_pre=2, nu_post=2), False),
+    ("pgs-nu2-0", dict(nu_pre=2, nu_post=0), False),
+    ("pgs-nu0-2", dict(nu_pre=0, nu_post=2), False),
+    ("bjac", dict(full_smoother=1), False),
+    ("pjac-bjac-fp32", dict(smoother=1, jacobi_weight=0.8, full_smoother=1), True),
+    ("pgs-nu2-fp32", dict(nu_pre=2, nu_post=2), True),
+]
+
+
+@pytest.mark.parametrize("name,opts,fp32", OPTION_CASES, ids=[c[0] for c in OPTION_CASES])
+def test_smoother_options_match_oracle(name, opts, fp32):
+    sys = synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4")
+    announce(sys.name, name, fp32)
+    g = msp.Solver(max_coarse=200, precond_fp32=fp32, **opts)
+    o = O.OracleSolver(max_coarse=200, precond_fp32=fp32, **opts)
+    g.setup(sys)
+    o.setup(sys)
+    assert g.nlevels == o.nlevels >= 2
+    rng = np.random.default_rng(17)
+    if not fp32:
+        # one sweep of the configured smoother on every smoothed level
+        for l in range(o.nlevels - 1):
+            L = o.level(l)
+            f = rng.uniform(-1, 1, L["n"])
+            x0 = rng.uniform(-1, 1, L["n"])
+            if opts.get("smoother", 0) == 1:
+                xo = O.jacobi_sweep(L["row_ptr"], L["col_ind"], L["val"],
+                                    opts["jacobi_weight"], f, x0)
+            else:
+                xo = O.gs_sweep(L["row_ptr"], L["col_ind"], L["val"], L["color"],
+                                L["ncolors"], f, x0, True)
+            assert relerr(to_np(g.smooth(l, f, x0, True)), xo) <= 1e-12, l
+        r = rng.uniform(-1, 1, sys.N)
+        assert relerr(to_np(g.bilu_apply(r)), o.bilu_apply(r)) <= 1e-12
+        f0 = rng.uniform(-1, 1, sys.n)
+        assert relerr(to_np(g.vcycle(f0)), o.vcycle(f0)) <= _coarse_tol(o)
+    v = rng.uniform(-1, 1, sys.N)
+    tol = 1e-5 if fp32 else _coarse_tol(o)
+    assert relerr(to_np(g.apply(v)), o.apply(v)) <= tol
+    xg, ig = g.solve(sys.rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-6)
+    assert ig["status"] == 0 and st == 0
+    assert abs(ig["iterations"] - it) <= 1, (ig["iterations"], it)
+    assert ig["rel_true_residual"] <= 1e-6
+    g.close()
+    o.close()
+
+
+def test_block_jacobi_fp32_storage_is_rne():
+    sys = synth.config(0)
+    g = msp.Solver(max_coarse=64, precond_fp32=True, full_smoother=1)
+    o = O.OracleSolver(max_coarse=64, precond_fp32=True, full_smoother=1)
+    g.setup(sys)
+    o.setup(sys)
+    _, D64 = g.bilu(False)
+    _, D32 = g.bilu(True)
+    _, Do = o.bilu()
+    assert relerr(D64, Do) <= 1e-12
+    assert np.array_equal(D32, D64.astype(np.float32))
+
+
+def test_invalid_smoother_options_are_rejected():
+    for kw in [dict(smoother=2), dict(nu_pre=9), dict(nu_post=-1), dict(full_smoother=2),
+               dict(jacobi_weight=0.0), dict(jacobi_weight=2.5)]:
+        with pytest.raises(msp.MspError):
+            msp.Solver(**kw)
+
+
+# --------------------------------------------------------------------------
 # adaptive setup and error handling
 # --------------------------------------------------------------------------
 def test_adaptive_setup_matches_oracle():

@@ -373,11 +373,11 @@ def _dense_operator(fn, n):
     return np.stack([fn(np.eye(n)[:, j]) for j in range(n)], axis=1)
 
 
-@pytest.mark.parametrize("max_coarse", [10000, 4])
-def test_reduced_apply_equals_literal_alg31(max_coarse):
+@pytest.mark.parametrize("max_coarse,full_smoother", [(10000, 0), (4, 0), (4, 1)])
+def test_reduced_apply_equals_literal_alg31(max_coarse, full_smoother):
     sys = synth.lognormal_grid(3, 3, 2, 3, 7, 1.0, 1.0, [0])
     n, b, p, N = sys.n, sys.b, sys.p, sys.N
-    s = O.OracleSolver(max_coarse=max_coarse, bilu_order=0)
+    s = O.OracleSolver(max_coarse=max_coarse, bilu_order=0, full_smoother=full_smoother)
     s.setup(sys)
     A = sys.to_dense()
     W = np.zeros((N, N))
@@ -391,12 +391,19 @@ def test_reduced_apply_equals_literal_alg31(max_coarse):
     np.testing.assert_allclose(dense_from_csr(L0["row_ptr"], L0["col_ind"], L0["val"]),
                                PiP.T @ Ah @ PiP, rtol=1e-12, atol=1e-13)
     BP = _dense_operator(s.vcycle, n)
-    # R = (ILU0(W A))^{-1}: factor the decoupled blocks (a different input)
-    vals_hat = np.stack([np.linalg.inv(sys.vals[sys.diag_pos[c]]) @ sys.vals[k]
-                         for c in range(n) for k in range(sys.row_ptr[c], sys.row_ptr[c + 1])])
-    Fh, Dh = O.bilu0_factor(n, b, sys.row_ptr, sys.col_ind, vals_hat)
-    Lh, Uh = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, Fh, Dh, n, b)
-    R = np.linalg.inv(Lh @ Uh)
+    if full_smoother == 0:
+        # R = (ILU0(W A))^{-1}: factor the decoupled blocks (a different input)
+        vals_hat = np.stack([np.linalg.inv(sys.vals[sys.diag_pos[c]]) @ sys.vals[k]
+                             for c in range(n) for k in range(sys.row_ptr[c], sys.row_ptr[c + 1])])
+        Fh, Dh = O.bilu0_factor(n, b, sys.row_ptr, sys.col_ind, vals_hat)
+        Lh, Uh = _dense_lu_from_factors(sys.row_ptr, sys.col_ind, Fh, Dh, n, b)
+        R = np.linalg.inv(Lh @ Uh)
+    else:
+        # block Jacobi on the decoupled system: its diagonal blocks are I
+        np.testing.assert_allclose(np.stack([Ah[c * b:(c + 1) * b, c * b:(c + 1) * b]
+                                             for c in range(n)]),
+                                   np.broadcast_to(np.eye(b), (n, b, b)), atol=1e-13)
+        R = np.eye(N)
     # Alg. 3.1 with w = 0, stages P then R: the operator on g
     I = np.eye(N)
     Bg = PiP @ BP @ PiP.T + R @ (I - Ah @ PiP @ BP @ PiP.T)
@@ -413,28 +420,36 @@ def test_reduced_apply_equals_literal_alg31(max_coarse):
 # --------------------------------------------------------------------------
 # O10 V-cycle -- pin P6
 # --------------------------------------------------------------------------
-def _vcycle_dense(levels, l, coarse_inv):
+def _vcycle_dense(levels, l, coarse_inv, smoother=0, w=1.0, nu_pre=1, nu_post=1):
+    """Textbook V-cycle operator: every smoothing sweep is the stationary step
+    x <- x + S (f - A x) with S = (D + L_pi)^-1 / (D + U_pi)^-1 (Gauss-Seidel
+    on the color-permuted matrix, forward / backward) or S = w D^-1 (Jacobi);
+    nu_pre sweeps from x = 0, coarse correction, nu_post sweeps."""
     L = levels[l]
     n = L["n"]
     A = dense_from_csr(L["row_ptr"], L["col_ind"], L["val"])
     if L["color"] is None:
         return coarse_inv
-    perm = np.argsort(L["color"], kind="stable")
-    inv = np.argsort(perm)
-    Ap = A[np.ix_(perm, perm)]
-    Mf = np.tril(Ap)
-    Mb = np.triu(Ap)
-    # M^{-1} in natural numbering
-    Mf_inv = np.linalg.inv(Mf)[np.ix_(inv, inv)]
-    Mb_inv = np.linalg.inv(Mb)[np.ix_(inv, inv)]
+    if smoother == 0:
+        perm = np.argsort(L["color"], kind="stable")
+        inv = np.argsort(perm)
+        Ap = A[np.ix_(perm, perm)]
+        # M^{-1} in natural numbering
+        Sf = np.linalg.inv(np.tril(Ap))[np.ix_(inv, inv)]
+        Sb = np.linalg.inv(np.triu(Ap))[np.ix_(inv, inv)]
+    else:
+        Sf = Sb = w * np.diag(1.0 / np.diag(A))
     P = np.zeros((n, L["nc"]))
     P[np.arange(n), L["agg"]] = 1.0
-    Bc = _vcycle_dense(levels, l + 1, coarse_inv)
+    Bc = _vcycle_dense(levels, l + 1, coarse_inv, smoother, w, nu_pre, nu_post)
     I = np.eye(n)
-    X1 = Mf_inv
-    X2 = X1 + P @ Bc @ P.T @ (I - A @ X1)
-    X3 = X2 + Mb_inv @ (I - A @ X2)
-    return X3
+    X = np.zeros((n, n))
+    for _ in range(nu_pre):
+        X = X + Sf @ (I - A @ X)
+    X = X + P @ Bc @ P.T @ (I - A @ X)
+    for _ in range(nu_post):
+        X = X + Sb @ (I - A @ X)
+    return X
 
 
 @pytest.mark.parametrize("shape,max_coarse", [((64,), 20), ((64,), 4), ((8, 8, 8), 40), ((6, 6, 6), 10)])
@@ -462,6 +477,109 @@ def test_vcycle_is_textbook_multigrid(shape, max_coarse):
     e2 = E @ e
     rate = np.linalg.norm(e2) / np.linalg.norm(e)
     assert rate <= rho * 1.05 + 1e-12
+
+
+@pytest.mark.parametrize("shape,max_coarse", [((64,), 4), ((6, 6, 6), 10)])
+@pytest.mark.parametrize("smoother,w,nu_pre,nu_post", [
+    (0, 1.0, 2, 1), (0, 1.0, 0, 2), (0, 1.0, 2, 2),
+    (1, 2.0 / 3.0, 1, 1), (1, 2.0 / 3.0, 2, 2), (1, 1.0, 1, 1), (1, 0.8, 0, 3)])
+def test_vcycle_smoothers_and_sweeps_are_textbook(shape, max_coarse, smoother, w, nu_pre,
+                                                  nu_post):
+    rp, ci, val = synth.poisson_csr(shape)
+    n = len(rp) - 1
+    s = O.OracleSolver(max_coarse=max_coarse, smoother=smoother, jacobi_weight=w,
+                       nu_pre=nu_pre, nu_post=nu_post)
+    s.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=bsr_b1(rp, ci, val))
+    levels = [s.level(l) for l in range(s.nlevels)]
+    assert s.nlevels >= 2
+    Lc = levels[-1]
+    coarse_inv = np.linalg.inv(dense_from_csr(Lc["row_ptr"], Lc["col_ind"], Lc["val"]))
+    Bd = _vcycle_dense(levels, 0, coarse_inv, smoother, w, nu_pre, nu_post)
+    Bo = _dense_operator(s.vcycle, n)
+    np.testing.assert_allclose(Bo, Bd, rtol=1e-10, atol=1e-12)
+    if smoother == 1 and w <= 2.0 / 3.0 + 1e-12 and nu_pre + nu_post >= 2:
+        # damped Jacobi on Poisson smooths every mode: the V-cycle contracts
+        A0 = dense_from_csr(levels[0]["row_ptr"], levels[0]["col_ind"], levels[0]["val"])
+        assert max(abs(np.linalg.eigvals(np.eye(n) - Bo @ A0))) < 1.0
+
+
+def _diag_dominant(n, seed, density=0.05):
+    rp, ci = random_pattern(n, density, seed, symmetric=False)
+    rng = np.random.default_rng(seed + 1)
+    val = rng.uniform(-1.0, 1.0, len(ci))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    d = rows == ci
+    rowsum = np.zeros(n)
+    np.add.at(rowsum, rows[~d], np.abs(val[~d]))
+    val[d] = (1.5 + rng.random(n)) * (rowsum + 1.0)
+    return rp, ci, val
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_jacobi_sweep_reads_only_the_old_iterate(seed):
+    """Every row of a Jacobi sweep equals that row swept alone against the old
+    iterate (bit for bit): a sweep that read values updated earlier in the
+    same sweep (Gauss-Seidel-like) would differ."""
+    n = 120
+    rp, ci, val = _diag_dominant(n, seed)
+    rng = np.random.default_rng(seed + 7)
+    f = rng.uniform(-1, 1, n)
+    x = rng.uniform(-1, 1, n)
+    y = O.jacobi_sweep(rp, ci, val, 0.7, f, x)
+    assert not np.array_equal(y, x)
+    for i in range(n):
+        cols = ci[rp[i]:rp[i + 1]]
+        k = len(cols)
+        di = int(np.nonzero(cols == i)[0][0])
+        # local system: row di is row i (same stored order); the others are
+        # unit rows that keep their old value
+        rows = [np.arange(k, dtype=np.int32) if r == di else np.array([r], dtype=np.int32)
+                for r in range(k)]
+        prl = np.zeros(k + 1, dtype=np.int32)
+        prl[1:] = np.cumsum([len(rr) for rr in rows])
+        cil = np.concatenate(rows).astype(np.int32)
+        vall = np.concatenate([val[rp[i]:rp[i + 1]] if r == di else np.array([1.0])
+                               for r in range(k)])
+        fl = x[cols].copy()
+        fl[di] = f[i]
+        yl = O.jacobi_sweep(prl, cil, vall, 0.7, fl, x[cols])
+        assert yl[di] == y[i]
+
+
+def test_jacobi_fixed_point_is_the_solution():
+    n = 200
+    rp, ci, val = _diag_dominant(n, 5)
+    A = dense_from_csr(rp, ci, val)
+    f = np.random.default_rng(6).uniform(-1, 1, n)
+    x = np.zeros(n)
+    for _ in range(400):
+        x = O.jacobi_sweep(rp, ci, val, 1.0, f, x)
+    np.testing.assert_allclose(x, np.linalg.solve(A, f), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("b", [1, 3, 7])
+def test_block_jacobi_r_stage_is_blockwise_solve(b):
+    n = 60
+    rp, ci, vals = synth.random_bsr(n, b, 0.05, 21 + b)
+    s = O.OracleSolver(max_coarse=10000, full_smoother=1)
+    s.setup(n=n, b=b, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    r = np.random.default_rng(3).uniform(-1, 1, n * b)
+    z = s.bilu_apply(r)
+    diag = [int(np.nonzero(ci[rp[c]:rp[c + 1]] == c)[0][0]) + rp[c] for c in range(n)]
+    ref = np.concatenate([np.linalg.solve(vals[diag[c]], r[c * b:(c + 1) * b]) for c in range(n)])
+    np.testing.assert_allclose(z, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_block_jacobi_exact_on_uncoupled_cells():
+    """No couplings between cells: block Jacobi is the exact inverse, so the
+    whole preconditioner is exact and FGMRES takes one iteration (cf. P8)."""
+    n, b = 40, 4
+    rp, ci, vals = synth.random_bsr(n, b, 0.0, 5)
+    s = O.OracleSolver(max_coarse=8, full_smoother=1)
+    s.setup(n=n, b=b, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    rhs = np.random.default_rng(2).uniform(-1, 1, n * b)
+    x, it, rr, st = s.solve(rhs, 1e-10)
+    assert st == 0 and it == 1 and rr <= 1e-12
 
 
 # --------------------------------------------------------------------------
