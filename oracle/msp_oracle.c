@@ -780,7 +780,8 @@ typedef struct {
 typedef struct {
     /* options */
     int mu, restart, max_iter, max_coarse, precond_fp32, bilu_order;
-    int smoother;          /* 0: PGS-MC (Alg. 4.3), 1: point Jacobi */
+    int smoother;          /* 0: PGS-MC (Alg. 4.3), 1: point Jacobi, 2: natural-order
+                              sequential Gauss-Seidel (comparison reference) */
     double jacobi_weight;  /* weight of the Jacobi correction */
     int nu_pre, nu_post;   /* smoothing sweeps before / after the coarse correction */
     int full_smoother;     /* R stage: 0 block ILU(0), 1 block Jacobi */

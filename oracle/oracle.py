@@ -227,7 +227,9 @@ def lu_solve(lu, piv, f):
 # Solver context: adaptive setup + FGMRES (a Newton sequence of systems)
 # --------------------------------------------------------------------------
 class OracleSolver:
-    """smoother: 0 = PGS-MC, 1 = weighted point Jacobi (jacobi_weight);
+    """smoother: 0 = PGS-MC, 1 = weighted point Jacobi (jacobi_weight), 2 =
+    sequential Gauss-Seidel in natural order (a comparison reference; the
+    library has no such smoother);
     nu_pre/nu_post: sweeps around the coarse correction; full_smoother:
     0 = block ILU(0), 1 = block Jacobi."""
 

@@ -437,6 +437,9 @@ def _vcycle_dense(levels, l, coarse_inv, smoother=0, w=1.0, nu_pre=1, nu_post=1)
         # M^{-1} in natural numbering
         Sf = np.linalg.inv(np.tril(Ap))[np.ix_(inv, inv)]
         Sb = np.linalg.inv(np.triu(Ap))[np.ix_(inv, inv)]
+    elif smoother == 2:
+        Sf = np.linalg.inv(np.tril(A))
+        Sb = np.linalg.inv(np.triu(A))
     else:
         Sf = Sb = w * np.diag(1.0 / np.diag(A))
     P = np.zeros((n, L["nc"]))
@@ -482,7 +485,8 @@ def test_vcycle_is_textbook_multigrid(shape, max_coarse):
 @pytest.mark.parametrize("shape,max_coarse", [((64,), 4), ((6, 6, 6), 10)])
 @pytest.mark.parametrize("smoother,w,nu_pre,nu_post", [
     (0, 1.0, 2, 1), (0, 1.0, 0, 2), (0, 1.0, 2, 2),
-    (1, 2.0 / 3.0, 1, 1), (1, 2.0 / 3.0, 2, 2), (1, 1.0, 1, 1), (1, 0.8, 0, 3)])
+    (1, 2.0 / 3.0, 1, 1), (1, 2.0 / 3.0, 2, 2), (1, 1.0, 1, 1), (1, 0.8, 0, 3),
+    (2, 1.0, 1, 1)])
 def test_vcycle_smoothers_and_sweeps_are_textbook(shape, max_coarse, smoother, w, nu_pre,
                                                   nu_post):
     rp, ci, val = synth.poisson_csr(shape)
