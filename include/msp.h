@@ -90,6 +90,10 @@ typedef struct {
     int full_smoother; /* relaxation operator R of the last stage (Sec. 3.1): 0 (default)
                           block ILU(0), 1 block Jacobi (z_c = A_cc^-1 r_c) */
     double jacobi_weight; /* weight of the Jacobi correction, (0, 2] (default 1) */
+    int n_stage;      /* 1: the concentration stage B_N of eq. MSP runs first in Alg. 3.1,
+                         as one block Gauss-Seidel sweep on the decoupled concentration
+                         block in the groups of Alg. 4.2 on the block graph; 0 (default):
+                         the two stages P then R */
 } msp_options;
 
 typedef struct {

@@ -72,6 +72,13 @@ int msp_stage_get_bilu(msp_ctx *ctx, double *F, double *Dinv);
  * only); precond_fp32 only. */
 int msp_stage_get_bilu_f32(msp_ctx *ctx, float *F, float *Dinv);
 
+/* Setup data of the concentration stage (n_stage = 1, b >= 2), FP64, HOST
+ * pointers (either may be NULL): Dn double[n*(b-1)*b], rows N (the unknowns
+ * other than p, ascending) of D_c^{-1} per cell; Ann double[nnzb*(b-1)^2],
+ * (D_c^{-1} A_cd)[N, N] per stored block in BSR order (identity on the
+ * diagonal blocks).  MSP_ERR_STATE if the stage is off. */
+int msp_stage_get_nstage(msp_ctx *ctx, double *Dn, double *Ann);
+
 /* Stage ids for msp_stage_repeat. */
 #define MSP_STAGE_SPMV 0    /* out = A in (double[n*b]) */
 #define MSP_STAGE_GS0 1     /* one forward PGS-MC sweep on AMG level 0 (all colors) on the

@@ -785,6 +785,7 @@ typedef struct {
     double jacobi_weight;  /* weight of the Jacobi correction */
     int nu_pre, nu_post;   /* smoothing sweeps before / after the coarse correction */
     int full_smoother;     /* R stage: 0 block ILU(0), 1 block Jacobi */
+    int n_stage;           /* 1: the concentration stage B_N runs first (Alg. 3.1) */
     /* current matrix (used by the Krylov SpMV and the pressure-column residual) */
     int n, b, p;
     long nnzb;
@@ -805,17 +806,23 @@ typedef struct {
     float *F32, *Dinv32;
     double *Djac;  /* block Jacobi: inverses of the diagonal blocks A_cc */
     float *Djac32;
+    /* N stage: groups of the block graph, rows N of D_c^-1 ((b-1) x b per   */
+    /* cell) and the N-N part of every decoupled block D_c^-1 A_cd             */
+    int *ncolor, ng;
+    double *Dn, *Ann;
+    float *Dn32, *Ann32;
     /* adaptive state */
     int it_prev, setup_calls, solves;
 } or_ctx;
 
 or_ctx *or_create(int mu, int restart, int max_iter, int max_coarse, int precond_fp32,
                   int bilu_order, int smoother, double jacobi_weight, int nu_pre, int nu_post,
-                  int full_smoother)
+                  int full_smoother, int n_stage)
 {
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     if (!c)
         return NULL;
+    c->n_stage = n_stage;
     c->smoother = smoother;
     c->jacobi_weight = jacobi_weight;
     c->nu_pre = nu_pre;
@@ -843,6 +850,8 @@ static void free_B(or_ctx *c)
     free(c->coarse_dense); free(c->LU); free(c->piv);
     free(c->Brp); free(c->Bci); free(c->Bord); free(c->F); free(c->Dinv); free(c->F32); free(c->Dinv32);
     free(c->Djac); free(c->Djac32);
+    free(c->ncolor); free(c->Dn); free(c->Ann); free(c->Dn32); free(c->Ann32);
+    c->ncolor = NULL; c->Dn = NULL; c->Ann = NULL; c->Dn32 = NULL; c->Ann32 = NULL;
     c->omega = NULL; c->coarse_dense = NULL; c->LU = NULL; c->piv = NULL;
     c->Brp = NULL; c->Bci = NULL; c->Bord = NULL; c->F = NULL; c->Dinv = NULL; c->F32 = NULL; c->Dinv32 = NULL;
     c->Djac = NULL; c->Djac32 = NULL;
@@ -866,6 +875,59 @@ static float *round_f32(const double *x, long m)
         for (long q = 0; q < m; ++q)
             y[q] = (float)x[q];
     return y;
+}
+
+/* N stage (the concentration stage of eq. MSP, B_N = one block Gauss-      */
+/* Seidel sweep): on the decoupled system W A (W = blockdiag(D_c^-1)) the    */
+/* concentration block has N-N blocks (D_c^-1 A_cd)[N, N] and identity       */
+/* diagonal blocks; its right-hand side is (D_c^-1 v_c)[N].  The sweep runs  */
+/* in the order of the block graph's groups (Alg. 4.2).  N = the unknowns    */
+/* other than p, ascending.                                                  */
+static int setup_n_stage(or_ctx *c, int n, int b, int p, const int *rp, const int *ci,
+                         const double *vals, long nnzb)
+{
+    const int m = b - 1, bb = b * b;
+    c->ncolor = (int *)malloc(sizeof(int) * (size_t)n);
+    c->Dn = (double *)calloc((size_t)n * (size_t)(m > 0 ? m * b : 1), sizeof(double));
+    c->Ann = (double *)calloc((size_t)nnzb * (size_t)(m > 0 ? m * m : 1), sizeof(double));
+    if (!c->ncolor || !c->Dn || !c->Ann)
+        return OR_ERR_NOMEM;
+    int g = or_color(n, rp, ci, c->ncolor);
+    if (g < 0)
+        return g;
+    c->ng = g;
+    double Dinv[OR_MAXB * OR_MAXB], P[OR_MAXB * OR_MAXB];
+    for (int cc = 0; cc < n; ++cc) {
+        int kd = find_col(rp, ci, cc, cc);
+        int st = block_inverse(b, vals + (long)kd * bb, Dinv);
+        if (st != OR_OK)
+            return st;
+        for (int a = 0, ra = 0; a < b; ++a) {
+            if (a == p) continue;
+            for (int s2 = 0; s2 < b; ++s2)
+                c->Dn[((long)cc * m + ra) * b + s2] = Dinv[a * b + s2];
+            ++ra;
+        }
+        for (int q = rp[cc]; q < rp[cc + 1]; ++q) {
+            double *out = c->Ann + (long)q * m * m;
+            if (ci[q] == cc) {
+                for (int a = 0; a < m; ++a)
+                    out[a * m + a] = 1.0;
+                continue;
+            }
+            block_mul(b, Dinv, vals + (long)q * bb, P);
+            for (int a = 0, ra = 0; a < b; ++a) {
+                if (a == p) continue;
+                for (int t = 0, rt = 0; t < b; ++t) {
+                    if (t == p) continue;
+                    out[ra * m + rt] = P[a * b + t];
+                    ++rt;
+                }
+                ++ra;
+            }
+        }
+    }
+    return OR_OK;
 }
 
 /* O3  Hierarchy: A_0 = A_P; while n_l > max_coarse, color A_l, aggregate in */
@@ -1037,12 +1099,22 @@ int or_setup(or_ctx *c, int n, int b, int p, const int *rp, const int *ci, const
         if (st != OR_OK)
             return st;
     }
+    if (c->n_stage) {
+        st = setup_n_stage(c, n, b, p, rp, ci, vals, nnzb);
+        if (st != OR_OK)
+            return st;
+    }
     if (c->precond_fp32) {
         /* O13: FP32 copies by IEEE round-to-nearest-even of the FP64 setup */
         for (int l = 0; l < c->nlev; ++l) {
             or_level *L = &c->lev[l];
             L->val32 = round_f32(L->val, L->rp[L->n]);
             if (!L->val32) return OR_ERR_NOMEM;
+        }
+        if (c->n_stage) {
+            c->Dn32 = round_f32(c->Dn, (long)n * (b - 1) * b);
+            c->Ann32 = round_f32(c->Ann, nnzb * (b - 1) * (b - 1));
+            if (!c->Dn32 || !c->Ann32) return OR_ERR_NOMEM;
         }
         if (c->full_smoother == 1) {
             c->Djac32 = round_f32(c->Djac, (long)n * b * b);
@@ -1118,6 +1190,8 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #define BILU_F(c) ((c)->F)
 #define BILU_D(c) ((c)->Dinv)
 #define DJAC(c) ((c)->Djac)
+#define DN(c) ((c)->Dn)
+#define ANN(c) ((c)->Ann)
 #include "oracle_cycle.inc"
 #undef REAL
 #undef SFX
@@ -1126,6 +1200,8 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #undef BILU_F
 #undef BILU_D
 #undef DJAC
+#undef DN
+#undef ANN
 #define REAL float
 #define SFX(name) name##_f32
 #define LEVVAL(L) ((L)->val32)
@@ -1133,6 +1209,8 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #define BILU_F(c) ((c)->F32)
 #define BILU_D(c) ((c)->Dinv32)
 #define DJAC(c) ((c)->Djac32)
+#define DN(c) ((c)->Dn32)
+#define ANN(c) ((c)->Ann32)
 #include "oracle_cycle.inc"
 #undef REAL
 #undef SFX
@@ -1141,6 +1219,8 @@ void or_lu_solve(int m, const double *LU, const int *piv, const double *f, doubl
 #undef BILU_F
 #undef BILU_D
 #undef DJAC
+#undef DN
+#undef ANN
 
 /* z = B v, the multiplicative two-stage preconditioner (Alg. 3.1, stages P  */
 /* then R, initial w = 0) in the reduced form                                  */
@@ -1325,6 +1405,17 @@ void or_get_level(const or_ctx *c, int l, int *rp, int *ci, double *val, int *co
 void or_get_omega(const or_ctx *c, double *out)
 {
     memcpy(out, c->omega, sizeof(double) * (size_t)c->Bn * c->Bb);
+}
+
+/* N-stage data (n_stage = 1): Dn (n x (b-1) x b) and Ann (nnzb x (b-1)^2). */
+int or_get_nstage(const or_ctx *c, double *Dn, double *Ann)
+{
+    if (!c->has_B || !c->n_stage || !c->Dn)
+        return OR_ERR_STATE;
+    const long m = c->Bb - 1;
+    if (Dn) memcpy(Dn, c->Dn, sizeof(double) * (size_t)(c->Bn * m * c->Bb));
+    if (Ann) memcpy(Ann, c->Ann, sizeof(double) * (size_t)(c->Bnnzb * m * m));
+    return OR_OK;
 }
 
 /* R-stage data: block ILU(0) factors F and pivot inverses, or (block Jacobi) */

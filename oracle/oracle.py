@@ -76,7 +76,7 @@ def lib():
     L.or_gs_sweep.restype = None
     L.or_lu_solve.argtypes = [C.c_int, f64p, i32p, f64p, f64p]
     L.or_lu_solve.restype = None
-    L.or_create.argtypes = [C.c_int] * 7 + [C.c_double, C.c_int, C.c_int, C.c_int]
+    L.or_create.argtypes = [C.c_int] * 7 + [C.c_double, C.c_int, C.c_int, C.c_int, C.c_int]
     L.or_create.restype = vp
     L.or_destroy.argtypes = [vp]
     L.or_destroy.restype = None
@@ -102,6 +102,7 @@ def lib():
     L.or_get_level.restype = None
     L.or_get_omega.argtypes = [vp, f64p]
     L.or_get_omega.restype = None
+    L.or_get_nstage.argtypes = [vp, vp, vp]
     L.or_get_bilu.argtypes = [vp, vp, vp]
     L.or_get_bilu.restype = None
     _LIB = L
@@ -231,16 +232,17 @@ class OracleSolver:
     sequential Gauss-Seidel in natural order (a comparison reference; the
     library has no such smoother);
     nu_pre/nu_post: sweeps around the coarse correction; full_smoother:
-    0 = block ILU(0), 1 = block Jacobi."""
+    0 = block ILU(0), 1 = block Jacobi; n_stage: 1 runs the concentration
+    stage B_N (one block Gauss-Seidel sweep) before the pressure stage."""
 
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
                  bilu_order=1, smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1,
-                 full_smoother=0):
+                 full_smoother=0, n_stage=0):
         self._lib = lib()
         self.h = self._lib.or_create(int(mu), int(restart), int(max_iter), int(max_coarse),
                                      1 if precond_fp32 else 0, int(bilu_order), int(smoother),
                                      float(jacobi_weight), int(nu_pre), int(nu_post),
-                                     int(full_smoother))
+                                     int(full_smoother), int(n_stage))
         if not self.h:
             raise MemoryError("or_create")
         self.n = self.b = self.p = None
@@ -334,3 +336,12 @@ class OracleSolver:
         D = np.zeros(self.n * self.b * self.b)
         self._lib.or_get_bilu(self.h, F.ctypes.data_as(C.c_void_p), D.ctypes.data_as(C.c_void_p))
         return F.reshape(-1, self.b, self.b), D.reshape(self.n, self.b, self.b)
+
+    def nstage(self):
+        m = self.b - 1
+        nnzb = int(self.level(0)["row_ptr"][-1])
+        Dn = np.zeros(self.n * m * self.b)
+        Ann = np.zeros(nnzb * m * m)
+        _check(self._lib.or_get_nstage(self.h, Dn.ctypes.data_as(C.c_void_p),
+                                       Ann.ctypes.data_as(C.c_void_p)), "nstage")
+        return Dn.reshape(self.n, m, self.b), Ann.reshape(nnzb, m, m)

@@ -86,6 +86,18 @@ struct Level {
     void *f = nullptr, *x = nullptr, *r = nullptr;  // work vectors in the precond precision
 };
 
+// N stage (concentration block, block Gauss-Seidel in the groups of the
+// block graph): setup data and work vectors, valid with B.
+struct NStage {
+    bool on = false;
+    std::vector<int> grp_ptr;  // cells of group k: cells[grp_ptr[k] .. grp_ptr[k+1])
+    int *cells = nullptr;
+    double *Dn64 = nullptr, *Ann64 = nullptr;
+    float *Dn32 = nullptr, *Ann32 = nullptr;
+    void *gN = nullptr, *y = nullptr;  // preconditioner precision, n (b-1)
+    double *w1 = nullptr, *r1 = nullptr;  // N
+};
+
 struct BiluData {
     std::vector<int> ord;  // elimination order
     std::vector<int> fwd_rows, fwd_ptr, bwd_rows, bwd_ptr;
@@ -111,7 +123,7 @@ struct msp_ctx {
     long long nnzb = 0;
     std::vector<int> rp, ci, diag_pos;
     DevSell SA;
-    int *rp_d = nullptr, *diag_d = nullptr;
+    int *rp_d = nullptr, *diag_d = nullptr, *ci_d = nullptr;
     double *valA = nullptr;
     float *pcol32 = nullptr;
     bool haveA = false;
@@ -124,6 +136,7 @@ struct msp_ctx {
     int nL = 0, ldL = 0;
     double *cinv = nullptr;
     BiluData bilu;
+    NStage ns;
     void *e_nat = nullptr, *ybuf = nullptr;
     // captured preconditioner apply (valid for the current B and A layout)
     double *vin = nullptr, *zout = nullptr;
@@ -191,7 +204,7 @@ struct msp_ctx {
         return d;
     }
     void sync() { HIPCHK(hipStreamSynchronize(stream)); }
-    // flag[0] is written by work on `stream`, flag[1] by work on `side`
+    // flag[0] is written by work on `stream`, flag[1] and flag[2] by work on `side`
     int read_flag(int i = 0)
     {
         hipStream_t s_ = i == 0 ? stream : side;
@@ -241,6 +254,7 @@ void build_layout_A(msp_ctx *c)
                     : nullptr;
     c->rp_d = c->upload(c->rp, c->allocA);
     c->diag_d = c->upload(c->diag_pos, c->allocA);
+    c->ci_d = c->upload(c->ci, c->allocA);
 }
 
 // --------------------------------------------------------------------------
@@ -261,6 +275,7 @@ void release_B(msp_ctx *c)
     c->release(c->allocB);
     c->lev.clear();
     c->bilu = BiluData();
+    c->ns = NStage();
     c->hasB = false;
     c->omega = nullptr;
     c->cinv = nullptr;
@@ -629,6 +644,42 @@ void block_jacobi_device(msp_ctx *c, const double *vals)
     }
 }
 
+// N stage setup on the side stream: the groups of the block graph (cells
+// sorted by group, host) and the decoupled concentration blocks (device;
+// flag[2] on a singular diagonal block).
+void n_stage_device(msp_ctx *c, const double *vals, const std::vector<int> &color, int g)
+{
+    NStage &S = c->ns;
+    const int n = c->n, b = c->b, m = b - 1;
+    S.on = true;
+    S.grp_ptr.assign(g + 1, 0);
+    std::vector<int> cells(n);
+    {
+        std::vector<int> cnt(g + 1, 0);
+        for (int i = 0; i < n; ++i) ++cnt[color[i]];
+        for (int k = 1; k <= g; ++k) S.grp_ptr[k] = S.grp_ptr[k - 1] + cnt[k];
+        std::vector<int> f(S.grp_ptr.begin(), S.grp_ptr.end() - 1);
+        for (int i = 0; i < n; ++i) cells[f[color[i] - 1]++] = i;
+    }
+    S.cells = c->upload(cells, c->allocB);
+    S.Dn64 = (double *)c->dalloc(sizeof(double) * (size_t)n * m * b, c->allocB);
+    S.Ann64 = (double *)c->dalloc(sizeof(double) * (size_t)c->nnzb * m * m, c->allocB);
+    c->clear_flag(2);
+    HIPCHK(launch_decouple_n(b, c->p, n, c->rp_d, c->ci_d, c->diag_d, vals, S.Dn64, S.Ann64,
+                             c->flag + 2, c->side));
+    const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
+    if (c->fp32()) {
+        S.Dn32 = (float *)c->dalloc(sizeof(float) * (size_t)n * m * b, c->allocB);
+        S.Ann32 = (float *)c->dalloc(sizeof(float) * (size_t)c->nnzb * m * m, c->allocB);
+        HIPCHK(launch_from_double<float>((long long)n * m * b, S.Dn64, S.Dn32, c->side));
+        HIPCHK(launch_from_double<float>((long long)c->nnzb * m * m, S.Ann64, S.Ann32, c->side));
+    }
+    S.gN = c->dalloc(tsz * (size_t)n * m, c->allocB);
+    S.y = c->dalloc(tsz * (size_t)n * m, c->allocB);
+    S.w1 = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
+    S.r1 = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
+}
+
 // Scope guards for the setup: temporary device buffers are released (after
 // both setup streams drained) and uploads return to `stream` on every exit.
 struct ReleaseScope {
@@ -776,10 +827,14 @@ void rebuild_B(msp_ctx *c, const double *vals)
         } else {
             block_jacobi_device(c, vals);
         }
+        if (c->opt.n_stage == 1 && b > 1) {
+            const Groups &G0 = groups0.get();
+            n_stage_device(c, vals, G0.color, G0.g);
+        }
     }
     HIPCHK(hipEventRecord(c->ev_side, c->side));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
-    const int bad_bilu = c->read_flag(1);
+    const int bad_bilu = c->read_flag(1) | (c->ns.on ? c->read_flag(2) : 0);
     phase(6);
     const int bad_coarse = c->read_flag(0);
     c->release(tmp);
@@ -899,16 +954,35 @@ void bilu_solve(msp_ctx *c, T *y)
 }
 
 template <typename T>
-void apply_T(msp_ctx *c, const double *v, double *z)
+void apply_T(msp_ctx *c, const double *v_in, double *z)
 {
     Level &L0 = c->lev[0];
+    const double *v = v_in;
+    NStage &S = c->ns;
+    if (S.on) {
+        // N stage: y = block GS sweep from 0, w1 = Pi_N y, r1 = v - A w1
+        const bool f32 = std::is_same<T, float>::value;
+        const T *Dn = f32 ? (const T *)S.Dn32 : (const T *)S.Dn64;
+        const T *Ann = f32 ? (const T *)S.Ann32 : (const T *)S.Ann64;
+        const int m = c->b - 1;
+        HIPCHK(launch_n_rhs<T>(c->b, c->n, Dn, v_in, (T *)S.gN, c->stream));
+        HIPCHK(launch_zero<T>(c->n * m, (T *)S.y, c->stream));
+        for (size_t k = 0; k + 1 < S.grp_ptr.size(); ++k)
+            HIPCHK(launch_bgs_group<T>(c->b, S.grp_ptr[k + 1] - S.grp_ptr[k],
+                                       S.cells + S.grp_ptr[k], c->rp_d, c->ci_d, Ann,
+                                       (const T *)S.gN, (T *)S.y, c->stream));
+        HIPCHK(launch_expand_n<T>(c->b, c->p, c->n, (const T *)S.y, S.w1, c->stream));
+        HIPCHK(launch_spmv(c->b, c->SA.all(), c->valA, S.w1, v_in, S.r1, c->stream));
+        v = S.r1;
+    }
     HIPCHK(launch_decouple_restrict<T>(c->b, c->n, L0.iperm_d, c->omega, v, (T *)L0.f, c->stream));
     vcycle<T>(c, 0);
     HIPCHK(launch_unpermute<T>(c->n, L0.perm_d, (const T *)L0.x, (T *)c->e_nat, c->stream));
     HIPCHK(launch_pcol_residual<T>(c->b, c->p, c->SA.all(), c->valA, c->pcol32, v,
                                    (const T *)c->e_nat, (T *)c->ybuf, c->stream));
     bilu_solve<T>(c, (T *)c->ybuf);
-    HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, (const T *)c->e_nat, z,
+    HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, (const T *)c->e_nat,
+                            S.on ? S.w1 : nullptr, z,
                             c->stream));
 }
 
@@ -1109,7 +1183,7 @@ bool valid_options(const msp_options &o)
            ((o.dev_alloc == nullptr) == (o.dev_free == nullptr)) &&
            (o.smoother == 0 || o.smoother == 1) && o.nu_pre >= 0 && o.nu_pre <= 8 &&
            o.nu_post >= 0 && o.nu_post <= 8 && (o.full_smoother == 0 || o.full_smoother == 1) &&
-           o.jacobi_weight > 0.0 && o.jacobi_weight <= 2.0;
+           o.jacobi_weight > 0.0 && o.jacobi_weight <= 2.0 && (o.n_stage == 0 || o.n_stage == 1);
 }
 
 // copy a device sliced layout back to natural block order (host)
@@ -1187,6 +1261,7 @@ int msp_default_options(msp_options *opt)
     opt->nu_post = 1;
     opt->full_smoother = 0;
     opt->jacobi_weight = 1.0;
+    opt->n_stage = 0;
     return MSP_OK;
 }
 
@@ -1544,6 +1619,23 @@ int msp_stage_get_bilu(msp_ctx *c, double *F, double *Dinv)
                                   hipMemcpyDeviceToHost, c->stream));
         if (Dinv)
             HIPCHK(hipMemcpyAsync(Dinv, c->bilu.Dinv, sizeof(double) * (size_t)c->Bn * E,
+                                  hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        return MSP_OK;
+    });
+}
+
+int msp_stage_get_nstage(msp_ctx *c, double *Dn, double *Ann)
+{
+    if (!c) return MSP_ERR_ARG;
+    if (!c->hasB || !c->ns.on) return MSP_ERR_STATE;
+    return guarded([&]() {
+        const long long m = c->Bb - 1;
+        if (Dn)
+            HIPCHK(hipMemcpyAsync(Dn, c->ns.Dn64, sizeof(double) * (size_t)(c->Bn * m * c->Bb),
+                                  hipMemcpyDeviceToHost, c->stream));
+        if (Ann)
+            HIPCHK(hipMemcpyAsync(Ann, c->ns.Ann64, sizeof(double) * (size_t)(c->Bnnzb * m * m),
                                   hipMemcpyDeviceToHost, c->stream));
         c->sync();
         return MSP_OK;

@@ -110,7 +110,22 @@ template <typename T>
 hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *Uval,
                            const T *Dval, T *z, hipStream_t st);
 template <typename T>
-hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, double *z, hipStream_t st);
+hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, const double *w1, double *z,
+                         hipStream_t st);
+// N stage (concentration block, block Gauss-Seidel): setup of Dn = rows N of
+// D_c^-1 (n x (b-1) x b) and Ann = (D_c^-1 A_cd)[N, N] per stored block
+// (nnzb x (b-1)^2, identity on the diagonal blocks), FP64; the right-hand side
+// gN = Dn v; one group of the sweep; w1 = Pi_N y.  All no-ops for b = 1.
+hipError_t launch_decouple_n(int b, int p, int n, const int *rp, const int *ci,
+                             const int *diag_pos, const double *vals, double *Dn, double *Ann,
+                             int *bad, hipStream_t st);
+template <typename T>
+hipError_t launch_n_rhs(int b, int n, const T *Dn, const double *v, T *gN, hipStream_t st);
+template <typename T>
+hipError_t launch_bgs_group(int b, int ncell, const int *cells, const int *rp, const int *ci,
+                            const T *Ann, const T *gN, T *y, hipStream_t st);
+template <typename T>
+hipError_t launch_expand_n(int b, int p, int n, const T *y, double *w1, hipStream_t st);
 template <typename T>
 hipError_t launch_to_double(long long n, const T *x, double *y, hipStream_t st);
 template <typename T>

@@ -692,13 +692,128 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
 template <int B, typename T>
 __global__ __launch_bounds__(kThreads) void k_finish(int p, int n, const T *__restrict__ zz,
                                                      const T *__restrict__ e,
+                                                     const double *__restrict__ w1,
                                                      double *__restrict__ z)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (q >= (long long)n * B) return;
     const int k = (int)(q % B);
     const long long c = q / B;
-    z[q] = (double)zz[q] + (k == p ? (double)e[c] : 0.0);
+    const double v = (double)zz[q] + (k == p ? (double)e[c] : 0.0);
+    z[q] = w1 ? v + w1[q] : v;
+}
+
+// ---------------------------------------------------------------------------
+// N stage (the concentration stage B_N of eq. MSP): one block Gauss-Seidel
+// sweep on the decoupled concentration block.  With D_c = A_cc its diagonal
+// blocks are the identity; the off-diagonal blocks are (D_c^-1 A_cd)[N, N]
+// and the right-hand side is (D_c^-1 v_c)[N], N = unknowns other than p.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kThreads) void k_decouple_n(int n, int p, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci,
+                                                         const int *__restrict__ diag_pos,
+                                                         const double *__restrict__ vals,
+                                                         double *__restrict__ Dn,
+                                                         double *__restrict__ Ann, int *bad)
+{
+    constexpr int E = B * B, M = B - 1;
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= n) return;
+    double Dm[E], Di[E];
+    const double *dblk = vals + (long long)diag_pos[c] * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) Dm[e] = dblk[e];
+    if (!invert_block<B>(Dm, Di)) atomicOr(bad, 1);
+#pragma unroll
+    for (int a = 0, ra = 0; a < B; ++a) {
+        if (a == p) continue;
+#pragma unroll
+        for (int s = 0; s < B; ++s) Dn[((long long)c * M + ra) * B + s] = Di[a * B + s];
+        ++ra;
+    }
+    for (int q = rp[c]; q < rp[c + 1]; ++q) {
+        double *out = Ann + (long long)q * M * M;
+        const double *blk = vals + (long long)q * E;
+        const bool dg = ci[q] == c;
+        for (int a = 0, ra = 0; a < B; ++a) {
+            if (a == p) continue;
+            for (int t = 0, rt = 0; t < B; ++t) {
+                if (t == p) continue;
+                double acc = 0.0;
+#pragma unroll
+                for (int u = 0; u < B; ++u) acc = acc + Di[a * B + u] * blk[u * B + t];
+                out[ra * M + rt] = dg ? (ra == rt ? 1.0 : 0.0) : acc;
+                ++rt;
+            }
+            ++ra;
+        }
+    }
+}
+
+// gN_c = Dn_c v_c (rows N of D_c^-1 times v_c), in the preconditioner precision
+template <int B, typename T>
+__global__ __launch_bounds__(kThreads) void k_n_rhs(int n, const T *__restrict__ Dn,
+                                                    const double *__restrict__ v,
+                                                    T *__restrict__ gN)
+{
+    constexpr int M = B - 1;
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= n) return;
+    T vc[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) vc[s] = (T)v[(long long)c * B + s];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int s = 0; s < B; ++s) acc = acc + Dn[((long long)c * M + a) * B + s] * vc[s];
+        gN[(long long)c * M + a] = acc;
+    }
+}
+
+// one group of the sweep: y_c = gN_c - sum_{d != c} Ann_cd y_d for the cells
+// of the group (independent: no stored block joins two cells of one group)
+template <int B, typename T>
+__global__ __launch_bounds__(kThreads) void k_bgs_group(int ncell, const int *__restrict__ cells,
+                                                        const int *__restrict__ rp,
+                                                        const int *__restrict__ ci,
+                                                        const T *__restrict__ Ann,
+                                                        const T *__restrict__ gN, T *y)
+{
+    constexpr int M = B - 1, M1 = M > 0 ? M : 1;
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= ncell) return;
+    const int c = cells[idx];
+    T acc[M1];
+#pragma unroll
+    for (int a = 0; a < M; ++a) acc[a] = gN[(long long)c * M + a];
+    for (int q = rp[c]; q < rp[c + 1]; ++q) {
+        const int d = ci[q];
+        if (d == c) continue;
+        T yd[M1];
+#pragma unroll
+        for (int t = 0; t < M; ++t) yd[t] = y[(long long)d * M + t];
+        const T *blk = Ann + (long long)q * M * M;
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int t = 0; t < M; ++t) acc[a] = acc[a] - blk[a * M + t] * yd[t];
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) y[(long long)c * M + a] = acc[a];
+}
+
+// w1 = Pi_N y (FP64, zero at the pressure unknowns)
+template <int B, typename T>
+__global__ __launch_bounds__(kThreads) void k_expand_n(int n, int p, const T *__restrict__ y,
+                                                       double *__restrict__ w1)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long long)n * B) return;
+    const int k = (int)(q % B);
+    const long long c = q / B;
+    w1[q] = (k == p) ? 0.0 : (double)y[c * (B - 1) + (k < p ? k : k - 1)];
 }
 
 template <typename T>
@@ -1506,10 +1621,48 @@ hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *U
 }
 
 template <typename T>
-hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, double *z, hipStream_t st)
+hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, const double *w1,
+                         double *z, hipStream_t st)
 {
     MSP_SWITCH_B(b, (k_finish<B, T><<<blocks_for((long long)n * B), kThreads, 0, st>>>(p, n, zz,
-                                                                                      e, z)));
+                                                                                      e, w1, z)));
+    return hipGetLastError();
+}
+
+hipError_t launch_decouple_n(int b, int p, int n, const int *rp, const int *ci,
+                             const int *diag_pos, const double *vals, double *Dn, double *Ann,
+                             int *bad, hipStream_t st)
+{
+    if (b < 2 || n <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_decouple_n<B><<<blocks_for(n), kThreads, 0, st>>>(n, p, rp, ci, diag_pos,
+                                                                        vals, Dn, Ann, bad)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_n_rhs(int b, int n, const T *Dn, const double *v, T *gN, hipStream_t st)
+{
+    if (b < 2 || n <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_n_rhs<B, T><<<blocks_for(n), kThreads, 0, st>>>(n, Dn, v, gN)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bgs_group(int b, int ncell, const int *cells, const int *rp, const int *ci,
+                            const T *Ann, const T *gN, T *y, hipStream_t st)
+{
+    if (b < 2 || ncell <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_bgs_group<B, T><<<blocks_for(ncell), kThreads, 0, st>>>(ncell, cells, rp,
+                                                                              ci, Ann, gN, y)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_expand_n(int b, int p, int n, const T *y, double *w1, hipStream_t st)
+{
+    if (b < 2 || n <= 0) return hipSuccess;
+    MSP_SWITCH_B(b, (k_expand_n<B, T><<<blocks_for((long long)n * B), kThreads, 0, st>>>(n, p, y,
+                                                                                        w1)));
     return hipGetLastError();
 }
 
@@ -1555,8 +1708,12 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
                                            hipStream_t);                                       \
     template hipError_t launch_bilu_bwd<T>(int, const SellView &, const int *, const T *,      \
                                            const T *, T *, hipStream_t);                       \
-    template hipError_t launch_finish<T>(int, int, int, const T *, const T *, double *,        \
-                                         hipStream_t);                                         \
+    template hipError_t launch_finish<T>(int, int, int, const T *, const T *, const double *,  \
+                                         double *, hipStream_t);                               \
+    template hipError_t launch_n_rhs<T>(int, int, const T *, const double *, T *, hipStream_t); \
+    template hipError_t launch_bgs_group<T>(int, int, const int *, const int *, const int *,   \
+                                            const T *, const T *, T *, hipStream_t);           \
+    template hipError_t launch_expand_n<T>(int, int, int, const T *, double *, hipStream_t);   \
     template hipError_t launch_to_double<T>(long long, const T *, double *, hipStream_t);      \
     template hipError_t launch_from_double<T>(long long, const double *, T *, hipStream_t);
 

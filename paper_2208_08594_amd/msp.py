@@ -32,7 +32,8 @@ class MspOptions(C.Structure):
                 ("max_coarse", C.c_int), ("precond_fp32", C.c_int), ("bilu_order", C.c_int),
                 ("use_graphs", C.c_int), ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("smoother", C.c_int), ("nu_pre", C.c_int),
-                ("nu_post", C.c_int), ("full_smoother", C.c_int), ("jacobi_weight", C.c_double)]
+                ("nu_post", C.c_int), ("full_smoother", C.c_int), ("jacobi_weight", C.c_double),
+                ("n_stage", C.c_int)]
 
 
 class MspInfo(C.Structure):
@@ -80,6 +81,7 @@ SIGNATURES = {
     "msp_stage_get_bilu": ([_vp, _vp, _vp], _i),
     "msp_stage_get_bilu_f32": ([_vp, _vp, _vp], _i),
     "msp_stage_repeat": ([_vp, _i, _i, _vp, _vp], _i),
+    "msp_stage_get_nstage": ([_vp, _vp, _vp], _i),
 }
 STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE, STAGE_GJ_UPDATE = \
     range(7)
@@ -166,7 +168,8 @@ class Solver:
 
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
                  bilu_order=1, stream=None, device=None, torch_allocator=True, use_graphs=True,
-                 smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1, full_smoother=0):
+                 smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1, full_smoother=0,
+                 n_stage=0):
         import torch
         self.torch = torch
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -183,6 +186,7 @@ class Solver:
         opt.use_graphs = 1 if use_graphs else 0
         opt.smoother, opt.jacobi_weight = int(smoother), float(jacobi_weight)
         opt.nu_pre, opt.nu_post, opt.full_smoother = int(nu_pre), int(nu_post), int(full_smoother)
+        opt.n_stage = int(n_stage)
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         self._alloc = None
         if torch_allocator:
@@ -332,6 +336,16 @@ class Solver:
         out = np.zeros(self.n * self.b)
         _check(self._lib.msp_stage_get_omega(self.h, out.ctypes.data_as(C.c_void_p)), "omega")
         return out.reshape(self.n, self.b)
+
+    def nstage(self):
+        """(Dn, Ann) of the concentration stage (FP64, host)."""
+        m = self.b - 1
+        nnzb = int(self.level(0)["row_ptr"][-1])
+        Dn = np.zeros(self.n * m * self.b)
+        Ann = np.zeros(nnzb * m * m)
+        _check(self._lib.msp_stage_get_nstage(self.h, Dn.ctypes.data_as(C.c_void_p),
+                                              Ann.ctypes.data_as(C.c_void_p)), "nstage")
+        return Dn.reshape(self.n, m, self.b), Ann.reshape(nnzb, m, m)
 
     def bilu(self, f32=False):
         nnzb = int(self.level(0)["row_ptr"][-1])

@@ -351,6 +351,52 @@ def test_smoother_options_match_oracle(name, opts, fp32):
     o.close()
 
 
+NSTAGE_CASES = [
+    ("cfg0-mc64", lambda: synth.config(0), 64, dict(), False),
+    ("grid20x18x9b3", lambda: synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4"), 200,
+     dict(), False),
+    ("grid13x11x7b7-bjac", lambda: synth.lognormal_grid(13, 11, 7, 7, 8, 1.0, 0.1, "lateral4"),
+     100, dict(full_smoother=1), False),
+    ("grid20x18x9b3-fp32", lambda: synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1, "lateral4"),
+     200, dict(), True),
+]
+
+
+@pytest.mark.parametrize("name,mk,mc,opts,fp32", NSTAGE_CASES, ids=[c[0] for c in NSTAGE_CASES])
+def test_n_stage_matches_oracle(name, mk, mc, opts, fp32):
+    sys = mk()
+    announce(sys.name, "n_stage", name)
+    g = msp.Solver(max_coarse=mc, precond_fp32=fp32, n_stage=1, **opts)
+    o = O.OracleSolver(max_coarse=mc, precond_fp32=fp32, n_stage=1, **opts)
+    g.setup(sys)
+    o.setup(sys)
+    Dg, Ag = g.nstage()
+    Do, Ao = o.nstage()
+    assert relerr(Dg, Do) <= 1e-12 and relerr(Ag, Ao) <= 1e-12
+    v = np.random.default_rng(31).uniform(-1, 1, sys.N)
+    tol = 1e-5 if fp32 else _coarse_tol(o)
+    assert relerr(to_np(g.apply(v)), o.apply(v)) <= tol
+    xg, ig = g.solve(sys.rhs, rtol=1e-6)
+    xo, it, rr, st = o.solve(sys.rhs, 1e-6)
+    assert ig["status"] == 0 and st == 0
+    assert abs(ig["iterations"] - it) <= 1, (ig["iterations"], it)
+    assert ig["rel_true_residual"] <= 1e-6
+    g.close()
+    o.close()
+
+
+def test_n_stage_is_a_no_op_for_scalar_systems():
+    rp, ci, vals = synth.random_bsr(200, 1, 0.03, 9)
+    v = np.random.default_rng(4).uniform(-1, 1, 200)
+    out = []
+    for ns in (0, 1):
+        g = msp.Solver(max_coarse=50, n_stage=ns)
+        g.setup(n=200, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+        out.append(to_np(g.apply(v)))
+        g.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_block_jacobi_fp32_storage_is_rne():
     sys = synth.config(0)
     g = msp.Solver(max_coarse=64, precond_fp32=True, full_smoother=1)

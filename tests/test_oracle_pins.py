@@ -373,11 +373,13 @@ def _dense_operator(fn, n):
     return np.stack([fn(np.eye(n)[:, j]) for j in range(n)], axis=1)
 
 
-@pytest.mark.parametrize("max_coarse,full_smoother", [(10000, 0), (4, 0), (4, 1)])
-def test_reduced_apply_equals_literal_alg31(max_coarse, full_smoother):
+@pytest.mark.parametrize("max_coarse,full_smoother,n_stage", [
+    (10000, 0, 0), (4, 0, 0), (4, 1, 0), (4, 0, 1), (4, 1, 1), (10000, 0, 1)])
+def test_reduced_apply_equals_literal_alg31(max_coarse, full_smoother, n_stage):
     sys = synth.lognormal_grid(3, 3, 2, 3, 7, 1.0, 1.0, [0])
     n, b, p, N = sys.n, sys.b, sys.p, sys.N
-    s = O.OracleSolver(max_coarse=max_coarse, bilu_order=0, full_smoother=full_smoother)
+    s = O.OracleSolver(max_coarse=max_coarse, bilu_order=0, full_smoother=full_smoother,
+                       n_stage=n_stage)
     s.setup(sys)
     A = sys.to_dense()
     W = np.zeros((N, N))
@@ -404,12 +406,39 @@ def test_reduced_apply_equals_literal_alg31(max_coarse, full_smoother):
                                              for c in range(n)]),
                                    np.broadcast_to(np.eye(b), (n, b, b)), atol=1e-13)
         R = np.eye(N)
-    # Alg. 3.1 with w = 0, stages P then R: the operator on g
     I = np.eye(N)
-    Bg = PiP @ BP @ PiP.T + R @ (I - Ah @ PiP @ BP @ PiP.T)
-    # eq. MSP: I - B A = (I - R A)(I - Pi_P B_P Pi_P^T A)
-    np.testing.assert_allclose(I - Bg @ Ah, (I - R @ Ah) @ (I - PiP @ BP @ PiP.T @ Ah),
-                               atol=1e-10)
+    if n_stage:
+        # B_N: one block Gauss-Seidel sweep on the decoupled concentration
+        # block, cells in the order of the block graph's groups
+        keep = np.array([k for c in range(n) for k in range(c * b, (c + 1) * b) if k != c * b + p])
+        PiN = np.zeros((N, len(keep)))
+        PiN[keep, np.arange(len(keep))] = 1.0
+        Ann = PiN.T @ Ah @ PiN
+        col, _ = O.color(sys.row_ptr, sys.col_ind)
+        m = b - 1
+        order = np.argsort(col, kind="stable")
+        perm = np.concatenate([np.arange(c * m, (c + 1) * m) for c in order])
+        Ap = Ann[np.ix_(perm, perm)]
+        lower = np.zeros_like(Ap)
+        for bi in range(n):
+            for bj in range(bi + 1):
+                lower[bi * m:(bi + 1) * m, bj * m:(bj + 1) * m] = Ap[bi * m:(bi + 1) * m,
+                                                                      bj * m:(bj + 1) * m]
+        inv = np.argsort(perm)
+        BN = np.linalg.inv(lower)[np.ix_(inv, inv)]
+        # Alg. 3.1 with w = 0, stages N, P, R: the operator on g
+        X1 = PiN @ BN @ PiN.T
+        X2 = X1 + PiP @ BP @ PiP.T @ (I - Ah @ X1)
+        Bg = X2 + R @ (I - Ah @ X2)
+        # eq. MSP: I - B A = (I - R A)(I - Pi_P B_P Pi_P^T A)(I - Pi_N B_N Pi_N^T A)
+        np.testing.assert_allclose(I - Bg @ Ah, (I - R @ Ah) @ (I - PiP @ BP @ PiP.T @ Ah)
+                                   @ (I - X1 @ Ah), atol=1e-10)
+    else:
+        # Alg. 3.1 with w = 0, stages P then R: the operator on g
+        Bg = PiP @ BP @ PiP.T + R @ (I - Ah @ PiP @ BP @ PiP.T)
+        # eq. MSP: I - B A = (I - R A)(I - Pi_P B_P Pi_P^T A)
+        np.testing.assert_allclose(I - Bg @ Ah, (I - R @ Ah) @ (I - PiP @ BP @ PiP.T @ Ah),
+                                   atol=1e-10)
     Bor = _dense_operator(s.apply, N)
     np.testing.assert_allclose(Bor, Bg @ W, rtol=1e-9, atol=1e-11)
     if max_coarse >= n:
@@ -548,6 +577,25 @@ def test_jacobi_sweep_reads_only_the_old_iterate(seed):
         fl[di] = f[i]
         yl = O.jacobi_sweep(prl, cil, vall, 0.7, fl, x[cols])
         assert yl[di] == y[i]
+
+
+@pytest.mark.parametrize("b,p", [(3, 0), (4, 2), (7, 6)])
+def test_n_stage_blocks_are_decoupled_concentration_blocks(b, p):
+    """Dn = rows N of D_c^-1 and Ann = (D_c^-1 A_cd)[N, N] against numpy
+    inverses, N = all unknowns but p, ascending."""
+    n = 30
+    rp, ci, vals = synth.random_bsr(n, b, 0.1, 40 + b)
+    s = O.OracleSolver(max_coarse=10000, n_stage=1)
+    s.setup(n=n, b=b, p=p, row_ptr=rp, col_ind=ci, vals=vals)
+    Dn, Ann = s.nstage()
+    N = [k for k in range(b) if k != p]
+    for c in range(n):
+        kd = rp[c] + int(np.nonzero(ci[rp[c]:rp[c + 1]] == c)[0][0])
+        Di = np.linalg.inv(vals[kd])
+        np.testing.assert_allclose(Dn[c], Di[N, :], rtol=1e-12, atol=1e-14)
+        for q in range(rp[c], rp[c + 1]):
+            ref = np.eye(b - 1) if ci[q] == c else (Di @ vals[q])[np.ix_(N, N)]
+            np.testing.assert_allclose(Ann[q], ref, rtol=1e-11, atol=1e-13)
 
 
 def test_jacobi_fixed_point_is_the_solution():
