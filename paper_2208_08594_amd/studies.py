@@ -7,6 +7,9 @@ the oracle beside it where noted.
   FGMRES iterations and time are reported.  The oracle adds sequential
   Gauss-Seidel in natural row order as the reference that PGS-MC is compared
   with (iterations only).
+* Stages: the two-stage preconditioner (pressure, then R) against the
+  paper's three stages (concentration, pressure, R; eq. MSP), with block
+  ILU(0) or block Jacobi as R.
 * Adaptive-setup sweep (the analogue of Tables 2/4/6, Sec. 6): the same
   sequence is solved with mu in {0, 10, 20, 30, 40}; reported are the number
   of preconditioner regenerations (SetupCalls), the fraction of time spent in
@@ -16,7 +19,7 @@ The Newton sequence is the request model of the serving loop: system s is
 the base Jacobian with every stored value outside the Dirichlet rows scaled
 by (1 + 0.05 u), u ~ U[-1, 1] drawn per step, and a fresh right-hand side.
 
-    python -m paper_2208_08594_amd.studies --smoothers --mu-sweep [--workload cfg1]
+    python -m paper_2208_08594_amd.studies --smoothers --mu-sweep --stages [--workload cfg1]
 """
 from __future__ import annotations
 
@@ -103,6 +106,16 @@ def smoother_study(seq, dev_arrays, oracle_systems=0):
     return res
 
 
+def stage_study(seq, dev_arrays):
+    """Two stages (P, R; the default) against the paper's three (N, P, R),
+    with block ILU(0) or block Jacobi as R."""
+    run_sequence(seq[:1], dev_arrays)  # warm-up
+    variants = [("P,R  R=BILU(0)", dict()), ("N,P,R  R=BILU(0)", dict(n_stage=1)),
+                ("P,R  R=block Jacobi", dict(full_smoother=1)),
+                ("N,P,R  R=block Jacobi", dict(full_smoother=1, n_stage=1))]
+    return {name: _summary(run_sequence(seq, dev_arrays, **opts)) for name, opts in variants}
+
+
 def mu_sweep(seq, dev_arrays, mus=(0, 10, 20, 30, 40)):
     run_sequence(seq[:1], dev_arrays)  # warm-up
     return {str(mu): _summary(run_sequence(seq, dev_arrays, mu=mu)) for mu in mus}
@@ -114,6 +127,7 @@ def main():
     ap.add_argument("--systems", type=int, default=12, help="length of the Newton sequence")
     ap.add_argument("--smoothers", action="store_true")
     ap.add_argument("--mu-sweep", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="two versus three stages")
     ap.add_argument("--oracle-systems", type=int, default=0,
                     help="also run the oracle on this many systems (smoother study)")
     args = ap.parse_args()
@@ -129,6 +143,8 @@ def main():
         out["smoothers"] = smoother_study(seq, arrays, args.oracle_systems)
     if args.mu_sweep:
         out["mu_sweep"] = mu_sweep(seq, arrays)
+    if args.stages:
+        out["stages"] = stage_study(seq, arrays)
     print(json.dumps(out), flush=True)
 
 
