@@ -12,6 +12,12 @@ namespace msp {
 
 namespace {
 
+int host_threads()
+{
+    unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::min(hc ? hc : 1u, 8u);
+}
+
 // Runs f(lo, hi, t) over nparts contiguous, ordered chunks of [0, n) on
 // worker threads (chunk t on thread t); results that each chunk keeps apart
 // and the caller joins in chunk order are identical to a sequential pass.
@@ -33,9 +39,7 @@ void for_chunks(int n, int nparts, F f)
 int host_parts(int n)
 {
     // worth splitting only for large levels; a few threads are enough
-    unsigned hc = std::thread::hardware_concurrency();
-    int p = (int)std::min(hc ? hc : 1u, 8u);
-    return n >= 16384 ? p : 1;
+    return n >= 16384 ? host_threads() : 1;
 }
 
 }  // namespace
@@ -221,10 +225,12 @@ int pairwise_pass(const Csr &A, std::vector<int> &agg)
 {
     const int n = A.n;
     const int parts = host_parts(n);
-    // transpose with values: AT row j lists (i, a_ij) for stored (i, j), i
+    // transpose with values: A^T row j lists (i, a_ij) for stored (i, j), i
     // ascending.  For a structurally symmetric pattern row j of A^T has the
     // columns of row j of A, so only the values are gathered (through the
-    // mirror position of each entry, in parallel); otherwise a counting sort.
+    // mirror position of each entry, in parallel); otherwise a counting sort
+    // over row chunks (per-chunk column counts, offsets in (column, chunk)
+    // order, each chunk scattering its rows in order).
     std::vector<int> tp;
     std::unique_ptr<int[]> ti_own;
     const int *ti = A.ci.data();
@@ -235,14 +241,16 @@ int pairwise_pass(const Csr &A, std::vector<int> &agg)
         for_chunks(n, parts, [&](int lo, int hi, int t) {
             for (int i = lo; i < hi && !miss[t]; ++i)
                 for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                    // rows are short: a forward scan finds the mirror entry
                     const int j = A.ci[k];
-                    auto b = A.ci.begin() + A.rp[j], e = A.ci.begin() + A.rp[j + 1];
-                    auto it = std::lower_bound(b, e, i);
-                    if (it == e || *it != i) {
+                    int q = A.rp[j];
+                    const int qe = A.rp[j + 1];
+                    while (q < qe && A.ci[q] < i) ++q;
+                    if (q == qe || A.ci[q] != i) {
                         miss[t] = 1;
                         break;
                     }
-                    tv[k] = A.val[it - A.ci.begin()];
+                    tv[k] = A.val[q];
                 }
         });
         for (unsigned char m : miss) symmetric = symmetric && !m;
@@ -252,35 +260,47 @@ int pairwise_pass(const Csr &A, std::vector<int> &agg)
     } else {
         tp.assign(n + 1, 0);
         ti_own.reset(new int[A.ci.size() + 1]);
-        for (size_t k = 0; k < A.ci.size(); ++k) ++tp[A.ci[k] + 1];
-        for (int j = 0; j < n; ++j) tp[j + 1] += tp[j];
-        std::vector<int> f(tp.begin(), tp.end() - 1);
-        for (int i = 0; i < n; ++i)
-            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-                int q = f[A.ci[k]]++;
-                ti_own[q] = i;
-                tv[q] = A.val[k];
+        std::vector<int> hist((size_t)n * parts, 0);  // [column][chunk]
+        for_chunks(n, parts, [&](int lo, int hi, int t) {
+            for (int k = A.rp[lo]; k < A.rp[hi]; ++k) ++hist[(size_t)A.ci[k] * parts + t];
+        });
+        int run = 0;
+        for (int c = 0; c < n; ++c) {
+            tp[c] = run;
+            int *h = &hist[(size_t)c * parts];
+            for (int t = 0; t < parts; ++t) {
+                const int v = h[t];
+                h[t] = run;
+                run += v;
             }
+        }
+        tp[n] = run;
+        for_chunks(n, parts, [&](int lo, int hi, int t) {
+            for (int i = lo; i < hi; ++i)
+                for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                    const int q = hist[(size_t)A.ci[k] * parts + t]++;
+                    ti_own[q] = i;
+                    tv[q] = A.val[k];
+                }
+        });
         ti = ti_own.get();
     }
     // symmetrised neighbours of i = merge of row i of A and row i of A^T
-    // (both ascending), with s_ij = -(a_ij + a_ji)/2, built per row chunk.
-    // A chunk writes from the bound offset rp[lo] + tp[lo] (a row has at most
-    // rowlen(A) + rowlen(A^T) neighbours) into memory allocated here; the
-    // chunks are then packed in order.
+    // (both ascending), with s_ij = -(a_ij + a_ji)/2, built per row chunk at
+    // the bound offset start[i] = rp[i] + tp[i] (a row has at most
+    // rowlen(A) + rowlen(A^T) neighbours)
     std::vector<double> smax(n, 0.0);
     std::vector<unsigned char> eligible(n, 0);
     const size_t bound = (size_t)A.rp[n] + (size_t)tp[n];
     std::unique_ptr<int[]> nbr(new int[bound + 1]);
     std::unique_ptr<double[]> s(new double[bound + 1]);
-    std::vector<int> cnt(n, 0), chunk_lo(parts + 1, n);
-    for_chunks(n, parts, [&](int lo, int hi, int t) {
-        chunk_lo[t] = lo;
-        size_t o = (size_t)A.rp[lo] + (size_t)tp[lo];
+    std::vector<int> cnt(n, 0);
+    for_chunks(n, parts, [&](int lo, int hi, int) {
         for (int i = lo; i < hi; ++i) {
             int a = A.rp[i], ae = A.rp[i + 1], q = tp[i], te = tp[i + 1];
             bool coupled = false, any = false;
             double mx = 0.0;
+            size_t o = (size_t)A.rp[i] + (size_t)tp[i];
             const size_t before = o;
             while (a < ae || q < te) {
                 int ja = a < ae ? A.ci[a] : n, jt = q < te ? ti[q] : n;
@@ -302,30 +322,46 @@ int pairwise_pass(const Csr &A, std::vector<int> &agg)
             eligible[i] = coupled && any && mx > 0.0;
         }
     });
-    std::vector<int> nptr(n + 1, 0);
-    for (int i = 0; i < n; ++i) nptr[i + 1] = nptr[i] + cnt[i];
-    for (int t = 0; t < parts && chunk_lo[t] < n; ++t) {
-        const int lo = chunk_lo[t], hi = chunk_lo[t + 1];
-        const size_t from = (size_t)A.rp[lo] + (size_t)tp[lo], len = nptr[hi] - nptr[lo];
-        if (from != (size_t)nptr[lo] && len) {
-            std::copy(nbr.get() + from, nbr.get() + from + len, nbr.get() + nptr[lo]);
-            std::copy(s.get() + from, s.get() + from + len, s.get() + nptr[lo]);
+    // Candidates of each eligible row: eligible neighbours j with
+    // s_ij >= 0.25 max_k s_ik, ordered by s_ij descending, then j ascending.
+    // The first one still free is then the strongest free eligible partner
+    // (lowest index among equals), exactly what a scan of the row picks.
+    std::vector<int> ncand(n, 0);
+    for_chunks(n, parts, [&](int lo, int hi, int) {
+        for (int i = lo; i < hi; ++i) {
+            if (!eligible[i]) continue;
+            const double thr = 0.25 * smax[i];
+            const size_t b0 = (size_t)A.rp[i] + (size_t)tp[i];
+            int m = 0;
+            for (int q = 0; q < cnt[i]; ++q) {
+                const int j = nbr[b0 + q];
+                const double sj = s[b0 + q];
+                if (!eligible[j] || !(sj >= thr)) continue;
+                // insertion into the sorted prefix [b0, b0 + m)
+                int r = m;
+                while (r > 0 && (s[b0 + r - 1] < sj || (s[b0 + r - 1] == sj && nbr[b0 + r - 1] > j))) {
+                    nbr[b0 + r] = nbr[b0 + r - 1];
+                    s[b0 + r] = s[b0 + r - 1];
+                    --r;
+                }
+                nbr[b0 + r] = j;
+                s[b0 + r] = sj;
+                ++m;
+            }
+            ncand[i] = m;
         }
-    }
+    });
     agg.assign(n, -1);
     int nc = 0;
     for (int i = 0; i < n; ++i) {
         if (agg[i] >= 0) continue;
         int best = -1;
-        double bs = 0.0;
-        if (eligible[i]) {
-            const double thr = 0.25 * smax[i];
-            for (int q = nptr[i]; q < nptr[i + 1]; ++q) {
-                int j = nbr[q];
-                if (agg[j] >= 0 || !eligible[j]) continue;
-                if (s[q] >= thr && (best < 0 || s[q] > bs)) { best = j; bs = s[q]; }
+        const int *cb = nbr.get() + (size_t)A.rp[i] + (size_t)tp[i];
+        for (int q = 0; q < ncand[i]; ++q)
+            if (agg[cb[q]] < 0) {
+                best = cb[q];
+                break;
             }
-        }
         agg[i] = nc;
         if (best >= 0) agg[best] = nc;
         ++nc;
