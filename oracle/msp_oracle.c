@@ -457,6 +457,77 @@ int or_npair_pass(int n, const int *rp, const int *ci, const double *val, int *a
     return nc;
 }
 
+/* Stalled coarsening (the two pairwise passes of a level kept more than    */
+/* 90% of its rows): every eligible row alone in its aggregate joins the     */
+/* aggregate of its strongest neighbour j with s_ij >= 0.25 max_k s_ik among  */
+/* the neighbours in aggregates of two or more rows (sizes before any move,  */
+/* lowest j among equals; the strengths and eligibility of the pairwise      */
+/* pass).  Aggregates left empty are dropped, the others keep their order.   */
+/* Returns the new number of aggregates.                                      */
+int or_absorb_singletons(int n, const int *rp, const int *ci, const double *val, int *agg,
+                         int nc)
+{
+    or_graph G;
+    int st = build_sym_graph(n, rp, ci, &G);
+    if (st != OR_OK)
+        return st;
+    int *size = (int *)calloc((size_t)nc, sizeof(int));
+    int *target = (int *)malloc(sizeof(int) * (size_t)n);
+    int *map = (int *)malloc(sizeof(int) * (size_t)nc);
+    if (!size || !target || !map) {
+        free(size); free(target); free(map); free_graph(&G);
+        return OR_ERR_NOMEM;
+    }
+    for (int i = 0; i < n; ++i)
+        size[agg[i]]++;
+    for (int i = 0; i < n; ++i) {
+        target[i] = agg[i];
+        if (size[agg[i]] != 1)
+            continue;
+        int offdiag_nonzero = 0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] != i && val[k] != 0.0)
+                offdiag_nonzero = 1;
+        int has = 0;
+        double mx = 0.0;
+        for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
+            int j = G.adj[q];
+            double s = -(csr_value(rp, ci, val, i, j) + csr_value(rp, ci, val, j, i)) / 2.0;
+            if (!has || s > mx)
+                mx = s;
+            has = 1;
+        }
+        if (!(offdiag_nonzero && has && mx > 0.0))
+            continue;
+        int best = -1;
+        double bs = 0.0;
+        for (int q = G.ptr[i]; q < G.ptr[i + 1]; ++q) {
+            int j = G.adj[q];
+            if (size[agg[j]] < 2)
+                continue;
+            double s = -(csr_value(rp, ci, val, i, j) + csr_value(rp, ci, val, j, i)) / 2.0;
+            if (s >= 0.25 * mx && (best < 0 || s > bs)) {
+                best = j;
+                bs = s;
+            }
+        }
+        if (best >= 0)
+            target[i] = agg[best];
+    }
+    for (int a = 0; a < nc; ++a)
+        map[a] = -1;
+    for (int i = 0; i < n; ++i)
+        map[target[i]] = 0;
+    int k = 0;
+    for (int a = 0; a < nc; ++a)
+        if (map[a] == 0)
+            map[a] = k++;
+    for (int i = 0; i < n; ++i)
+        agg[i] = map[target[i]];
+    free(size); free(target); free(map); free_graph(&G);
+    return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* O6  Galerkin coarse operator A_c = P^T A P for piecewise-constant P       */
 /*     (unsmoothed aggregation, Sec. 5): A_c[agg(i), agg(j)] accumulates     */
@@ -976,6 +1047,17 @@ static int build_hierarchy(or_ctx *c, int *rp0, int *ci0, double *val0, int n0)
         if (!cur->agg) return OR_ERR_NOMEM;
         for (int i = 0; i < cur->n; ++i)
             cur->agg[i] = agg2[agg1[i]];
+        if ((double)nc2 > 0.9 * (double)cur->n) {
+            /* stalled: absorb singletons, then one Galerkin product on A_l */
+            int nc3 = or_absorb_singletons(cur->n, cur->rp, cur->ci, cur->val, cur->agg, nc2);
+            if (nc3 < 0) return nc3;
+            if (nc3 < nc2) {
+                cnnz = or_galerkin(cur->n, cur->rp, cur->ci, cur->val, cur->agg, nc3, c_rp, c_ci,
+                                   c_val);
+                if (cnnz < 0) return (int)cnnz;
+                nc2 = nc3;
+            }
+        }
         cur->nc = nc2;
         free(agg1); free(agg2); free(m_rp); free(m_ci); free(m_val);
         ++l;

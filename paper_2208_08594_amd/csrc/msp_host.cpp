@@ -443,6 +443,71 @@ Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc)
     return C;
 }
 
+int absorb_singletons(const Csr &A, std::vector<int> &agg, int nc)
+{
+    const int n = A.n;
+    const size_t nnz = A.ci.size();
+    // A^T with values (counting sort), for the symmetrised strengths
+    std::vector<int> tp(n + 1, 0), ti(nnz);
+    std::vector<double> tv(nnz);
+    for (size_t k = 0; k < nnz; ++k) ++tp[A.ci[k] + 1];
+    for (int j = 0; j < n; ++j) tp[j + 1] += tp[j];
+    {
+        std::vector<int> f(tp.begin(), tp.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                const int q = f[A.ci[k]]++;
+                ti[q] = i;
+                tv[q] = A.val[k];
+            }
+    }
+    std::vector<int> size(nc, 0), target(agg);
+    for (int i = 0; i < n; ++i) ++size[agg[i]];
+    std::vector<int> nb;
+    std::vector<double> sv;
+    for (int i = 0; i < n; ++i) {
+        if (size[agg[i]] != 1) continue;
+        // neighbours of i in the symmetrised pattern, ascending, with s_ij
+        nb.clear();
+        sv.clear();
+        bool coupled = false, any = false;
+        double mx = 0.0;
+        int a = A.rp[i], ae = A.rp[i + 1], q = tp[i], te = tp[i + 1];
+        while (a < ae || q < te) {
+            const int ja = a < ae ? A.ci[a] : n, jt = q < te ? ti[q] : n;
+            const int j = ja < jt ? ja : jt;
+            double aij = 0.0, aji = 0.0;
+            if (ja == j) { aij = A.val[a]; ++a; }
+            if (jt == j) { aji = tv[q]; ++q; }
+            if (j == i) continue;
+            if (ja == j && aij != 0.0) coupled = true;
+            const double sij = -(aij + aji) / 2.0;
+            nb.push_back(j);
+            sv.push_back(sij);
+            if (!any || sij > mx) mx = sij;
+            any = true;
+        }
+        if (!(coupled && any && mx > 0.0)) continue;
+        int best = -1;
+        double bs = 0.0;
+        for (size_t t = 0; t < nb.size(); ++t) {
+            if (size[agg[nb[t]]] < 2) continue;
+            if (sv[t] >= 0.25 * mx && (best < 0 || sv[t] > bs)) {
+                best = nb[t];
+                bs = sv[t];
+            }
+        }
+        if (best >= 0) target[i] = agg[best];
+    }
+    std::vector<int> map(nc, -1);
+    for (int i = 0; i < n; ++i) map[target[i]] = 0;
+    int k = 0;
+    for (int c = 0; c < nc; ++c)
+        if (map[c] == 0) map[c] = k++;
+    for (int i = 0; i < n; ++i) agg[i] = map[target[i]];
+    return k;
+}
+
 int color_level(const Csr &A, std::vector<int> &color)
 {
     Adjacency G = build_adjacency(A.n, A.rp.data(), A.ci.data());
@@ -472,6 +537,11 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         Csr Cn = galerkin(M1, a2, nc2);
         std::vector<int> agg(cur.n);
         for (int i = 0; i < cur.n; ++i) agg[i] = a2[a1[i]];
+        if ((double)nc2 > 0.9 * (double)cur.n) {
+            // stalled: absorb singletons, then one Galerkin product on A_l
+            const int nc3 = absorb_singletons(cur, agg, nc2);
+            if (nc3 < nc2) Cn = galerkin(cur, agg, nc3);
+        }
         H.agg.push_back(std::move(agg));
         H.A.push_back(std::move(Cn));
     }

@@ -38,6 +38,14 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color);
 // One pairwise-matching pass; agg[i] in [0, nc), returns nc.
 int pairwise_pass(const Csr &A, std::vector<int> &agg);
 
+// Stalled coarsening (the two pairwise passes of a level kept more than 90%
+// of its rows): every eligible row alone in its aggregate joins the aggregate
+// of its strongest neighbour with s_ij >= 0.25 max_k s_ik among neighbours in
+// aggregates of two or more rows (sizes before any move, lowest index among
+// equals).  Emptied aggregates are dropped, the rest keep their order; agg is
+// renumbered in place and the new count returned.
+int absorb_singletons(const Csr &A, std::vector<int> &agg, int nc);
+
 // Galerkin product P^T A P for a piecewise-constant P given by agg; entries
 // summed in (fine row, fine column) ascending order, structural pattern.
 Csr galerkin(const Csr &A, const std::vector<int> &agg, int nc);

@@ -227,16 +227,22 @@ def config(idx: int, seed: int = 0) -> BSRSystem:
     if idx == 2:
         return lognormal_grid(128, 128, 64, 7, seed, 1.5, 0.1, "lateral4", "cfg2_128x128x64_b7")
     if idx == 3:
-        nx, ny, nz = 60, 220, 85
-        rng = np.random.default_rng(seed)
-        logk = layered_logk(nx, ny, nz, rng)
-        phi = rng.uniform(0.05, 0.3, size=nx * ny * nz)
-        kh = 10.0 ** logk
-        kv = 0.1 * kh
-        acc = phi / 0.175
-        w = lateral_corner_wells(nx, ny) + [cell(nx, ny, nx // 2, ny // 2, 0)]
-        return assemble("cfg3_60x220x85_b4", nx, ny, nz, 4, kh, kv, acc, rng, w)
+        return layered_grid(60, 220, 85, 4, seed, "cfg3_60x220x85_b4")
     raise ValueError(f"no config {idx}")
+
+
+def layered_grid(nx, ny, nz, b, seed, name=None) -> BSRSystem:
+    """The heterogeneous layered/channelised case at any size: permeability
+    from ``layered_logk``, k_z = 0.1 k_h, porosity U[0.05, 0.3] (accumulation
+    phi / 0.175), wells at the four lateral corners and the centre of k = 0."""
+    rng = np.random.default_rng(seed)
+    logk = layered_logk(nx, ny, nz, rng)
+    phi = rng.uniform(0.05, 0.3, size=nx * ny * nz)
+    kh = 10.0 ** logk
+    kv = 0.1 * kh
+    acc = phi / 0.175
+    w = lateral_corner_wells(nx, ny) + [cell(nx, ny, nx // 2, ny // 2, 0)]
+    return assemble(name or f"layered_{nx}x{ny}x{nz}_b{b}", nx, ny, nz, b, kh, kv, acc, rng, w)
 
 
 SERVING_SIDES = (16, 24, 32, 48, 64, 96)

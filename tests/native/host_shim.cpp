@@ -46,6 +46,31 @@ long long shim_galerkin(int n, const int *rp, const int *ci, const double *val, 
     return (long long)C.ci.size();
 }
 
+// The library's whole aggregation chain (no groups): returns the number of
+// levels; sizes[l] = rows of level l; aggs = the fine-to-coarse maps of the
+// non-coarsest levels, concatenated; the coarsest level's CSR is copied to
+// crp/cci/cval (capacity nnz of the input).
+int shim_hierarchy(int n, const int *rp, const int *ci, const double *val, int max_coarse,
+                   int *sizes, int *aggs, int *crp, int *cci, double *cval)
+{
+    msp::Hierarchy H;
+    int st = msp::build_hierarchy(make(n, rp, ci, val), max_coarse, 25, 1 << 30, H, false);
+    if (st != 0) return st;
+    long long off = 0;
+    for (size_t l = 0; l < H.A.size(); ++l) {
+        sizes[l] = H.A[l].n;
+        if (l + 1 < H.A.size()) {
+            std::memcpy(aggs + off, H.agg[l].data(), sizeof(int) * H.A[l].n);
+            off += H.A[l].n;
+        }
+    }
+    const msp::Csr &C = H.A.back();
+    std::memcpy(crp, C.rp.data(), sizeof(int) * (C.n + 1));
+    std::memcpy(cci, C.ci.data(), sizeof(int) * C.ci.size());
+    std::memcpy(cval, C.val.data(), sizeof(double) * C.val.size());
+    return (int)H.A.size();
+}
+
 int shim_pattern(int n, const int *rp, const int *ci, long long nnz)
 {
     return msp::check_pattern(n, rp, ci, nnz);

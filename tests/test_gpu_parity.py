@@ -57,6 +57,7 @@ CASES = [
     ("grid33x17x5b2", lambda: synth.lognormal_grid(33, 17, 5, 2, 9, 1.5, 1.0, "corners2"), 150, 0),
     ("grid40x40x12b4-mcbilu", lambda: synth.lognormal_grid(40, 40, 12, 4, 10, 1.5, 0.1,
                                                            "lateral4"), 10000, 1),
+    ("layered24x60x25b4-stall", lambda: synth.layered_grid(24, 60, 25, 4, 0), 100, 1),
 ]
 
 

@@ -133,6 +133,7 @@ def shim():
     i32 = np.ctypeslib.ndpointer(np.int32, flags="C")
     f64 = np.ctypeslib.ndpointer(np.float64, flags="C")
     L.shim_color.argtypes = [C.c_int, i32, i32, i32]
+    L.shim_hierarchy.argtypes = [C.c_int, i32, i32, f64, C.c_int, i32, i32, i32, i32, f64]
     L.shim_pair.argtypes = [C.c_int, i32, i32, f64, i32]
     L.shim_galerkin.argtypes = [C.c_int, i32, i32, f64, i32, C.c_int, i32, i32, f64]
     L.shim_galerkin.restype = C.c_longlong
@@ -231,6 +232,40 @@ def test_library_pair_and_galerkin_large(shim, case):
     orp, oci, ov = O.galerkin(rp, ci, val, o1, onc1)
     assert np.array_equal(crp, orp) and np.array_equal(cci[:m], oci)
     assert np.array_equal(cv[:m], ov)
+
+
+@pytest.mark.parametrize("dims,mc", [((24, 60, 25), 100), ((20, 44, 17), 60)])
+def test_library_hierarchy_with_stalled_level_matches_oracle(shim, dims, mc):
+    """Layered channelised grids whose coarsening stalls (the two pairwise
+    passes keep more than 90% of a level's rows), so singletons are absorbed:
+    the library's chain against the oracle's, bit for bit."""
+    sys = synth.layered_grid(*dims, 4, 0)
+    o = O.OracleSolver(max_coarse=mc)
+    o.setup(sys)
+    L0 = o.level(0)
+    rp, ci, val = L0["row_ptr"], L0["col_ind"], L0["val"]
+    shim.shim_hierarchy.restype = C.c_int
+    sizes = np.zeros(32, dtype=np.int32)
+    aggs = np.zeros(4 * len(rp), dtype=np.int32)
+    crp = np.zeros(len(rp), dtype=np.int32)
+    cci = np.zeros(len(ci), dtype=np.int32)
+    cv = np.zeros(len(ci))
+    nl = shim.shim_hierarchy(len(rp) - 1, rp, ci, val, mc, sizes, aggs, crp, cci, cv)
+    assert nl == o.nlevels
+    sizes_o = [o.level(l)["n"] for l in range(nl)]
+    assert list(sizes[:nl]) == sizes_o
+    # the stall rule fired: some level shrank by more than the pairwise factor
+    assert any(sizes_o[l + 1] < sizes_o[l] / 5 for l in range(nl - 1))
+    off = 0
+    for l in range(nl - 1):
+        n_l = sizes_o[l]
+        assert np.array_equal(aggs[off:off + n_l], o.level(l)["agg"])
+        off += n_l
+    Lc = o.level(nl - 1)
+    m = Lc["n"]
+    assert np.array_equal(crp[:m + 1], Lc["row_ptr"])
+    nnz = Lc["row_ptr"][-1]
+    assert np.array_equal(cci[:nnz], Lc["col_ind"]) and np.array_equal(cv[:nnz], Lc["val"])
 
 
 def test_library_pattern_check(shim):

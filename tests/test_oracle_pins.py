@@ -281,6 +281,43 @@ def test_galerkin_is_dense_ptap(seed):
         assert np.all(np.diff(cci[crp[I]:crp[I + 1]]) > 0)
 
 
+def test_stalled_level_absorbs_singletons_into_connected_aggregates():
+    """A layered channelised grid whose coarsening stalls: the absorbed level
+    still has compact aggregate ids, every aggregate is connected in the
+    symmetrised pattern (an absorbed row joins a neighbour's aggregate), and
+    the coarse matrix is the dense P^T A P of that level."""
+    sys = synth.layered_grid(20, 44, 17, 4, 0)
+    s = O.OracleSolver(max_coarse=60)
+    s.setup(sys)
+    sizes = [s.level(l)["n"] for l in range(s.nlevels)]
+    jumps = [l for l in range(len(sizes) - 1) if sizes[l + 1] < sizes[l] / 5]
+    assert jumps, sizes
+    l = jumps[0]
+    L = s.level(l)
+    n, nc, agg = L["n"], L["nc"], L["agg"]
+    assert sorted(set(agg.tolist())) == list(range(nc))
+    S = sym_adjacency(L["row_ptr"], L["col_ind"])
+    members = [[] for _ in range(nc)]
+    for i in range(n):
+        members[agg[i]].append(i)
+    for mem in members:
+        seen, stack = {mem[0]}, [mem[0]]
+        ms = set(mem)
+        while stack:
+            u = stack.pop()
+            for v in S[u]:
+                if v in ms and v not in seen:
+                    seen.add(v)
+                    stack.append(v)
+        assert seen == ms
+    A = dense_from_csr(L["row_ptr"], L["col_ind"], L["val"])
+    P = np.zeros((n, nc))
+    P[np.arange(n), agg] = 1.0
+    C = s.level(l + 1)
+    np.testing.assert_allclose(dense_from_csr(C["row_ptr"], C["col_ind"], C["val"]), P.T @ A @ P,
+                               rtol=1e-12, atol=1e-12 * np.abs(A).max())
+
+
 def test_hierarchy_levels_and_coarsest():
     sys = synth.config(0)
     s = O.OracleSolver(max_coarse=64)
