@@ -253,6 +253,9 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    solver.close()
+    torch.cuda.synchronize()
+    log("done")
 
 
 def source_hash():

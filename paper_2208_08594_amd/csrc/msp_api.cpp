@@ -1304,19 +1304,9 @@ int msp_destroy(msp_ctx *c)
 {
     if (!c) return MSP_OK;
     int st = guarded([&]() {
+        // Device memory first: release() synchronises every stream of the
+        // context, so the streams must still exist at that point.
         drop_graph(c);
-        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-        if (c->side) (void)hipStreamDestroy(c->side);
-        if (c->gj.aux) (void)hipStreamDestroy(c->gj.aux);
-        if (c->gj.main) (void)hipStreamDestroy(c->gj.main);
-        if (c->gj.ev_start) (void)hipEventDestroy(c->gj.ev_start);
-        if (c->gj.ev_done) (void)hipEventDestroy(c->gj.ev_done);
-        for (int i = 0; i < 2; ++i) {
-            if (c->gj.ev_block[i]) (void)hipEventDestroy(c->gj.ev_block[i]);
-            if (c->gj.ev_inv[i]) (void)hipEventDestroy(c->gj.ev_inv[i]);
-        }
-        if (c->ev_main) (void)hipEventDestroy(c->ev_main);
-        if (c->ev_side) (void)hipEventDestroy(c->ev_side);
         c->release(c->allocA);
         c->release(c->allocB);
         c->release(c->allocW);
@@ -1325,7 +1315,28 @@ int msp_destroy(msp_ctx *c)
                 c->opt.dev_free(c->flag, c->opt.alloc_user);
             else
                 (void)hipFree(c->flag);
+            c->flag = nullptr;
         }
+        auto kill_stream = [](hipStream_t &s) {
+            if (s) (void)hipStreamDestroy(s);
+            s = nullptr;
+        };
+        auto kill_event = [](hipEvent_t &e) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        };
+        kill_stream(c->cap_stream);
+        kill_stream(c->side);
+        kill_stream(c->gj.aux);
+        kill_stream(c->gj.main);
+        kill_event(c->gj.ev_start);
+        kill_event(c->gj.ev_done);
+        for (int i = 0; i < 2; ++i) {
+            kill_event(c->gj.ev_block[i]);
+            kill_event(c->gj.ev_inv[i]);
+        }
+        kill_event(c->ev_main);
+        kill_event(c->ev_side);
         if (c->hhost) (void)hipHostFree(c->hhost);
         if (c->flag_host) (void)hipHostFree(c->flag_host);
         return MSP_OK;
