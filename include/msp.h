@@ -94,6 +94,10 @@ typedef struct {
                          as one block Gauss-Seidel sweep on the decoupled concentration
                          block in the groups of Alg. 4.2 on the block graph; 0 (default):
                          the two stages P then R */
+    int host_chain;   /* 0 (default): the aggregation chain (pairwise passes and Galerkin
+                         products of every level) runs on the device whenever the block
+                         pattern is structurally symmetric, else on the host; 1: always on
+                         the host.  Both give the same hierarchy bit for bit. */
 } msp_options;
 
 typedef struct {

@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
     host = os.path.join(BUILD, "msp_host.o")
     _run(["g++", *HOSTFLAGS, "-c", os.path.join(CSRC, "msp_host.cpp"), "-o", host], verbose)
     objs.append(host)
-    for src in ("msp_kernels.hip", "msp_api.cpp"):
+    for src in ("msp_kernels.hip", "msp_chain.hip", "msp_api.cpp"):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         _run(["hipcc", *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "msp.h"
+#include "msp_chain.h"
 #include "msp_host.h"
 #include "msp_kernels.h"
 #include "msp_stages.h"
@@ -29,6 +30,10 @@ struct MspError {
 };
 
 [[noreturn]] void fail(int code) { throw MspError{code}; }
+[[noreturn]] void fail_hip(hipError_t e)
+{
+    fail(e == hipErrorOutOfMemory ? MSP_ERR_NOMEM : MSP_ERR_HIP);
+}
 
 #define HIPCHK(expr)                                 \
     do {                                             \
@@ -157,6 +162,7 @@ struct msp_ctx {
            *ydev = nullptr, *tmpN = nullptr, *tmpN2 = nullptr;
     double *hhost = nullptr;  // pinned
     int *flag = nullptr, *flag_host = nullptr;
+    int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
     // adaptive state and statistics
     int it_prev = -1, setup_calls = 0, solves = 0;
     msp_info info{};
@@ -775,18 +781,27 @@ void rebuild_B(msp_ctx *c, const double *vals)
     // groups and layout of each coarser smoothed level start as soon as the
     // chain has produced it
     std::vector<std::future<LevelWork>> work(MSP_MAX_LEVELS);
-    int st = build_hierarchy(
-        std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
-        [&work, fp32](int l, int nl, const int *rp, const int *ci, const double *val) {
-            if (l == 0) return;  // level 0: the pattern's groups above
-            work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32]() {
-                LevelWork W;
-                Adjacency adj = build_adjacency(nl, rp, ci);
-                W.G.g = vertices_grouping(adj, W.G.color);
-                level_layout(nl, rp, ci, val, W.G.color, W.G.g, fp32, W.lay);
-                return W;
-            });
+    const LevelCallback start_level = [&work, fp32](int l, int nl, const int *rp, const int *ci,
+                                                    const double *val) {
+        if (l == 0) return;  // level 0: the pattern's groups above
+        work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32]() {
+            LevelWork W;
+            Adjacency adj = build_adjacency(nl, rp, ci);
+            W.G.g = vertices_grouping(adj, W.G.color);
+            level_layout(nl, rp, ci, val, W.G.color, W.G.g, fp32, W.lay);
+            return W;
         });
+    };
+    // the chain on the device (structurally symmetric patterns), else on the host
+    int st = 1;
+    if (c->opt.host_chain == 0)
+        st = device_hierarchy(
+            A0, c->rp_d, c->ci_d, ap, c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, start_level,
+            c->stream, [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip,
+            c->chain_host);
+    if (st == 1)
+        st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
+                             start_level);
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
     const int nlev = (int)H.A.size();
@@ -1183,7 +1198,8 @@ bool valid_options(const msp_options &o)
            ((o.dev_alloc == nullptr) == (o.dev_free == nullptr)) &&
            (o.smoother == 0 || o.smoother == 1) && o.nu_pre >= 0 && o.nu_pre <= 8 &&
            o.nu_post >= 0 && o.nu_post <= 8 && (o.full_smoother == 0 || o.full_smoother == 1) &&
-           o.jacobi_weight > 0.0 && o.jacobi_weight <= 2.0 && (o.n_stage == 0 || o.n_stage == 1);
+           o.jacobi_weight > 0.0 && o.jacobi_weight <= 2.0 && (o.n_stage == 0 || o.n_stage == 1) &&
+           (o.host_chain == 0 || o.host_chain == 1);
 }
 
 // copy a device sliced layout back to natural block order (host)
@@ -1262,6 +1278,7 @@ int msp_default_options(msp_options *opt)
     opt->full_smoother = 0;
     opt->jacobi_weight = 1.0;
     opt->n_stage = 0;
+    opt->host_chain = 0;
     return MSP_OK;
 }
 
@@ -1286,6 +1303,7 @@ int msp_create(msp_ctx **ctx, const msp_options *opt)
         c->stream = (hipStream_t)o.stream;
         HIPCHK(hipHostMalloc((void **)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&c->chain_host, sizeof(int) * 16, hipHostMallocDefault));
         c->flag = (int *)c->dalloc(sizeof(int) * 4, c->allocW);
         c->wsN = -1;
         return MSP_OK;
@@ -1339,6 +1357,7 @@ int msp_destroy(msp_ctx *c)
         kill_event(c->ev_side);
         if (c->hhost) (void)hipHostFree(c->hhost);
         if (c->flag_host) (void)hipHostFree(c->flag_host);
+        if (c->chain_host) (void)hipHostFree(c->chain_host);
         return MSP_OK;
     });
     delete c;

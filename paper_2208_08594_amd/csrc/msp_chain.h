@@ -1,0 +1,47 @@
+// The aggregation chain of the AMG setup on the device: the pairwise passes
+// and Galerkin products of every level, with the same aggregates and the
+// same coarse matrices, bit for bit, as the host chain of msp_host.h.
+//
+// A pairwise pass visits rows in ascending order and pairs each free
+// eligible row with its strongest free eligible candidate (lowest index among
+// equals).  Row i only ever pairs with a candidate j > i (every lower row is
+// already placed when i is visited), so the pass is the greedy maximal
+// matching of the directed edge list {(i, j) : j a candidate of i, j > i}
+// taken in the order (i ascending, candidate rank ascending).  That matching
+// is the lexicographically first maximal matching for this edge order, and
+// it is also what repeated rounds of "take every free edge that comes first
+// at both of its endpoints" produce; the device pass runs those rounds.  The
+// smallest free row always decides in a round, so there are at most n rounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <functional>
+
+#include "msp_host.h"
+
+namespace msp {
+
+// Device memory for the chain's work arrays (freed by the caller after the
+// setup; may throw).
+using DeviceAlloc = std::function<void *(size_t)>;
+// Called with every HIP error; must not return (it throws).
+using HipFail = void (*)(hipError_t);
+
+// Builds the hierarchy of A0 on `st`.  A0 is the host copy of level 0 and
+// rp0/ci0/val0 the same matrix in device memory.  Same contract as
+// build_hierarchy (with_colors = false): H.A holds every level on the host,
+// H.agg every aggregation map, on_smoothed is called for each smoothed level
+// as soon as it is known; returns 0, -3 or -9.  Returns 1 without touching
+// A0 or H when the level-0 pattern is not structurally symmetric (the pass
+// reads a_ji through the mirror entry); the caller then runs the host chain.
+// `pinned` is a host-pinned buffer of at least 16 ints.  A stalled level
+// (the two passes keep more than 90% of its rows) is finished on the host
+// with absorb_singletons and galerkin, and its coarse matrix uploaded.
+int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
+                     int max_coarse, int max_levels, int max_dense, Hierarchy &H,
+                     const LevelCallback &on_smoothed, hipStream_t st,
+                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned);
+
+}  // namespace msp

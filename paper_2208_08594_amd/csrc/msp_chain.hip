@@ -1,0 +1,607 @@
+// Aggregation chain of the AMG setup on the device (Sec. 5 hierarchy, the
+// pairwise rule of the host builder): strength and candidate lists per row,
+// the pairwise pass as rounds of locally first edges, the numbering of the
+// aggregates in creation order and the Galerkin product per coarse row.  The
+// results equal the host chain bit for bit; msp_chain.h gives the argument.
+#include "msp_chain.h"
+
+#include <algorithm>
+#include <vector>
+
+// every sum and comparison below is a single IEEE operation, as on the host
+#pragma clang fp contract(off)
+
+namespace msp {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kScanTile = 1024;  // elements per block of the scan (4 per thread)
+constexpr int kFree = 0, kSingle = 1, kLow = 2, kHigh = 3;
+constexpr int kNone = 0x7fffffff;
+constexpr int kBatch = 16;  // rounds queued between two reads of the free count
+
+inline unsigned nblocks(long long n, int per = kThreads)
+{
+    return (unsigned)std::max<long long>(1, (n + per - 1) / per);
+}
+
+__global__ void k_fill_i32(int *p, int v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Row i of a structurally symmetric M: s_ij = -(m_ij + m_ji)/2 for every
+// stored off-diagonal j (m_ji read through the mirror entry), the largest
+// s_ij, and eligibility (a stored nonzero off-diagonal value, and a positive
+// largest s_ij).  A missing mirror entry sets *asym.
+__global__ void k_strength(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ val, double *__restrict__ s,
+                           double *__restrict__ smax, unsigned char *__restrict__ elig,
+                           int *__restrict__ asym)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool coupled = false, any = false;
+    double mx = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = ci[k];
+        if (j == i) continue;
+        const double aij = val[k];
+        int lo = rp[j], hi = rp[j + 1];
+        const int end = hi;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        double aji = 0.0;
+        if (lo < end && ci[lo] == i)
+            aji = val[lo];
+        else
+            atomicOr(asym, 1);
+        if (aij != 0.0) coupled = true;
+        const double sij = -(aij + aji) / 2.0;
+        s[k] = sij;
+        if (!any || sij > mx) mx = sij;
+        any = true;
+    }
+    smax[i] = mx;
+    elig[i] = (coupled && any && mx > 0.0) ? 1 : 0;
+}
+
+// Candidates of an eligible row i: eligible j > i with s_ij >= 0.25 max_k
+// s_ik, ordered by s_ij descending then j ascending, written over the row's
+// own slots [rp[i], rp[i] + ncand[i]).  (Candidates j < i never matter: they
+// are placed before i is visited.)
+__global__ void k_candidates(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const double *__restrict__ s, const double *__restrict__ smax,
+                             const unsigned char *__restrict__ elig, int *__restrict__ cj,
+                             double *__restrict__ cs, int *__restrict__ ncand)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int m = 0;
+    if (elig[i]) {
+        const double thr = 0.25 * smax[i];
+        const int b0 = rp[i];
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = ci[k];
+            if (j <= i || !elig[j]) continue;
+            const double sj = s[k];
+            if (!(sj >= thr)) continue;
+            int r = m;
+            while (r > 0 && (cs[b0 + r - 1] < sj || (cs[b0 + r - 1] == sj && cj[b0 + r - 1] > j))) {
+                cj[b0 + r] = cj[b0 + r - 1];
+                cs[b0 + r] = cs[b0 + r - 1];
+                --r;
+            }
+            cj[b0 + r] = j;
+            cs[b0 + r] = sj;
+            ++m;
+        }
+    }
+    ncand[i] = m;
+}
+
+// First half of a round.  Every free row i records its first free candidate
+// (its proposal) and, for each free candidate j, offers i as the lowest free
+// row with an edge into j.  The free rows are counted into *nfree.
+__global__ void __launch_bounds__(kThreads)
+k_round_scatter(int n, const int *__restrict__ rp, const int *__restrict__ cj,
+                const int *__restrict__ ncand, const int *__restrict__ state,
+                int *__restrict__ prop, int *__restrict__ min_in, int *__restrict__ nfree)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool fr = false;
+    if (i < n && state[i] == kFree) {
+        fr = true;
+        int p = -1;
+        const int b0 = rp[i], m = ncand[i];
+        for (int q = 0; q < m; ++q) {
+            const int j = cj[b0 + q];
+            if (state[j] == kFree) {
+                if (p < 0) p = j;
+                atomicMin(&min_in[j], i);
+            }
+        }
+        prop[i] = p;
+    }
+    const int cnt = __syncthreads_count(fr);
+    if (threadIdx.x == 0 && cnt) atomicAdd(nfree, cnt);
+}
+
+// Second half.  A free row with no free lower row pointing at it either has
+// no free candidate left (it stays alone) or takes its proposal j when i is
+// the lowest free row pointing at j: that edge comes first at both ends.
+// Also resets the other min_in buffer and the next round's counter.
+__global__ void __launch_bounds__(kThreads)
+k_round_decide(int n, int *__restrict__ state, int *__restrict__ partner,
+               const int *__restrict__ prop, const int *__restrict__ min_in,
+               int *__restrict__ min_in_next, int *__restrict__ nfree_next)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *nfree_next = 0;
+    if (i >= n) return;
+    min_in_next[i] = kNone;
+    // state[i] may turn kHigh during this kernel only when min_in[i] names
+    // another row, which returns here either way
+    if (state[i] != kFree || min_in[i] != kNone) return;
+    const int j = prop[i];
+    if (j < 0) {
+        state[i] = kSingle;
+        return;
+    }
+    if (min_in[j] == i) {
+        state[i] = kLow;
+        state[j] = kHigh;
+        partner[i] = j;
+        partner[j] = i;
+    }
+}
+
+// A row opens an aggregate when it is alone or the lower row of its pair.
+__global__ void k_leaders(int n, const int *__restrict__ state, int *__restrict__ flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = state[i] != kHigh;
+}
+
+// Aggregate numbers in order of their lowest row (= creation order of the
+// ascending visit) and the member rows of every aggregate.
+__global__ void k_number(int n, const int *__restrict__ state, const int *__restrict__ partner,
+                         const int *__restrict__ pos, int *__restrict__ agg,
+                         int *__restrict__ mem0, int *__restrict__ mem1)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int st = state[i];
+    if (st == kHigh) {
+        agg[i] = pos[partner[i]];
+        return;
+    }
+    const int I = pos[i];
+    agg[i] = I;
+    mem0[I] = i;
+    mem1[I] = st == kLow ? partner[i] : -1;
+}
+
+// ---- exclusive scan of n ints: out[0..n], out[n] = total ----------------
+__device__ inline int block_inclusive(int *sh, int t)
+{
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const int x = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += x;
+        __syncthreads();
+    }
+    return sh[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_tile(const int *__restrict__ in, int *__restrict__ out, int *__restrict__ tile_sum, int n)
+{
+    __shared__ int sh[kThreads];
+    const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
+    int v[4], t = 0;
+    for (int q = 0; q < 4; ++q) {
+        const long long i = base + q;
+        v[q] = i < n ? in[i] : 0;
+        t += v[q];
+    }
+    const int incl = block_inclusive(sh, t);
+    int run = incl - t;
+    for (int q = 0; q < 4; ++q) {
+        const long long i = base + q;
+        if (i < n) out[i] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == kThreads - 1) tile_sum[blockIdx.x] = incl;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_sums(int *__restrict__ tile_sum, int ntiles, int *__restrict__ total)
+{
+    __shared__ int sh[kThreads];
+    __shared__ int carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < ntiles; c0 += kThreads) {
+        const int i = c0 + threadIdx.x;
+        const int t = i < ntiles ? tile_sum[i] : 0;
+        const int carry = carry_s;
+        const int incl = block_inclusive(sh, t);
+        if (i < ntiles) tile_sum[i] = carry + incl - t;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) carry_s = carry + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry_s;
+}
+
+__global__ void k_scan_add(int *__restrict__ out, const int *__restrict__ tile_sum, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_sum[i / kScanTile];
+}
+
+// ---- Galerkin product for aggregates of one or two rows -----------------
+// Coarse row I gathers the rows mem0[I] < mem1[I] in order, column by column;
+// entry (I, agg(j)) is the first term, then plus each later term, in that
+// order (the host's (fine row, fine column) order).  The running list,
+// sorted by coarse column, lives in the member rows' own slots of wj/wv
+// (position t < len0 in row mem0, the rest in row mem1).
+__device__ inline int gal_slot(int t, int b0, int len0, int b1)
+{
+    return t < len0 ? b0 + t : b1 + (t - len0);
+}
+
+__global__ void k_gal_rows(int nc, const int *__restrict__ rp, const int *__restrict__ ci,
+                           const double *__restrict__ val, const int *__restrict__ agg,
+                           const int *__restrict__ mem0, const int *__restrict__ mem1,
+                           int *__restrict__ wj, double *__restrict__ wv, int *__restrict__ cnt)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int r0 = mem0[I], r1 = mem1[I];
+    const int b0 = rp[r0], len0 = rp[r0 + 1] - b0;
+    const int b1 = r1 >= 0 ? rp[r1] : 0;
+    int m = 0;
+    for (int w = 0; w < 2; ++w) {
+        const int r = w == 0 ? r0 : r1;
+        if (r < 0) break;
+        for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const int J = agg[ci[k]];
+            const double v = val[k];
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (wj[gal_slot(mid, b0, len0, b1)] < J)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < m && wj[gal_slot(lo, b0, len0, b1)] == J) {
+                const int q = gal_slot(lo, b0, len0, b1);
+                wv[q] = wv[q] + v;
+                continue;
+            }
+            for (int t = m; t > lo; --t) {
+                const int d = gal_slot(t, b0, len0, b1), sidx = gal_slot(t - 1, b0, len0, b1);
+                wj[d] = wj[sidx];
+                wv[d] = wv[sidx];
+            }
+            const int q = gal_slot(lo, b0, len0, b1);
+            wj[q] = J;
+            wv[q] = v;
+            ++m;
+        }
+    }
+    cnt[I] = m;
+}
+
+__global__ void k_gal_fill(int nc, const int *__restrict__ rp, const int *__restrict__ mem0,
+                           const int *__restrict__ mem1, const int *__restrict__ wj,
+                           const double *__restrict__ wv, const int *__restrict__ rpc,
+                           int *__restrict__ cic, double *__restrict__ valc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int r0 = mem0[I], r1 = mem1[I];
+    const int b0 = rp[r0], len0 = rp[r0 + 1] - b0;
+    const int b1 = r1 >= 0 ? rp[r1] : 0;
+    const int o = rpc[I], m = rpc[I + 1] - o;
+    for (int t = 0; t < m; ++t) {
+        const int q = gal_slot(t, b0, len0, b1);
+        cic[o + t] = wj[q];
+        valc[o + t] = wv[q];
+    }
+}
+
+__global__ void k_compose(int n, const int *__restrict__ a1, const int *__restrict__ a2,
+                          int *__restrict__ agg)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) agg[i] = a2[a1[i]];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct DevLevel {
+    int n = 0;
+    int *rp = nullptr, *ci = nullptr;
+    double *val = nullptr;
+};
+
+struct Chain {
+    hipStream_t st = nullptr;
+    HipFail hip_fail = nullptr;
+    int *pinned = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    // work arrays, sized for level 0 (no later matrix is larger)
+    double *s = nullptr, *cs = nullptr, *smax = nullptr;
+    int *cj = nullptr, *ncand = nullptr, *state = nullptr, *partner = nullptr, *prop = nullptr;
+    int *min_in[2] = {nullptr, nullptr};
+    int *pos = nullptr, *flag = nullptr, *cnt = nullptr, *tiles = nullptr, *ctr = nullptr;
+    int *a1 = nullptr, *a2 = nullptr, *aggf = nullptr, *mem0 = nullptr, *mem1 = nullptr;
+    unsigned char *elig = nullptr;
+    DevLevel set[3];  // M1 and two alternating coarse levels
+
+    void ck(hipError_t e) const
+    {
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            hip_fail(e);
+        }
+    }
+    void launched() const { ck(hipGetLastError()); }
+    int read_int(const int *d, int slot)
+    {
+        ck(hipMemcpyAsync(pinned + slot, d, sizeof(int), hipMemcpyDeviceToHost, st));
+        ck(hipStreamSynchronize(st));
+        return pinned[slot];
+    }
+    void fill(int *p, int v, int n)
+    {
+        if (n <= 0) return;
+        k_fill_i32<<<nblocks(n), kThreads, 0, st>>>(p, v, n);
+        launched();
+    }
+    // out[0..n] = exclusive scan of in[0..n), out[n] = total
+    void scan(const int *in, int *out, int n)
+    {
+        const int ntiles = (int)std::max<long long>(1, ((long long)n + kScanTile - 1) / kScanTile);
+        k_scan_tile<<<ntiles, kThreads, 0, st>>>(in, out, tiles, n);
+        launched();
+        k_scan_sums<<<1, kThreads, 0, st>>>(tiles, ntiles, out + n);
+        launched();
+        k_scan_add<<<nblocks(n), kThreads, 0, st>>>(out, tiles, n);
+        launched();
+    }
+    void strength(const DevLevel &L)
+    {
+        k_strength<<<nblocks(L.n), kThreads, 0, st>>>(L.n, L.rp, L.ci, L.val, s, smax, elig,
+                                                      ctr + 2);
+        launched();
+    }
+    // One pairwise pass on L (strength already computed when have_s); agg
+    // into `agg`, members into mem0/mem1; returns the aggregate count.
+    int pass(const DevLevel &L, bool have_s, int *agg)
+    {
+        const int n = L.n;
+        if (!have_s) strength(L);
+        k_candidates<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, L.ci, s, smax, elig, cj, cs, ncand);
+        launched();
+        fill(state, kFree, n);
+        fill(min_in[0], kNone, n);
+        fill(ctr, 0, 2);
+        long long r = 0;
+        int batch = 0, pending = -1;
+        const long long cap = (long long)n + 4LL * kBatch + 4;
+        for (;;) {
+            for (int q = 0; q < kBatch; ++q, ++r) {
+                const int a = (int)(r & 1), b = a ^ 1;
+                k_round_scatter<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, state, prop,
+                                                                 min_in[a], ctr + a);
+                launched();
+                k_round_decide<<<nblocks(n), kThreads, 0, st>>>(n, state, partner, prop,
+                                                                min_in[a], min_in[b], ctr + b);
+                launched();
+            }
+            // free rows seen by the last scatter of this batch
+            const int slot = batch & 1;
+            ck(hipMemcpyAsync(pinned + slot, ctr + ((r - 1) & 1), sizeof(int),
+                              hipMemcpyDeviceToHost, st));
+            ck(hipEventRecord(ev[slot], st));
+            if (pending >= 0) {
+                ck(hipEventSynchronize(ev[pending & 1]));
+                if (pinned[pending & 1] == 0) break;
+            }
+            pending = batch++;
+            // every round settles at least the lowest free row
+            if (r > cap) hip_fail(hipErrorUnknown);
+        }
+        k_leaders<<<nblocks(n), kThreads, 0, st>>>(n, state, flag);
+        launched();
+        scan(flag, pos, n);
+        k_number<<<nblocks(n), kThreads, 0, st>>>(n, state, partner, pos, agg, mem0, mem1);
+        launched();
+        return read_int(pos + n, 2);
+    }
+    // C = P^T L P for the pass just numbered (aggregates of one or two rows);
+    // returns nnz(C).  The candidate arrays serve as the row lists.
+    long long galerkin(const DevLevel &L, const int *agg, int nc, DevLevel &C)
+    {
+        C.n = nc;
+        k_gal_rows<<<nblocks(nc), kThreads, 0, st>>>(nc, L.rp, L.ci, L.val, agg, mem0, mem1, cj,
+                                                     s, cnt);
+        launched();
+        scan(cnt, C.rp, nc);
+        k_gal_fill<<<nblocks(nc), kThreads, 0, st>>>(nc, L.rp, mem0, mem1, cj, s, C.rp, C.ci,
+                                                     C.val);
+        launched();
+        return read_int(C.rp + nc, 3);
+    }
+    void to_host(const DevLevel &C, long long nnz, Csr &H)
+    {
+        H.n = C.n;
+        H.rp.resize(C.n + 1);
+        H.ci.resize(nnz);
+        H.val.resize(nnz);
+        ck(hipMemcpyAsync(H.rp.data(), C.rp, sizeof(int) * (C.n + 1), hipMemcpyDeviceToHost, st));
+        if (nnz) {
+            ck(hipMemcpyAsync(H.ci.data(), C.ci, sizeof(int) * nnz, hipMemcpyDeviceToHost, st));
+            ck(hipMemcpyAsync(H.val.data(), C.val, sizeof(double) * nnz, hipMemcpyDeviceToHost,
+                              st));
+        }
+    }
+    void to_device(const Csr &H, DevLevel &C)
+    {
+        C.n = H.n;
+        ck(hipMemcpyAsync(C.rp, H.rp.data(), sizeof(int) * (H.n + 1), hipMemcpyHostToDevice, st));
+        if (H.nnz()) {
+            ck(hipMemcpyAsync(C.ci, H.ci.data(), sizeof(int) * H.nnz(), hipMemcpyHostToDevice, st));
+            ck(hipMemcpyAsync(C.val, H.val.data(), sizeof(double) * H.nnz(),
+                              hipMemcpyHostToDevice, st));
+        }
+        ck(hipStreamSynchronize(st));
+    }
+};
+
+struct EventGuard {
+    hipEvent_t *ev;
+    ~EventGuard()
+    {
+        for (int i = 0; i < 2; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
+};
+
+template <typename T>
+T *carve(char *&p, long long count)
+{
+    T *r = (T *)p;
+    p += (((size_t)std::max<long long>(count, 1) * sizeof(T)) + 255) & ~(size_t)255;
+    return r;
+}
+
+}  // namespace
+
+int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
+                     int max_coarse, int max_levels, int max_dense, Hierarchy &H,
+                     const LevelCallback &on_smoothed, hipStream_t st,
+                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned)
+{
+    const int n0 = A0.n;
+    const long long nnz0 = A0.nnz();
+    if (n0 <= max_coarse || max_levels <= 1) {
+        H = Hierarchy();
+        H.A.push_back(std::move(A0));
+        return check_hierarchy(H, max_dense);
+    }
+    Chain X;
+    X.st = st;
+    X.hip_fail = hip_fail;
+    X.pinned = pinned;
+    EventGuard guard{X.ev};
+    for (int i = 0; i < 2; ++i) X.ck(hipEventCreateWithFlags(&X.ev[i], hipEventDisableTiming));
+    // one allocation for every work array
+    const long long n1 = (long long)n0 + 1, ntiles = n0 / kScanTile + 2;
+    size_t bytes = 0;
+    auto add = [&](long long count, size_t sz) {
+        bytes += (((size_t)std::max<long long>(count, 1) * sz) + 255) & ~(size_t)255;
+    };
+    add(nnz0, 8); add(nnz0, 8); add(n0, 8);                         // s, cs, smax
+    add(nnz0, 4);                                                   // cj
+    for (int k = 0; k < 9; ++k) add(n0, 4);                         // ncand .. mem1 (n)
+    add(n1, 4); add(n1, 4); add(ntiles, 4); add(4, 4); add(n0, 1);  // pos, cnt, tiles, ctr, elig
+    add(n1, 4);                                                     // flag
+    for (int k = 0; k < 3; ++k) {
+        add(n1, 4);
+        add(nnz0, 4);
+        add(nnz0, 8);
+    }
+    char *p = (char *)alloc(bytes);
+    X.s = carve<double>(p, nnz0);
+    X.cs = carve<double>(p, nnz0);
+    X.smax = carve<double>(p, n0);
+    X.cj = carve<int>(p, nnz0);
+    X.ncand = carve<int>(p, n0);
+    X.state = carve<int>(p, n0);
+    X.partner = carve<int>(p, n0);
+    X.prop = carve<int>(p, n0);
+    X.min_in[0] = carve<int>(p, n0);
+    X.min_in[1] = carve<int>(p, n0);
+    X.a1 = carve<int>(p, n0);
+    X.a2 = carve<int>(p, n0);
+    X.aggf = carve<int>(p, n0);
+    X.mem0 = carve<int>(p, n1);
+    X.mem1 = carve<int>(p, n1);
+    X.pos = carve<int>(p, n1);
+    X.cnt = carve<int>(p, n1);
+    X.tiles = carve<int>(p, ntiles);
+    X.ctr = carve<int>(p, 4);
+    X.elig = carve<unsigned char>(p, n0);
+    X.flag = carve<int>(p, n1);
+    for (int k = 0; k < 3; ++k) {
+        X.set[k].rp = carve<int>(p, n1);
+        X.set[k].ci = carve<int>(p, nnz0);
+        X.set[k].val = carve<double>(p, nnz0);
+    }
+    // level 0: strength first, which also tells whether the pattern is
+    // structurally symmetric
+    DevLevel cur;
+    cur.n = n0;
+    cur.rp = const_cast<int *>(rp0);
+    cur.ci = const_cast<int *>(ci0);
+    cur.val = const_cast<double *>(val0);
+    X.fill(X.ctr + 2, 0, 1);
+    X.strength(cur);
+    if (X.read_int(X.ctr + 2, 0) != 0) return 1;
+
+    H = Hierarchy();
+    H.A.push_back(std::move(A0));
+    bool have_s = true;
+    int next = 1;  // set[0] holds M1; levels alternate between set[1] and set[2]
+    for (int l = 0;; ++l) {
+        const Csr &hc = H.A[l];
+        const bool last = hc.n <= max_coarse || l == max_levels - 1 ||
+                          (l > 0 && (double)hc.n > 0.9 * (double)H.A[l - 1].n);
+        if (last) break;
+        if (on_smoothed) on_smoothed(l, hc.n, hc.rp.data(), hc.ci.data(), hc.val.data());
+        const int nc1 = X.pass(cur, have_s, X.a1);
+        have_s = false;
+        DevLevel &M1 = X.set[0];
+        X.galerkin(cur, X.a1, nc1, M1);
+        const int nc2 = X.pass(M1, false, X.a2);
+        DevLevel &C = X.set[next];
+        const long long nnzc = X.galerkin(M1, X.a2, nc2, C);
+        k_compose<<<nblocks(cur.n), kThreads, 0, st>>>(cur.n, X.a1, X.a2, X.aggf);
+        X.launched();
+        std::vector<int> agg(cur.n);
+        X.ck(hipMemcpyAsync(agg.data(), X.aggf, sizeof(int) * cur.n, hipMemcpyDeviceToHost, st));
+        Csr Cn;
+        X.to_host(C, nnzc, Cn);
+        X.ck(hipStreamSynchronize(st));
+        if ((double)nc2 > 0.9 * (double)cur.n) {
+            // stalled: absorb singletons, then one Galerkin product on A_l
+            const int nc3 = absorb_singletons(H.A[l], agg, nc2);
+            if (nc3 < nc2) {
+                Cn = msp::galerkin(H.A[l], agg, nc3);
+                X.to_device(Cn, C);
+            }
+        }
+        H.agg.push_back(std::move(agg));
+        H.A.push_back(std::move(Cn));
+        cur = C;
+        next = 3 - next;
+    }
+    return check_hierarchy(H, max_dense);
+}
+
+}  // namespace msp

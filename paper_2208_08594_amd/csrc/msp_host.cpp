@@ -545,6 +545,11 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         H.agg.push_back(std::move(agg));
         H.A.push_back(std::move(Cn));
     }
+    return check_hierarchy(H, max_dense);
+}
+
+int check_hierarchy(const Hierarchy &H, int max_dense)
+{
     for (size_t l = 0; l + 1 < H.A.size(); ++l) {
         const Csr &A = H.A[l];
         for (int i = 0; i < A.n; ++i) {

@@ -67,6 +67,9 @@ struct Hierarchy {
 using LevelCallback = std::function<void(int, int, const int *, const int *, const double *)>;
 int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                     bool with_colors = true, const LevelCallback &on_smoothed = nullptr);
+// The final checks of build_hierarchy: 0, -3 (zero diagonal on a smoothed
+// level) or -9 (coarsest level above max_dense rows).
+int check_hierarchy(const Hierarchy &H, int max_dense);
 // groups of Alg. 4.2 on one level: fills color, returns g
 int color_level(const Csr &A, std::vector<int> &color);
 

@@ -33,7 +33,7 @@ class MspOptions(C.Structure):
                 ("use_graphs", C.c_int), ("stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_user", C.c_void_p), ("smoother", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("full_smoother", C.c_int), ("jacobi_weight", C.c_double),
-                ("n_stage", C.c_int)]
+                ("n_stage", C.c_int), ("host_chain", C.c_int)]
 
 
 class MspInfo(C.Structure):
@@ -169,7 +169,7 @@ class Solver:
     def __init__(self, mu=0, restart=30, max_iter=1000, max_coarse=10000, precond_fp32=False,
                  bilu_order=1, stream=None, device=None, torch_allocator=True, use_graphs=True,
                  smoother=0, jacobi_weight=1.0, nu_pre=1, nu_post=1, full_smoother=0,
-                 n_stage=0):
+                 n_stage=0, host_chain=False):
         import torch
         self.torch = torch
         dev = torch.device("cuda") if device is None else torch.device(device)
@@ -187,6 +187,7 @@ class Solver:
         opt.smoother, opt.jacobi_weight = int(smoother), float(jacobi_weight)
         opt.nu_pre, opt.nu_post, opt.full_smoother = int(nu_pre), int(nu_post), int(full_smoother)
         opt.n_stage = int(n_stage)
+        opt.host_chain = 1 if host_chain else 0
         opt.stream = C.c_void_p(self.stream.cuda_stream)
         self._alloc = None
         if torch_allocator:

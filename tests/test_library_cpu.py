@@ -49,9 +49,10 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "msp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(msp_options), offsetof(msp_options, stream),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(msp_options), offsetof(msp_options, stream),
          offsetof(msp_options, alloc_user), offsetof(msp_options, full_smoother),
-         offsetof(msp_options, jacobi_weight), offsetof(msp_options, n_stage), sizeof(msp_info),
+         offsetof(msp_options, jacobi_weight), offsetof(msp_options, n_stage),
+         offsetof(msp_options, host_chain), sizeof(msp_info),
          offsetof(msp_info, rel_true_residual), offsetof(msp_info, phase_ms));
   return 0;
 }
@@ -64,7 +65,7 @@ int main(void) {
         vals = list(map(int, subprocess.check_output([exe]).split()))
     got = [C.sizeof(msp.MspOptions), msp.MspOptions.stream.offset, msp.MspOptions.alloc_user.offset,
            msp.MspOptions.full_smoother.offset, msp.MspOptions.jacobi_weight.offset,
-           msp.MspOptions.n_stage.offset,
+           msp.MspOptions.n_stage.offset, msp.MspOptions.host_chain.offset,
            C.sizeof(msp.MspInfo), msp.MspInfo.rel_true_residual.offset, msp.MspInfo.phase_ms.offset]
     assert vals == got
 
