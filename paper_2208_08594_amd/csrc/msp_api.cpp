@@ -794,11 +794,14 @@ void rebuild_B(msp_ctx *c, const double *vals)
     };
     // the chain on the device (structurally symmetric patterns), else on the host
     int st = 1;
-    if (c->opt.host_chain == 0)
+    if (c->opt.host_chain == 0) {
+        if (!c->cap_stream)
+            HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         st = device_hierarchy(
             A0, c->rp_d, c->ci_d, ap, c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, start_level,
-            c->stream, [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip,
-            c->chain_host);
+            c->stream, c->cap_stream, [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); },
+            fail_hip, c->chain_host);
+    }
     if (st == 1)
         st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
                              start_level);

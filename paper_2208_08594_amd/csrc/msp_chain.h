@@ -36,12 +36,14 @@ using HipFail = void (*)(hipError_t);
 // as soon as it is known; returns 0, -3 or -9.  Returns 1 without touching
 // A0 or H when the level-0 pattern is not structurally symmetric (the pass
 // reads a_ji through the mirror entry); the caller then runs the host chain.
-// `pinned` is a host-pinned buffer of at least 16 ints.  A stalled level
-// (the two passes keep more than 90% of its rows) is finished on the host
-// with absorb_singletons and galerkin, and its coarse matrix uploaded.
+// `cap` is an idle stream used only to capture batches of matching rounds
+// into a graph (nothing runs on it).  `pinned` is a host-pinned buffer of at
+// least 16 ints.  A stalled level (the two passes keep more than 90% of its
+// rows) is finished on the host with absorb_singletons and galerkin, and its
+// coarse matrix uploaded.
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                     const LevelCallback &on_smoothed, hipStream_t st,
+                     const LevelCallback &on_smoothed, hipStream_t st, hipStream_t cap,
                      const DeviceAlloc &alloc, HipFail hip_fail, int *pinned);
 
 }  // namespace msp

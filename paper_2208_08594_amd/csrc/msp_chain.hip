@@ -106,60 +106,94 @@ __global__ void k_candidates(int n, const int *__restrict__ rp, const int *__res
     ncand[i] = m;
 }
 
-// First half of a round.  Every free row i records its first free candidate
-// (its proposal) and, for each free candidate j, offers i as the lowest free
-// row with an edge into j.  The free rows are counted into *nfree.
-__global__ void __launch_bounds__(kThreads)
-k_round_scatter(int n, const int *__restrict__ rp, const int *__restrict__ cj,
-                const int *__restrict__ ncand, const int *__restrict__ state,
-                int *__restrict__ prop, int *__restrict__ min_in, int *__restrict__ nfree)
+// Lists of the lower rows pointing at each row: in_ptr/in_row, the
+// transpose of the candidate lists (order inside a list is free).
+__global__ void k_in_count(int n, const int *__restrict__ rp, const int *__restrict__ cj,
+                           const int *__restrict__ ncand, int *__restrict__ indeg)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int q = 0; q < ncand[i]; ++q) atomicAdd(&indeg[cj[rp[i] + q]], 1);
+}
+
+__global__ void k_in_fill(int n, const int *__restrict__ rp, const int *__restrict__ cj,
+                          const int *__restrict__ ncand, const int *__restrict__ in_ptr,
+                          int *__restrict__ cursor, int *__restrict__ in_row)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int q = 0; q < ncand[i]; ++q) {
+        const int j = cj[rp[i] + q];
+        in_row[in_ptr[j] + atomicAdd(&cursor[j], 1)] = i;
+    }
+}
+
+// lowest free row with a candidate edge into v (kNone if there is none)
+__device__ inline int lowest_free_in(int v, const int *__restrict__ in_ptr,
+                                     const int *__restrict__ in_row, const int *__restrict__ st)
+{
+    int m = kNone;
+    for (int q = in_ptr[v]; q < in_ptr[v + 1]; ++q) {
+        const int k = in_row[q];
+        if (k < m && st[k] == kFree) m = k;
+    }
+    return m;
+}
+
+// first free candidate of v (its proposal), -1 if none is left
+__device__ inline int first_free_cand(int v, const int *__restrict__ rp, const int *__restrict__ cj,
+                                      const int *__restrict__ ncand, const int *__restrict__ st)
+{
+    const int b0 = rp[v], m = ncand[v];
+    for (int q = 0; q < m; ++q) {
+        const int j = cj[b0 + q];
+        if (st[j] == kFree) return j;
+    }
+    return -1;
+}
+
+// One round.  An edge (i, j) between free rows is taken when i has no free
+// lower row pointing at it, j is i's first free candidate, and i is the
+// lowest free row pointing at j: the edge then comes first at both of its
+// ends.  A free row with no free lower row pointing at it and no free
+// candidate stays alone.  Every row evaluates this from the round's input
+// states (st) and writes only its own output state (st_next), so the two
+// ends of a taken edge reach the same verdict independently.  Free rows of
+// the input are counted into *nfree; *nfree_next is cleared for the next
+// round.
+__global__ void __launch_bounds__(kThreads)
+k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
+        const int *__restrict__ ncand, const int *__restrict__ in_ptr,
+        const int *__restrict__ in_row, const int *__restrict__ st, int *__restrict__ st_next,
+        int *__restrict__ partner, int *__restrict__ nfree, int *__restrict__ nfree_next)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) *nfree_next = 0;
     bool fr = false;
-    if (i < n && state[i] == kFree) {
-        fr = true;
-        int p = -1;
-        const int b0 = rp[i], m = ncand[i];
-        for (int q = 0; q < m; ++q) {
-            const int j = cj[b0 + q];
-            if (state[j] == kFree) {
-                if (p < 0) p = j;
-                atomicMin(&min_in[j], i);
+    if (v < n) {
+        const int s0 = st[v];
+        int s1 = s0;
+        if (s0 == kFree) {
+            fr = true;
+            const int m = lowest_free_in(v, in_ptr, in_row, st);
+            if (m == kNone) {
+                const int p = first_free_cand(v, rp, cj, ncand, st);
+                if (p < 0) {
+                    s1 = kSingle;
+                } else if (lowest_free_in(p, in_ptr, in_row, st) == v) {
+                    s1 = kLow;
+                    partner[v] = p;
+                }
+            } else if (lowest_free_in(m, in_ptr, in_row, st) == kNone &&
+                       first_free_cand(m, rp, cj, ncand, st) == v) {
+                s1 = kHigh;
+                partner[v] = m;
             }
         }
-        prop[i] = p;
+        st_next[v] = s1;
     }
     const int cnt = __syncthreads_count(fr);
     if (threadIdx.x == 0 && cnt) atomicAdd(nfree, cnt);
-}
-
-// Second half.  A free row with no free lower row pointing at it either has
-// no free candidate left (it stays alone) or takes its proposal j when i is
-// the lowest free row pointing at j: that edge comes first at both ends.
-// Also resets the other min_in buffer and the next round's counter.
-__global__ void __launch_bounds__(kThreads)
-k_round_decide(int n, int *__restrict__ state, int *__restrict__ partner,
-               const int *__restrict__ prop, const int *__restrict__ min_in,
-               int *__restrict__ min_in_next, int *__restrict__ nfree_next)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *nfree_next = 0;
-    if (i >= n) return;
-    min_in_next[i] = kNone;
-    // state[i] may turn kHigh during this kernel only when min_in[i] names
-    // another row, which returns here either way
-    if (state[i] != kFree || min_in[i] != kNone) return;
-    const int j = prop[i];
-    if (j < 0) {
-        state[i] = kSingle;
-        return;
-    }
-    if (min_in[j] == i) {
-        state[i] = kLow;
-        state[j] = kHigh;
-        partner[i] = j;
-        partner[j] = i;
-    }
 }
 
 // A row opens an aggregate when it is alone or the lower row of its pair.
@@ -345,8 +379,10 @@ struct Chain {
     hipEvent_t ev[2] = {nullptr, nullptr};
     // work arrays, sized for level 0 (no later matrix is larger)
     double *s = nullptr, *cs = nullptr, *smax = nullptr;
-    int *cj = nullptr, *ncand = nullptr, *state = nullptr, *partner = nullptr, *prop = nullptr;
-    int *min_in[2] = {nullptr, nullptr};
+    int *cj = nullptr, *ncand = nullptr, *partner = nullptr;
+    int *state[2] = {nullptr, nullptr};  // round input / output, alternating
+    int *in_ptr = nullptr, *in_row = nullptr;
+    hipStream_t cap = nullptr;            // capture stream for the round batches
     int *pos = nullptr, *flag = nullptr, *cnt = nullptr, *tiles = nullptr, *ctr = nullptr;
     int *a1 = nullptr, *a2 = nullptr, *aggf = nullptr, *mem0 = nullptr, *mem1 = nullptr;
     unsigned char *elig = nullptr;
@@ -397,25 +433,51 @@ struct Chain {
         if (!have_s) strength(L);
         k_candidates<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, L.ci, s, smax, elig, cj, cs, ncand);
         launched();
-        fill(state, kFree, n);
-        fill(min_in[0], kNone, n);
+        // in-lists (cnt counts, flag serves as the fill cursor)
+        fill(cnt, 0, n);
+        fill(flag, 0, n);
+        k_in_count<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, cnt);
+        launched();
+        scan(cnt, in_ptr, n);
+        k_in_fill<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, in_ptr, flag, in_row);
+        launched();
+        fill(state[0], kFree, n);
         fill(ctr, 0, 2);
+        // kBatch rounds (an even number: the states end in state[0]) as one graph
+        hipGraphExec_t exec = nullptr;
+        {
+            ck(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            for (int q = 0; q < kBatch; ++q) {
+                const int a = q & 1;
+                k_round<<<nblocks(n), kThreads, 0, cap>>>(n, L.rp, cj, ncand, in_ptr, in_row,
+                                                          state[a], state[a ^ 1], partner,
+                                                          ctr + a, ctr + (a ^ 1));
+            }
+            hipGraph_t g = nullptr;
+            const hipError_t e1 = hipStreamEndCapture(cap, &g);
+            const hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&exec, g, nullptr, nullptr, 0)
+                                                   : e1;
+            if (g) (void)hipGraphDestroy(g);
+            ck(e2);
+        }
+        struct ExecGuard {
+            hipGraphExec_t e;
+            hipStream_t s;
+            ~ExecGuard()
+            {
+                (void)hipStreamSynchronize(s);
+                (void)hipGraphExecDestroy(e);
+            }
+        } exec_guard{exec, st};
         long long r = 0;
         int batch = 0, pending = -1;
-        const long long cap = (long long)n + 4LL * kBatch + 4;
+        const long long cap_rounds = (long long)n + 4LL * kBatch + 4;
         for (;;) {
-            for (int q = 0; q < kBatch; ++q, ++r) {
-                const int a = (int)(r & 1), b = a ^ 1;
-                k_round_scatter<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, state, prop,
-                                                                 min_in[a], ctr + a);
-                launched();
-                k_round_decide<<<nblocks(n), kThreads, 0, st>>>(n, state, partner, prop,
-                                                                min_in[a], min_in[b], ctr + b);
-                launched();
-            }
-            // free rows seen by the last scatter of this batch
+            ck(hipGraphLaunch(exec, st));
+            r += kBatch;
+            // free rows at the start of the batch's last round
             const int slot = batch & 1;
-            ck(hipMemcpyAsync(pinned + slot, ctr + ((r - 1) & 1), sizeof(int),
+            ck(hipMemcpyAsync(pinned + slot, ctr + ((kBatch - 1) & 1), sizeof(int),
                               hipMemcpyDeviceToHost, st));
             ck(hipEventRecord(ev[slot], st));
             if (pending >= 0) {
@@ -424,12 +486,12 @@ struct Chain {
             }
             pending = batch++;
             // every round settles at least the lowest free row
-            if (r > cap) hip_fail(hipErrorUnknown);
+            if (r > cap_rounds) hip_fail(hipErrorUnknown);
         }
-        k_leaders<<<nblocks(n), kThreads, 0, st>>>(n, state, flag);
+        k_leaders<<<nblocks(n), kThreads, 0, st>>>(n, state[0], flag);
         launched();
         scan(flag, pos, n);
-        k_number<<<nblocks(n), kThreads, 0, st>>>(n, state, partner, pos, agg, mem0, mem1);
+        k_number<<<nblocks(n), kThreads, 0, st>>>(n, state[0], partner, pos, agg, mem0, mem1);
         launched();
         return read_int(pos + n, 2);
     }
@@ -482,19 +544,52 @@ struct EventGuard {
     }
 };
 
-template <typename T>
-T *carve(char *&p, long long count)
+// Sets every work array of X to its offset in one allocation at `base`,
+// each sized for level 0 (no later matrix is larger) and 256-byte aligned;
+// with base == nullptr it only measures.  Returns the bytes used.
+size_t place(Chain &X, char *base, int n0, long long nnz0)
 {
-    T *r = (T *)p;
-    p += (((size_t)std::max<long long>(count, 1) * sizeof(T)) + 255) & ~(size_t)255;
-    return r;
+    const long long n1 = (long long)n0 + 1, ntiles = n0 / kScanTile + 2;
+    size_t off = 0;
+    auto take = [&](long long count, size_t sz) -> void * {
+        void *r = base ? (void *)(base + off) : nullptr;
+        off += (((size_t)std::max<long long>(count, 1) * sz) + 255) & ~(size_t)255;
+        return r;
+    };
+    X.s = (double *)take(nnz0, sizeof(double));
+    X.cs = (double *)take(nnz0, sizeof(double));
+    X.smax = (double *)take(n0, sizeof(double));
+    X.cj = (int *)take(nnz0, sizeof(int));
+    X.in_row = (int *)take(nnz0, sizeof(int));
+    X.ncand = (int *)take(n0, sizeof(int));
+    X.state[0] = (int *)take(n0, sizeof(int));
+    X.state[1] = (int *)take(n0, sizeof(int));
+    X.partner = (int *)take(n0, sizeof(int));
+    X.a1 = (int *)take(n0, sizeof(int));
+    X.a2 = (int *)take(n0, sizeof(int));
+    X.aggf = (int *)take(n0, sizeof(int));
+    X.in_ptr = (int *)take(n1, sizeof(int));
+    X.mem0 = (int *)take(n1, sizeof(int));
+    X.mem1 = (int *)take(n1, sizeof(int));
+    X.pos = (int *)take(n1, sizeof(int));
+    X.cnt = (int *)take(n1, sizeof(int));
+    X.flag = (int *)take(n1, sizeof(int));
+    X.tiles = (int *)take(ntiles, sizeof(int));
+    X.ctr = (int *)take(4, sizeof(int));
+    X.elig = (unsigned char *)take(n0, 1);
+    for (int k = 0; k < 3; ++k) {
+        X.set[k].rp = (int *)take(n1, sizeof(int));
+        X.set[k].ci = (int *)take(nnz0, sizeof(int));
+        X.set[k].val = (double *)take(nnz0, sizeof(double));
+    }
+    return off;
 }
 
 }  // namespace
 
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                     const LevelCallback &on_smoothed, hipStream_t st,
+                     const LevelCallback &on_smoothed, hipStream_t st, hipStream_t cap,
                      const DeviceAlloc &alloc, HipFail hip_fail, int *pinned)
 {
     const int n0 = A0.n;
@@ -506,53 +601,14 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     }
     Chain X;
     X.st = st;
+    X.cap = cap;
     X.hip_fail = hip_fail;
     X.pinned = pinned;
     EventGuard guard{X.ev};
     for (int i = 0; i < 2; ++i) X.ck(hipEventCreateWithFlags(&X.ev[i], hipEventDisableTiming));
     // one allocation for every work array
-    const long long n1 = (long long)n0 + 1, ntiles = n0 / kScanTile + 2;
-    size_t bytes = 0;
-    auto add = [&](long long count, size_t sz) {
-        bytes += (((size_t)std::max<long long>(count, 1) * sz) + 255) & ~(size_t)255;
-    };
-    add(nnz0, 8); add(nnz0, 8); add(n0, 8);                         // s, cs, smax
-    add(nnz0, 4);                                                   // cj
-    for (int k = 0; k < 9; ++k) add(n0, 4);                         // ncand .. mem1 (n)
-    add(n1, 4); add(n1, 4); add(ntiles, 4); add(4, 4); add(n0, 1);  // pos, cnt, tiles, ctr, elig
-    add(n1, 4);                                                     // flag
-    for (int k = 0; k < 3; ++k) {
-        add(n1, 4);
-        add(nnz0, 4);
-        add(nnz0, 8);
-    }
-    char *p = (char *)alloc(bytes);
-    X.s = carve<double>(p, nnz0);
-    X.cs = carve<double>(p, nnz0);
-    X.smax = carve<double>(p, n0);
-    X.cj = carve<int>(p, nnz0);
-    X.ncand = carve<int>(p, n0);
-    X.state = carve<int>(p, n0);
-    X.partner = carve<int>(p, n0);
-    X.prop = carve<int>(p, n0);
-    X.min_in[0] = carve<int>(p, n0);
-    X.min_in[1] = carve<int>(p, n0);
-    X.a1 = carve<int>(p, n0);
-    X.a2 = carve<int>(p, n0);
-    X.aggf = carve<int>(p, n0);
-    X.mem0 = carve<int>(p, n1);
-    X.mem1 = carve<int>(p, n1);
-    X.pos = carve<int>(p, n1);
-    X.cnt = carve<int>(p, n1);
-    X.tiles = carve<int>(p, ntiles);
-    X.ctr = carve<int>(p, 4);
-    X.elig = carve<unsigned char>(p, n0);
-    X.flag = carve<int>(p, n1);
-    for (int k = 0; k < 3; ++k) {
-        X.set[k].rp = carve<int>(p, n1);
-        X.set[k].ci = carve<int>(p, nnz0);
-        X.set[k].val = carve<double>(p, nnz0);
-    }
+    char *base = (char *)alloc(place(X, nullptr, n0, nnz0));
+    place(X, base, n0, nnz0);
     // level 0: strength first, which also tells whether the pattern is
     // structurally symmetric
     DevLevel cur;
