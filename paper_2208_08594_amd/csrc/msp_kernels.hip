@@ -1003,6 +1003,8 @@ __device__ inline unsigned long long pivot_key(double v, int r)
 
 constexpr int kDP = 16;  // column panel of the diagonal-block inverse
 
+typedef double gjd4 __attribute__((ext_vector_type(4)));
+
 // Inverse of the kb x kb diagonal block at (K, K) (kb <= 128, padded with the
 // identity) by blocked Gauss-Jordan elimination with partial pivoting inside
 // the block.  Pivoting is implicit: column k is eliminated with the unused row
@@ -1012,9 +1014,12 @@ constexpr int kDP = 16;  // column panel of the diagonal-block inverse
 // Per panel of 16 columns, wave 0 eliminates the panel alone (pivot search
 // by DPP max over packed keys, pivot row by lane reads), tracking the panel's
 // row transformation T = I + (Z - E_P) E_P^T; then all four waves apply it to
-// the other columns as one rank-16 update S += (Z - E_P) S[P, :] and store Z
-// in the panel's slots.  Thread (tr, tc) holds rows tr + 16a and columns
-// tc + 16b (a, b < 8).  Dblk has leading dimension kNB.
+// the other columns as one rank-16 update S += (Z - E_P) S[P, :] on the FP64
+// matrix cores and store Z in the panel's slots.  S lives in MFMA
+// accumulator tiles of 16 x 16: wave w holds rows 32w .. 32w + 31 (tiles
+// rt = 0, 1) of every column tile ct; element r of lane (li, lk) of tile
+// (rt, ct) is S[32w + 16rt + lk + 4r][16ct + li].  Dblk has leading
+// dimension kNB.
 __global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
                                                  const double *__restrict__ M,
                                                  double *__restrict__ Dblk, int *bad)
@@ -1026,30 +1031,33 @@ __global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
     __shared__ int prow[kNB];             // pivot row of column k
     __shared__ int invp[kNB];             // column whose pivot row is i
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tr = tid >> 4, tc = tid & 15;
-    double S[8][8];
+    const int li = lane & 15, lk = lane >> 4;
+    const int row0 = 32 * wave + lk;  // + 16 rt + 4 r
+    gjd4 S[2][8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int r = tr + 16 * a, c = tc + 16 * b;
-            S[a][b] = (r < kb && c < kb) ? M[(long long)(K + r) * ld + K + c] : (r == c ? 1.0 : 0.0);
-        }
+        for (int ct = 0; ct < 8; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = row0 + 16 * rt + 4 * r, j = 16 * ct + li;
+                S[rt][ct][r] = (i < kb && j < kb) ? M[(long long)(K + i) * ld + K + j]
+                                                  : (i == j ? 1.0 : 0.0);
+            }
     if (tid < kNB) {
         prow[tid] = -1;
         invp[tid] = -1;
     }
     bool used0 = false, used1 = false;  // wave 0: rows lane and lane + 64
     for (int pnl = 0; pnl < kNB / kDP; ++pnl) {
-        // panel columns 16 pnl + tc are the slots b == pnl
+        // the panel's column tile to LDS
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            double v = 0.0;
+        for (int ct = 0; ct < 8; ++ct)
+            if (ct == pnl)
 #pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b == pnl) v = S[a][b];
-            Pn[tr + 16 * a][tc] = v;
-        }
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Pn[row0 + 16 * rt + 4 * r][li] = S[rt][ct][r];
         __syncthreads();
         if (wave == 0) {
             double P0[kDP], P1[kDP], Z0[kDP], Z1[kDP];
@@ -1132,30 +1140,34 @@ __global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
         __syncthreads();
         // pivot rows (before this panel's transformation) to LDS
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int t = rstep[tr + 16 * a];
-            if (t >= 0)
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                for (int b = 0; b < 8; ++b) Rp[t][tc + 16 * b] = S[a][b];
-        }
+            for (int r = 0; r < 4; ++r) {
+                const int t = rstep[row0 + 16 * rt + 4 * r];
+                if (t >= 0)
+#pragma unroll
+                    for (int ct = 0; ct < 8; ++ct) Rp[t][16 * ct + li] = S[rt][ct][r];
+            }
         __syncthreads();
-        // S += (Z - E_P) S[P, :] outside the panel; the panel slots take Z
+        // S += (Z - E_P) S[P, :] outside the panel; the panel tile takes Z
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int i = tr + 16 * a;
-            double z[kDP];
+        for (int rt = 0; rt < 2; ++rt) {
+            double av[kDP / 4];
 #pragma unroll
-            for (int t = 0; t < kDP; ++t) z[t] = Zm[i][t];
-            const double zpanel = z[tc] + (rstep[i] == tc ? 1.0 : 0.0);
+            for (int kk = 0; kk < kDP / 4; ++kk) av[kk] = Zm[32 * wave + 16 * rt + li][4 * kk + lk];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                if (b == pnl) {
-                    S[a][b] = zpanel;
+            for (int ct = 0; ct < 8; ++ct) {
+                if (ct == pnl) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = row0 + 16 * rt + 4 * r;
+                        S[rt][ct][r] = Zm[i][li] + (rstep[i] == li ? 1.0 : 0.0);
+                    }
                 } else {
-                    double acc = S[a][b];
 #pragma unroll
-                    for (int t = 0; t < kDP; ++t) acc += z[t] * Rp[t][tc + 16 * b];
-                    S[a][b] = acc;
+                    for (int kk = 0; kk < kDP / 4; ++kk)
+                        S[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            av[kk], Rp[4 * kk + lk][16 * ct + li], S[rt][ct], 0, 0, 0);
                 }
             }
         }
@@ -1165,14 +1177,16 @@ __global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
     __syncthreads();
     // S[i][c] = X[i][p_c] = A^-1[invp(i)][p_c]
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const int q = invp[tr + 16 * a];
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int col = prow[tc + 16 * b];
-            if (q >= 0 && q < kb && col >= 0 && col < kb) Dblk[q * kNB + col] = S[a][b];
+        for (int r = 0; r < 4; ++r) {
+            const int q = invp[row0 + 16 * rt + 4 * r];
+#pragma unroll
+            for (int ct = 0; ct < 8; ++ct) {
+                const int col = prow[16 * ct + li];
+                if (q >= 0 && q < kb && col >= 0 && col < kb) Dblk[q * kNB + col] = S[rt][ct][r];
+            }
         }
-    }
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
         const int r = idx / kNB, c = idx % kNB;
         if (r >= kb || c >= kb) Dblk[idx] = 0.0;
