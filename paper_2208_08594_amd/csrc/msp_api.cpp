@@ -163,6 +163,8 @@ struct msp_ctx {
     double *hhost = nullptr;  // pinned
     int *flag = nullptr, *flag_host = nullptr;
     int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
+    hipStream_t chain_copy = nullptr;  // device-to-host copies of the setup
+    hipEvent_t ev_a0 = nullptr;
     // adaptive state and statistics
     int it_prev = -1, setup_calls = 0, solves = 0;
     msp_info info{};
@@ -191,6 +193,7 @@ struct msp_ctx {
             if (side) (void)hipStreamSynchronize(side);
             if (gj.aux) (void)hipStreamSynchronize(gj.aux);
             if (gj.main) (void)hipStreamSynchronize(gj.main);
+            if (chain_copy) (void)hipStreamSynchronize(chain_copy);
         }
         for (void *p_ : list) {
             if (opt.dev_free)
@@ -714,17 +717,33 @@ void rebuild_B(msp_ctx *c, const double *vals)
     c->omega = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
     std::vector<void *> tmp;
     ReleaseScope release_tmp(c, tmp);
+    // H is declared before every future that reads or writes its arrays, so
+    // those are joined first on every exit; the level arrays only move
+    // (never copy) as the level list grows.
+    Hierarchy H;
+    static_assert(std::is_nothrow_move_constructible<Csr>::value,
+                  "level arrays must move, not copy, when the level list grows");
     double *ap = (double *)c->dalloc(sizeof(double) * (size_t)c->nnzb, tmp);
     c->clear_flag();
     HIPCHK(launch_decouple(b, c->p, n, c->rp_d, c->diag_d, vals, c->omega, ap, c->flag,
                            c->stream));
+    if (!c->ev_a0) HIPCHK(hipEventCreateWithFlags(&c->ev_a0, hipEventDisableTiming));
+    if (!c->chain_copy) HIPCHK(hipStreamCreateWithFlags(&c->chain_copy, hipStreamNonBlocking));
+    HIPCHK(hipEventRecord(c->ev_a0, c->stream));
     Csr A0;
     A0.n = n;
     A0.rp = c->rp;
     A0.ci = c->ci;
     A0.val.resize(c->nnzb);
-    HIPCHK(hipMemcpyAsync(A0.val.data(), ap, sizeof(double) * c->nnzb, hipMemcpyDeviceToHost,
-                          c->stream));
+    // the decoupled pressure values reach the host on a copy thread; the
+    // device chain below does not need them
+    std::shared_future<void> a0_ready =
+        std::async(std::launch::async, [c, dst = A0.val.data(), ap]() {
+            HIPCHK(hipStreamWaitEvent(c->chain_copy, c->ev_a0, 0));
+            HIPCHK(hipMemcpyAsync(dst, ap, sizeof(double) * c->nnzb, hipMemcpyDeviceToHost,
+                                  c->chain_copy));
+            HIPCHK(hipStreamSynchronize(c->chain_copy));
+        }).share();
     if (c->read_flag()) fail(MSP_ERR_SINGULAR);
     phase(2);
     // Host setup after the decoupling.  The aggregation chain (pairwise passes
@@ -749,12 +768,6 @@ void rebuild_B(msp_ctx *c, const double *vals)
         LevelLayout lay;
     };
     const bool fp32 = c->fp32();
-    // H is declared before every future that reads its arrays, so those are
-    // joined first on every exit; the level arrays only move (never copy) as
-    // the level list grows.
-    Hierarchy H;
-    static_assert(std::is_nothrow_move_constructible<Csr>::value,
-                  "level arrays must move, not copy, when the level list grows");
     const double *a0val = A0.val.data();
     const bool level0_smoothed = n > c->opt.max_coarse;
     std::shared_future<Groups> groups0 = std::async(std::launch::async, [c]() {
@@ -765,8 +778,9 @@ void rebuild_B(msp_ctx *c, const double *vals)
     }).share();
     std::future<LevelLayout> layout0;
     if (level0_smoothed)
-        layout0 = std::async(std::launch::async, [c, groups0, a0val, fp32]() {
+        layout0 = std::async(std::launch::async, [c, groups0, a0_ready, a0val, fp32]() {
             const Groups &G = groups0.get();
+            a0_ready.get();
             LevelLayout O;
             level_layout(c->n, c->rp.data(), c->ci.data(), a0val, G.color, G.g, fp32, O);
             return O;
@@ -799,12 +813,14 @@ void rebuild_B(msp_ctx *c, const double *vals)
             HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         st = device_hierarchy(
             A0, c->rp_d, c->ci_d, ap, c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, start_level,
-            c->stream, c->cap_stream, [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); },
-            fail_hip, c->chain_host);
+            [&a0_ready]() { a0_ready.get(); }, c->stream, c->cap_stream, c->chain_copy,
+            [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip, c->chain_host);
     }
-    if (st == 1)
+    if (st == 1) {
+        a0_ready.get();
         st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
                              start_level);
+    }
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
     const int nlev = (int)H.A.size();
@@ -1347,6 +1363,8 @@ int msp_destroy(msp_ctx *c)
             e = nullptr;
         };
         kill_stream(c->cap_stream);
+        kill_stream(c->chain_copy);
+        kill_event(c->ev_a0);
         kill_stream(c->side);
         kill_stream(c->gj.aux);
         kill_stream(c->gj.main);

@@ -33,7 +33,11 @@ using HipFail = void (*)(hipError_t);
 // rp0/ci0/val0 the same matrix in device memory.  Same contract as
 // build_hierarchy (with_colors = false): H.A holds every level on the host,
 // H.agg every aggregation map, on_smoothed is called for each smoothed level
-// as soon as it is known; returns 0, -3 or -9.  Returns 1 without touching
+// as soon as it is known (from another thread for all but the first level:
+// the host copy of a level runs on a copy thread, on `copy_st`, while the
+// device builds the next one); returns 0, -3 or -9.  A0's values may still
+// be on their way to the host: level0_values() is called (and must return
+// only once they are there) before they are read.  Returns 1 without touching
 // A0 or H when the level-0 pattern is not structurally symmetric (the pass
 // reads a_ji through the mirror entry); the caller then runs the host chain.
 // `cap` is an idle stream used only to capture batches of matching rounds
@@ -43,7 +47,8 @@ using HipFail = void (*)(hipError_t);
 // coarse matrix uploaded.
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                     const LevelCallback &on_smoothed, hipStream_t st, hipStream_t cap,
+                     const LevelCallback &on_smoothed, const std::function<void()> &level0_values,
+                     hipStream_t st, hipStream_t cap, hipStream_t copy_st,
                      const DeviceAlloc &alloc, HipFail hip_fail, int *pinned);
 
 }  // namespace msp

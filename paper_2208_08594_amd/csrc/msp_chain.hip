@@ -6,6 +6,7 @@
 #include "msp_chain.h"
 
 #include <algorithm>
+#include <future>
 #include <vector>
 
 // every sum and comparison below is a single IEEE operation, as on the host
@@ -18,7 +19,7 @@ constexpr int kThreads = 256;
 constexpr int kScanTile = 1024;  // elements per block of the scan (4 per thread)
 constexpr int kFree = 0, kSingle = 1, kLow = 2, kHigh = 3;
 constexpr int kNone = 0x7fffffff;
-constexpr int kBatch = 16;  // rounds queued between two reads of the free count
+constexpr int kBatch = 8;  // rounds queued between two reads of the free count (even)
 
 inline unsigned nblocks(long long n, int per = kThreads)
 {
@@ -377,6 +378,7 @@ struct Chain {
     HipFail hip_fail = nullptr;
     int *pinned = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev_lvl = nullptr;  // a new level is on the device
     // work arrays, sized for level 0 (no later matrix is larger)
     double *s = nullptr, *cs = nullptr, *smax = nullptr;
     int *cj = nullptr, *ncand = nullptr, *partner = nullptr;
@@ -537,10 +539,12 @@ struct Chain {
 
 struct EventGuard {
     hipEvent_t *ev;
+    hipEvent_t *ev_lvl;
     ~EventGuard()
     {
         for (int i = 0; i < 2; ++i)
             if (ev[i]) (void)hipEventDestroy(ev[i]);
+        if (*ev_lvl) (void)hipEventDestroy(*ev_lvl);
     }
 };
 
@@ -589,7 +593,8 @@ size_t place(Chain &X, char *base, int n0, long long nnz0)
 
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
-                     const LevelCallback &on_smoothed, hipStream_t st, hipStream_t cap,
+                     const LevelCallback &on_smoothed, const std::function<void()> &level0_values,
+                     hipStream_t st, hipStream_t cap, hipStream_t copy_st,
                      const DeviceAlloc &alloc, HipFail hip_fail, int *pinned)
 {
     const int n0 = A0.n;
@@ -597,6 +602,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     if (n0 <= max_coarse || max_levels <= 1) {
         H = Hierarchy();
         H.A.push_back(std::move(A0));
+        level0_values();
         return check_hierarchy(H, max_dense);
     }
     Chain X;
@@ -604,8 +610,9 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     X.cap = cap;
     X.hip_fail = hip_fail;
     X.pinned = pinned;
-    EventGuard guard{X.ev};
+    EventGuard guard{X.ev, &X.ev_lvl};
     for (int i = 0; i < 2; ++i) X.ck(hipEventCreateWithFlags(&X.ev[i], hipEventDisableTiming));
+    X.ck(hipEventCreateWithFlags(&X.ev_lvl, hipEventDisableTiming));
     // one allocation for every work array
     char *base = (char *)alloc(place(X, nullptr, n0, nnz0));
     place(X, base, n0, nnz0);
@@ -622,14 +629,29 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
 
     H = Hierarchy();
     H.A.push_back(std::move(A0));
+    // The host copy of each new level (and of the aggregation map that made
+    // it) runs on a copy thread while the device goes on with the next level;
+    // that thread also starts the level's host work (on_smoothed).  A level
+    // is joined before its device buffers can be reused: the previous level's
+    // copy before this level's aggregation map is composed (aggf is shared,
+    // the level buffers alternate), and every copy before the host reads it.
+    std::future<void> pending;
+    const auto join = [&pending]() {
+        if (pending.valid()) pending.get();
+    };
     bool have_s = true;
+    bool main_calls = true;  // level l's on_smoothed is due on this thread
     int next = 1;  // set[0] holds M1; levels alternate between set[1] and set[2]
     for (int l = 0;; ++l) {
-        const Csr &hc = H.A[l];
-        const bool last = hc.n <= max_coarse || l == max_levels - 1 ||
-                          (l > 0 && (double)hc.n > 0.9 * (double)H.A[l - 1].n);
+        const int nl = H.A[l].n;
+        const bool last = nl <= max_coarse || l == max_levels - 1 ||
+                          (l > 0 && (double)nl > 0.9 * (double)H.A[l - 1].n);
         if (last) break;
-        if (on_smoothed) on_smoothed(l, hc.n, hc.rp.data(), hc.ci.data(), hc.val.data());
+        if (main_calls && on_smoothed) {
+            if (l > 0) join();
+            const Csr &hc = H.A[l];
+            on_smoothed(l, hc.n, hc.rp.data(), hc.ci.data(), hc.val.data());
+        }
         const int nc1 = X.pass(cur, have_s, X.a1);
         have_s = false;
         DevLevel &M1 = X.set[0];
@@ -637,26 +659,71 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         const int nc2 = X.pass(M1, false, X.a2);
         DevLevel &C = X.set[next];
         const long long nnzc = X.galerkin(M1, X.a2, nc2, C);
+        join();
         k_compose<<<nblocks(cur.n), kThreads, 0, st>>>(cur.n, X.a1, X.a2, X.aggf);
         X.launched();
-        std::vector<int> agg(cur.n);
-        X.ck(hipMemcpyAsync(agg.data(), X.aggf, sizeof(int) * cur.n, hipMemcpyDeviceToHost, st));
-        Csr Cn;
-        X.to_host(C, nnzc, Cn);
-        X.ck(hipStreamSynchronize(st));
-        if ((double)nc2 > 0.9 * (double)cur.n) {
+        X.ck(hipEventRecord(X.ev_lvl, st));
+        {
+            Csr Cn;
+            Cn.n = nc2;
+            Cn.rp.resize(nc2 + 1);
+            Cn.ci.resize(nnzc);
+            Cn.val.resize(nnzc);
+            H.agg.emplace_back(cur.n);
+            H.A.push_back(std::move(Cn));
+        }
+        const bool stalled = (double)nc2 > 0.9 * (double)cur.n;
+        // level l+1 is smoothed unless it is the last one (a stalled level
+        // may still change below, so its host work starts on this thread)
+        const bool next_smoothed =
+            !stalled && !(nc2 <= max_coarse || l + 1 == max_levels - 1);
+        {
+            Csr &hn = H.A[l + 1];
+            int *hagg = H.agg[l].data();
+            const int nf = cur.n;
+            const DevLevel Cd = C;
+            const int *aggf = X.aggf;
+            const hipEvent_t ready = X.ev_lvl;
+            const int lnext = l + 1;
+            const bool call = next_smoothed && on_smoothed;
+            pending = std::async(std::launch::async, [&hn, hagg, nf, Cd, aggf, ready, nnzc, copy_st,
+                                                      hip_fail, call, lnext, &on_smoothed]() {
+                auto ck = [hip_fail](hipError_t e) {
+                    if (e != hipSuccess) {
+                        (void)hipGetLastError();
+                        hip_fail(e);
+                    }
+                };
+                ck(hipStreamWaitEvent(copy_st, ready, 0));
+                ck(hipMemcpyAsync(hagg, aggf, sizeof(int) * nf, hipMemcpyDeviceToHost, copy_st));
+                ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
+                                  hipMemcpyDeviceToHost, copy_st));
+                if (nnzc) {
+                    ck(hipMemcpyAsync(hn.ci.data(), Cd.ci, sizeof(int) * nnzc,
+                                      hipMemcpyDeviceToHost, copy_st));
+                    ck(hipMemcpyAsync(hn.val.data(), Cd.val, sizeof(double) * nnzc,
+                                      hipMemcpyDeviceToHost, copy_st));
+                }
+                ck(hipStreamSynchronize(copy_st));
+                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), hn.ci.data(), hn.val.data());
+            });
+        }
+        main_calls = !next_smoothed;
+        if (stalled) {
             // stalled: absorb singletons, then one Galerkin product on A_l
-            const int nc3 = absorb_singletons(H.A[l], agg, nc2);
+            join();
+            if (l == 0) level0_values();
+            const int nc3 = absorb_singletons(H.A[l], H.agg[l], nc2);
             if (nc3 < nc2) {
-                Cn = msp::galerkin(H.A[l], agg, nc3);
-                X.to_device(Cn, C);
+                H.A[l + 1] = msp::galerkin(H.A[l], H.agg[l], nc3);
+                X.to_device(H.A[l + 1], C);
             }
         }
-        H.agg.push_back(std::move(agg));
-        H.A.push_back(std::move(Cn));
         cur = C;
         next = 3 - next;
     }
+    join();
+    level0_values();
     return check_hierarchy(H, max_dense);
 }
 

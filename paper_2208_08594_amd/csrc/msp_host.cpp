@@ -130,12 +130,17 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     color.assign(n, 0);
     // Static priority: larger |S_i| first, smaller index on ties (Alg. 4.1 picks
     // any vertex of maximal |S_i|; the lowest index makes the choice unique).
+    // (a counting sort by degree: buckets from the largest degree down,
+    // ascending indices inside a bucket)
     std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) {
-        int da = G.degree(a), db = G.degree(b);
-        return da != db ? da > db : a < b;
-    });
+    {
+        int dmax = 0;
+        for (int i = 0; i < n; ++i) dmax = std::max(dmax, G.degree(i));
+        std::vector<int> start(dmax + 2, 0);
+        for (int i = 0; i < n; ++i) ++start[dmax - G.degree(i) + 1];
+        for (int d = 0; d <= dmax; ++d) start[d + 1] += start[d];
+        for (int i = 0; i < n; ++i) order[start[dmax - G.degree(i)]++] = i;
+    }
     // Candidates W^ are taken in the same priority, i.e. smallest position in
     // `order` first: a two-level bit set over positions (words of 64
     // positions and a summary bit per word) gives that position quickly.
@@ -144,15 +149,18 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     const int nw = (n + 63) / 64, ns = (nw + 63) / 64;
     std::vector<unsigned long long> bits(nw, 0ull), summ(ns, 0ull);
     int nqueued = 0;
+    int s_lo = ns;  // no summary word below s_lo is set
     auto hat_push = [&](int v) {
         const int q = pos[v];
         bits[q >> 6] |= 1ull << (q & 63);
         summ[q >> 12] |= 1ull << ((q >> 6) & 63);
+        s_lo = std::min(s_lo, q >> 12);
         ++nqueued;
     };
     auto hat_pop = [&]() -> int {  // requires nqueued > 0
-        int s = 0;
+        int s = s_lo;
         while (summ[s] == 0ull) ++s;
+        s_lo = s;
         const int w = (s << 6) + __builtin_ctzll(summ[s]);
         const int b = __builtin_ctzll(bits[w]);
         bits[w] &= bits[w] - 1;
@@ -178,6 +186,7 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         std::fill(bits.begin(), bits.end(), 0ull);
         std::fill(summ.begin(), summ.end(), 0ull);
         nqueued = 0;
+        s_lo = ns;
         size_t cursor = 0;
         while (avail > 0) {
             int v = -1;
