@@ -163,6 +163,9 @@ struct msp_ctx {
     double *hhost = nullptr;  // pinned
     int *flag = nullptr, *flag_host = nullptr;
     int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
+    bool pattern_ok = false;    // rp/ci (host) and rp_d/ci_d hold a checked pattern
+    long long pattern_gen = 0;  // counts pattern changes
+    long long lev0_gen = -1;    // pattern_gen when lev[0].A was built
     hipStream_t chain_copy = nullptr;  // device-to-host copies of the setup
     hipEvent_t ev_a0 = nullptr;
     // adaptive state and statistics
@@ -326,35 +329,54 @@ void level_layout(int n, const int *rp, const int *ci, const double *val,
             O.iperm[t] = i;
         }
     }
-    std::vector<int> ent_ptr(n + 1, 0), ent_col, ent_src;
+    // off-diagonal entries per position (row i = iperm[t] keeps its order),
+    // counted first so that row chunks fill their own ranges in parallel
+    const int parts = host_parts(n);
+    std::vector<int> ent_ptr(n + 1, 0);
     std::vector<double> diag(n, 0.0);
-    ent_col.reserve(rp[n]);
-    ent_src.reserve(rp[n]);
-    for (int t = 0; t < n; ++t) {
-        int i = O.iperm[t];
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-            int j = ci[k];
-            if (j == i) {
-                diag[t] = val[k];
-            } else {
-                ent_col.push_back(O.perm[j]);
-                ent_src.push_back(k);
+    for_chunks(n, parts, [&](int lo, int hi, int) {
+        for (int t = lo; t < hi; ++t) {
+            const int i = O.iperm[t];
+            int m = 0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) m += ci[k] != i;
+            ent_ptr[t + 1] = m;
+        }
+    });
+    for (int t = 0; t < n; ++t) ent_ptr[t + 1] += ent_ptr[t];
+    std::vector<int> ent_col(ent_ptr[n]), ent_src(ent_ptr[n]);
+    for_chunks(n, parts, [&](int lo, int hi, int) {
+        for (int t = lo; t < hi; ++t) {
+            const int i = O.iperm[t];
+            int o = ent_ptr[t];
+            for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                const int j = ci[k];
+                if (j == i) {
+                    diag[t] = val[k];
+                } else {
+                    ent_col[o] = O.perm[j];
+                    ent_src[o] = k;
+                    ++o;
+                }
             }
         }
-        ent_ptr[t + 1] = (int)ent_col.size();
-    }
+    });
     build_sell(n, O.seg_row, ent_ptr, ent_col, ent_src, O.lay);
     const long long sl = O.lay.slot_lanes;
+    const int nsl = (int)(sl / 64);
     if (fp32) {
         O.v32.assign(sl, 0.0f);
         O.d32.resize(n);
-        for (long long q = 0; q < sl; ++q)
-            if (O.lay.src[q] >= 0) O.v32[q] = (float)val[O.lay.src[q]];
+        for_chunks(nsl, parts, [&](int lo, int hi, int) {
+            for (long long q = (long long)lo * 64; q < (long long)hi * 64; ++q)
+                if (O.lay.src[q] >= 0) O.v32[q] = (float)val[O.lay.src[q]];
+        });
         for (int t = 0; t < n; ++t) O.d32[t] = (float)diag[t];
     } else {
         O.v64.assign(sl, 0.0);
-        for (long long q = 0; q < sl; ++q)
-            if (O.lay.src[q] >= 0) O.v64[q] = val[O.lay.src[q]];
+        for_chunks(nsl, parts, [&](int lo, int hi, int) {
+            for (long long q = (long long)lo * 64; q < (long long)hi * 64; ++q)
+                if (O.lay.src[q] >= 0) O.v64[q] = val[O.lay.src[q]];
+        });
         O.d64 = std::move(diag);
     }
 }
@@ -524,61 +546,136 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
     }
     std::vector<int> pos(n);
     for (int t = 0; t < n; ++t) pos[D.ord[t]] = t;
-    triangular_levels(n, c->rp.data(), c->ci.data(), D.ord, true, D.fwd_rows, D.fwd_ptr);
-    triangular_levels(n, c->rp.data(), c->ci.data(), D.ord, false, D.bwd_rows, D.bwd_ptr);
+    const int *rp = c->rp.data(), *ci = c->ci.data();
+    {
+        auto bwd = std::async(std::launch::async, [&]() {
+            triangular_levels(n, rp, ci, D.ord, false, D.bwd_rows, D.bwd_ptr);
+        });
+        triangular_levels(n, rp, ci, D.ord, true, D.fwd_rows, D.fwd_ptr);
+        bwd.get();
+    }
     // factorisation tasks per block row: lower entries in elimination order and
-    // their update pairs (F_ij -= F_ik F_kj for stored j after k, (k,j) stored)
-    P.lt_ptr.assign(n + 1, 0);
-    std::vector<int> low;
-    for (int i = 0; i < n; ++i) {
-        low.clear();
-        for (int q = c->rp[i]; q < c->rp[i + 1]; ++q)
-            if (pos[c->ci[q]] < pos[i]) low.push_back(q);
-        std::sort(low.begin(), low.end(),
-                  [&](int a, int bq) { return pos[c->ci[a]] < pos[c->ci[bq]]; });
-        for (int kk : low) {
-            int k = c->ci[kk];
-            P.lt_kk.push_back(kk);
-            P.lt_k.push_back(k);
-            P.lt_pp.push_back((int)P.pr_jj.size());
-            for (int jj = c->rp[i]; jj < c->rp[i + 1]; ++jj) {
-                int j = c->ci[jj];
-                if (pos[j] <= pos[k]) continue;
-                auto b0 = c->ci.begin() + c->rp[k], b1 = c->ci.begin() + c->rp[k + 1];
-                auto it = std::lower_bound(b0, b1, j);
-                if (it != b1 && *it == j) {
-                    P.pr_jj.push_back(jj);
-                    P.pr_kj.push_back((int)(it - c->ci.begin()));
+    // their update pairs (F_ij -= F_ik F_kj for stored j after k, (k,j) stored:
+    // the merge of rows i and k), built per row chunk and joined in order
+    const int parts = host_parts(n);
+    struct Part {
+        std::vector<int> rowcnt, lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
+    };
+    std::vector<Part> part(parts);
+    for_chunks(n, parts, [&](int lo, int hi, int t) {
+        Part &Q = part[t];
+        std::vector<int> low;
+        for (int i = lo; i < hi; ++i) {
+            low.clear();
+            for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                if (pos[ci[q]] >= pos[i]) continue;
+                size_t u = low.size();  // insertion by elimination position
+                low.push_back(q);
+                while (u > 0 && pos[ci[low[u - 1]]] > pos[ci[q]]) {
+                    low[u] = low[u - 1];
+                    --u;
+                }
+                low[u] = q;
+            }
+            Q.rowcnt.push_back((int)low.size());
+            for (int kk : low) {
+                const int k = ci[kk];
+                Q.lt_kk.push_back(kk);
+                Q.lt_k.push_back(k);
+                Q.lt_pp.push_back((int)Q.pr_jj.size());
+                int x = rp[i], y = rp[k];
+                const int xe = rp[i + 1], ye = rp[k + 1];
+                while (x < xe && y < ye) {
+                    const int jx = ci[x], jy = ci[y];
+                    if (jx < jy) {
+                        ++x;
+                    } else if (jy < jx) {
+                        ++y;
+                    } else {
+                        if (pos[jx] > pos[k]) {
+                            Q.pr_jj.push_back(x);
+                            Q.pr_kj.push_back(y);
+                        }
+                        ++x;
+                        ++y;
+                    }
                 }
             }
         }
-        P.lt_ptr[i + 1] = (int)P.lt_kk.size();
+    });
+    // join the chunks: offsets first, then each chunk copies its own part
+    std::vector<size_t> tbase(parts + 1, 0), pbase(parts + 1, 0);
+    for (int t = 0; t < parts; ++t) {
+        tbase[t + 1] = tbase[t] + part[t].lt_kk.size();
+        pbase[t + 1] = pbase[t] + part[t].pr_jj.size();
     }
+    P.lt_ptr.assign(n + 1, 0);
+    {
+        int i = 0;
+        for (const Part &Q : part)
+            for (int cnt : Q.rowcnt) {
+                P.lt_ptr[i + 1] = P.lt_ptr[i] + cnt;
+                ++i;
+            }
+    }
+    P.lt_kk.resize(tbase[parts]);
+    P.lt_k.resize(tbase[parts]);
+    P.lt_pp.resize(tbase[parts]);
+    P.pr_jj.resize(pbase[parts]);
+    P.pr_kj.resize(pbase[parts]);
+    for_chunks(parts, parts, [&](int lo, int hi, int) {
+        for (int t = lo; t < hi; ++t) {
+            const Part &Q = part[t];
+            std::copy(Q.lt_kk.begin(), Q.lt_kk.end(), P.lt_kk.begin() + tbase[t]);
+            std::copy(Q.lt_k.begin(), Q.lt_k.end(), P.lt_k.begin() + tbase[t]);
+            for (size_t q = 0; q < Q.lt_pp.size(); ++q)
+                P.lt_pp[tbase[t] + q] = (int)pbase[t] + Q.lt_pp[q];
+            std::copy(Q.pr_jj.begin(), Q.pr_jj.end(), P.pr_jj.begin() + pbase[t]);
+            std::copy(Q.pr_kj.begin(), Q.pr_kj.end(), P.pr_kj.begin() + pbase[t]);
+        }
+    });
     P.lt_pp.push_back((int)P.pr_jj.size());
-    // sliced layouts of the lower (forward levels) and upper (backward levels) parts
+    // sliced layouts of the lower (forward levels) and upper (backward levels)
+    // parts, the entries of each row in elimination order
     auto make = [&](const std::vector<int> &rows, const std::vector<int> &lptr, bool lower,
                     SellLayout &lay) {
-        std::vector<int> ent_ptr(n + 1, 0), ent_col, ent_src;
-        std::vector<int> tmpk;
-        for (int t = 0; t < n; ++t) {
-            int i = rows[t];
-            tmpk.clear();
-            for (int q = c->rp[i]; q < c->rp[i + 1]; ++q) {
-                int j = c->ci[q];
-                if (lower ? pos[j] < pos[i] : pos[j] > pos[i]) tmpk.push_back(q);
+        auto part_of = [&](int i, int j) { return lower ? pos[j] < pos[i] : pos[j] > pos[i]; };
+        std::vector<int> ent_ptr(n + 1, 0);
+        for_chunks(n, parts, [&](int lo, int hi, int) {
+            for (int r = lo; r < hi; ++r) {
+                const int i = rows[r];
+                int m = 0;
+                for (int q = rp[i]; q < rp[i + 1]; ++q) m += part_of(i, ci[q]);
+                ent_ptr[r + 1] = m;
             }
-            std::sort(tmpk.begin(), tmpk.end(),
-                      [&](int a, int bq) { return pos[c->ci[a]] < pos[c->ci[bq]]; });
-            for (int q : tmpk) {
-                ent_col.push_back(c->ci[q]);
-                ent_src.push_back(q);
+        });
+        for (int r = 0; r < n; ++r) ent_ptr[r + 1] += ent_ptr[r];
+        std::vector<int> ent_col(ent_ptr[n]), ent_src(ent_ptr[n]);
+        for_chunks(n, parts, [&](int lo, int hi, int) {
+            for (int r = lo; r < hi; ++r) {
+                const int i = rows[r], o = ent_ptr[r];
+                int m = 0;
+                for (int q = rp[i]; q < rp[i + 1]; ++q) {
+                    if (!part_of(i, ci[q])) continue;
+                    // insertion by elimination position (rows are short)
+                    int u = m++;
+                    while (u > 0 && pos[ci[ent_src[o + u - 1]]] > pos[ci[q]]) {
+                        ent_src[o + u] = ent_src[o + u - 1];
+                        --u;
+                    }
+                    ent_src[o + u] = q;
+                }
+                for (int u = 0; u < m; ++u) ent_col[o + u] = ci[ent_src[o + u]];
             }
-            ent_ptr[t + 1] = (int)ent_col.size();
-        }
+        });
         build_sell(n, lptr, ent_ptr, ent_col, ent_src, lay);
     };
-    make(D.fwd_rows, D.fwd_ptr, true, D.L.lay);
-    make(D.bwd_rows, D.bwd_ptr, false, D.U.lay);
+    {
+        auto up = std::async(std::launch::async,
+                             [&]() { make(D.bwd_rows, D.bwd_ptr, false, D.U.lay); });
+        make(D.fwd_rows, D.fwd_ptr, true, D.L.lay);
+        up.get();
+    }
     P.dsrc.assign(D.U.lay.slice_row0.size() * 64, -1);
     for (size_t s = 0; s < D.U.lay.slice_row0.size(); ++s)
         for (int l = 0; l < D.U.lay.slice_rows[s]; ++l)
@@ -705,6 +802,13 @@ struct CopyStreamScope {
 
 void rebuild_B(msp_ctx *c, const double *vals)
 {
+    // Level 0 of the previous hierarchy has the same pattern arrays when the
+    // pattern has not changed since: its host arrays are taken over (the
+    // values are overwritten below) instead of copied and cleared again.
+    Csr A0;
+    if (!c->lev.empty() && c->lev0_gen == c->pattern_gen && c->lev[0].A.n == c->n &&
+        (long long)c->lev[0].A.ci.size() == c->nnzb)
+        A0 = std::move(c->lev[0].A);
     release_B(c);
     const int n = c->n, b = c->b;
     double tp = now_ms();
@@ -730,11 +834,12 @@ void rebuild_B(msp_ctx *c, const double *vals)
     if (!c->ev_a0) HIPCHK(hipEventCreateWithFlags(&c->ev_a0, hipEventDisableTiming));
     if (!c->chain_copy) HIPCHK(hipStreamCreateWithFlags(&c->chain_copy, hipStreamNonBlocking));
     HIPCHK(hipEventRecord(c->ev_a0, c->stream));
-    Csr A0;
-    A0.n = n;
-    A0.rp = c->rp;
-    A0.ci = c->ci;
-    A0.val.resize(c->nnzb);
+    if (A0.n != n) {
+        A0.n = n;
+        A0.rp = c->rp;
+        A0.ci = c->ci;
+        A0.val.resize(c->nnzb);
+    }
     // the decoupled pressure values reach the host on a copy thread; the
     // device chain below does not need them
     std::shared_future<void> a0_ready =
@@ -845,6 +950,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     for (int l = 0; l < nlev; ++l) {
         Level &L = c->lev[l];
         L.A = std::move(H.A[l]);
+        if (l == 0) c->lev0_gen = c->pattern_gen;
         L.n = L.A.n;
         if (l + 1 < nlev) L.agg = std::move(H.agg[l]);
     }
@@ -1394,19 +1500,36 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
     const double t0 = now_ms();
     int st = guarded([&]() {
         c->haveA = false;
-        std::vector<int> rp(n + 1), ci(nnzb);
-        HIPCHK(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
-                              c->stream));
-        c->sync();
-        if (rp[0] != 0 || (long long)rp[n] != nnzb) fail(MSP_ERR_PATTERN);
-        HIPCHK(hipMemcpyAsync(ci.data(), col_ind, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
-                              c->stream));
-        c->sync();
-        if (check_pattern(n, rp.data(), ci.data(), nnzb) != 0) fail(MSP_ERR_PATTERN);
         for (double &ph : c->info.phase_ms) ph = 0.0;
-        const bool layout_changed = !c->haveA || n != c->n || b != c->b || p != c->p ||
-                                    nnzb != c->nnzb || rp != c->rp || ci != c->ci;
+        // Same sizes as the pattern already ingested (and checked): compare
+        // the caller's arrays with the context's device copy on the device;
+        // only a new pattern comes to the host to be checked and laid out.
+        bool same = false;
+        if (c->pattern_ok && n == c->n && b == c->b && p == c->p && nnzb == c->nnzb) {
+            c->clear_flag();
+            HIPCHK(launch_diff_i32(row_ptr, c->rp_d, (long long)n + 1, c->flag, c->stream));
+            HIPCHK(launch_diff_i32(col_ind, c->ci_d, nnzb, c->flag, c->stream));
+            same = c->read_flag() == 0;
+        }
+        std::vector<int> rp, ci;
+        if (!same) {
+            rp.resize(n + 1);
+            ci.resize(nnzb);
+            HIPCHK(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int) * (n + 1),
+                                  hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            if (rp[0] != 0 || (long long)rp[n] != nnzb) fail(MSP_ERR_PATTERN);
+            HIPCHK(hipMemcpyAsync(ci.data(), col_ind, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
+                                  c->stream));
+            c->sync();
+            if (check_pattern(n, rp.data(), ci.data(), nnzb) != 0) fail(MSP_ERR_PATTERN);
+        }
+        const bool layout_changed = !same && (!c->pattern_ok || n != c->n || b != c->b ||
+                                              p != c->p || nnzb != c->nnzb || rp != c->rp ||
+                                              ci != c->ci);
         if (layout_changed) {
+            c->pattern_ok = false;
+            ++c->pattern_gen;
             c->n = n;
             c->b = b;
             c->p = p;
@@ -1419,6 +1542,7 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
                     if (c->ci[k] == i) c->diag_pos[i] = k;
             build_layout_A(c);
         }
+        c->pattern_ok = true;
         const double ti = now_ms();
         c->info.phase_ms[0] = ti - t0;
         c->clear_flag();

@@ -10,30 +10,10 @@
 
 namespace msp {
 
-namespace {
-
 int host_threads()
 {
     unsigned hc = std::thread::hardware_concurrency();
     return (int)std::min(hc ? hc : 1u, 8u);
-}
-
-// Runs f(lo, hi, t) over nparts contiguous, ordered chunks of [0, n) on
-// worker threads (chunk t on thread t); results that each chunk keeps apart
-// and the caller joins in chunk order are identical to a sequential pass.
-template <class F>
-void for_chunks(int n, int nparts, F f)
-{
-    if (nparts <= 1 || n < 2 * nparts) {
-        f(0, n, 0);
-        return;
-    }
-    std::vector<std::thread> th;
-    th.reserve(nparts - 1);
-    for (int t = 1; t < nparts; ++t)
-        th.emplace_back([&, t]() { f((int)((long long)n * t / nparts), (int)((long long)n * (t + 1) / nparts), t); });
-    f(0, (int)((long long)n / nparts), 0);
-    for (auto &x : th) x.join();
 }
 
 int host_parts(int n)
@@ -41,8 +21,6 @@ int host_parts(int n)
     // worth splitting only for large levels; a few threads are enough
     return n >= 16384 ? host_threads() : 1;
 }
-
-}  // namespace
 
 int check_pattern(int n, const int *rp, const int *ci, long long nnz)
 {
@@ -624,17 +602,20 @@ void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<in
     L.slot_lanes = off;
     L.col.assign(off, -1);
     L.src.assign(off, -1);
-    for (size_t s = 0; s < L.slice_row0.size(); ++s) {
-        for (int l = 0; l < L.slice_rows[s]; ++l) {
-            int t = L.slice_row0[s] + l;
-            for (int k = ent_ptr[t]; k < ent_ptr[t + 1]; ++k) {
-                int slot = k - ent_ptr[t];
-                long q = (long)L.slice_off[s] + slot * 64 + l;
-                L.col[q] = ent_col[k];
-                L.src[q] = ent_src[k];
+    const int nsl = (int)L.slice_row0.size();
+    for_chunks(nsl, host_parts(nrows), [&](int lo, int hi, int) {
+        for (int s = lo; s < hi; ++s) {
+            for (int l = 0; l < L.slice_rows[s]; ++l) {
+                int t = L.slice_row0[s] + l;
+                for (int k = ent_ptr[t]; k < ent_ptr[t + 1]; ++k) {
+                    int slot = k - ent_ptr[t];
+                    long q = (long)L.slice_off[s] + slot * 64 + l;
+                    L.col[q] = ent_col[k];
+                    L.src[q] = ent_src[k];
+                }
             }
         }
-    }
+    });
 }
 
 }  // namespace msp

@@ -5,9 +5,34 @@
 
 #include <cstdint>
 #include <functional>
+#include <thread>
 #include <vector>
 
 namespace msp {
+
+// Threads for the host setup loops: min(hardware threads, 8).
+int host_threads();
+// host_threads() for levels of at least 16384 rows, else 1.
+int host_parts(int n);
+// Runs f(lo, hi, t) over nparts contiguous, ordered chunks of [0, n) on
+// worker threads (chunk t on thread t); results that each chunk keeps apart
+// and the caller joins in chunk order are identical to a sequential pass.
+template <class F>
+void for_chunks(int n, int nparts, F f)
+{
+    if (nparts <= 1 || n < 2 * nparts) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nparts - 1);
+    for (int t = 1; t < nparts; ++t)
+        th.emplace_back([&, t]() {
+            f((int)((long long)n * t / nparts), (int)((long long)n * (t + 1) / nparts), t);
+        });
+    f(0, (int)((long long)n / nparts), 0);
+    for (auto &x : th) x.join();
+}
 
 // Scalar CSR matrix (one AMG level).
 struct Csr {

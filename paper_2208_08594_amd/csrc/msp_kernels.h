@@ -30,6 +30,8 @@ hipError_t launch_ingest_bsr(int b, int p, long long slot_lanes, const int *src,
 hipError_t launch_gather_blocks(int b, long long slot_lanes, const int *src, const double *blocks,
                                 double *dst64, float *dst32, hipStream_t st);
 hipError_t launch_check_finite(const double *x, long long n, int *bad, hipStream_t st);
+// Sets *bad to 1 if a[i] != b[i] for some i < n.
+hipError_t launch_diff_i32(const int *a, const int *b, long long n, int *bad, hipStream_t st);
 hipError_t launch_round_f32(const double *x, float *y, long long n, hipStream_t st);
 
 // ---- decoupling (ABF) ----------------------------------------------------

@@ -105,6 +105,14 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(long long slot_lanes
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_diff_i32(const int *__restrict__ a,
+                                                       const int *__restrict__ b, long long n,
+                                                       int *bad)
+{
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && a[i] != b[i]) atomicOr(bad, 1);
+}
+
 __global__ __launch_bounds__(kThreads) void k_check_finite(const double *__restrict__ x,
                                                            long long n, int *bad)
 {
@@ -1439,6 +1447,13 @@ hipError_t launch_gather_blocks(int b, long long slot_lanes, const int *src, con
     if (slot_lanes <= 0) return hipSuccess;
     MSP_SWITCH_B(b, (k_gather_blocks<B><<<blocks_for(slot_lanes), kThreads, 0, st>>>(
                         slot_lanes, src, blocks, dst64, dst32)));
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_i32(const int *a, const int *b, long long n, int *bad, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_diff_i32<<<blocks_for(n), kThreads, 0, st>>>(a, b, n, bad);
     return hipGetLastError();
 }
 
