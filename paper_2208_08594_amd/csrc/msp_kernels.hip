@@ -1299,10 +1299,16 @@ __device__ inline void xcd_tile(int wg, int Ty, int Tx, int &ti, int &tj)
     tj = c0 + gl % w;
 }
 
-template <int TM, int TN, int WM, int WN>
-__device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restrict__ A, int lda,
+// One TM x TN tile at (i0, j0).  FULL: the tile lies inside C and Kd is a
+// multiple of the k-chunk, so no load or store needs a bounds check (the
+// loads of a chunk and the C reads of the epilogue then issue back to back).
+template <int TM, int TN, int WM, int WN, bool FULL>
+__device__ inline void dgemm_body(int i0, int j0, int Mr, int Nc, int Kd,
+                                  const double *__restrict__ A, int lda,
                                   const double *__restrict__ B, int ldb, double *__restrict__ C,
-                                  int ldc, double alpha, double beta)
+                                  int ldc, double alpha, double beta,
+                                  double (*__restrict__ As)[TM][kGK + 1],
+                                  double (*__restrict__ Bs)[kGK][TN + 1])
 {
     constexpr int T = 64 * WM * WN;         // threads
     constexpr int FM = TM / WM / 16, FN = TN / WN / 16;
@@ -1310,11 +1316,6 @@ __device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restri
     constexpr int BK = T / TN;              // B k-rows fetched per pass
     static_assert(TM % AR == 0 && kGK % BK == 0, "fetch mapping");
     constexpr int AU = TM / AR, BU = kGK / BK;
-    __shared__ double As[2][TM][kGK + 1];
-    __shared__ double Bs[2][kGK][TN + 1];
-    int ti, tj;
-    xcd_tile(blockIdx.x, (Mr + TM - 1) / TM, (Nc + TN - 1) / TN, ti, tj);
-    const int i0 = ti * TM, j0 = tj * TN;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = (wave / WN) * (TM / WM), wc = (wave % WN) * (TN / WN);
     const int li = lane & 15, lk = lane >> 4;
@@ -1333,6 +1334,13 @@ __device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restri
     const int arows = Mr - i0 - r0;  // row r0 + AR u valid iff AR u < arows
     double ra[AU], rb[BU];
     auto fetch = [&](int k0) {
+        if (FULL) {
+#pragma unroll
+            for (int u = 0; u < AU; ++u) ra[u] = pa[(long long)(AR * u) * lda + k0];
+#pragma unroll
+            for (int u = 0; u < BU; ++u) rb[u] = pb[(long long)(k0 + bk0 + BK * u) * ldb];
+            return;
+        }
         const bool ak_ok = k0 + ac < Kd;
 #pragma unroll
         for (int u = 0; u < AU; ++u)
@@ -1372,6 +1380,35 @@ __device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restri
         if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
+    if (FULL) {
+        // the C reads of one 16-row block go out together, then their writes
+        constexpr int FH = 1;
+#pragma unroll
+        for (int h = 0; h < FM; h += FH) {
+            double cv[FH][4][FN];
+            if (beta != 0.0) {
+#pragma unroll
+                for (int a = 0; a < FH; ++a)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int b = 0; b < FN; ++b)
+                            cv[a][r][b] = C[(long long)(i0 + wr + (h + a) * 16 + lk + 4 * r) * ldc +
+                                            j0 + wc + b * 16 + li];
+            }
+#pragma unroll
+            for (int a = 0; a < FH; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) {
+                        const double v = alpha * acc[h + a][b][r];
+                        C[(long long)(i0 + wr + (h + a) * 16 + lk + 4 * r) * ldc + j0 + wc + b * 16 +
+                          li] = (beta != 0.0) ? v + beta * cv[a][r][b] : v;
+                    }
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -1387,6 +1424,25 @@ __device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restri
                 *c = (beta != 0.0) ? v + beta * *c : v;
             }
         }
+}
+
+
+template <int TM, int TN, int WM, int WN>
+__device__ inline void dgemm_tile(int Mr, int Nc, int Kd, const double *__restrict__ A, int lda,
+                                  const double *__restrict__ B, int ldb, double *__restrict__ C,
+                                  int ldc, double alpha, double beta)
+{
+    __shared__ double As[2][TM][kGK + 1];
+    __shared__ double Bs[2][kGK][TN + 1];
+    int ti, tj;
+    xcd_tile(blockIdx.x, (Mr + TM - 1) / TM, (Nc + TN - 1) / TN, ti, tj);
+    const int i0 = ti * TM, j0 = tj * TN;
+    if (i0 + TM <= Mr && j0 + TN <= Nc && Kd % kGK == 0)
+        dgemm_body<TM, TN, WM, WN, true>(i0, j0, Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta,
+                                         As, Bs);
+    else
+        dgemm_body<TM, TN, WM, WN, false>(i0, j0, Mr, Nc, Kd, A, lda, B, ldb, C, ldc, alpha, beta,
+                                          As, Bs);
 }
 
 // Large products: 128x128 tiles, 8 waves of 64x32; two work-groups per CU (68
