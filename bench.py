@@ -31,7 +31,17 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gj_update_traffic.md")
-GJ_PANEL = 256  # Gauss-Jordan panel width of the coarsest-level inverse
+KERNEL_HDR = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.h")
+
+
+def gj_panel():
+    """Gauss-Jordan panel width of the coarsest-level inverse (kGJPanel)."""
+    import re
+    m = re.search(r"constexpr int kGJPanel = (\d+);", open(KERNEL_HDR).read())
+    return int(m.group(1))
+
+
+GJ_PANEL = gj_panel()
 WORKLOADS = {
     "cfg0": (0, "10x10x10 cells, b=4, lognormal sigma=1, 2 wells (4,000 unknowns)"),
     "cfg1": (1, "64x64x32 cells, b=4, lognormal sigma=1.5, kz/kh=0.1, 4 wells (524,288 unknowns)"),
@@ -199,8 +209,9 @@ def main():
                 "precond_apply_us": stage_ms(s32, stream, msp.STAGE_PRECOND, 10, xin, yout) * 1e3}
         s32.close()
 
-    # dominant kernel of a step: the rank-256 update of the coarsest-level
-    # Gauss-Jordan inverse (FP64 matrix cores); algorithmic work 2 n_L^2 256 flops
+    # dominant kernel of a step: the rank-P update of the coarsest-level
+    # Gauss-Jordan inverse (FP64 matrix cores, P = GJ_PANEL); algorithmic work
+    # 2 n_L^2 P flops
     upd_flops = 2.0 * nL * nL * GJ_PANEL
     achieved = upd_flops / (t_upd * 1e-3) / 1e12
     roofline = {"kernel": f"k_dgemm (rank-{GJ_PANEL} update of the coarsest-level inverse, "
@@ -260,8 +271,9 @@ def main():
 
 def source_hash():
     """sha256[:16] of the dominant kernel's source: the FP64 GEMM tile code
-    (from its header comment to the end of the small-tile kernel) and its
-    launcher, so edits elsewhere in the file keep the stored counters valid."""
+    (from its header comment to the end of the small-tile kernel), its
+    launcher and the panel width (the update's k), so edits elsewhere in the
+    file keep the stored counters valid."""
     import hashlib
     src = open(KERNEL_SRC).read()
     a = src.index("// C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.")
@@ -269,7 +281,8 @@ def source_hash():
     b = src.index("\n}\n", b) + 3
     c = src.index("hipError_t launch_dgemm(")
     d = src.index("\n}\n", c) + 3
-    return hashlib.sha256((src[a:b] + src[c:d]).encode()).hexdigest()[:16]
+    key = src[a:b] + src[c:d] + f"panel={GJ_PANEL}"
+    return hashlib.sha256(key.encode()).hexdigest()[:16]
 
 
 def stored_traffic():

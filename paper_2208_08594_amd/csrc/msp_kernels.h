@@ -173,7 +173,7 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // of panel s (cols_end likewise by columns), entries outside the window are
 // still those of the original sparse matrix.  work must hold
 // dense_inverse_work(n) doubles.
-constexpr int kGJPanel = 256;
+constexpr int kGJPanel = 384;
 struct GjLookAhead {
     hipStream_t main, aux;
     hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2];

@@ -278,10 +278,10 @@ def _pivoting_matrix(n, seed):
     return rp, ci, val.reshape(-1, 1, 1)
 
 
-@pytest.mark.parametrize("n", [600, 129])
+@pytest.mark.parametrize("n", [1000, 600, 129])
 def test_coarse_direct_solve_needs_pivoting(n):
-    """The whole matrix is the coarsest level (several 256-wide panels, ragged
-    last block), so the V-cycle is the direct solve alone, on a matrix whose
+    """The whole matrix is the coarsest level (several 384-wide panels of the
+    Gauss-Jordan pass, ragged last block), so the V-cycle is the direct solve alone, on a matrix whose
     diagonal is 10x smaller than the largest entry of its row."""
     rp, ci, vals = _pivoting_matrix(n, 11)
     announce("pivoting", n)
