@@ -164,6 +164,7 @@ struct msp_ctx {
     int *flag = nullptr, *flag_host = nullptr;
     int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
     bool pattern_ok = false;    // rp/ci (host) and rp_d/ci_d hold a checked pattern
+    bool pattern_sym = false;   // that pattern is structurally symmetric
     long long pattern_gen = 0;  // counts pattern changes
     long long lev0_gen = -1;    // pattern_gen when lev[0].A was built
     hipStream_t chain_copy = nullptr;  // device-to-host copies of the setup
@@ -877,7 +878,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     const bool level0_smoothed = n > c->opt.max_coarse;
     std::shared_future<Groups> groups0 = std::async(std::launch::async, [c]() {
         Groups G;
-        Adjacency adj = build_adjacency(c->n, c->rp.data(), c->ci.data());
+        Adjacency adj = build_adjacency(c->n, c->rp.data(), c->ci.data(), c->pattern_sym);
         G.g = vertices_grouping(adj, G.color);
         return G;
     }).share();
@@ -900,12 +901,17 @@ void rebuild_B(msp_ctx *c, const double *vals)
     // groups and layout of each coarser smoothed level start as soon as the
     // chain has produced it
     std::vector<std::future<LevelWork>> work(MSP_MAX_LEVELS);
-    const LevelCallback start_level = [&work, fp32](int l, int nl, const int *rp, const int *ci,
-                                                    const double *val) {
+    // levels that the device chain produced are structurally symmetric (it
+    // runs only on a symmetric level 0, and Galerkin products keep that)
+    bool device_levels = false;
+    const LevelCallback start_level = [&work, &device_levels, fp32](
+                                          int l, int nl, const int *rp, const int *ci,
+                                          const double *val) {
         if (l == 0) return;  // level 0: the pattern's groups above
-        work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32]() {
+        const bool sym = device_levels;
+        work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32, sym]() {
             LevelWork W;
-            Adjacency adj = build_adjacency(nl, rp, ci);
+            Adjacency adj = build_adjacency(nl, rp, ci, sym);
             W.G.g = vertices_grouping(adj, W.G.color);
             level_layout(nl, rp, ci, val, W.G.color, W.G.g, fp32, W.lay);
             return W;
@@ -916,12 +922,14 @@ void rebuild_B(msp_ctx *c, const double *vals)
     if (c->opt.host_chain == 0) {
         if (!c->cap_stream)
             HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        device_levels = true;  // no level callback runs if the chain declines (st == 1)
         st = device_hierarchy(
             A0, c->rp_d, c->ci_d, ap, c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, start_level,
             [&a0_ready]() { a0_ready.get(); }, c->stream, c->cap_stream, c->chain_copy,
             [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip, c->chain_host);
     }
     if (st == 1) {
+        device_levels = false;
         a0_ready.get();
         st = build_hierarchy(std::move(A0), c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, false,
                              start_level);
@@ -1540,6 +1548,7 @@ int msp_setup(msp_ctx *c, int n, int b, int p, const int *row_ptr, const int *co
             for (int i = 0; i < n; ++i)
                 for (int k = c->rp[i]; k < c->rp[i + 1]; ++k)
                     if (c->ci[k] == i) c->diag_pos[i] = k;
+            c->pattern_sym = pattern_symmetric(n, c->rp.data(), c->ci.data());
             build_layout_A(c);
         }
         c->pattern_ok = true;

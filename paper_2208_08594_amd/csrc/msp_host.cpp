@@ -40,37 +40,52 @@ int check_pattern(int n, const int *rp, const int *ci, long long nnz)
     return 0;
 }
 
-Adjacency build_adjacency(int n, const int *rp, const int *ci)
+bool pattern_symmetric(int n, const int *rp, const int *ci)
+{
+    const int parts = host_parts(n);
+    std::vector<unsigned char> miss(parts, 0);
+    for_chunks(n, parts, [&](int lo, int hi, int t) {
+        for (int i = lo; i < hi && !miss[t]; ++i)
+            for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                const int j = ci[k];
+                if (!std::binary_search(ci + rp[j], ci + rp[j + 1], i)) {
+                    miss[t] = 1;
+                    break;
+                }
+            }
+    });
+    for (unsigned char m : miss)
+        if (m) return false;
+    return true;
+}
+
+Adjacency build_adjacency(int n, const int *rp, const int *ci, bool known_symmetric)
 {
     // A structurally symmetric pattern is its own symmetrisation: the
-    // neighbours of i are row i without the diagonal (already ascending).
-    {
+    // neighbours of i are row i without the diagonal (already ascending),
+    // copied by row chunks in parallel.
+    if (known_symmetric || pattern_symmetric(n, rp, ci)) {
+        Adjacency G;
+        G.n = n;
+        G.ptr.assign(n + 1, 0);
         const int parts = host_parts(n);
-        std::vector<unsigned char> miss(parts, 0);
-        for_chunks(n, parts, [&](int lo, int hi, int t) {
-            for (int i = lo; i < hi && !miss[t]; ++i)
-                for (int k = rp[i]; k < rp[i + 1]; ++k) {
-                    const int j = ci[k];
-                    if (!std::binary_search(ci + rp[j], ci + rp[j + 1], i)) {
-                        miss[t] = 1;
-                        break;
-                    }
-                }
-        });
-        bool symmetric = true;
-        for (unsigned char m : miss) symmetric = symmetric && !m;
-        if (symmetric) {
-            Adjacency G;
-            G.n = n;
-            G.ptr.assign(n + 1, 0);
-            G.nbr.reserve((size_t)rp[n]);
-            for (int i = 0; i < n; ++i) {
-                for (int k = rp[i]; k < rp[i + 1]; ++k)
-                    if (ci[k] != i) G.nbr.push_back(ci[k]);
-                G.ptr[i + 1] = (int)G.nbr.size();
+        for_chunks(n, parts, [&](int lo, int hi, int) {
+            for (int i = lo; i < hi; ++i) {
+                int m = 0;
+                for (int k = rp[i]; k < rp[i + 1]; ++k) m += ci[k] != i;
+                G.ptr[i + 1] = m;
             }
-            return G;
-        }
+        });
+        for (int i = 0; i < n; ++i) G.ptr[i + 1] += G.ptr[i];
+        G.nbr.resize(G.ptr[n]);
+        for_chunks(n, parts, [&](int lo, int hi, int) {
+            for (int i = lo; i < hi; ++i) {
+                int o = G.ptr[i];
+                for (int k = rp[i]; k < rp[i + 1]; ++k)
+                    if (ci[k] != i) G.nbr[o++] = ci[k];
+            }
+        });
+        return G;
     }
     // otherwise count both directions of every off-diagonal entry, then sort
     // and drop duplicates
@@ -150,16 +165,22 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     // scanned: neighbourhood already enumerated for this group.  A vertex never
     // re-enters V inside a group, so enumerating a neighbourhood a second time
     // cannot add a candidate: each neighbourhood is scanned at most once per group.
-    std::vector<unsigned char> open(n), queued(n), scanned(n);
+    // per vertex: kOpen (in V), kQueued (already a second-ring candidate of this
+    // group), kScanned (neighbourhood already enumerated for this group), in
+    // one byte so that each visit touches one cache line
+    constexpr unsigned char kOpen = 1, kQueued = 2, kScanned = 4;
+    std::vector<unsigned char> fl(n);
+    // unc[u]: neighbours of u not yet in any group; a vertex with none has
+    // nothing left to add to a second ring, so its neighbourhood is skipped
+    std::vector<int> unc(n);
+    for (int u = 0; u < n; ++u) unc[u] = G.degree(u);
     int left = n, g = 0;
     while (left > 0) {
         ++g;  // one call of VerticesSplitting builds group g
         int avail = 0;
         for (int i = 0; i < n; ++i) {
-            open[i] = color[i] == 0;  // V: undetermined vertices
-            queued[i] = 0;
-            scanned[i] = 0;
-            avail += open[i];
+            fl[i] = color[i] == 0 ? kOpen : 0;  // V: undetermined vertices
+            avail += fl[i];
         }
         std::fill(bits.begin(), bits.end(), 0ull);
         std::fill(summ.begin(), summ.end(), 0ull);
@@ -170,28 +191,30 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             int v = -1;
             while (nqueued > 0) {  // second-ring candidates W^ that are still in V
                 int t = hat_pop();
-                if (open[t]) { v = t; break; }
+                if (fl[t] & kOpen) { v = t; break; }
             }
             if (v < 0) {
-                while (!open[order[cursor]]) ++cursor;
+                while (!(fl[order[cursor]] & kOpen)) ++cursor;
                 v = order[cursor];
             }
             color[v] = g;  // v joins W
-            open[v] = 0;
+            fl[v] &= (unsigned char)~kOpen;
             --avail;
             --left;
             for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // S_v leaves V (W-bar)
                 int u = G.nbr[q];
-                if (open[u]) { open[u] = 0; --avail; }
+                __builtin_prefetch(&G.nbr[G.ptr[u]]);  // read by the second ring below
+                --unc[u];
+                if (fl[u] & kOpen) { fl[u] &= (unsigned char)~kOpen; --avail; }
             }
             for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // second ring enters W^
                 int u = G.nbr[q];
-                if (scanned[u]) continue;
-                scanned[u] = 1;
+                if ((fl[u] & kScanned) || unc[u] == 0) continue;
+                fl[u] |= kScanned;
                 for (int t = G.ptr[u]; t < G.ptr[u + 1]; ++t) {
                     int w = G.nbr[t];
-                    if (open[w] && !queued[w]) {
-                        queued[w] = 1;
+                    if ((fl[w] & (kOpen | kQueued)) == kOpen) {
+                        fl[w] |= kQueued;
                         hat_push(w);
                     }
                 }

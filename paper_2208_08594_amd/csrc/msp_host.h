@@ -53,7 +53,11 @@ struct Adjacency {
     std::vector<int> ptr, nbr;
     int degree(int i) const { return ptr[i + 1] - ptr[i]; }
 };
-Adjacency build_adjacency(int n, const int *rp, const int *ci);
+// known_symmetric skips the symmetry test (pattern_symmetric) when the caller
+// already knows the answer.
+Adjacency build_adjacency(int n, const int *rp, const int *ci, bool known_symmetric = false);
+// True if every stored (i, j) has a stored (j, i).
+bool pattern_symmetric(int n, const int *rp, const int *ci);
 
 // Alg. 4.2 (VerticesGrouping) around Alg. 4.1 (VerticesSplitting): color[i]
 // in 1..g, returns g.  Largest static degree first, lowest index on ties,
