@@ -480,6 +480,66 @@ def test_errors_and_edge_cases():
     assert info["status"] == 1 and info["iterations"] == 2
 
 
+def _permuted(sys_, seed):
+    """The same system with its cells renumbered: same n and nnzb, another
+    block pattern."""
+    import dataclasses
+    n = sys_.n
+    perm = np.random.default_rng(seed).permutation(n)  # new index of old cell
+    inv = np.argsort(perm)
+    rp = sys_.row_ptr.astype(np.int64)
+    rows, cols, blocks = [], [], []
+    for new_i in range(n):
+        old = inv[new_i]
+        ks = np.arange(rp[old], rp[old + 1])
+        nc = perm[sys_.col_ind[ks]]
+        o = np.argsort(nc)
+        cols.append(nc[o])
+        blocks.append(sys_.vals[ks[o]])
+        rows.append(len(ks))
+    row_ptr = np.concatenate([[0], np.cumsum(rows)]).astype(np.int32)
+    col_ind = np.concatenate(cols).astype(np.int32)
+    vals = np.concatenate(blocks)
+    b = sys_.b
+    rhs = sys_.rhs.reshape(n, b)[inv].reshape(-1).copy()
+    r = np.repeat(np.arange(n), np.diff(row_ptr))
+    return dataclasses.replace(sys_, name=sys_.name + "-perm", row_ptr=row_ptr, col_ind=col_ind,
+                               vals=vals, rhs=rhs, wells=np.sort(perm[sys_.wells]),
+                               diag_pos=np.nonzero(col_ind == r)[0])
+
+
+def test_new_pattern_of_the_same_size_is_ingested_again():
+    """A second pattern with the same n and nnzb (cells renumbered) is told
+    apart from the first on the device and taken in anew: the context then
+    solves it exactly as a fresh context does."""
+    a = synth.config(0)
+    bsys = _permuted(a, 7)
+    assert bsys.n == a.n and bsys.nnzb == a.nnzb
+    assert not np.array_equal(bsys.col_ind, a.col_ind)
+    announce("same-size pattern change")
+    g = msp.Solver(max_coarse=64)
+    g.setup(a)
+    g.solve(a.rhs)
+    g.setup(bsys)
+    x1, i1 = g.solve(bsys.rhs)
+    f = msp.Solver(max_coarse=64)
+    f.setup(bsys)
+    x2, i2 = f.solve(bsys.rhs)
+    assert i1["iterations"] == i2["iterations"]
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    o = O.OracleSolver(max_coarse=64)
+    o.setup(bsys)
+    for l in range(o.nlevels):
+        assert np.array_equal(g.level(l)["col_ind"], o.level(l)["col_ind"])
+    # and back to the first pattern
+    g.setup(a)
+    x3, i3 = g.solve(a.rhs)
+    assert i3["rel_true_residual"] <= 1e-6
+    g.close()
+    f.close()
+    o.close()
+
+
 def test_deterministic_bitwise():
     sys = synth.config(0)
     announce("determinism")
