@@ -938,6 +938,10 @@ void rebuild_B(msp_ctx *c, const double *vals)
     if (st == -9) fail(MSP_ERR_COARSE);
     const int nlev = (int)H.A.size();
     launch_coarse(c, H.A.back(), tmp);
+    // zero diagonals on the smoothed levels (the device chain leaves this
+    // test to here, behind the coarsest inverse already queued)
+    a0_ready.get();
+    if (device_levels && check_diagonals(H) != 0) fail(MSP_ERR_SINGULAR);
     phase(3);
     c->lev.resize(nlev);
     std::vector<LevelLayout> lays(nlev);

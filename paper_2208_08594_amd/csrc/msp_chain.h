@@ -35,9 +35,12 @@ using HipFail = void (*)(hipError_t);
 // H.agg every aggregation map, on_smoothed is called for each smoothed level
 // as soon as it is known (from another thread for all but the first level:
 // the host copy of a level runs on a copy thread, on `copy_st`, while the
-// device builds the next one); returns 0, -3 or -9.  A0's values may still
-// be on their way to the host: level0_values() is called (and must return
-// only once they are there) before they are read.  Returns 1 without touching
+// device builds the next one); returns 0 or -9.  The zero-diagonal test of
+// build_hierarchy is left to the caller (check_diagonals), so that the
+// coarsest-level work can start first.  A0's values may still be on their
+// way to the host: level0_values() is called (and must return only once they
+// are there) before they are read here, and before returning when level 0 is
+// the coarsest level.  Returns 1 without touching
 // A0 or H when the level-0 pattern is not structurally symmetric (the pass
 // reads a_ji through the mirror entry); the caller then runs the host chain.
 // `cap` is an idle stream used only to capture batches of matching rounds

@@ -602,8 +602,8 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     if (n0 <= max_coarse || max_levels <= 1) {
         H = Hierarchy();
         H.A.push_back(std::move(A0));
-        level0_values();
-        return check_hierarchy(H, max_dense);
+        level0_values();  // level 0 is the coarsest: the caller inverts it next
+        return H.A.back().n > max_dense ? -9 : 0;
     }
     Chain X;
     X.st = st;
@@ -664,12 +664,10 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         X.launched();
         X.ck(hipEventRecord(X.ev_lvl, st));
         {
+            // sized (and cleared) by the copy thread, off this thread's path
             Csr Cn;
             Cn.n = nc2;
-            Cn.rp.resize(nc2 + 1);
-            Cn.ci.resize(nnzc);
-            Cn.val.resize(nnzc);
-            H.agg.emplace_back(cur.n);
+            H.agg.emplace_back();
             H.A.push_back(std::move(Cn));
         }
         const bool stalled = (double)nc2 > 0.9 * (double)cur.n;
@@ -679,15 +677,19 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
             !stalled && !(nc2 <= max_coarse || l + 1 == max_levels - 1);
         {
             Csr &hn = H.A[l + 1];
-            int *hagg = H.agg[l].data();
+            std::vector<int> &hagg = H.agg[l];
             const int nf = cur.n;
             const DevLevel Cd = C;
             const int *aggf = X.aggf;
             const hipEvent_t ready = X.ev_lvl;
             const int lnext = l + 1;
             const bool call = next_smoothed && on_smoothed;
-            pending = std::async(std::launch::async, [&hn, hagg, nf, Cd, aggf, ready, nnzc, copy_st,
+            pending = std::async(std::launch::async, [&hn, &hagg, nf, Cd, aggf, ready, nnzc, copy_st,
                                                       hip_fail, call, lnext, &on_smoothed]() {
+                hagg.resize(nf);
+                hn.rp.resize(Cd.n + 1);
+                hn.ci.resize(nnzc);
+                hn.val.resize(nnzc);
                 auto ck = [hip_fail](hipError_t e) {
                     if (e != hipSuccess) {
                         (void)hipGetLastError();
@@ -695,7 +697,8 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                     }
                 };
                 ck(hipStreamWaitEvent(copy_st, ready, 0));
-                ck(hipMemcpyAsync(hagg, aggf, sizeof(int) * nf, hipMemcpyDeviceToHost, copy_st));
+                ck(hipMemcpyAsync(hagg.data(), aggf, sizeof(int) * nf, hipMemcpyDeviceToHost,
+                                  copy_st));
                 ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
                                   hipMemcpyDeviceToHost, copy_st));
                 if (nnzc) {
@@ -723,8 +726,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         next = 3 - next;
     }
     join();
-    level0_values();
-    return check_hierarchy(H, max_dense);
+    return H.A.back().n > max_dense ? -9 : 0;
 }
 
 }  // namespace msp

@@ -558,15 +558,29 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
     return check_hierarchy(H, max_dense);
 }
 
-int check_hierarchy(const Hierarchy &H, int max_dense)
+int check_diagonals(const Hierarchy &H)
 {
     for (size_t l = 0; l + 1 < H.A.size(); ++l) {
         const Csr &A = H.A[l];
-        for (int i = 0; i < A.n; ++i) {
-            double d = entry(A, i, i);
-            if (d == 0.0) return -3;
-        }
+        const int parts = host_parts(A.n);
+        std::vector<unsigned char> zero(parts, 0);
+        for_chunks(A.n, parts, [&](int lo, int hi, int t) {
+            for (int i = lo; i < hi; ++i)
+                if (entry(A, i, i) == 0.0) {
+                    zero[t] = 1;
+                    break;
+                }
+        });
+        for (unsigned char z : zero)
+            if (z) return -3;
     }
+    return 0;
+}
+
+int check_hierarchy(const Hierarchy &H, int max_dense)
+{
+    const int st = check_diagonals(H);
+    if (st) return st;
     if (H.A.back().n > max_dense) return -9;
     return 0;
 }

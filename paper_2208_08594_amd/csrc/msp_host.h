@@ -99,6 +99,8 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
 // The final checks of build_hierarchy: 0, -3 (zero diagonal on a smoothed
 // level) or -9 (coarsest level above max_dense rows).
 int check_hierarchy(const Hierarchy &H, int max_dense);
+// Its first part: 0, or -3 for a zero diagonal on a smoothed level.
+int check_diagonals(const Hierarchy &H);
 // groups of Alg. 4.2 on one level: fills color, returns g
 int color_level(const Csr &A, std::vector<int> &color);
 
