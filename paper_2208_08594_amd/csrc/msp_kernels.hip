@@ -444,6 +444,34 @@ __global__ __launch_bounds__(kThreads) void k_gs_first(int npos, int p0, int p1,
     x[t] = (t >= p0 && t < p1) ? f[t] / diag[t] : T(0);
 }
 
+// sum0 + sum over the stored entries k < width of one sliced-ELL row (lane
+// stride 64) of val[k] x[col[k]], in k order, padding (col < 0) skipped.  The
+// entries go in batches of 8: the column and value loads of a batch issue
+// together, then its gathers of x, so a row costs two memory round trips per
+// batch instead of two per entry.
+template <typename T>
+__device__ inline T sell_row_dot(const int *__restrict__ cb, const T *__restrict__ vb, int width,
+                                 const T *x, T sum0 = 0)
+{
+    T sum = sum0;
+    for (int k0 = 0; k0 < width; k0 += 8) {
+        int c[8];
+        T v[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool in = k0 + u < width;
+            c[u] = in ? cb[(k0 + u) * 64] : -1;
+            v[u] = in ? vb[(k0 + u) * 64] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c[u] >= 0) sum += v[u] * xv[u];
+    }
+    return sum;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gs_color(const int4 *__restrict__ slices,
                                                        const int *__restrict__ col, int s0,
@@ -457,14 +485,9 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(const int4 *__restrict__ 
     const int4 d = slices[s];
     if (lane >= d.y) return;
     const int row = d.x + lane;
-    const int *cb = col + d.w + lane;
-    const T *vb = val + d.w + lane;
-    T sum = 0;
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) sum += vb[k * 64] * x[c];
-    }
-    x[row] = (f[row] - sum) / diag[row];
+    const T fr = f[row], dr = diag[row];
+    const T sum = sell_row_dot<T>(col + d.w + lane, val + d.w + lane, d.z, x);
+    x[row] = (fr - sum) / dr;
 }
 
 template <typename T>
@@ -482,14 +505,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int4 *__restrict__ 
     const int4 d = slices[s];
     if (lane >= d.y) return;
     const int row = d.x + lane;
-    const int *cb = col + d.w + lane;
-    const T *vb = val + d.w + lane;
-    T sum = diag[row] * x[row];
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) sum += vb[k * 64] * x[c];
-    }
-    r[row] = f[row] - sum;
+    const T fr = f[row];
+    const T sum = sell_row_dot<T>(col + d.w + lane, val + d.w + lane, d.z, x, diag[row] * x[row]);
+    r[row] = fr - sum;
 }
 
 // Weighted point-Jacobi smoothing (the PJAC ablation of Sec. 6): the first
