@@ -1639,6 +1639,7 @@ int msp_footprint(int n, long long nnzb, int b, const msp_options *opt, size_t *
     double vecs = (double)n * b * (8 + 2 * ts) + (double)n * 8 * b;
     double krylov = 8.0 * (double)n * b * (2.0 * o.restart + 4) + 8.0 * kDotBlocks * (o.restart + 2);
     double setup_tmp = 8.0 * nnzb + 8.0 * (double)dense_inverse_work(o.max_coarse);
+    if (o.host_chain == 0 && n > o.max_coarse) setup_tmp += (double)device_chain_bytes(n, nnzb);
     *bytes = (size_t)(A + amg + coarse + bilu + vecs + krylov + setup_tmp + (1 << 20));
     return MSP_OK;
 }

@@ -48,6 +48,10 @@ using HipFail = void (*)(hipError_t);
 // least 16 ints.  A stalled level (the two passes keep more than 90% of its
 // rows) is finished on the host with absorb_singletons and galerkin, and its
 // coarse matrix uploaded.
+// Bytes of the one device allocation the chain makes for a level 0 of n0
+// rows and nnz0 entries (freed with the setup's other temporaries).
+size_t device_chain_bytes(int n0, long long nnz0);
+
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                      const LevelCallback &on_smoothed, const std::function<void()> &level0_values,

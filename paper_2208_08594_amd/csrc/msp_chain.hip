@@ -591,6 +591,12 @@ size_t place(Chain &X, char *base, int n0, long long nnz0)
 
 }  // namespace
 
+size_t device_chain_bytes(int n0, long long nnz0)
+{
+    Chain X;
+    return place(X, nullptr, n0, nnz0);
+}
+
 int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0,
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                      const LevelCallback &on_smoothed, const std::function<void()> &level0_values,
