@@ -396,17 +396,25 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int4 *__restrict__ slic
     for (int r = 0; r < B; ++r) acc[r] = 0.0;
     const int *cb = col + d.w + lane;
     const double *vb = val + (long long)(d.w >> 6) * 64 * E + lane;
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) {
-            double xv[B];
+    // the column indices of a batch of 8 entries load together, then the
+    // entries' blocks and x-blocks (one round trip for the indices per batch)
+    for (int k0 = 0; k0 < d.z; k0 += 8) {
+        int cc[8];
 #pragma unroll
-            for (int u = 0; u < B; ++u) xv[u] = x[(long long)c * B + u];
-            const double *v = vb + (long long)k * 64 * E;
+        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
 #pragma unroll
-            for (int r = 0; r < B; ++r)
+        for (int q = 0; q < 8; ++q) {
+            const int c = cc[q];
+            if (c >= 0) {
+                double xv[B];
 #pragma unroll
-                for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * xv[u];
+                for (int u = 0; u < B; ++u) xv[u] = x[(long long)c * B + u];
+                const double *v = vb + (long long)(k0 + q) * 64 * E;
+#pragma unroll
+                for (int r = 0; r < B; ++r)
+#pragma unroll
+                    for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * xv[u];
+            }
         }
     }
 #pragma unroll
@@ -615,11 +623,18 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
 #pragma unroll
     for (int k = 0; k < B; ++k) acc[k] = 0;
     const int *cb = col + d.w + lane;
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) {
-            const T ec = e[c];
-            const long long sb = (long long)(d.w >> 6) + k;
+    for (int k0 = 0; k0 < d.z; k0 += 8) {  // column indices, then e, in batches of 8
+        int cc[8];
+        T ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ev[u] = cc[u] >= 0 ? e[cc[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (cc[u] < 0) continue;
+            const T ec = ev[u];
+            const long long sb = (long long)(d.w >> 6) + k0 + u;
 #pragma unroll
             for (int q = 0; q < B; ++q) {
                 T a;
@@ -653,17 +668,23 @@ __global__ __launch_bounds__(kThreads) void k_bilu_fwd(const int4 *__restrict__ 
     for (int r = 0; r < B; ++r) acc[r] = 0;
     const int *cb = col + d.w + lane;
     const T *vb = Lval + (long long)(d.w >> 6) * 64 * E + lane;
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) {
-            T yk[B];
+    for (int k0 = 0; k0 < d.z; k0 += 8) {  // column indices in batches of 8
+        int cc[8];
 #pragma unroll
-            for (int u = 0; u < B; ++u) yk[u] = y[(long long)c * B + u];
-            const T *v = vb + (long long)k * 64 * E;
+        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
 #pragma unroll
-            for (int r = 0; r < B; ++r)
+        for (int q = 0; q < 8; ++q) {
+            const int c = cc[q];
+            if (c >= 0) {
+                T yk[B];
 #pragma unroll
-                for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * yk[u];
+                for (int u = 0; u < B; ++u) yk[u] = y[(long long)c * B + u];
+                const T *v = vb + (long long)(k0 + q) * 64 * E;
+#pragma unroll
+                for (int r = 0; r < B; ++r)
+#pragma unroll
+                    for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * yk[u];
+            }
         }
     }
 #pragma unroll
@@ -689,19 +710,25 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
     for (int r = 0; r < B; ++r) t[r] = z[i * B + r];
     const int *cb = col + d.w + lane;
     const T *vb = Uval + (long long)(d.w >> 6) * 64 * E + lane;
-    for (int k = 0; k < d.z; ++k) {
-        const int c = cb[k * 64];
-        if (c >= 0) {
-            T zk[B];
+    for (int k0 = 0; k0 < d.z; k0 += 8) {  // column indices in batches of 8
+        int cc[8];
 #pragma unroll
-            for (int u = 0; u < B; ++u) zk[u] = z[(long long)c * B + u];
-            const T *v = vb + (long long)k * 64 * E;
+        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                T a = 0;
+        for (int q = 0; q < 8; ++q) {
+            const int c = cc[q];
+            if (c >= 0) {
+                T zk[B];
 #pragma unroll
-                for (int u = 0; u < B; ++u) a += v[(r * B + u) * 64] * zk[u];
-                t[r] -= a;
+                for (int u = 0; u < B; ++u) zk[u] = z[(long long)c * B + u];
+                const T *v = vb + (long long)(k0 + q) * 64 * E;
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    T a = 0;
+#pragma unroll
+                    for (int u = 0; u < B; ++u) a += v[(r * B + u) * 64] * zk[u];
+                    t[r] -= a;
+                }
             }
         }
     }
