@@ -163,6 +163,28 @@ def test_library_grouping_matches_oracle(shim, seed):
     assert g_lib == g_or and np.array_equal(c_lib, c_or)
 
 
+@pytest.mark.parametrize("n", [20000, 40000])
+def test_library_grouping_large_symmetric_matches_oracle(shim, n):
+    """Structurally symmetric patterns large enough for the row-chunked
+    (threaded) adjacency build and symmetry test, with enough groups that
+    vertices run out of undetermined neighbours while the groups are built."""
+    rng = np.random.default_rng(n)
+    rows = rng.integers(0, n, 5 * n)
+    cols = (rows + rng.integers(1, 400, 5 * n)) % n
+    i = np.concatenate([rows, cols, np.arange(n)])
+    j = np.concatenate([cols, rows, np.arange(n)])
+    key = np.unique(i.astype(np.int64) * n + j)
+    r, c = key // n, key % n
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, r + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    ci = c.astype(np.int32)
+    c_lib, g_lib = _lib_color(shim, rp, ci)
+    c_or, g_or = O.color(rp, ci)
+    assert g_lib > 4
+    assert g_lib == g_or and np.array_equal(c_lib, c_or)
+
+
 def test_library_hierarchy_steps_match_oracle(shim):
     for sys, mc in [(synth.config(0), 64), (synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1,
                                                                   "lateral4"), 200)]:
