@@ -243,7 +243,7 @@ def main():
                    "bilu_order": "natural" if args.bilu_order == 0 else "multicolor"},
         "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
         "setup_ms": setup_ms, "solve_ms": solve_ms, "iterations": last["iterations"],
-        "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "aggregation_host",
+        "setup_phase_ms": dict(zip(["pattern", "ingest", "decouple", "aggregation_chain",
                                     "level_layouts", "coarse_inverse_wait", "bilu",
                                     "worker_wait"],
                                    [round(v, 3) for v in last["phase_ms"][:8]])),

@@ -117,14 +117,16 @@ typedef struct {
     double rebuild_ms;        /* ... of which preconditioner regeneration */
     double solve_ms;          /* host wall time of the last solve */
     /* host wall time of the phases of the last setup (ms):
-     * [0] pattern copy and check, [1] value ingest, [2] decoupling,
-     * [3] aggregation chain on the host (pairwise passes and Galerkin
-     *     products) up to queueing the coarsest-level inverse,
-     * [7] waiting for the host worker threads (groups of the smoothed
-     *     levels, block ILU(0) plan) after the chain,
-     * [4] level layouts and uploads (while the coarsest inverse runs on the
-     *     device),
-     * [6] block ILU(0) factorisation and layouts (likewise overlapped),
+     * [0] pattern check (a device comparison when the pattern is unchanged),
+     * [1] value ingest, [2] decoupling,
+     * [3] aggregation chain (pairwise passes and Galerkin products, on the
+     *     device unless the pattern is not structurally symmetric) up to
+     *     queueing the coarsest-level inverse,
+     * [7] waiting for the host worker threads (block ILU(0) plan, groups and
+     *     layouts of the smoothed levels) after the chain,
+     * [6] block ILU(0) uploads and factorisation (while the coarsest inverse
+     *     runs on the device) and the final wait for the side stream,
+     * [4] level uploads (likewise overlapped),
      * [5] what remains of the coarsest-level inverse after [4], [6], [7] */
     double phase_ms[8];
 } msp_info;

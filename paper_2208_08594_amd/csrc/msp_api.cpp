@@ -943,35 +943,12 @@ void rebuild_B(msp_ctx *c, const double *vals)
     a0_ready.get();
     if (device_levels && check_diagonals(H) != 0) fail(MSP_ERR_SINGULAR);
     phase(3);
-    c->lev.resize(nlev);
     std::vector<LevelLayout> lays(nlev);
-    for (int l = 0; l + 1 < nlev; ++l) {
-        Groups G;
-        if (l == 0) {
-            G = groups0.get();
-            lays[0] = layout0.get();
-        } else {
-            LevelWork W = work[l].get();
-            G = std::move(W.G);
-            lays[l] = std::move(W.lay);
-        }
-        c->lev[l].color = std::move(G.color);
-        c->lev[l].g = G.g;
-    }
-    phase(7);
-    for (int l = 0; l < nlev; ++l) {
-        Level &L = c->lev[l];
-        L.A = std::move(H.A[l]);
-        if (l == 0) c->lev0_gen = c->pattern_gen;
-        L.n = L.A.n;
-        if (l + 1 < nlev) L.agg = std::move(H.agg[l]);
-    }
-    for (int l = 0; l + 1 < nlev; ++l) c->lev[l].nc = c->lev[l + 1].A.n;
     {
         CopyStreamScope on_side(c, c->side);
-        for (int l = 0; l < nlev; ++l) build_level_device(c, l, l == nlev - 1, &lays[l]);
-        link_levels(c);
-        phase(4);
+        // The R stage first: its plan needs only the level-0 groups, so it is
+        // usually ready well before the coarse levels' host work, and its
+        // uploads and factorisation then overlap that work.
         if (c->opt.full_smoother == 0) {
             planned.get();
             phase(7);
@@ -983,6 +960,33 @@ void rebuild_B(msp_ctx *c, const double *vals)
             const Groups &G0 = groups0.get();
             n_stage_device(c, vals, G0.color, G0.g);
         }
+        phase(6);
+        c->lev.resize(nlev);
+        for (int l = 0; l + 1 < nlev; ++l) {
+            Groups G;
+            if (l == 0) {
+                G = groups0.get();
+                lays[0] = layout0.get();
+            } else {
+                LevelWork W = work[l].get();
+                G = std::move(W.G);
+                lays[l] = std::move(W.lay);
+            }
+            c->lev[l].color = std::move(G.color);
+            c->lev[l].g = G.g;
+        }
+        phase(7);
+        for (int l = 0; l < nlev; ++l) {
+            Level &L = c->lev[l];
+            L.A = std::move(H.A[l]);
+            if (l == 0) c->lev0_gen = c->pattern_gen;
+            L.n = L.A.n;
+            if (l + 1 < nlev) L.agg = std::move(H.agg[l]);
+        }
+        for (int l = 0; l + 1 < nlev; ++l) c->lev[l].nc = c->lev[l + 1].A.n;
+        for (int l = 0; l < nlev; ++l) build_level_device(c, l, l == nlev - 1, &lays[l]);
+        link_levels(c);
+        phase(4);
     }
     HIPCHK(hipEventRecord(c->ev_side, c->side));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
