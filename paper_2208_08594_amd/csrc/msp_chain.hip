@@ -377,7 +377,7 @@ struct Chain {
     hipStream_t st = nullptr;
     HipFail hip_fail = nullptr;
     int *pinned = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_lvl = nullptr;  // a new level is on the device
     // work arrays, sized for level 0 (no later matrix is larger)
     double *s = nullptr, *cs = nullptr, *smax = nullptr;
@@ -471,22 +471,23 @@ struct Chain {
                 (void)hipGraphExecDestroy(e);
             }
         } exec_guard{exec, st};
+        // batches are queued two ahead of the one whose free count is read,
+        // so the device always has rounds queued while the host checks
         long long r = 0;
-        int batch = 0, pending = -1;
-        const long long cap_rounds = (long long)n + 4LL * kBatch + 4;
-        for (;;) {
+        const long long cap_rounds = (long long)n + 6LL * kBatch + 4;
+        for (int batch = 0;; ++batch) {
             ck(hipGraphLaunch(exec, st));
             r += kBatch;
             // free rows at the start of the batch's last round
-            const int slot = batch & 1;
+            const int slot = batch % 3;
             ck(hipMemcpyAsync(pinned + slot, ctr + ((kBatch - 1) & 1), sizeof(int),
                               hipMemcpyDeviceToHost, st));
             ck(hipEventRecord(ev[slot], st));
-            if (pending >= 0) {
-                ck(hipEventSynchronize(ev[pending & 1]));
-                if (pinned[pending & 1] == 0) break;
+            if (batch >= 2) {
+                const int old = (batch - 2) % 3;
+                ck(hipEventSynchronize(ev[old]));
+                if (pinned[old] == 0) break;
             }
-            pending = batch++;
             // every round settles at least the lowest free row
             if (r > cap_rounds) hip_fail(hipErrorUnknown);
         }
@@ -495,11 +496,12 @@ struct Chain {
         scan(flag, pos, n);
         k_number<<<nblocks(n), kThreads, 0, st>>>(n, state[0], partner, pos, agg, mem0, mem1);
         launched();
-        return read_int(pos + n, 2);
+        return read_int(pos + n, 4);
     }
-    // C = P^T L P for the pass just numbered (aggregates of one or two rows);
-    // returns nnz(C).  The candidate arrays serve as the row lists.
-    long long galerkin(const DevLevel &L, const int *agg, int nc, DevLevel &C)
+    // C = P^T L P for the pass just numbered (aggregates of one or two rows),
+    // queued without a wait (nnz(C) is C.rp[nc] on the device).  The
+    // candidate arrays serve as the row lists.
+    void galerkin(const DevLevel &L, const int *agg, int nc, DevLevel &C)
     {
         C.n = nc;
         k_gal_rows<<<nblocks(nc), kThreads, 0, st>>>(nc, L.rp, L.ci, L.val, agg, mem0, mem1, cj,
@@ -509,20 +511,6 @@ struct Chain {
         k_gal_fill<<<nblocks(nc), kThreads, 0, st>>>(nc, L.rp, mem0, mem1, cj, s, C.rp, C.ci,
                                                      C.val);
         launched();
-        return read_int(C.rp + nc, 3);
-    }
-    void to_host(const DevLevel &C, long long nnz, Csr &H)
-    {
-        H.n = C.n;
-        H.rp.resize(C.n + 1);
-        H.ci.resize(nnz);
-        H.val.resize(nnz);
-        ck(hipMemcpyAsync(H.rp.data(), C.rp, sizeof(int) * (C.n + 1), hipMemcpyDeviceToHost, st));
-        if (nnz) {
-            ck(hipMemcpyAsync(H.ci.data(), C.ci, sizeof(int) * nnz, hipMemcpyDeviceToHost, st));
-            ck(hipMemcpyAsync(H.val.data(), C.val, sizeof(double) * nnz, hipMemcpyDeviceToHost,
-                              st));
-        }
     }
     void to_device(const Csr &H, DevLevel &C)
     {
@@ -542,7 +530,7 @@ struct EventGuard {
     hipEvent_t *ev_lvl;
     ~EventGuard()
     {
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 3; ++i)
             if (ev[i]) (void)hipEventDestroy(ev[i]);
         if (*ev_lvl) (void)hipEventDestroy(*ev_lvl);
     }
@@ -617,7 +605,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     X.hip_fail = hip_fail;
     X.pinned = pinned;
     EventGuard guard{X.ev, &X.ev_lvl};
-    for (int i = 0; i < 2; ++i) X.ck(hipEventCreateWithFlags(&X.ev[i], hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) X.ck(hipEventCreateWithFlags(&X.ev[i], hipEventDisableTiming));
     X.ck(hipEventCreateWithFlags(&X.ev_lvl, hipEventDisableTiming));
     // one allocation for every work array
     char *base = (char *)alloc(place(X, nullptr, n0, nnz0));
@@ -664,7 +652,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         X.galerkin(cur, X.a1, nc1, M1);
         const int nc2 = X.pass(M1, false, X.a2);
         DevLevel &C = X.set[next];
-        const long long nnzc = X.galerkin(M1, X.a2, nc2, C);
+        X.galerkin(M1, X.a2, nc2, C);
         join();
         k_compose<<<nblocks(cur.n), kThreads, 0, st>>>(cur.n, X.a1, X.a2, X.aggf);
         X.launched();
@@ -690,12 +678,10 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
             const hipEvent_t ready = X.ev_lvl;
             const int lnext = l + 1;
             const bool call = next_smoothed && on_smoothed;
-            pending = std::async(std::launch::async, [&hn, &hagg, nf, Cd, aggf, ready, nnzc, copy_st,
+            pending = std::async(std::launch::async, [&hn, &hagg, nf, Cd, aggf, ready, copy_st,
                                                       hip_fail, call, lnext, &on_smoothed]() {
                 hagg.resize(nf);
                 hn.rp.resize(Cd.n + 1);
-                hn.ci.resize(nnzc);
-                hn.val.resize(nnzc);
                 auto ck = [hip_fail](hipError_t e) {
                     if (e != hipSuccess) {
                         (void)hipGetLastError();
@@ -707,6 +693,10 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                                   copy_st));
                 ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
                                   hipMemcpyDeviceToHost, copy_st));
+                ck(hipStreamSynchronize(copy_st));
+                const long long nnzc = hn.rp[Cd.n];
+                hn.ci.resize(nnzc);
+                hn.val.resize(nnzc);
                 if (nnzc) {
                     ck(hipMemcpyAsync(hn.ci.data(), Cd.ci, sizeof(int) * nnzc,
                                       hipMemcpyDeviceToHost, copy_st));
