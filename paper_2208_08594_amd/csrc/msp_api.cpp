@@ -139,7 +139,10 @@ struct msp_ctx {
     double *omega = nullptr;
     std::vector<Level> lev;
     int nL = 0, ldL = 0;
-    double *cinv = nullptr;
+    // coarsest-level solver A^-1 = W Y (W block upper, Y block unit lower
+    // triangular, both nL x nL with leading dimension ldL) and its FP64 work
+    // vector
+    double *cinv = nullptr, *cY = nullptr, *ct = nullptr;
     BiluData bilu;
     NStage ns;
     void *e_nat = nullptr, *ybuf = nullptr;
@@ -291,7 +294,7 @@ void release_B(msp_ctx *c)
     c->ns = NStage();
     c->hasB = false;
     c->omega = nullptr;
-    c->cinv = nullptr;
+    c->cinv = c->cY = c->ct = nullptr;
     c->e_nat = c->ybuf = nullptr;
     c->tC = c->tA = c->tB = nullptr;
 }
@@ -488,6 +491,8 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
     c->nL = m;
     c->ldL = (m + 15) & ~15;  // rows 128-byte aligned for the streaming GEMV
     c->cinv = (double *)c->dalloc(sizeof(double) * (size_t)m * c->ldL, c->allocB);
+    c->cY = (double *)c->dalloc(sizeof(double) * (size_t)m * c->ldL, c->allocB);
+    c->ct = (double *)c->dalloc(sizeof(double) * (size_t)m, c->allocB);
     int *rp = c->upload(A.rp, tmp);
     int *ci = c->upload(A.ci, tmp);
     double *val = c->upload(A.val, tmp);
@@ -495,8 +500,8 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
     HIPCHK(launch_fill((long long)m * c->ldL, 0.0, c->cinv, c->stream));
     HIPCHK(launch_dense_scatter(m, c->ldL, rp, ci, val, c->cinv, c->stream));
     if (!c->gj.aux) make_gj_streams(c);
-    // fill window of each panel step: a row first takes part in the step of
-    // the panel holding its first stored column, a column in that of its
+    // fill bound of each block step: a row first takes part in the step of
+    // the block holding its first stored column, a column in that of its
     // first stored row
     const int steps = (m + kGJPanel - 1) / kGJPanel;
     std::vector<int> rows_end(steps, 0), cols_end(steps, 0);
@@ -517,9 +522,11 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
             cols_end[s] = std::max(cols_end[s], cols_end[s - 1]);
         }
     }
+    double *lband =
+        (double *)c->dalloc(sizeof(double) * (dense_inverse_lband(m, rows_end.data()) + 1), tmp);
     c->clear_flag(0);
-    HIPCHK(dense_inverse(m, c->ldL, c->cinv, work, c->flag, c->stream, &c->gj, rows_end.data(),
-                         cols_end.data()));
+    HIPCHK(dense_inverse(m, c->ldL, c->cinv, c->cY, lband, work, c->flag, c->stream, &c->gj,
+                         rows_end.data(), cols_end.data()));
 }
 
 // Host-only part of the block ILU(0) setup: elimination order, dependency
@@ -1074,7 +1081,8 @@ void vcycle(msp_ctx *c, int l)
 {
     Level &L = c->lev[l];
     if (l == (int)c->lev.size() - 1) {
-        HIPCHK(launch_coarse_gemv<T>(L.n, c->ldL, c->cinv, (const T *)L.f, (T *)L.x, c->stream));
+        HIPCHK(launch_coarse_solve<T>(L.n, c->ldL, kGJPanel, c->cY, c->cinv, (const T *)L.f,
+                                      c->ct, (T *)L.x, c->stream));
         return;
     }
     Level &C = c->lev[l + 1];
@@ -1637,12 +1645,13 @@ int msp_footprint(int n, long long nnzb, int b, const msp_options *opt, size_t *
     const double ts = o.precond_fp32 ? 4.0 : 8.0;
     double A = slots * (E * 8 + 8) + (double)n * 8 + (o.precond_fp32 ? slots * b * 4 : 0);
     double amg = 2.0 * ((double)nnzb * 1.15 * (8 + ts + 8)) + 8.0 * n * (3 * ts + 16);
-    double coarse = 8.0 * (double)o.max_coarse * o.max_coarse * 1.0;
+    double coarse = 2 * 8.0 * (double)o.max_coarse * o.max_coarse + 8.0 * o.max_coarse;
     double bilu = (double)nnzb * E * 8 + (double)n * E * 8 + 2 * slots * (E * ts + 8) +
                   (double)n * (E * ts + 24);
     double vecs = (double)n * b * (8 + 2 * ts) + (double)n * 8 * b;
     double krylov = 8.0 * (double)n * b * (2.0 * o.restart + 4) + 8.0 * kDotBlocks * (o.restart + 2);
-    double setup_tmp = 8.0 * nnzb + 8.0 * (double)dense_inverse_work(o.max_coarse);
+    double setup_tmp = 8.0 * nnzb + 8.0 * (double)dense_inverse_work(o.max_coarse) +
+                       8.0 * (double)dense_inverse_lband(o.max_coarse, nullptr);
     if (o.host_chain == 0 && n > o.max_coarse) setup_tmp += (double)device_chain_bytes(n, nnzb);
     *bytes = (size_t)(A + amg + coarse + bilu + vecs + krylov + setup_tmp + (1 << 20));
     return MSP_OK;
@@ -1885,24 +1894,24 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
     if (stage == MSP_STAGE_GS0 && c->lev.size() < 2) return MSP_ERR_STATE;
     return guarded([&]() {
         const bool f32 = c->fp32();
-        if (stage == MSP_STAGE_GJ_UPDATE) {
-            // scratch operands of the coarsest size (made on first use, kept with
-            // B): C = copy of the inverse, A (n x P) and B (P x n) constant, P
-            // the Gauss-Jordan panel width
-            const int m = c->nL, ld = c->ldL;
+        if (stage == MSP_STAGE_TRI_SWEEP) {
+            // the largest step of the triangular-inverse sweeps of the
+            // coarsest solver: C = -A B with A (n_L - P) x 3P, B 3P x P, on
+            // scratch operands made on first use and kept with B (P the block
+            // size); C is overwritten, so every repetition does the same work
+            const int m = c->nL;
             constexpr int P = kGJPanel;
+            const int mr = m > P ? m - P : m;
             if (!c->tC) {
-                c->tC = (double *)c->dalloc(sizeof(double) * (size_t)m * ld, c->allocB);
-                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)m * P, c->allocB);
-                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)P * m, c->allocB);
-                HIPCHK(hipMemcpyAsync(c->tC, c->cinv, sizeof(double) * (size_t)m * ld,
-                                      hipMemcpyDeviceToDevice, c->stream));
-                HIPCHK(launch_fill((long long)m * P, 1e-3, c->tA, c->stream));
-                HIPCHK(launch_fill((long long)m * P, 1e-3, c->tB, c->stream));
+                c->tC = (double *)c->dalloc(sizeof(double) * (size_t)mr * P, c->allocB);
+                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)mr * 3 * P, c->allocB);
+                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)3 * P * P, c->allocB);
+                HIPCHK(launch_fill((long long)mr * 3 * P, 1e-3, c->tA, c->stream));
+                HIPCHK(launch_fill((long long)3 * P * P, 1e-3, c->tB, c->stream));
                 c->sync();
             }
             for (int r = 0; r < reps; ++r)
-                HIPCHK(launch_dgemm(m, m, P, c->tA, P, c->tB, m, c->tC, ld, -1.0, 1.0,
+                HIPCHK(launch_dgemm(mr, P, 3 * P, c->tA, 3 * P, c->tB, P, c->tC, P, -1.0, 0.0,
                                     c->stream));
             c->sync();
             return MSP_OK;
@@ -1926,11 +1935,13 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
             case MSP_STAGE_COARSE: {
                 Level &L = c->lev.back();
                 if (f32)
-                    HIPCHK(launch_coarse_gemv<float>(L.n, c->ldL, c->cinv, (const float *)L.f,
-                                                     (float *)L.x, c->stream));
+                    HIPCHK(launch_coarse_solve<float>(L.n, c->ldL, kGJPanel, c->cY, c->cinv,
+                                                      (const float *)L.f, c->ct, (float *)L.x,
+                                                      c->stream));
                 else
-                    HIPCHK(launch_coarse_gemv<double>(L.n, c->ldL, c->cinv, (const double *)L.f,
-                                                      (double *)L.x, c->stream));
+                    HIPCHK(launch_coarse_solve<double>(L.n, c->ldL, kGJPanel, c->cY, c->cinv,
+                                                       (const double *)L.f, c->ct,
+                                                       (double *)L.x, c->stream));
                 break;
             }
             }

@@ -79,9 +79,12 @@ hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *
                            hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st);
-// x = Ainv f with the row-major n x n inverse of leading dimension ld (even)
+// Coarsest-level solve x = A^-1 f = W (Y f) with the factors of
+// dense_inverse (row-major, leading dimension ld even, block size P even):
+// t = Y f (FP64 work vector of n entries), then x = W t.
 template <typename T>
-hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st);
+hipError_t launch_coarse_solve(int n, int ld, int P, const double *Y, const double *W,
+                               const T *f, double *t, T *x, hipStream_t st);
 // weighted point-Jacobi smoothing: x = w D^-1 f (first sweep from zero) and
 // x += w D^-1 r; launch_zero clears a level vector (kernel, graph-safe)
 template <typename T>
@@ -157,21 +160,27 @@ hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, con
 // C = alpha A B + beta C, row-major FP64 (matrix-core tiles).
 hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
                         double *C, int ldc, double alpha, double beta, hipStream_t st);
-// In-place inverse of the n x n row-major matrix M (leading dimension ld) by
-// block Gauss-Jordan over kGJPanel-wide panels.  Each diagonal block is
-// inverted by an inner Gauss-Jordan pass over 128-wide panels with partial
-// pivoting inside each 128 x 128 diagonal block; *bad is set on a zero pivot.
-// With `la`, the inverse of the next diagonal block (formed apart from the
-// step's update) runs on la->aux while the full rank-kGJPanel update runs on
-// la->main (look-ahead); events order the streams, and st waits for the whole
-// inverse.  The two streams are meant to own disjoint sets of compute units,
-// so the latency-bound diagonal chain never waits for slots behind the
-// update.  Without `la` everything runs on st.  rows_end/cols_end (host
-// arrays, one entry per panel step s, or null for the full matrix) bound the
-// window [0, rows_end[s]) x [0, cols_end[s]) that step s changes: with
-// rows_end[s] = 1 + the last row whose first stored column lies before the end
-// of panel s (cols_end likewise by columns), entries outside the window are
-// still those of the original sparse matrix.  work must hold
+// Direct solver of the n x n row-major matrix M (leading dimension ld), in
+// the form A^-1 = W Y.  A block LU factorisation over kGJPanel-wide blocks,
+// A = L U with L unit block-lower triangular, makes no row interchanges
+// across blocks; each pivot block is inverted by an inner Gauss-Jordan pass
+// over 128-wide panels with partial pivoting inside each 128 x 128 diagonal
+// block (*bad is set on a zero pivot).  Then W = U^-1 (block upper
+// triangular) overwrites M, with zeros below its diagonal blocks, and Y =
+// L^-1 (block unit lower triangular: identity diagonal blocks, zeros above)
+// fills Y (n x n, leading dimension ld).  With `la`, the inverse of the next
+// pivot block (formed apart from the step's Schur update) runs on la->aux
+// while the rest of the update runs on la->main (look-ahead); events order
+// the streams, and st waits for the whole solver.  The two streams are meant
+// to own disjoint sets of compute units, so the latency-bound pivot chain
+// never waits for slots behind the updates.  Without `la` everything runs on
+// st.  rows_end/cols_end (host arrays, one entry per block step s, or null
+// for the full matrix) bound the fill: with rows_end[s] = 1 + the last row
+// whose first stored column lies before the end of block s (cols_end likewise
+// by columns), L and U have no entries outside rows [0, rows_end[s]) of
+// block column s and columns [0, cols_end[s]) of block row s, and the
+// factorisation never touches them.  lband must hold
+// dense_inverse_lband(n, rows_end) doubles (the blocks of L) and work
 // dense_inverse_work(n) doubles.
 constexpr int kGJPanel = 384;
 struct GjLookAhead {
@@ -179,7 +188,9 @@ struct GjLookAhead {
     hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2];
 };
 size_t dense_inverse_work(int n);
-hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t st,
-                         const GjLookAhead *la, const int *rows_end, const int *cols_end);
+size_t dense_inverse_lband(int n, const int *rows_end);
+hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
+                         hipStream_t st, const GjLookAhead *la, const int *rows_end,
+                         const int *cols_end);
 
 }  // namespace msp

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "msp_kernels.h"
 
@@ -574,26 +575,33 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int n, const int *__restri
 
 // x = Ainv f on the coarsest level, FP64 arithmetic, one wave per row; rows
 // are 16-byte aligned (ld even) so each lane streams pairs of doubles.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, int ld,
-                                                          const double *__restrict__ inv,
-                                                          const T *__restrict__ f,
-                                                          T *__restrict__ x)
+// One triangle of the coarsest-level solve x = W (Y f), row-major FP64
+// factors of leading dimension ld (even) and block size P (even).  With
+// LOWER, out_i = in_i + sum over j < bs(i) of Y_ij in_j, where bs(i) is the
+// first row of i's block (Y is block unit lower triangular); otherwise
+// out_i = sum over j >= bs(i) of W_ij in_j (W is block upper triangular).
+// One wavefront per row, 16-byte loads from bs(i) (a multiple of P) on.
+template <bool LOWER, typename TI, typename TO>
+__global__ __launch_bounds__(kThreads) void k_coarse_tri(int n, int ld, int P,
+                                                         const double *__restrict__ F,
+                                                         const TI *__restrict__ in,
+                                                         TO *__restrict__ out)
 {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
     const int lane = threadIdx.x & 63;
-    const double2 *a = reinterpret_cast<const double2 *>(inv + (long long)row * ld);
-    const int n2 = n >> 1;
+    const int bs = row - row % P;
+    const int lo = LOWER ? 0 : bs, hi = LOWER ? bs : n;
+    const double2 *a = reinterpret_cast<const double2 *>(F + (long long)row * ld);
     double acc = 0.0;
 #pragma unroll 4
-    for (int j2 = lane; j2 < n2; j2 += 64) {
+    for (int j2 = (lo >> 1) + lane; j2 < (hi >> 1); j2 += 64) {
         const double2 v = a[j2];
-        acc += v.x * (double)f[2 * j2] + v.y * (double)f[2 * j2 + 1];
+        acc += v.x * (double)in[2 * j2] + v.y * (double)in[2 * j2 + 1];
     }
-    if ((n & 1) && lane == 0) acc += inv[(long long)row * ld + n - 1] * (double)f[n - 1];
+    if ((hi & 1) && lane == 0) acc += F[(long long)row * ld + hi - 1] * (double)in[hi - 1];
     acc = wave_sum(acc);
-    if (lane == 0) x[row] = (T)acc;
+    if (lane == 0) out[row] = (TO)(LOWER ? acc + (double)in[row] : acc);
 }
 
 template <typename T>
@@ -1695,9 +1703,13 @@ hipError_t launch_block_jacobi(int b, int n, const T *Dinv, T *y, hipStream_t st
 }
 
 template <typename T>
-hipError_t launch_coarse_gemv(int n, int ld, const double *inv, const T *f, T *x, hipStream_t st)
+hipError_t launch_coarse_solve(int n, int ld, int P, const double *Y, const double *W,
+                               const T *f, double *t, T *x, hipStream_t st)
 {
-    k_coarse_gemv<T><<<(unsigned)((n + 3) / 4), kThreads, 0, st>>>(n, ld, inv, f, x);
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 3) / 4);
+    k_coarse_tri<true, T, double><<<g, kThreads, 0, st>>>(n, ld, P, Y, f, t);
+    k_coarse_tri<false, double, T><<<g, kThreads, 0, st>>>(n, ld, P, W, t, x);
     return hipGetLastError();
 }
 
@@ -1828,8 +1840,8 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
     template hipError_t launch_jacobi_update<T>(int, T, const T *, const T *, T *, hipStream_t); \
     template hipError_t launch_zero<T>(int, T *, hipStream_t);                                 \
     template hipError_t launch_block_jacobi<T>(int, int, const T *, T *, hipStream_t);         \
-    template hipError_t launch_coarse_gemv<T>(int, int, const double *, const T *, T *,        \
-                                              hipStream_t);                                    \
+    template hipError_t launch_coarse_solve<T>(int, int, int, const double *, const double *, \
+                                               const T *, double *, T *, hipStream_t);         \
     template hipError_t launch_unpermute<T>(int, const int *, const T *, T *, hipStream_t);    \
     template hipError_t launch_pcol_residual<T>(int, int, const SellView &, const double *,    \
                                                 const float *, const double *, const T *, T *, \
@@ -1956,13 +1968,59 @@ size_t gj128_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
 
 }  // namespace
 
-size_t dense_inverse_work(int n)
+namespace {
+
+// L rows of LU step s: [K + kb, lu_end(n, s, ends)), where ends[s] bounds the
+// window of step s; the window always covers the next diagonal block (the
+// look-ahead reads it).
+int lu_end(int n, int s, const int *ends)
 {
-    return (size_t)3 * kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+    const int K = s * kGJPanel;
+    const int cover = n - K < 2 * kGJPanel ? n : K + 2 * kGJPanel;
+    const int e = ends ? std::max(ends[s], cover) : n;
+    return std::min(e, n);
 }
 
-hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipStream_t caller,
-                         const GjLookAhead *la, const int *rows_end, const int *cols_end)
+}  // namespace
+
+// M[r][0 .. kb) -> C[r][0 .. kb) (ld P) for r < nr, and zero there
+__global__ __launch_bounds__(kThreads) void k_lu_take(int nr, int kb, int ld, int P,
+                                                      double *__restrict__ M,
+                                                      double *__restrict__ C)
+{
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long long)nr * kb) return;
+    const int r = (int)(q / kb), t = (int)(q % kb);
+    double *m = M + (long long)r * ld + t;
+    C[(long long)r * P + t] = *m;
+    *m = 0.0;
+}
+
+// Y[i][i] = 1 for i < n
+__global__ __launch_bounds__(kThreads) void k_unit_diag(int n, int ld, double *__restrict__ Y)
+{
+    int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) Y[(long long)i * ld + i] = 1.0;
+}
+
+size_t dense_inverse_work(int n)
+{
+    return (size_t)2 * kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+}
+
+size_t dense_inverse_lband(int n, const int *rows_end)
+{
+    size_t q = 0;
+    for (int K = 0, s = 0; K < n; K += kGJPanel, ++s) {
+        const int r0 = std::min(K + kGJPanel, n);
+        q += (size_t)(lu_end(n, s, rows_end) - r0) * kGJPanel;
+    }
+    return q;
+}
+
+hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
+                         hipStream_t caller, const GjLookAhead *la, const int *rows_end,
+                         const int *cols_end)
 {
     hipError_t e;
     hipStream_t st = caller;
@@ -1972,13 +2030,18 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
         if ((e = hipStreamWaitEvent(st, la->ev_start, 0)) != hipSuccess) return e;
     }
     constexpr int P = kGJPanel;
+    const int steps = (n + P - 1) / P;
     double *Ccol = work;                                // n x P
-    double *Mrow = Ccol + (long long)P * n;             // P x n
-    double *Trow = Mrow + (long long)P * n;             // P x n
-    double *Nblk[2] = {Trow + (long long)P * n,         // P x P, two buffers
-                       Trow + (long long)P * n + (long long)P * P};
+    double *Tcol = Ccol + (long long)P * n;             // n x P
+    double *Nblk[2] = {Tcol + (long long)P * n,         // P x P, two buffers
+                       Tcol + (long long)P * n + (long long)P * P};
     double *iwork = Nblk[1] + (long long)P * P;         // inner inverse
     const hipStream_t aux = la ? la->aux : st;
+    std::vector<long long> loff(steps + 1, 0);
+    for (int s = 0; s < steps; ++s)
+        loff[s + 1] = loff[s] + (long long)(lu_end(n, s, rows_end) - std::min((s + 1) * P, n)) * P;
+    if ((e = launch_fill((long long)n * ld, 0.0, Y, st)) != hipSuccess) return e;
+    k_unit_diag<<<blocks_for(n), kThreads, 0, st>>>(n, ld, Y);
     // block 0: copy out and invert on the side stream
     {
         const int kb0 = n < P ? n : P;
@@ -1991,31 +2054,33 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
         if ((e = gj_inverse_128(kb0, P, Nblk[0], iwork, bad, aux)) != hipSuccess) return e;
         if (la && (e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
     }
-    for (int K = 0, s = 0; K < n; K += P, ++s) {
-        const int kb = n - K < P ? n - K : P;
-        // window of this step (the look-ahead block included)
-        const int cover = n - K < 2 * P ? n : K + 2 * P;
-        const int nr = rows_end ? std::max(rows_end[s], cover) : n;
-        const int ncol = cols_end ? std::max(cols_end[s], cover) : n;
+    // block LU: A = L U with unit block-lower L and U_ss = the pivot blocks,
+    // whose inverses D_s replace them on the diagonal of M; the blocks of L
+    // go to lband (column block s: rows [r0, r1) with ld P) and their places
+    // in M are cleared
+    for (int s = 0; s < steps; ++s) {
+        const int K = s * P, kb = std::min(P, n - K);
         const double *D = Nblk[s & 1];
         if (la && (e = hipStreamWaitEvent(st, la->ev_inv[s & 1], 0)) != hipSuccess) return e;
-        k_gj_extract<<<blocks_for((long long)nr * P + (long long)kb * ncol), kThreads, 0, st>>>(
-            n, nr, ncol, ld, P, K, kb, M, Ccol, Mrow);
-        if ((e = launch_dgemm(kb, ncol, kb, D, P, Mrow, n, Trow, n, 1.0, 0.0, st)) != hipSuccess)
+        k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
+            kb, D, P, M + (long long)K * ld + K, ld);
+        const int r0 = K + kb, r1 = lu_end(n, s, rows_end);
+        const int c0 = K + kb, c1 = lu_end(n, s, cols_end);
+        if (r1 <= r0) break;  // last block
+        double *Ls = lband + loff[s];
+        k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
+            r1 - r0, kb, ld, P, M + (long long)r0 * ld + K, Ccol);
+        if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, st)) != hipSuccess)
             return e;
-        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)nr * kb), kThreads, 0, st>>>(
-            n, nr, ld, P, K, kb, D, Trow, M);
-        // look-ahead: the next diagonal block after this step's update,
-        // computed apart and inverted on the side stream while the full
-        // update runs here
-        const int Kn = K + P;
-        if (Kn < n) {
-            const int kb2 = n - Kn < P ? n - Kn : P;
+        // look-ahead: the next pivot block, formed apart and inverted on the
+        // side stream while the rest of the Schur complement is updated here
+        {
+            const int Kn = r0, kb2 = std::min(P, n - Kn);
             double *Nn = Nblk[(s + 1) & 1];
             k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, st>>>(
                 kb2, M + (long long)Kn * ld + Kn, ld, Nn, P);
-            if ((e = launch_dgemm(kb2, kb2, kb, Ccol + (long long)Kn * P, P, Trow + Kn, n, Nn, P,
-                                  -1.0, 1.0, st)) != hipSuccess)
+            if ((e = launch_dgemm(kb2, kb2, kb, Ls, P, M + (long long)K * ld + Kn, ld, Nn, P, -1.0,
+                                  1.0, st)) != hipSuccess)
                 return e;
             if (la) {
                 if ((e = hipEventRecord(la->ev_block[(s + 1) & 1], st)) != hipSuccess) return e;
@@ -2025,13 +2090,35 @@ hipError_t dense_inverse(int n, int ld, double *M, double *work, int *bad, hipSt
             if ((e = gj_inverse_128(kb2, P, Nn, iwork, bad, aux)) != hipSuccess) return e;
             if (la && (e = hipEventRecord(la->ev_inv[(s + 1) & 1], aux)) != hipSuccess) return e;
         }
-        if ((e = launch_dgemm(nr, ncol, kb, Ccol, P, Trow, n, M, ld, -1.0, 1.0, st)) !=
+        if ((e = launch_dgemm(r1 - r0, c1 - c0, kb, Ls, P, M + (long long)K * ld + c0, ld,
+                              M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
+            return e;
+    }
+    // W = U^-1 in place, column block J from left to right: W(:J, J) =
+    // -W(:J, lo:J) U(lo:J, J) D_J, where lo is the first row of U's band in
+    // column block J (rows above it are zero in U); W_JJ = D_J is in place
+    for (int J = 1, us = 0; J < steps; ++J) {
+        const int K = J * P, kb = std::min(P, n - K);
+        while (us < J && lu_end(n, us, cols_end) <= K) ++us;
+        const int lo = us * P;
+        if (lo >= K) continue;
+        if ((e = launch_dgemm(K - lo, kb, kb, M + (long long)lo * ld + K, ld,
+                              M + (long long)K * ld + K, ld, Tcol, P, 1.0, 0.0, st)) != hipSuccess)
+            return e;
+        if ((e = launch_dgemm(K, kb, K - lo, M + lo, ld, Tcol, P, M + K, ld, -1.0, 0.0, st)) !=
             hipSuccess)
             return e;
-        k_gj_putrow<<<blocks_for((long long)kb * ncol), kThreads, 0, st>>>(n, ncol, ld, K, kb,
-                                                                         Trow, M);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // Y = L^-1 (block unit lower), column block J from right to left:
+    // Y(r0:, J) = -Y(r0:, r0:r1) L(r0:r1, J)
+    for (int J = steps - 2; J >= 0; --J) {
+        const int K = J * P, r0 = K + P, r1 = lu_end(n, J, rows_end);
+        if ((e = launch_dgemm(n - r0, P, r1 - r0, Y + (long long)r0 * ld + r0, ld,
+                              lband + loff[J], P, Y + (long long)r0 * ld + K, ld, -1.0, 0.0, st)) !=
+            hipSuccess)
+            return e;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (la) {
         if ((e = hipEventRecord(la->ev_done, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(caller, la->ev_done, 0)) != hipSuccess) return e;

@@ -83,7 +83,7 @@ SIGNATURES = {
     "msp_stage_repeat": ([_vp, _i, _i, _vp, _vp], _i),
     "msp_stage_get_nstage": ([_vp, _vp, _vp], _i),
 }
-STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE, STAGE_GJ_UPDATE = \
+STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE, STAGE_TRI_SWEEP = \
     range(7)
 
 _LIB = None
