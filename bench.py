@@ -212,18 +212,19 @@ def main():
 
     # dominant kernel of a step: the GEMM steps of the triangular-inverse
     # sweeps of the coarsest-level solver (FP64 matrix cores); the timed
-    # launch is the largest one, C = -A B with A (n_L - P) x 3P and B 3P x P
-    # (P = GJ_PANEL): algorithmic work 2 (n_L - P) P 3P flops
+    # launch is the largest one, C = -A B with A (n_L - P) x k and B k x P
+    # (P = GJ_PANEL, k = sweep_depth): algorithmic work 2 (n_L - P) P k flops
     P = GJ_PANEL
     mr = nL - P if nL > P else nL
-    upd_flops = 2.0 * mr * P * 3 * P
+    kd = sweep_depth(solver.level(len(last["level_rows"]) - 1), P)
+    upd_flops = 2.0 * mr * P * kd
     achieved = upd_flops / (t_upd * 1e-3) / 1e12
     roofline = {"kernel": f"k_dgemm_s (largest triangular-inverse sweep step of the coarsest-level "
-                          f"solver, {mr}x{P}x{3 * P}, n_L={nL})", "bound": "mfma",
+                          f"solver, {mr}x{P}x{kd}, n_L={nL})", "bound": "mfma",
                 "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": stored_traffic(),
                 "flops_per_launch": upd_flops, "avg_launch_us": t_upd * 1e3,
-                "algorithmic_bytes_per_launch": (mr * 3 * P + 3 * P * P + mr * P) * 8}
+                "algorithmic_bytes_per_launch": (mr * kd + kd * P + mr * P) * 8}
     roofline_spmv = {"kernel": f"k_spmv<{sys_.b}>", "bound": "hbm",
                      "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS, "bytes_per_launch": b_spmv,
@@ -270,6 +271,18 @@ def main():
     solver.close()
     torch.cuda.synchronize()
     log("done")
+
+
+def sweep_depth(level, P):
+    """Rows of L below the first pivot block of the coarsest solver's block LU
+    (the depth k of its largest sweep step): up to the last row whose first
+    stored column lies in block 0, and at least the next block."""
+    rp, ci = level["row_ptr"], level["col_ind"]
+    n = len(rp) - 1
+    first = ci[rp[:-1]]
+    ends = np.nonzero(first < P)[0]
+    r1 = max(int(ends[-1]) + 1 if len(ends) else 0, min(n, 2 * P))
+    return max(r1 - min(P, n), 1)
 
 
 def source_hash():

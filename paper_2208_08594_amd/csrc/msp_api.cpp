@@ -138,7 +138,7 @@ struct msp_ctx {
     long long Bnnzb = 0;
     double *omega = nullptr;
     std::vector<Level> lev;
-    int nL = 0, ldL = 0;
+    int nL = 0, ldL = 0, sweepK = 0;
     // coarsest-level solver A^-1 = W Y (W block upper, Y block unit lower
     // triangular, both nL x nL with leading dimension ldL) and its FP64 work
     // vector
@@ -200,6 +200,7 @@ struct msp_ctx {
             if (side) (void)hipStreamSynchronize(side);
             if (gj.aux) (void)hipStreamSynchronize(gj.aux);
             if (gj.main) (void)hipStreamSynchronize(gj.main);
+            if (gj.third) (void)hipStreamSynchronize(gj.third);
             if (chain_copy) (void)hipStreamSynchronize(chain_copy);
         }
         for (void *p_ : list) {
@@ -437,11 +438,11 @@ void link_levels(msp_ctx *c)
     }
 }
 
-// Streams of the coarsest-level inverse: the update stream gets all compute
-// units but kGjAuxCUs, the diagonal-block stream those few, so the short
-// kernels of the diagonal chain never queue for slots behind the large
-// update GEMMs.  Where a compute-unit mask cannot be set both streams are
-// plain (same results, less overlap).
+// Streams of the coarsest-level solver: the update stream and the stream of
+// the Y sweep get all compute units but kGjAuxCUs, the pivot-block stream
+// those few, so the short kernels of the pivot chain never queue for slots
+// behind the large GEMMs.  Where a compute-unit mask cannot be set the
+// streams are plain (same results, less overlap).
 constexpr int kGjAuxCUs = 8;
 void make_gj_streams(msp_ctx *c)
 {
@@ -458,24 +459,30 @@ void make_gj_streams(msp_ctx *c)
             else
                 mmain[cu / 32] |= 1u << (cu % 32);
         }
-        hipStream_t a = nullptr, m = nullptr;
+        hipStream_t a = nullptr, m = nullptr, t = nullptr;
         if (hipExtStreamCreateWithCUMask(&m, (uint32_t)words, mmain.data()) == hipSuccess &&
-            hipExtStreamCreateWithCUMask(&a, (uint32_t)words, maux.data()) == hipSuccess) {
+            hipExtStreamCreateWithCUMask(&a, (uint32_t)words, maux.data()) == hipSuccess &&
+            hipExtStreamCreateWithCUMask(&t, (uint32_t)words, mmain.data()) == hipSuccess) {
             c->gj.main = m;
             c->gj.aux = a;
+            c->gj.third = t;
             masked = true;
         } else {
             (void)hipGetLastError();
             if (m) (void)hipStreamDestroy(m);
             if (a) (void)hipStreamDestroy(a);
+            if (t) (void)hipStreamDestroy(t);
         }
     }
     if (!masked) {
         HIPCHK(hipStreamCreateWithFlags(&c->gj.main, hipStreamNonBlocking));
         HIPCHK(hipStreamCreateWithFlags(&c->gj.aux, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&c->gj.third, hipStreamNonBlocking));
     }
     HIPCHK(hipEventCreateWithFlags(&c->gj.ev_start, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->gj.ev_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->gj.ev_l, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->gj.ev_y, hipEventDisableTiming));
     for (int i = 0; i < 2; ++i) {
         HIPCHK(hipEventCreateWithFlags(&c->gj.ev_block[i], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->gj.ev_inv[i], hipEventDisableTiming));
@@ -524,6 +531,7 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
     }
     double *lband =
         (double *)c->dalloc(sizeof(double) * (dense_inverse_lband(m, rows_end.data()) + 1), tmp);
+    c->sweepK = dense_inverse_sweep_k(m, rows_end.data());
     c->clear_flag(0);
     HIPCHK(dense_inverse(m, c->ldL, c->cinv, c->cY, lband, work, c->flag, c->stream, &c->gj,
                          rows_end.data(), cols_end.data()));
@@ -1498,8 +1506,11 @@ int msp_destroy(msp_ctx *c)
         kill_stream(c->side);
         kill_stream(c->gj.aux);
         kill_stream(c->gj.main);
+        kill_stream(c->gj.third);
         kill_event(c->gj.ev_start);
         kill_event(c->gj.ev_done);
+        kill_event(c->gj.ev_l);
+        kill_event(c->gj.ev_y);
         for (int i = 0; i < 2; ++i) {
             kill_event(c->gj.ev_block[i]);
             kill_event(c->gj.ev_inv[i]);
@@ -1896,22 +1907,23 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
         const bool f32 = c->fp32();
         if (stage == MSP_STAGE_TRI_SWEEP) {
             // the largest step of the triangular-inverse sweeps of the
-            // coarsest solver: C = -A B with A (n_L - P) x 3P, B 3P x P, on
-            // scratch operands made on first use and kept with B (P the block
-            // size); C is overwritten, so every repetition does the same work
-            const int m = c->nL;
+            // coarsest solver: C = -A B with A (n_L - P) x k, B k x P, k the
+            // rows of L below pivot block 0, on scratch operands made on
+            // first use and kept with B (P the block size); C is
+            // overwritten, so every repetition does the same work
+            const int m = c->nL, kd = std::max(c->sweepK, 1);
             constexpr int P = kGJPanel;
             const int mr = m > P ? m - P : m;
             if (!c->tC) {
                 c->tC = (double *)c->dalloc(sizeof(double) * (size_t)mr * P, c->allocB);
-                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)mr * 3 * P, c->allocB);
-                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)3 * P * P, c->allocB);
-                HIPCHK(launch_fill((long long)mr * 3 * P, 1e-3, c->tA, c->stream));
-                HIPCHK(launch_fill((long long)3 * P * P, 1e-3, c->tB, c->stream));
+                c->tA = (double *)c->dalloc(sizeof(double) * (size_t)mr * kd, c->allocB);
+                c->tB = (double *)c->dalloc(sizeof(double) * (size_t)kd * P, c->allocB);
+                HIPCHK(launch_fill((long long)mr * kd, 1e-3, c->tA, c->stream));
+                HIPCHK(launch_fill((long long)kd * P, 1e-3, c->tB, c->stream));
                 c->sync();
             }
             for (int r = 0; r < reps; ++r)
-                HIPCHK(launch_dgemm(mr, P, 3 * P, c->tA, 3 * P, c->tB, P, c->tC, P, -1.0, 0.0,
+                HIPCHK(launch_dgemm(mr, P, kd, c->tA, kd, c->tB, P, c->tC, P, -1.0, 0.0,
                                     c->stream));
             c->sync();
             return MSP_OK;

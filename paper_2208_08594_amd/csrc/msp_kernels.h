@@ -182,13 +182,15 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // factorisation never touches them.  lband must hold
 // dense_inverse_lband(n, rows_end) doubles (the blocks of L) and work
 // dense_inverse_work(n) doubles.
-constexpr int kGJPanel = 384;
+constexpr int kGJPanel = 128;
 struct GjLookAhead {
-    hipStream_t main, aux;
-    hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2];
+    hipStream_t main, aux, third;
+    hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2], ev_l, ev_y;
 };
 size_t dense_inverse_work(int n);
 size_t dense_inverse_lband(int n, const int *rows_end);
+// Depth of the largest step of the Y sweep (rows of L below pivot block 0).
+int dense_inverse_sweep_k(int n, const int *rows_end);
 hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
                          hipStream_t st, const GjLookAhead *la, const int *rows_end,
                          const int *cols_end);

@@ -2003,12 +2003,52 @@ __global__ __launch_bounds__(kThreads) void k_unit_diag(int n, int ld, double *_
     if (i < n) Y[(long long)i * ld + i] = 1.0;
 }
 
-size_t dense_inverse_work(int n)
+// Rows [r0, r1) of block column s of L (Ls, ld P) into the row-block
+// layout: row r of row block I = I0 + b goes to dst + off[b] + (r - I P) ld[b].
+struct LrowMap {
+    static constexpr int kMax = 16;
+    long long off[kMax];
+    int ld[kMax];
+};
+__global__ __launch_bounds__(kThreads) void k_lrow_scatter(int r0, int r1, int I0, int P,
+                                                           const double *__restrict__ Ls,
+                                                           const LrowMap map,
+                                                           double *__restrict__ dst)
 {
-    return (size_t)2 * kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long long)(r1 - r0) * P) return;
+    const int r = r0 + (int)(q / P), t = (int)(q % P);
+    const int b = r / P - I0;
+    dst[map.off[b] + (long long)(r % P) * map.ld[b] + t] = Ls[q];
 }
 
-size_t dense_inverse_lband(int n, const int *rows_end)
+namespace {
+
+// Row-block layout of L: row block I (1 <= I < steps) holds its blocks
+// L(I, f_I .. I-1) side by side, P rows by (I - f_I) P columns, where f_I is
+// the first block step whose L rows reach row block I.
+struct LrowLayout {
+    std::vector<int> f;
+    std::vector<long long> off;  // steps + 1 entries
+};
+
+LrowLayout lrow_layout(int n, const int *rows_end)
+{
+    constexpr int P = kGJPanel;
+    const int steps = (n + P - 1) / P;
+    LrowLayout L;
+    L.f.assign(steps, 0);
+    L.off.assign(steps + 1, 0);
+    for (int I = 1, s = 0; I < steps; ++I) {
+        while (s < I - 1 && lu_end(n, s, rows_end) <= I * P) ++s;
+        L.f[I] = s;
+        L.off[I + 1] = L.off[I] + (long long)P * (I - s) * P;
+    }
+    if (steps > 0) L.off[1] = 0;
+    return L;
+}
+
+size_t lband_col(int n, const int *rows_end)
 {
     size_t q = 0;
     for (int K = 0, s = 0; K < n; K += kGJPanel, ++s) {
@@ -2016,6 +2056,42 @@ size_t dense_inverse_lband(int n, const int *rows_end)
         q += (size_t)(lu_end(n, s, rows_end) - r0) * kGJPanel;
     }
     return q;
+}
+
+}  // namespace
+
+size_t dense_inverse_work(int n)
+{
+    return (size_t)2 * kGJPanel * n + (size_t)4 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+}
+
+size_t dense_inverse_lband(int n, const int *rows_end)
+{
+    const int steps = (n + kGJPanel - 1) / kGJPanel;
+    return lband_col(n, rows_end) + (size_t)lrow_layout(n, rows_end).off[steps];
+}
+
+namespace {
+
+// Inverse of the kb x kb pivot block N (ld kGJPanel) into D (ld kGJPanel):
+// one k_gj_diag when the block is one inner panel, else the inner
+// Gauss-Jordan pass in place (D == N)
+hipError_t pivot_inverse(int kb, double *N, double *D, double *iwork, int *bad, hipStream_t st)
+{
+    if constexpr (kGJPanel == kNB) {
+        k_gj_diag<<<1, 256, 0, st>>>(kGJPanel, 0, kb, N, D, bad);
+        return hipGetLastError();
+    } else {
+        return gj_inverse_128(kb, kGJPanel, N, iwork, bad, st);
+    }
+}
+
+}  // namespace
+
+int dense_inverse_sweep_k(int n, const int *rows_end)
+{
+    const int r0 = std::min(kGJPanel, n);
+    return lu_end(n, 0, rows_end) - r0;
 }
 
 hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
@@ -2035,13 +2111,51 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     double *Tcol = Ccol + (long long)P * n;             // n x P
     double *Nblk[2] = {Tcol + (long long)P * n,         // P x P, two buffers
                        Tcol + (long long)P * n + (long long)P * P};
-    double *iwork = Nblk[1] + (long long)P * P;         // inner inverse
+    // pivot-block inverses (the same buffers when the inner pass runs in place)
+    double *Dblk[2] = {Nblk[0], Nblk[1]};
+    if constexpr (P == kNB) {
+        Dblk[0] = Nblk[1] + (long long)P * P;
+        Dblk[1] = Dblk[0] + (long long)P * P;
+    }
+    double *iwork = Nblk[1] + (long long)3 * P * P;     // inner inverse
     const hipStream_t aux = la ? la->aux : st;
+    // Y stream: the Y sweep in row form, row block I as soon as LU step I-1
+    // has produced the last block of L's row block I
+    const hipStream_t ys = la ? la->third : st;
     std::vector<long long> loff(steps + 1, 0);
     for (int s = 0; s < steps; ++s)
         loff[s + 1] = loff[s] + (long long)(lu_end(n, s, rows_end) - std::min((s + 1) * P, n)) * P;
-    if ((e = launch_fill((long long)n * ld, 0.0, Y, st)) != hipSuccess) return e;
-    k_unit_diag<<<blocks_for(n), kThreads, 0, st>>>(n, ld, Y);
+    const LrowLayout lr = lrow_layout(n, rows_end);
+    double *lrow = lband + loff[steps];
+    if (la && (e = hipStreamWaitEvent(ys, la->ev_start, 0)) != hipSuccess) return e;
+    if ((e = launch_fill((long long)n * ld, 0.0, Y, ys)) != hipSuccess) return e;
+    k_unit_diag<<<blocks_for(n), kThreads, 0, ys>>>(n, ld, Y);
+    if ((e = launch_fill(lr.off[steps], 0.0, lrow, ys)) != hipSuccess) return e;
+    // after LU step s: its L rows into the row-block layout, then Y's row
+    // block s + 1: Y(I, :I) = -L(I, f_I:I) Y(f_I:I, :I)
+    auto y_row = [&](int s) -> hipError_t {
+        const int K = s * P, r0 = K + P, r1 = lu_end(n, s, rows_end);
+        hipError_t r;
+        if (la) {
+            if ((r = hipEventRecord(la->ev_l, st)) != hipSuccess) return r;
+            if ((r = hipStreamWaitEvent(ys, la->ev_l, 0)) != hipSuccess) return r;
+        }
+        for (int I0 = r0 / P; I0 * P < r1; I0 += LrowMap::kMax) {
+            LrowMap map;
+            for (int b = 0; b < LrowMap::kMax; ++b) {
+                const int I = std::min(I0 + b, steps - 1);
+                map.ld[b] = (I - lr.f[I]) * P;
+                map.off[b] = lr.off[I] + (long long)(s - lr.f[I]) * P;
+            }
+            const int a0 = std::max(r0, I0 * P), a1 = std::min(r1, (I0 + LrowMap::kMax) * P);
+            k_lrow_scatter<<<blocks_for((long long)(a1 - a0) * P), kThreads, 0, ys>>>(
+                a0, a1, I0, P, lband + loff[s] + (long long)(a0 - r0) * P, map, lrow);
+        }
+        const int I = s + 1, kbI = std::min(P, n - I * P), w = (I - lr.f[I]) * P;
+        return launch_dgemm(kbI, I * P, w, lrow + lr.off[I], w,
+                            Y + (long long)lr.f[I] * P * ld, ld, Y + (long long)I * P * ld, ld,
+                            -1.0, 0.0, ys);
+    };
     // block 0: copy out and invert on the side stream
     {
         const int kb0 = n < P ? n : P;
@@ -2051,30 +2165,44 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
             if ((e = hipEventRecord(la->ev_block[0], st)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(aux, la->ev_block[0], 0)) != hipSuccess) return e;
         }
-        if ((e = gj_inverse_128(kb0, P, Nblk[0], iwork, bad, aux)) != hipSuccess) return e;
+        if ((e = pivot_inverse(kb0, Nblk[0], Dblk[0], iwork, bad, aux)) != hipSuccess) return e;
         if (la && (e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
     }
+    // W = U^-1 in place, column block J (once LU step J has put D_J on the
+    // diagonal and every earlier step has finished block column J of U):
+    // W(:J, J) = -W(:J, lo:J) U(lo:J, J) D_J, where lo is the first row of
+    // U's band in column block J (rows above it are zero in U)
+    int us = 0;
+    auto w_column = [&](int J) -> hipError_t {
+        const int K = J * P, kb = std::min(P, n - K);
+        while (us < J && lu_end(n, us, cols_end) <= K) ++us;
+        const int lo = us * P;
+        if (lo >= K) return hipSuccess;
+        hipError_t r = launch_dgemm(K - lo, kb, kb, M + (long long)lo * ld + K, ld,
+                                    M + (long long)K * ld + K, ld, Tcol, P, 1.0, 0.0, st);
+        if (r != hipSuccess) return r;
+        return launch_dgemm(K, kb, K - lo, M + lo, ld, Tcol, P, M + K, ld, -1.0, 0.0, st);
+    };
     // block LU: A = L U with unit block-lower L and U_ss = the pivot blocks,
     // whose inverses D_s replace them on the diagonal of M; the blocks of L
     // go to lband (column block s: rows [r0, r1) with ld P) and their places
-    // in M are cleared
+    // in M are cleared.  Column block s of W follows each step.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
-        const double *D = Nblk[s & 1];
+        const double *D = Dblk[s & 1];
         if (la && (e = hipStreamWaitEvent(st, la->ev_inv[s & 1], 0)) != hipSuccess) return e;
-        k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
-            kb, D, P, M + (long long)K * ld + K, ld);
         const int r0 = K + kb, r1 = lu_end(n, s, rows_end);
         const int c0 = K + kb, c1 = lu_end(n, s, cols_end);
-        if (r1 <= r0) break;  // last block
-        double *Ls = lband + loff[s];
-        k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
-            r1 - r0, kb, ld, P, M + (long long)r0 * ld + K, Ccol);
-        if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, st)) != hipSuccess)
-            return e;
-        // look-ahead: the next pivot block, formed apart and inverted on the
-        // side stream while the rest of the Schur complement is updated here
-        {
+        if (r1 > r0) {
+            double *Ls = lband + loff[s];
+            k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
+                r1 - r0, kb, ld, P, M + (long long)r0 * ld + K, Ccol);
+            if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = y_row(s)) != hipSuccess) return e;
+            // look-ahead: the next pivot block, formed apart and inverted on
+            // the side stream while the rest of the step runs here
             const int Kn = r0, kb2 = std::min(P, n - Kn);
             double *Nn = Nblk[(s + 1) & 1];
             k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, st>>>(
@@ -2087,39 +2215,22 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
                 if ((e = hipStreamWaitEvent(aux, la->ev_block[(s + 1) & 1], 0)) != hipSuccess)
                     return e;
             }
-            if ((e = gj_inverse_128(kb2, P, Nn, iwork, bad, aux)) != hipSuccess) return e;
+            if ((e = pivot_inverse(kb2, Nn, Dblk[(s + 1) & 1], iwork, bad, aux)) != hipSuccess)
+                return e;
             if (la && (e = hipEventRecord(la->ev_inv[(s + 1) & 1], aux)) != hipSuccess) return e;
         }
-        if ((e = launch_dgemm(r1 - r0, c1 - c0, kb, Ls, P, M + (long long)K * ld + c0, ld,
-                              M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
+        k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
+            kb, D, P, M + (long long)K * ld + K, ld);
+        if (r1 > r0 &&
+            (e = launch_dgemm(r1 - r0, c1 - c0, kb, lband + loff[s], P, M + (long long)K * ld + c0,
+                              ld, M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
             return e;
-    }
-    // W = U^-1 in place, column block J from left to right: W(:J, J) =
-    // -W(:J, lo:J) U(lo:J, J) D_J, where lo is the first row of U's band in
-    // column block J (rows above it are zero in U); W_JJ = D_J is in place
-    for (int J = 1, us = 0; J < steps; ++J) {
-        const int K = J * P, kb = std::min(P, n - K);
-        while (us < J && lu_end(n, us, cols_end) <= K) ++us;
-        const int lo = us * P;
-        if (lo >= K) continue;
-        if ((e = launch_dgemm(K - lo, kb, kb, M + (long long)lo * ld + K, ld,
-                              M + (long long)K * ld + K, ld, Tcol, P, 1.0, 0.0, st)) != hipSuccess)
-            return e;
-        if ((e = launch_dgemm(K, kb, K - lo, M + lo, ld, Tcol, P, M + K, ld, -1.0, 0.0, st)) !=
-            hipSuccess)
-            return e;
-    }
-    // Y = L^-1 (block unit lower), column block J from right to left:
-    // Y(r0:, J) = -Y(r0:, r0:r1) L(r0:r1, J)
-    for (int J = steps - 2; J >= 0; --J) {
-        const int K = J * P, r0 = K + P, r1 = lu_end(n, J, rows_end);
-        if ((e = launch_dgemm(n - r0, P, r1 - r0, Y + (long long)r0 * ld + r0, ld,
-                              lband + loff[J], P, Y + (long long)r0 * ld + K, ld, -1.0, 0.0, st)) !=
-            hipSuccess)
-            return e;
+        if ((e = w_column(s)) != hipSuccess) return e;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (la) {
+        if ((e = hipEventRecord(la->ev_y, ys)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st, la->ev_y, 0)) != hipSuccess) return e;
         if ((e = hipEventRecord(la->ev_done, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(caller, la->ev_done, 0)) != hipSuccess) return e;
     }
