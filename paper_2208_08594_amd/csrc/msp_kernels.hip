@@ -2135,11 +2135,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     // block s + 1: Y(I, :I) = -L(I, f_I:I) Y(f_I:I, :I)
     auto y_row = [&](int s) -> hipError_t {
         const int K = s * P, r0 = K + P, r1 = lu_end(n, s, rows_end);
-        hipError_t r;
-        if (la) {
-            if ((r = hipEventRecord(la->ev_l, st)) != hipSuccess) return r;
-            if ((r = hipStreamWaitEvent(ys, la->ev_l, 0)) != hipSuccess) return r;
-        }
         for (int I0 = r0 / P; I0 * P < r1; I0 += LrowMap::kMax) {
             LrowMap map;
             for (int b = 0; b < LrowMap::kMax; ++b) {
@@ -2179,9 +2174,9 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         const int lo = us * P;
         if (lo >= K) return hipSuccess;
         hipError_t r = launch_dgemm(K - lo, kb, kb, M + (long long)lo * ld + K, ld,
-                                    M + (long long)K * ld + K, ld, Tcol, P, 1.0, 0.0, st);
+                                    M + (long long)K * ld + K, ld, Tcol, P, 1.0, 0.0, ys);
         if (r != hipSuccess) return r;
-        return launch_dgemm(K, kb, K - lo, M + lo, ld, Tcol, P, M + K, ld, -1.0, 0.0, st);
+        return launch_dgemm(K, kb, K - lo, M + lo, ld, Tcol, P, M + K, ld, -1.0, 0.0, ys);
     };
     // block LU: A = L U with unit block-lower L and U_ss = the pivot blocks,
     // whose inverses D_s replace them on the diagonal of M; the blocks of L
@@ -2200,7 +2195,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
             if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, st)) !=
                 hipSuccess)
                 return e;
-            if ((e = y_row(s)) != hipSuccess) return e;
             // look-ahead: the next pivot block, formed apart and inverted on
             // the side stream while the rest of the step runs here
             const int Kn = r0, kb2 = std::min(P, n - Kn);
@@ -2221,11 +2215,17 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         }
         k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
             kb, D, P, M + (long long)K * ld + K, ld);
+        // hand-off to the Y stream: W's column block s and Y's row block s + 1
+        if (la) {
+            if ((e = hipEventRecord(la->ev_l, st)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(ys, la->ev_l, 0)) != hipSuccess) return e;
+        }
+        if ((e = w_column(s)) != hipSuccess) return e;
+        if (r1 > r0 && (e = y_row(s)) != hipSuccess) return e;
         if (r1 > r0 &&
             (e = launch_dgemm(r1 - r0, c1 - c0, kb, lband + loff[s], P, M + (long long)K * ld + c0,
                               ld, M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
             return e;
-        if ((e = w_column(s)) != hipSuccess) return e;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (la) {
