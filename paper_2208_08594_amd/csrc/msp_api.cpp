@@ -489,10 +489,14 @@ void make_gj_streams(msp_ctx *c)
     }
 }
 
-// Queues the coarsest-level inverse on `stream` and returns without waiting;
-// flag[0] is set on a singular pivot block.  The upload and work buffers go
-// to `tmp`, which the caller releases after the stream has drained.
-void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
+// Starts the coarsest-level solver and returns without waiting: the dense
+// matrix is scattered on `stream`, and a host thread queues the solver's
+// kernels on the solver streams (several thousand launches, off the setup's
+// own thread).  The returned future completes once everything is queued;
+// then `stream` must wait for gj.ev_done.  flag[0] is set on a singular
+// pivot block.  The upload and work buffers go to `tmp`, which the caller
+// releases after the streams have drained.
+std::future<void> launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
 {
     const int m = A.n;
     c->nL = m;
@@ -533,8 +537,12 @@ void launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &tmp)
         (double *)c->dalloc(sizeof(double) * (dense_inverse_lband(m, rows_end.data()) + 1), tmp);
     c->sweepK = dense_inverse_sweep_k(m, rows_end.data());
     c->clear_flag(0);
-    HIPCHK(dense_inverse(m, c->ldL, c->cinv, c->cY, lband, work, c->flag, c->stream, &c->gj,
-                         rows_end.data(), cols_end.data()));
+    HIPCHK(hipEventRecord(c->gj.ev_start, c->stream));
+    return std::async(std::launch::async, [c, m, lband, work, re = std::move(rows_end),
+                                           ce = std::move(cols_end)]() {
+        HIPCHK(dense_inverse(m, c->ldL, c->cinv, c->cY, lband, work, c->flag, c->stream, &c->gj,
+                             re.data(), ce.data()));
+    });
 }
 
 // Host-only part of the block ILU(0) setup: elimination order, dependency
@@ -952,7 +960,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     if (st == -3) fail(MSP_ERR_SINGULAR);
     if (st == -9) fail(MSP_ERR_COARSE);
     const int nlev = (int)H.A.size();
-    launch_coarse(c, H.A.back(), tmp);
+    std::future<void> coarse_queued = launch_coarse(c, H.A.back(), tmp);
     // zero diagonals on the smoothed levels (the device chain leaves this
     // test to here, behind the coarsest inverse already queued)
     a0_ready.get();
@@ -1003,6 +1011,8 @@ void rebuild_B(msp_ctx *c, const double *vals)
         link_levels(c);
         phase(4);
     }
+    coarse_queued.get();
+    HIPCHK(hipStreamWaitEvent(c->stream, c->gj.ev_done, 0));
     HIPCHK(hipEventRecord(c->ev_side, c->side));
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
     const int bad_bilu = c->read_flag(1) | (c->ns.on ? c->read_flag(2) : 0);

@@ -2102,7 +2102,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     hipStream_t st = caller;
     if (la) {
         st = la->main;
-        if ((e = hipEventRecord(la->ev_start, caller)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(st, la->ev_start, 0)) != hipSuccess) return e;
     }
     constexpr int P = kGJPanel;
@@ -2232,7 +2231,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         if ((e = hipEventRecord(la->ev_y, ys)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(st, la->ev_y, 0)) != hipSuccess) return e;
         if ((e = hipEventRecord(la->ev_done, st)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(caller, la->ev_done, 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
