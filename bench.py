@@ -212,10 +212,11 @@ def main():
 
     # dominant kernel of a step: the GEMM steps of the triangular-inverse
     # sweeps of the coarsest-level solver (FP64 matrix cores); the timed
-    # launch is the largest one, C = -A B with A (n_L - P) x k and B k x P
-    # (P = GJ_PANEL, k = sweep_depth): algorithmic work 2 (n_L - P) P k flops
+    # launch is the largest one, W's last block column: C = -A B with A
+    # (J P) x k and B k x P (P = GJ_PANEL, J the last block, k = sweep_depth):
+    # algorithmic work 2 J P P k flops
     P = GJ_PANEL
-    mr = nL - P if nL > P else nL
+    mr = max((nL - 1) // P * P, 1)
     kd = sweep_depth(solver.level(len(last["level_rows"]) - 1), P)
     upd_flops = 2.0 * mr * P * kd
     achieved = upd_flops / (t_upd * 1e-3) / 1e12
@@ -274,15 +275,25 @@ def main():
 
 
 def sweep_depth(level, P):
-    """Rows of L below the first pivot block of the coarsest solver's block LU
-    (the depth k of its largest sweep step): up to the last row whose first
-    stored column lies in block 0, and at least the next block."""
+    """Depth k of the largest sweep step of the coarsest solver, W's last block
+    column J: J P minus the first row of U's band there.  U's block row s
+    reaches columns below max(1 + the last column whose first stored row lies
+    in blocks <= s, the end of block s + 1)."""
     rp, ci = level["row_ptr"], level["col_ind"]
     n = len(rp) - 1
-    first = ci[rp[:-1]]
-    ends = np.nonzero(first < P)[0]
-    r1 = max(int(ends[-1]) + 1 if len(ends) else 0, min(n, 2 * P))
-    return max(r1 - min(P, n), 1)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    first_row = np.full(n, n)
+    np.minimum.at(first_row, ci, rows)
+    steps = (n + P - 1) // P
+    ends = np.zeros(steps, dtype=np.int64)
+    np.maximum.at(ends, first_row // P, np.arange(n) + 1)
+    ends = np.maximum.accumulate(ends)
+    J = steps - 1
+    K = J * P
+    us = 0
+    while us < J and max(int(ends[us]), min(n, us * P + 2 * P)) <= K:
+        us += 1
+    return max(K - us * P, 1)
 
 
 def source_hash():
@@ -297,7 +308,7 @@ def source_hash():
     b = src.index("\n}\n", b) + 3
     c = src.index("hipError_t launch_dgemm(")
     d = src.index("\n}\n", c) + 3
-    key = src[a:b] + src[c:d] + f"tri_sweep block={GJ_PANEL}"
+    key = src[a:b] + src[c:d] + f"tri_sweep W-last-column block={GJ_PANEL}"
     return hashlib.sha256(key.encode()).hexdigest()[:16]
 
 

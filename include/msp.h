@@ -121,13 +121,14 @@ typedef struct {
      * [1] value ingest, [2] decoupling,
      * [3] aggregation chain (pairwise passes and Galerkin products, on the
      *     device unless the pattern is not structurally symmetric) up to
-     *     queueing the coarsest-level inverse,
+     *     starting the coarsest-level solver (its kernels are queued from a
+     *     host thread of their own),
      * [7] waiting for the host worker threads (block ILU(0) plan, groups and
      *     layouts of the smoothed levels) after the chain,
-     * [6] block ILU(0) uploads and factorisation (while the coarsest inverse
-     *     runs on the device) and the final wait for the side stream,
+     * [6] block ILU(0) uploads and factorisation (while the coarsest-level
+     *     solver runs on the device) and the final wait for the side stream,
      * [4] level uploads (likewise overlapped),
-     * [5] what remains of the coarsest-level inverse after [4], [6], [7] */
+     * [5] what remains of the coarsest-level solver after [4], [6], [7] */
     double phase_ms[8];
 } msp_info;
 

@@ -89,10 +89,11 @@ int msp_stage_get_nstage(msp_ctx *ctx, double *Dn, double *Ann);
 #define MSP_STAGE_VCYCLE 4  /* level-0 V-cycle on the library's work vectors; in/out unused */
 #define MSP_STAGE_COARSE 5  /* coarsest-level solve on the library's work vectors */
 #define MSP_STAGE_TRI_SWEEP 6 /* the largest step of the triangular-inverse sweeps of
-                                 the coarsest-level solver: C = -A B with A (n_L - P) x k
-                                 and B k x P, P = 128 the block size of its block LU and
-                                 k the rows of L below its first pivot block (FP64 matrix
-                                 cores), on scratch operands; in/out unused */
+                                 the coarsest-level solver, W's last block column: C = -A B
+                                 with A (J P) x k and B k x P, P = 128 the block size of
+                                 its block LU, J its last block and k the depth of U's band
+                                 there (FP64 matrix cores), on scratch operands; in/out
+                                 unused */
 
 /* Enqueue `reps` (>= 1) back-to-back executions of one stage on the context's
  * stream with no host synchronisation between them, then synchronise.  Meant

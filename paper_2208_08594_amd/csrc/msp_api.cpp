@@ -535,7 +535,7 @@ std::future<void> launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &t
     }
     double *lband =
         (double *)c->dalloc(sizeof(double) * (dense_inverse_lband(m, rows_end.data()) + 1), tmp);
-    c->sweepK = dense_inverse_sweep_k(m, rows_end.data());
+    c->sweepK = dense_inverse_sweep_k(m, cols_end.data());
     c->clear_flag(0);
     HIPCHK(hipEventRecord(c->gj.ev_start, c->stream));
     return std::async(std::launch::async, [c, m, lband, work, re = std::move(rows_end),
@@ -1917,13 +1917,14 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
         const bool f32 = c->fp32();
         if (stage == MSP_STAGE_TRI_SWEEP) {
             // the largest step of the triangular-inverse sweeps of the
-            // coarsest solver: C = -A B with A (n_L - P) x k, B k x P, k the
-            // rows of L below pivot block 0, on scratch operands made on
-            // first use and kept with B (P the block size); C is
-            // overwritten, so every repetition does the same work
-            const int m = c->nL, kd = std::max(c->sweepK, 1);
+            // coarsest solver, W's last block column: C = -A B with A
+            // (J P) x k and B k x P, J = the last block, k the depth of U's
+            // band there, on scratch operands made on first use and kept
+            // with B (P the block size); C is overwritten, so every
+            // repetition does the same work
             constexpr int P = kGJPanel;
-            const int mr = m > P ? m - P : m;
+            const int m = c->nL, kd = std::max(c->sweepK, 1);
+            const int mr = std::max((m - 1) / P * P, 1);
             if (!c->tC) {
                 c->tC = (double *)c->dalloc(sizeof(double) * (size_t)mr * P, c->allocB);
                 c->tA = (double *)c->dalloc(sizeof(double) * (size_t)mr * kd, c->allocB);

@@ -163,25 +163,32 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // Direct solver of the n x n row-major matrix M (leading dimension ld), in
 // the form A^-1 = W Y.  A block LU factorisation over kGJPanel-wide blocks,
 // A = L U with L unit block-lower triangular, makes no row interchanges
-// across blocks; each pivot block is inverted by an inner Gauss-Jordan pass
-// over 128-wide panels with partial pivoting inside each 128 x 128 diagonal
-// block (*bad is set on a zero pivot).  Then W = U^-1 (block upper
-// triangular) overwrites M, with zeros below its diagonal blocks, and Y =
-// L^-1 (block unit lower triangular: identity diagonal blocks, zeros above)
-// fills Y (n x n, leading dimension ld).  With `la`, the inverse of the next
-// pivot block (formed apart from the step's Schur update) runs on la->aux
-// while the rest of the update runs on la->main (look-ahead); events order
-// the streams, and st waits for the whole solver.  The two streams are meant
-// to own disjoint sets of compute units, so the latency-bound pivot chain
-// never waits for slots behind the updates.  Without `la` everything runs on
-// st.  rows_end/cols_end (host arrays, one entry per block step s, or null
-// for the full matrix) bound the fill: with rows_end[s] = 1 + the last row
-// whose first stored column lies before the end of block s (cols_end likewise
-// by columns), L and U have no entries outside rows [0, rows_end[s]) of
-// block column s and columns [0, cols_end[s]) of block row s, and the
+// across blocks; each pivot block is inverted by k_gj_diag, with partial
+// pivoting inside the block (*bad is set on a zero pivot).  Then W = U^-1
+// (block upper triangular) overwrites M, with zeros below its diagonal
+// blocks, and Y = L^-1 (block unit lower triangular: identity diagonal
+// blocks, zeros above) fills Y (n x n, leading dimension ld).
+//
+// With `la` the work runs on three streams that wait for la->ev_start (the
+// caller records it on its stream before the call): la->aux inverts the
+// pivot blocks, one step ahead (the next pivot block is formed apart from
+// the step's Schur update); la->main runs the LU steps; la->third computes
+// W's block column s and Y's block row s + 1 as soon as LU step s has
+// produced them (W by columns, Y by rows in the row-block copy of L).  The
+// solver is complete once la->ev_done, recorded on la->main at the end, has
+// fired; the caller makes its stream wait for it.  aux is meant to own a few
+// compute units of its own, so the latency-bound pivot chain never waits
+// for slots behind the GEMMs of the other two.  Without `la` everything
+// runs in order on st.
+//
+// rows_end/cols_end (host arrays, one entry per block step s, or null for
+// the full matrix) bound the fill: with rows_end[s] = 1 + the last row whose
+// first stored column lies before the end of block s (cols_end likewise by
+// columns), L and U have no entries outside rows [0, rows_end[s]) of block
+// column s and columns [0, cols_end[s]) of block row s, and the
 // factorisation never touches them.  lband must hold
-// dense_inverse_lband(n, rows_end) doubles (the blocks of L) and work
-// dense_inverse_work(n) doubles.
+// dense_inverse_lband(n, rows_end) doubles (L by block columns, then by
+// block rows) and work dense_inverse_work(n) doubles.
 constexpr int kGJPanel = 128;
 struct GjLookAhead {
     hipStream_t main, aux, third;
@@ -189,8 +196,9 @@ struct GjLookAhead {
 };
 size_t dense_inverse_work(int n);
 size_t dense_inverse_lband(int n, const int *rows_end);
-// Depth of the largest step of the Y sweep (rows of L below pivot block 0).
-int dense_inverse_sweep_k(int n, const int *rows_end);
+// Depth of the W product of the last block column J (the largest step of
+// the sweeps): J P minus the first row of U's band in that column.
+int dense_inverse_sweep_k(int n, const int *cols_end);
 hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
                          hipStream_t st, const GjLookAhead *la, const int *rows_end,
                          const int *cols_end);

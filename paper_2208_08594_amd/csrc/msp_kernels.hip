@@ -2088,10 +2088,13 @@ hipError_t pivot_inverse(int kb, double *N, double *D, double *iwork, int *bad, 
 
 }  // namespace
 
-int dense_inverse_sweep_k(int n, const int *rows_end)
+int dense_inverse_sweep_k(int n, const int *cols_end)
 {
-    const int r0 = std::min(kGJPanel, n);
-    return lu_end(n, 0, rows_end) - r0;
+    constexpr int P = kGJPanel;
+    const int steps = (n + P - 1) / P, J = steps - 1, K = J * P;
+    int us = 0;
+    while (us < J && lu_end(n, us, cols_end) <= K) ++us;
+    return K - us * P;
 }
 
 hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, double *work, int *bad,
@@ -2162,10 +2165,11 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         if ((e = pivot_inverse(kb0, Nblk[0], Dblk[0], iwork, bad, aux)) != hipSuccess) return e;
         if (la && (e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
     }
-    // W = U^-1 in place, column block J (once LU step J has put D_J on the
-    // diagonal and every earlier step has finished block column J of U):
-    // W(:J, J) = -W(:J, lo:J) U(lo:J, J) D_J, where lo is the first row of
-    // U's band in column block J (rows above it are zero in U)
+    // W = U^-1 in place, column block J on the Y stream (once LU step J has
+    // put D_J on the diagonal and every earlier step has finished block
+    // column J of U): W(:J, J) = -W(:J, lo:J) U(lo:J, J) D_J, where lo is the
+    // first row of U's band in column block J (rows above it are zero in U).
+    // Later LU steps touch only rows below block J, so the two never meet.
     int us = 0;
     auto w_column = [&](int J) -> hipError_t {
         const int K = J * P, kb = std::min(P, n - K);
@@ -2180,7 +2184,8 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     // block LU: A = L U with unit block-lower L and U_ss = the pivot blocks,
     // whose inverses D_s replace them on the diagonal of M; the blocks of L
     // go to lband (column block s: rows [r0, r1) with ld P) and their places
-    // in M are cleared.  Column block s of W follows each step.
+    // in M are cleared.  After each step the Y stream takes W's column block
+    // s and Y's row block s + 1.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
         const double *D = Dblk[s & 1];
