@@ -7,8 +7,9 @@ Bars:
     bit-exact;
   * FP64 kernels: relative error <= 1e-12 (SpMV, GS sweep, BILU factors and
     solve, preconditioner without the coarsest solve); the coarsest level is
-    an explicit inverse on the GPU and LU factors in the oracle, so stages
-    that include it are held to kappa(A_L) * 1e-15 (at most 1e-10 here);
+    solved through the triangular inverses of a block LU on the GPU and
+    through LAPACK's LU factors in the oracle, so stages that include it are
+    held to kappa(A_L) * 1e-15 (at most 1e-10 here);
   * FGMRES: the same iteration count +-1 and both true residuals <= rtol;
   * FP32 preconditioner: stored values equal RNE(FP64), bit for bit, and the
     apply agrees with the oracle's FP32 apply to 1e-5.
@@ -278,11 +279,57 @@ def _pivoting_matrix(n, seed):
     return rp, ci, val.reshape(-1, 1, 1)
 
 
+def _variable_band_matrix(n, seed):
+    """Scalar CSR, structurally symmetric, diagonally dominant: a narrow band
+    (|i - j| <= 3) everywhere and a few rows coupled 200 to 500 columns away
+    on either side.  The fill bound of the block LU then differs from block
+    to block."""
+    rng = np.random.default_rng(seed)
+    ent = [dict() for _ in range(n)]
+    def add(i, j, v):
+        ent[i][j] = ent[i].get(j, 0.0) + v
+        ent[j][i] = ent[j].get(i, 0.0) + v * rng.uniform(0.5, 1.5)
+    for i in range(n):
+        for d in (1, 2, 3):
+            if i + d < n:
+                add(i, i + d, rng.uniform(-1, 1))
+    for i in rng.choice(n, 12, replace=False):
+        j = int(i) + int(rng.integers(200, 500)) * (1 if rng.random() < 0.5 else -1)
+        if 0 <= j < n and j != i:
+            add(int(i), j, rng.uniform(-1, 1))
+    for i in range(n):
+        ent[i][i] = sum(abs(v) for v in ent[i].values()) + 1.0
+    rows = [sorted(e.items()) for e in ent]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([j for r in rows for j, _ in r], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in r])
+    return rp, ci, val.reshape(-1, 1, 1)
+
+
+@pytest.mark.parametrize("n", [1100, 300, 257])
+def test_coarse_direct_solve_on_a_variable_band(n):
+    """The whole matrix is the coarsest level, with a fill bound that changes
+    from block to block (ragged last block)."""
+    rp, ci, vals = _variable_band_matrix(n, 21)
+    announce("variable band", n)
+    g = msp.Solver(max_coarse=10000)
+    o = O.OracleSolver(max_coarse=10000)
+    g.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    o.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    assert o.nlevels == 1 and g.nlevels == 1
+    f = np.random.default_rng(22).uniform(-1, 1, n)
+    assert relerr(to_np(g.vcycle(f)), o.vcycle(f)) <= _coarse_tol(o)
+    g.close()
+    o.close()
+
+
 @pytest.mark.parametrize("n", [1000, 600, 129])
 def test_coarse_direct_solve_needs_pivoting(n):
-    """The whole matrix is the coarsest level (several 384-wide panels of the
-    Gauss-Jordan pass, ragged last block), so the V-cycle is the direct solve alone, on a matrix whose
-    diagonal is 10x smaller than the largest entry of its row."""
+    """The whole matrix is the coarsest level (several 128-wide blocks of the
+    block LU, ragged last block), so the V-cycle is the direct solve alone, on
+    a matrix whose diagonal is 10x smaller than the largest entry of its
+    row."""
     rp, ci, vals = _pivoting_matrix(n, 11)
     announce("pivoting", n)
     g = msp.Solver(max_coarse=10000)
