@@ -443,7 +443,7 @@ void link_levels(msp_ctx *c)
 // those few, so the short kernels of the pivot chain never queue for slots
 // behind the large GEMMs.  Where a compute-unit mask cannot be set the
 // streams are plain (same results, less overlap).
-constexpr int kGjAuxCUs = 8;
+constexpr int kGjAuxCUs = 16;
 void make_gj_streams(msp_ctx *c)
 {
     hipDeviceProp_t prop;

@@ -170,16 +170,17 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // blocks, zeros above) fills Y (n x n, leading dimension ld).
 //
 // With `la` the work runs on three streams that wait for la->ev_start (the
-// caller records it on its stream before the call): la->aux inverts the
-// pivot blocks, one step ahead (the next pivot block is formed apart from
-// the step's Schur update); la->main runs the LU steps; la->third computes
-// W's block column s and Y's block row s + 1 as soon as LU step s has
-// produced them (W by columns, Y by rows in the row-block copy of L).  The
-// solver is complete once la->ev_done, recorded on la->main at the end, has
-// fired; the caller makes its stream wait for it.  aux is meant to own a few
-// compute units of its own, so the latency-bound pivot chain never waits
-// for slots behind the GEMMs of the other two.  Without `la` everything
-// runs in order on st.
+// caller records it on its stream before the call).  la->aux runs the
+// critical chain of each step: L's block column, the next pivot block
+// (formed apart from the step's Schur update) and its inverse.  la->main
+// puts each pivot inverse on the diagonal and runs the Schur updates.
+// la->third computes W's block column s and Y's block row s + 1 as soon as
+// LU step s has produced them (W by columns, Y by rows in the row-block copy
+// of L).  The solver is complete once la->ev_done, recorded on la->main at
+// the end, has fired; the caller makes its stream wait for it.  aux is meant
+// to own a few compute units of its own, so the latency-bound chain never
+// waits for slots behind the GEMMs of the other two.  Without `la`
+// everything runs in order on st.
 //
 // rows_end/cols_end (host arrays, one entry per block step s, or null for
 // the full matrix) bound the fill: with rows_end[s] = 1 + the last row whose

@@ -2163,7 +2163,6 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
             if ((e = hipStreamWaitEvent(aux, la->ev_block[0], 0)) != hipSuccess) return e;
         }
         if ((e = pivot_inverse(kb0, Nblk[0], Dblk[0], iwork, bad, aux)) != hipSuccess) return e;
-        if (la && (e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
     }
     // W = U^-1 in place, column block J on the Y stream (once LU step J has
     // put D_J on the diagonal and every earlier step has finished block
@@ -2184,39 +2183,44 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     // block LU: A = L U with unit block-lower L and U_ss = the pivot blocks,
     // whose inverses D_s replace them on the diagonal of M; the blocks of L
     // go to lband (column block s: rows [r0, r1) with ld P) and their places
-    // in M are cleared.  After each step the Y stream takes W's column block
-    // s and Y's row block s + 1.
+    // in M are cleared.  Step s is split over the streams:
+    //  - pivot stream (aux): once the Schur update of step s - 1 is done, L's
+    //    block column s, then the next pivot block (formed apart) and its
+    //    inverse D_{s+1}; nothing of the critical chain crosses streams;
+    //  - update stream (main): D_s onto the diagonal, then the Schur update;
+    //  - Y stream: W's column block s and Y's row block s + 1.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
         const double *D = Dblk[s & 1];
-        if (la && (e = hipStreamWaitEvent(st, la->ev_inv[s & 1], 0)) != hipSuccess) return e;
         const int r0 = K + kb, r1 = lu_end(n, s, rows_end);
         const int c0 = K + kb, c1 = lu_end(n, s, cols_end);
+        double *Ls = lband + loff[s];
+        if (la && s > 0 && (e = hipStreamWaitEvent(aux, la->ev_block[1], 0)) != hipSuccess)
+            return e;
+        int kb2 = 0;
         if (r1 > r0) {
-            double *Ls = lband + loff[s];
-            k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
+            k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, aux>>>(
                 r1 - r0, kb, ld, P, M + (long long)r0 * ld + K, Ccol);
-            if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, st)) !=
+            if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, aux)) !=
                 hipSuccess)
                 return e;
-            // look-ahead: the next pivot block, formed apart and inverted on
-            // the side stream while the rest of the step runs here
-            const int Kn = r0, kb2 = std::min(P, n - Kn);
+            const int Kn = r0;
+            kb2 = std::min(P, n - Kn);
             double *Nn = Nblk[(s + 1) & 1];
-            k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, st>>>(
+            k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, aux>>>(
                 kb2, M + (long long)Kn * ld + Kn, ld, Nn, P);
             if ((e = launch_dgemm(kb2, kb2, kb, Ls, P, M + (long long)K * ld + Kn, ld, Nn, P, -1.0,
-                                  1.0, st)) != hipSuccess)
+                                  1.0, aux)) != hipSuccess)
                 return e;
-            if (la) {
-                if ((e = hipEventRecord(la->ev_block[(s + 1) & 1], st)) != hipSuccess) return e;
-                if ((e = hipStreamWaitEvent(aux, la->ev_block[(s + 1) & 1], 0)) != hipSuccess)
-                    return e;
-            }
-            if ((e = pivot_inverse(kb2, Nn, Dblk[(s + 1) & 1], iwork, bad, aux)) != hipSuccess)
-                return e;
-            if (la && (e = hipEventRecord(la->ev_inv[(s + 1) & 1], aux)) != hipSuccess) return e;
         }
+        if (la) {
+            if ((e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(st, la->ev_inv[0], 0)) != hipSuccess) return e;
+        }
+        if (r1 > r0 &&
+            (e = pivot_inverse(kb2, Nblk[(s + 1) & 1], Dblk[(s + 1) & 1], iwork, bad, aux)) !=
+                hipSuccess)
+            return e;
         k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
             kb, D, P, M + (long long)K * ld + K, ld);
         // hand-off to the Y stream: W's column block s and Y's row block s + 1
@@ -2227,9 +2231,10 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         if ((e = w_column(s)) != hipSuccess) return e;
         if (r1 > r0 && (e = y_row(s)) != hipSuccess) return e;
         if (r1 > r0 &&
-            (e = launch_dgemm(r1 - r0, c1 - c0, kb, lband + loff[s], P, M + (long long)K * ld + c0,
-                              ld, M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
+            (e = launch_dgemm(r1 - r0, c1 - c0, kb, Ls, P, M + (long long)K * ld + c0, ld,
+                              M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
             return e;
+        if (la && (e = hipEventRecord(la->ev_block[1], st)) != hipSuccess) return e;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (la) {
