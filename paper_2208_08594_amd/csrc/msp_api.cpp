@@ -106,7 +106,6 @@ struct NStage {
 struct BiluData {
     std::vector<int> ord;  // elimination order
     std::vector<int> fwd_rows, fwd_ptr, bwd_rows, bwd_ptr;
-    std::vector<int> rp, ci;  // pattern at regeneration
     DevSell L, U;
     int *fwd_rows_d = nullptr, *bwd_rows_d = nullptr;
     int *dsrc = nullptr;  // per U slice-lane: block row (for the pivot inverses)
@@ -211,8 +210,8 @@ struct msp_ctx {
         }
         list.clear();
     }
-    template <typename T>
-    T *upload(const std::vector<T> &h, std::vector<void *> &list)
+    template <typename T, typename A>
+    T *upload(const std::vector<T, A> &h, std::vector<void *> &list)
     {
         T *d = (T *)dalloc(sizeof(T) * std::max<size_t>(h.size(), 1), list);
         if (!h.empty())
@@ -549,7 +548,8 @@ std::future<void> launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &t
 // levels, factorisation tasks and the sliced layouts of L and U.  Touches no
 // device state, so it can run on a second host thread.
 struct BiluPlan {
-    std::vector<int> lt_ptr, lt_kk, lt_k, lt_pp, pr_jj, pr_kj, dsrc;
+    IVecU lt_ptr, lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
+    std::vector<int> dsrc;
 };
 
 // color/g: the Alg. 4.2 groups of the block pattern (used for the
@@ -557,13 +557,13 @@ struct BiluPlan {
 void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData &D, BiluPlan &P)
 {
     const int n = c->n;
-    D.rp = c->rp;
-    D.ci = c->ci;
     D.ord.resize(n);
+    std::vector<int> grp;  // group k of the multi-color order: [grp[k], grp[k+1])
     if (c->opt.bilu_order == 1) {
         std::vector<int> start(g + 2, 0);
         for (int i = 0; i < n; ++i) ++start[color[i] + 1];
         for (int l = 1; l <= g; ++l) start[l + 1] += start[l];
+        grp = start;  // colors may start at 0 or 1: an empty group is harmless
         for (int i = 0; i < n; ++i) D.ord[start[color[i]]++] = i;
     } else {
         std::iota(D.ord.begin(), D.ord.end(), 0);
@@ -572,10 +572,15 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
     for (int t = 0; t < n; ++t) pos[D.ord[t]] = t;
     const int *rp = c->rp.data(), *ci = c->ci.data();
     {
-        auto bwd = std::async(std::launch::async, [&]() {
-            triangular_levels(n, rp, ci, D.ord, false, D.bwd_rows, D.bwd_ptr);
-        });
-        triangular_levels(n, rp, ci, D.ord, true, D.fwd_rows, D.fwd_ptr);
+        // the groups of Alg. 4.2 are independent sets, so each is levelled
+        // in parallel; any other order takes the sequential pass
+        auto levels = [&](bool lower, std::vector<int> &rows, std::vector<int> &ptr) {
+            if (grp.empty() ||
+                !triangular_levels_groups(n, rp, ci, D.ord, grp, lower, rows, ptr))
+                triangular_levels(n, rp, ci, D.ord, lower, rows, ptr);
+        };
+        auto bwd = std::async(std::launch::async, [&]() { levels(false, D.bwd_rows, D.bwd_ptr); });
+        levels(true, D.fwd_rows, D.fwd_ptr);
         bwd.get();
     }
     // factorisation tasks per block row: lower entries in elimination order and
@@ -644,6 +649,7 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
     }
     P.lt_kk.resize(tbase[parts]);
     P.lt_k.resize(tbase[parts]);
+    P.lt_pp.reserve(tbase[parts] + 1);
     P.lt_pp.resize(tbase[parts]);
     P.pr_jj.resize(pbase[parts]);
     P.pr_kj.resize(pbase[parts]);

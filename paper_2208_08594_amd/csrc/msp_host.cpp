@@ -614,6 +614,61 @@ void triangular_levels(int n, const int *rp, const int *ci, const std::vector<in
     }
 }
 
+bool triangular_levels_groups(int n, const int *rp, const int *ci, const std::vector<int> &ord,
+                              const std::vector<int> &grp, bool lower,
+                              std::vector<int> &rows_by_level, std::vector<int> &level_ptr)
+{
+    const int g = (int)grp.size() - 1;
+    std::vector<int> pos(n), lev(n, 0);
+    for_chunks(n, host_parts(n), [&](int lo, int hi, int) {
+        for (int t = lo; t < hi; ++t) pos[ord[t]] = t;
+    });
+    const int parts = host_parts(n);
+    std::vector<int> pmax(parts, 0);
+    std::vector<char> pbad(parts, 0);
+    for (int q = 0; q < g; ++q) {
+        const int k = lower ? q : g - 1 - q;
+        const int g0 = grp[k], g1 = grp[k + 1];
+        // every dependency of the group lies in groups already levelled
+        for_chunks(g1 - g0, parts, [&](int lo, int hi, int w) {
+            int mx = pmax[w];
+            bool bad = false;
+            for (int t = g0 + lo; t < g0 + hi; ++t) {
+                const int i = ord[t];
+                int l = 0;
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    const int pj = pos[ci[e]];
+                    if (lower ? pj < t : pj > t) {
+                        if (pj >= g0 && pj < g1) {
+                            bad = true;
+                            continue;
+                        }
+                        l = std::max(l, lev[ci[e]] + 1);
+                    }
+                }
+                lev[i] = l;
+                mx = std::max(mx, l);
+            }
+            pmax[w] = mx;
+            if (bad) pbad[w] = 1;
+        });
+        for (char b : pbad)
+            if (b) return false;
+    }
+    int maxlev = 0;
+    for (int m : pmax) maxlev = std::max(maxlev, m);
+    level_ptr.assign(maxlev + 2, 0);
+    for (int i = 0; i < n; ++i) ++level_ptr[lev[i] + 1];
+    for (int l = 0; l <= maxlev; ++l) level_ptr[l + 1] += level_ptr[l];
+    rows_by_level.assign(n, 0);
+    std::vector<int> f(level_ptr.begin(), level_ptr.end() - 1);
+    for (int s = 0; s < n; ++s) {
+        int i = ord[lower ? s : n - 1 - s];
+        rows_by_level[f[lev[i]]++] = i;
+    }
+    return true;
+}
+
 void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
                 const std::vector<int> &ent_col, const std::vector<int> &ent_src, SellLayout &L)
 {

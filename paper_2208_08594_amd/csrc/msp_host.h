@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <functional>
 #include <thread>
+#include <memory>
+#include <utility>
 #include <vector>
 
 namespace msp {
@@ -33,6 +35,33 @@ void for_chunks(int n, int nparts, F f)
     f(0, (int)((long long)n / nparts), 0);
     for (auto &x : th) x.join();
 }
+
+// Allocator that leaves scalars uninitialised on resize: a large host array
+// is then first touched by the (parallel) code that fills it, instead of by
+// one thread zeroing it page by page.
+template <typename T>
+struct UninitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <typename U>
+    UninitAlloc(const UninitAlloc<U> &) noexcept
+    {
+    }
+    template <typename U>
+    void construct(U *p) noexcept
+    {
+        ::new ((void *)p) U;
+    }
+    template <typename U, typename... A>
+    void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+using IVecU = std::vector<int, UninitAlloc<int>>;
 
 // Scalar CSR matrix (one AMG level).
 struct Csr {
@@ -111,6 +140,14 @@ int color_level(const Csr &A, std::vector<int> &color);
 // the level boundaries.
 void triangular_levels(int n, const int *rp, const int *ci, const std::vector<int> &ord,
                        bool lower, std::vector<int> &rows_by_level, std::vector<int> &level_ptr);
+// The same levels for an order made of independent groups (no stored entry
+// joins two rows of one group): ord holds group k at positions
+// [grp[k], grp[k+1]).  The rows of a group are then levelled in parallel,
+// group after group.  Returns false, with nothing written, if some stored
+// entry joins two rows of one group.
+bool triangular_levels_groups(int n, const int *rp, const int *ci, const std::vector<int> &ord,
+                              const std::vector<int> &grp, bool lower,
+                              std::vector<int> &rows_by_level, std::vector<int> &level_ptr);
 
 // Sliced ELL with 64-row slices that never straddle a segment boundary.
 struct SellLayout {
