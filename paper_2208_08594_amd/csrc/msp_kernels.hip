@@ -1254,50 +1254,6 @@ __global__ __launch_bounds__(256) void k_gj_diag(int ld, int K, int kb,
     }
 }
 
-// Panel steps of a Gauss-Jordan pass with panel width P (block (K, K) of
-// size kb <= P) restricted to rows [0, nr) and columns [0, ncol) of the n x n
-// matrix: outside that window the step changes nothing (entries there are
-// still those of the original matrix, zero in the panel rows and columns).
-// Ccol[i][t] = M[i][K+t] for rows i < nr outside the block (0 inside), ld P;
-// Mrow[t][j] = M[K+t][j] for j < ncol, ld n.
-__global__ __launch_bounds__(kThreads) void k_gj_extract(int n, int nr, int ncol, int ld, int P,
-                                                         int K, int kb,
-                                                         const double *__restrict__ M,
-                                                         double *__restrict__ Ccol,
-                                                         double *__restrict__ Mrow)
-{
-    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    const long long nc = (long long)nr * P;
-    if (q < nc) {
-        int i = (int)(q / P), t = (int)(q % P);
-        bool inblk = i >= K && i < K + kb;
-        Ccol[q] = (t < kb && !inblk) ? M[(long long)i * ld + K + t] : 0.0;
-    } else if (q < nc + (long long)kb * ncol) {
-        long long r = q - nc;
-        int t = (int)(r / ncol), j = (int)(r % ncol);
-        Mrow[(long long)t * n + j] = M[(long long)(K + t) * ld + j];
-    }
-}
-
-// Trow[t][K+u] = Dblk[t][u] (Dblk with ld P, Trow with ld n); M[i][K+u] = 0
-// for rows i < nr outside the block.
-__global__ __launch_bounds__(kThreads) void k_gj_fix(int n, int nr, int ld, int P, int K, int kb,
-                                                     const double *__restrict__ Dblk,
-                                                     double *__restrict__ Trow,
-                                                     double *__restrict__ M)
-{
-    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    const long long nt = (long long)kb * kb;
-    if (q < nt) {
-        int t = (int)(q / kb), u = (int)(q % kb);
-        Trow[(long long)t * n + K + u] = Dblk[(long long)t * P + u];
-    } else if (q < nt + (long long)nr * kb) {
-        long long r = q - nt;
-        int i = (int)(r / kb), u = (int)(r % kb);
-        if (i < K || i >= K + kb) M[(long long)i * ld + K + u] = 0.0;
-    }
-}
-
 // B[r][c] = A[r][c] for r, c < kb (B with ld ldb)
 __global__ __launch_bounds__(kThreads) void k_copy_block(int kb, const double *__restrict__ A,
                                                          int lda, double *__restrict__ B,
@@ -1307,17 +1263,6 @@ __global__ __launch_bounds__(kThreads) void k_copy_block(int kb, const double *_
     if (q >= (long long)kb * kb) return;
     const int r = (int)(q / kb), c = (int)(q % kb);
     B[(long long)r * ldb + c] = A[(long long)r * lda + c];
-}
-
-// M[K+t][j] = Trow[t][j] for j < ncol (Trow with ld n)
-__global__ __launch_bounds__(kThreads) void k_gj_putrow(int n, int ncol, int ld, int K, int kb,
-                                                        const double *__restrict__ Trow,
-                                                        double *__restrict__ M)
-{
-    long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= (long long)kb * ncol) return;
-    const int t = (int)(q / ncol), j = (int)(q % ncol);
-    M[(long long)(K + t) * ld + j] = Trow[(long long)t * n + j];
 }
 
 // C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.  A
@@ -1935,38 +1880,6 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
     return hipGetLastError();
 }
 
-namespace {
-
-// Gauss-Jordan inverse of an n x n matrix (ld ld) in place with 128-wide
-// panels; each diagonal block is inverted by k_gj_diag (pivoting inside the
-// block).  work: 3 kNB n + kNB kNB doubles.
-hipError_t gj_inverse_128(int n, int ld, double *M, double *work, int *bad, hipStream_t st)
-{
-    double *Ccol = work;                       // n x kNB
-    double *Mrow = work + (long long)kNB * n;  // kNB x n
-    double *Trow = Mrow + (long long)kNB * n;  // kNB x n
-    double *Dblk = Trow + (long long)kNB * n;  // kNB x kNB
-    for (int K = 0; K < n; K += kNB) {
-        const int kb = n - K < kNB ? n - K : kNB;
-        k_gj_diag<<<1, 256, 0, st>>>(ld, K, kb, M, Dblk, bad);
-        k_gj_extract<<<blocks_for((long long)n * kNB + (long long)kb * n), kThreads, 0, st>>>(
-            n, n, n, ld, kNB, K, kb, M, Ccol, Mrow);
-        hipError_t e = launch_dgemm(kb, n, kb, Dblk, kNB, Mrow, n, Trow, n, 1.0, 0.0, st);
-        if (e != hipSuccess) return e;
-        k_gj_fix<<<blocks_for((long long)kb * kb + (long long)n * kb), kThreads, 0, st>>>(
-            n, n, ld, kNB, K, kb, Dblk, Trow, M);
-        e = launch_dgemm(n, n, kb, Ccol, kNB, Trow, n, M, ld, -1.0, 1.0, st);
-        if (e != hipSuccess) return e;
-        k_gj_putrow<<<blocks_for((long long)kb * n), kThreads, 0, st>>>(n, n, ld, K, kb, Trow, M);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-size_t gj128_work(int n) { return (size_t)3 * kNB * n + (size_t)kNB * kNB; }
-
-}  // namespace
 
 namespace {
 
@@ -1983,17 +1896,13 @@ int lu_end(int n, int s, const int *ends)
 
 }  // namespace
 
-// M[r][0 .. kb) -> C[r][0 .. kb) (ld P) for r < nr, and zero there
-__global__ __launch_bounds__(kThreads) void k_lu_take(int nr, int kb, int ld, int P,
-                                                      double *__restrict__ M,
-                                                      double *__restrict__ C)
+// M[r][0 .. kb) = 0 for r < nr
+__global__ __launch_bounds__(kThreads) void k_zero_rect(int nr, int kb, int ld,
+                                                        double *__restrict__ M)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (q >= (long long)nr * kb) return;
-    const int r = (int)(q / kb), t = (int)(q % kb);
-    double *m = M + (long long)r * ld + t;
-    C[(long long)r * P + t] = *m;
-    *m = 0.0;
+    M[(q / kb) * ld + q % kb] = 0.0;
 }
 
 // Y[i][i] = 1 for i < n
@@ -2062,7 +1971,7 @@ size_t lband_col(int n, const int *rows_end)
 
 size_t dense_inverse_work(int n)
 {
-    return (size_t)2 * kGJPanel * n + (size_t)4 * kGJPanel * kGJPanel + gj128_work(kGJPanel);
+    return (size_t)kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel;
 }
 
 size_t dense_inverse_lband(int n, const int *rows_end)
@@ -2071,22 +1980,6 @@ size_t dense_inverse_lband(int n, const int *rows_end)
     return lband_col(n, rows_end) + (size_t)lrow_layout(n, rows_end).off[steps];
 }
 
-namespace {
-
-// Inverse of the kb x kb pivot block N (ld kGJPanel) into D (ld kGJPanel):
-// one k_gj_diag when the block is one inner panel, else the inner
-// Gauss-Jordan pass in place (D == N)
-hipError_t pivot_inverse(int kb, double *N, double *D, double *iwork, int *bad, hipStream_t st)
-{
-    if constexpr (kGJPanel == kNB) {
-        k_gj_diag<<<1, 256, 0, st>>>(kGJPanel, 0, kb, N, D, bad);
-        return hipGetLastError();
-    } else {
-        return gj_inverse_128(kb, kGJPanel, N, iwork, bad, st);
-    }
-}
-
-}  // namespace
 
 int dense_inverse_sweep_k(int n, const int *cols_end)
 {
@@ -2109,17 +2002,11 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     }
     constexpr int P = kGJPanel;
     const int steps = (n + P - 1) / P;
-    double *Ccol = work;                                // n x P
-    double *Tcol = Ccol + (long long)P * n;             // n x P
-    double *Nblk[2] = {Tcol + (long long)P * n,         // P x P, two buffers
+    // the pivot blocks are inverted by one k_gj_diag each, in place of M
+    static_assert(kGJPanel == kNB, "one pivot kernel per block");
+    double *Tcol = work;                                // n x P
+    double *Dblk[2] = {Tcol + (long long)P * n,         // P x P, two buffers
                        Tcol + (long long)P * n + (long long)P * P};
-    // pivot-block inverses (the same buffers when the inner pass runs in place)
-    double *Dblk[2] = {Nblk[0], Nblk[1]};
-    if constexpr (P == kNB) {
-        Dblk[0] = Nblk[1] + (long long)P * P;
-        Dblk[1] = Dblk[0] + (long long)P * P;
-    }
-    double *iwork = Nblk[1] + (long long)3 * P * P;     // inner inverse
     const hipStream_t aux = la ? la->aux : st;
     // Y stream: the Y sweep in row form, row block I as soon as LU step I-1
     // has produced the last block of L's row block I
@@ -2153,17 +2040,9 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
                             Y + (long long)lr.f[I] * P * ld, ld, Y + (long long)I * P * ld, ld,
                             -1.0, 0.0, ys);
     };
-    // block 0: copy out and invert on the side stream
-    {
-        const int kb0 = n < P ? n : P;
-        k_copy_block<<<blocks_for((long long)kb0 * kb0), kThreads, 0, st>>>(kb0, M, ld, Nblk[0],
-                                                                           P);
-        if (la) {
-            if ((e = hipEventRecord(la->ev_block[0], st)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(aux, la->ev_block[0], 0)) != hipSuccess) return e;
-        }
-        if ((e = pivot_inverse(kb0, Nblk[0], Dblk[0], iwork, bad, aux)) != hipSuccess) return e;
-    }
+    // block 0: inverted on the pivot stream once the matrix is scattered
+    if (la && (e = hipStreamWaitEvent(aux, la->ev_start, 0)) != hipSuccess) return e;
+    k_gj_diag<<<1, 256, 0, aux>>>(ld, 0, std::min(n, P), M, Dblk[0], bad);
     // W = U^-1 in place, column block J on the Y stream (once LU step J has
     // put D_J on the diagonal and every earlier step has finished block
     // column J of U): W(:J, J) = -W(:J, lo:J) U(lo:J, J) D_J, where lo is the
@@ -2185,42 +2064,38 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     // go to lband (column block s: rows [r0, r1) with ld P) and their places
     // in M are cleared.  Step s is split over the streams:
     //  - pivot stream (aux): once the Schur update of step s - 1 is done, L's
-    //    block column s, then the next pivot block (formed apart) and its
-    //    inverse D_{s+1}; nothing of the critical chain crosses streams;
-    //  - update stream (main): D_s onto the diagonal, then the Schur update;
+    //    block column s, then the next pivot block (updated in place) and
+    //    its inverse D_{s+1}; nothing of the critical chain crosses streams;
+    //  - update stream (main): L's places cleared, D_s onto the diagonal,
+    //    then the Schur update of everything but the next pivot block;
     //  - Y stream: W's column block s and Y's row block s + 1.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
         const double *D = Dblk[s & 1];
         const int r0 = K + kb, r1 = lu_end(n, s, rows_end);
         const int c0 = K + kb, c1 = lu_end(n, s, cols_end);
+        const int kb2 = r1 > r0 ? std::min(P, n - r0) : 0;
         double *Ls = lband + loff[s];
+        double *Mn = M + (long long)r0 * ld + r0;  // the next pivot block
         if (la && s > 0 && (e = hipStreamWaitEvent(aux, la->ev_block[1], 0)) != hipSuccess)
             return e;
-        int kb2 = 0;
         if (r1 > r0) {
-            k_lu_take<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, aux>>>(
-                r1 - r0, kb, ld, P, M + (long long)r0 * ld + K, Ccol);
-            if ((e = launch_dgemm(r1 - r0, kb, kb, Ccol, P, D, P, Ls, P, 1.0, 0.0, aux)) !=
-                hipSuccess)
+            if ((e = launch_dgemm(r1 - r0, kb, kb, M + (long long)r0 * ld + K, ld, D, P, Ls, P,
+                                  1.0, 0.0, aux)) != hipSuccess)
                 return e;
-            const int Kn = r0;
-            kb2 = std::min(P, n - Kn);
-            double *Nn = Nblk[(s + 1) & 1];
-            k_copy_block<<<blocks_for((long long)kb2 * kb2), kThreads, 0, aux>>>(
-                kb2, M + (long long)Kn * ld + Kn, ld, Nn, P);
-            if ((e = launch_dgemm(kb2, kb2, kb, Ls, P, M + (long long)K * ld + Kn, ld, Nn, P, -1.0,
-                                  1.0, aux)) != hipSuccess)
+            if ((e = launch_dgemm(kb2, kb2, kb, Ls, P, M + (long long)K * ld + r0, ld, Mn, ld,
+                                  -1.0, 1.0, aux)) != hipSuccess)
                 return e;
         }
         if (la) {
             if ((e = hipEventRecord(la->ev_inv[0], aux)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(st, la->ev_inv[0], 0)) != hipSuccess) return e;
         }
-        if (r1 > r0 &&
-            (e = pivot_inverse(kb2, Nblk[(s + 1) & 1], Dblk[(s + 1) & 1], iwork, bad, aux)) !=
-                hipSuccess)
-            return e;
+        if (r1 > r0)
+            k_gj_diag<<<1, 256, 0, aux>>>(ld, r0, kb2, M, Dblk[(s + 1) & 1], bad);
+        if (r1 > r0)
+            k_zero_rect<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
+                r1 - r0, kb, ld, M + (long long)r0 * ld + K);
         k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
             kb, D, P, M + (long long)K * ld + K, ld);
         // hand-off to the Y stream: W's column block s and Y's row block s + 1
@@ -2230,10 +2105,18 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         }
         if ((e = w_column(s)) != hipSuccess) return e;
         if (r1 > r0 && (e = y_row(s)) != hipSuccess) return e;
-        if (r1 > r0 &&
-            (e = launch_dgemm(r1 - r0, c1 - c0, kb, Ls, P, M + (long long)K * ld + c0, ld,
-                              M + (long long)r0 * ld + c0, ld, -1.0, 1.0, st)) != hipSuccess)
-            return e;
+        // Schur update without the next pivot block (done on the pivot stream)
+        if (r1 > r0) {
+            if ((e = launch_dgemm(kb2, c1 - c0 - kb2, kb, Ls, P, M + (long long)K * ld + c0 + kb2,
+                                  ld, M + (long long)r0 * ld + c0 + kb2, ld, -1.0, 1.0, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = launch_dgemm(r1 - r0 - kb2, c1 - c0, kb, Ls + (long long)kb2 * P, P,
+                                  M + (long long)K * ld + c0, ld,
+                                  M + (long long)(r0 + kb2) * ld + c0, ld, -1.0, 1.0, st)) !=
+                hipSuccess)
+                return e;
+        }
         if (la && (e = hipEventRecord(la->ev_block[1], st)) != hipSuccess) return e;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
