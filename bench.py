@@ -223,7 +223,8 @@ def main():
     roofline = {"kernel": f"k_dgemm_s (largest triangular-inverse sweep step of the coarsest-level "
                           f"solver, {mr}x{P}x{kd}, n_L={nL})", "bound": "mfma",
                 "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": stored_traffic(),
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                "traffic": stored_traffic(f"{mr}x{P}x{kd}"),
                 "flops_per_launch": upd_flops, "avg_launch_us": t_upd * 1e3,
                 "algorithmic_bytes_per_launch": (mr * kd + kd * P + mr * P) * 8}
     roofline_spmv = {"kernel": f"k_spmv<{sys_.b}>", "bound": "hbm",
@@ -312,9 +313,10 @@ def source_hash():
     return hashlib.sha256(key.encode()).hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(shape):
     """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary, only if it was taken on the current kernel source."""
+    summary, only if it was taken on the current kernel source and at the
+    launch shape timed here (M x N x K)."""
     try:
         txt = open(TRAFFIC_FILE).read()
     except OSError:
@@ -325,6 +327,8 @@ def stored_traffic():
             k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel source sha256[:16]") != source_hash():
+        return None
+    if vals.get("launch shape") != shape:
         return None
     try:
         return float(vals["HBM bytes per launch"])
