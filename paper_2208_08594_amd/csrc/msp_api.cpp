@@ -154,7 +154,7 @@ struct msp_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
     hipStream_t copy_stream = nullptr;  // stream of upload(); null = `stream`
-    // look-ahead stream and events of the coarsest-level inverse
+    // streams and events of the coarsest-level solver
     GjLookAhead gj{};
     hipGraphExec_t apply_exec = nullptr;
     // krylov workspace

@@ -1005,7 +1005,8 @@ __global__ __launch_bounds__(kThreads) void k_fill(long long N, double v, double
 }
 
 // ---------------------------------------------------------------------------
-// dense coarsest level: scatter + block Gauss-Jordan inverse
+// dense coarsest level: scatter, pivot-block inverses, block LU and the
+// triangular-inverse sweeps
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, int ld,
                                                             const int *__restrict__ rp,
@@ -1018,7 +1019,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_scatter(int n, int ld,
     for (int k = rp[i]; k < rp[i + 1]; ++k) M[(long long)i * ld + ci[k]] = val[k];
 }
 
-constexpr int kNB = 128;  // Gauss-Jordan panel width
+constexpr int kNB = 128;  // pivot block of k_gj_diag
 
 // Largest 64-bit key over the wavefront: butterflies inside each row of 16
 // lanes by DPP moves, then the four row maxima read as scalars.
@@ -1885,7 +1886,7 @@ namespace {
 
 // L rows of LU step s: [K + kb, lu_end(n, s, ends)), where ends[s] bounds the
 // window of step s; the window always covers the next diagonal block (the
-// look-ahead reads it).
+// pivot stream forms it from these rows).
 int lu_end(int n, int s, const int *ends)
 {
     const int K = s * kGJPanel;
