@@ -324,6 +324,42 @@ def test_coarse_direct_solve_on_a_variable_band(n):
     o.close()
 
 
+def test_singular_pivot_block_is_reported_and_the_context_recovers():
+    """Rows 0 and 1 of the coarsest level (the whole matrix) are equal, so the
+    first pivot block is exactly singular while every diagonal entry is 1: the
+    block LU reports MSP_ERR_SINGULAR (its kernels run to the end on the
+    non-finite values), and the same context then sets up a regular system."""
+    n = 300
+    rp, ci, vals = _variable_band_matrix(n, 23)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A = np.zeros((n, n))
+    A[rows, ci] = vals[:, 0, 0]
+    A[0, :] = 0.0
+    A[1, :] = 0.0
+    A[0, 0] = A[0, 1] = A[1, 0] = A[1, 1] = 1.0
+    A[:, 0][2:] = 0.0
+    A[:, 1][2:] = 0.0
+    nz = np.nonzero((A != 0) | (A.T != 0))
+    order = np.lexsort((nz[1], nz[0]))
+    r_, c_ = nz[0][order], nz[1][order]
+    rp2 = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp2, r_ + 1, 1)
+    rp2 = np.cumsum(rp2).astype(np.int32)
+    announce("singular pivot block", n)
+    g = msp.Solver(max_coarse=10000)
+    with pytest.raises(msp.MspError) as e:
+        g.setup(n=n, b=1, p=0, row_ptr=rp2, col_ind=c_.astype(np.int32),
+                vals=A[r_, c_].reshape(-1, 1, 1))
+    assert e.value.code == -3
+    o = O.OracleSolver(max_coarse=10000)
+    g.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    o.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    f = np.random.default_rng(24).uniform(-1, 1, n)
+    assert relerr(to_np(g.vcycle(f)), o.vcycle(f)) <= _coarse_tol(o)
+    g.close()
+    o.close()
+
+
 @pytest.mark.parametrize("n", [1000, 600, 129])
 def test_coarse_direct_solve_needs_pivoting(n):
     """The whole matrix is the coarsest level (several 128-wide blocks of the
