@@ -2068,7 +2068,8 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     //    block column s, then the next pivot block (updated in place) and
     //    its inverse D_{s+1}; nothing of the critical chain crosses streams;
     //  - update stream (main): L's places cleared, D_s onto the diagonal,
-    //    then the Schur update of everything but the next pivot block;
+    //    then the Schur update of everything but the next pivot block, the
+    //    part the pivot stream needs for step s + 1 first;
     //  - Y stream: W's column block s and Y's row block s + 1.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
@@ -2099,26 +2100,29 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
                 r1 - r0, kb, ld, M + (long long)r0 * ld + K);
         k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
             kb, D, P, M + (long long)K * ld + K, ld);
-        // hand-off to the Y stream: W's column block s and Y's row block s + 1
-        if (la) {
-            if ((e = hipEventRecord(la->ev_l, st)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(ys, la->ev_l, 0)) != hipSuccess) return e;
-        }
-        if ((e = w_column(s)) != hipSuccess) return e;
-        if (r1 > r0 && (e = y_row(s)) != hipSuccess) return e;
-        // Schur update without the next pivot block (done on the pivot stream)
+        if (la && (e = hipEventRecord(la->ev_l, st)) != hipSuccess) return e;
+        // Schur update without the next pivot block (done on the pivot
+        // stream): first the two block columns the pivot stream reads next
+        // (L's column block s + 1 below its pivot block, and all of column
+        // block s + 2), then the event it waits for, then the rest
+        auto schur = [&](int rlo, int rhi, int clo, int chi) -> hipError_t {
+            if (rhi <= rlo || chi <= clo) return hipSuccess;
+            return launch_dgemm(rhi - rlo, chi - clo, kb, Ls + (long long)(rlo - r0) * P, P,
+                                M + (long long)K * ld + clo, ld, M + (long long)rlo * ld + clo,
+                                ld, -1.0, 1.0, st);
+        };
+        const int cn = std::min(c1, c0 + kb2 + P);
         if (r1 > r0) {
-            if ((e = launch_dgemm(kb2, c1 - c0 - kb2, kb, Ls, P, M + (long long)K * ld + c0 + kb2,
-                                  ld, M + (long long)r0 * ld + c0 + kb2, ld, -1.0, 1.0, st)) !=
-                hipSuccess)
-                return e;
-            if ((e = launch_dgemm(r1 - r0 - kb2, c1 - c0, kb, Ls + (long long)kb2 * P, P,
-                                  M + (long long)K * ld + c0, ld,
-                                  M + (long long)(r0 + kb2) * ld + c0, ld, -1.0, 1.0, st)) !=
-                hipSuccess)
-                return e;
+            if ((e = schur(r0 + kb2, r1, c0, c0 + kb2)) != hipSuccess) return e;
+            if ((e = schur(r0, r1, c0 + kb2, cn)) != hipSuccess) return e;
         }
         if (la && (e = hipEventRecord(la->ev_block[1], st)) != hipSuccess) return e;
+        if (r1 > r0 && (e = schur(r0, r1, cn, c1)) != hipSuccess) return e;
+        // the Y stream: W's column block s and Y's row block s + 1, queued
+        // after the critical work of this step
+        if (la && (e = hipStreamWaitEvent(ys, la->ev_l, 0)) != hipSuccess) return e;
+        if ((e = w_column(s)) != hipSuccess) return e;
+        if (r1 > r0 && (e = y_row(s)) != hipSuccess) return e;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (la) {
