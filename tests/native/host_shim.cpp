@@ -77,6 +77,28 @@ int shim_pattern(int n, const int *rp, const int *ci, long long nnz)
 }
 
 // levels of a triangular solve in natural order; returns the number of levels
+// dependency levels in a given elimination order: sequential pass, and the
+// group-parallel pass for an order made of groups (-1 when it declines)
+int shim_levels_ord(int n, const int *rp, const int *ci, const int *ord_in, int lower, int *rows,
+                    int *ptr)
+{
+    std::vector<int> ord(ord_in, ord_in + n), r, p;
+    msp::triangular_levels(n, rp, ci, ord, lower != 0, r, p);
+    std::memcpy(rows, r.data(), sizeof(int) * n);
+    std::memcpy(ptr, p.data(), sizeof(int) * p.size());
+    return (int)p.size() - 1;
+}
+
+int shim_levels_groups(int n, const int *rp, const int *ci, const int *ord_in, int ng,
+                       const int *grp_in, int lower, int *rows, int *ptr)
+{
+    std::vector<int> ord(ord_in, ord_in + n), grp(grp_in, grp_in + ng + 1), r, p;
+    if (!msp::triangular_levels_groups(n, rp, ci, ord, grp, lower != 0, r, p)) return -1;
+    std::memcpy(rows, r.data(), sizeof(int) * n);
+    std::memcpy(ptr, p.data(), sizeof(int) * p.size());
+    return (int)p.size() - 1;
+}
+
 int shim_levels(int n, const int *rp, const int *ci, int lower, int *rows_by_level)
 {
     std::vector<int> ord(n), rows, ptr;

@@ -9,6 +9,7 @@ import subprocess
 import tempfile
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import oracle as O
@@ -140,6 +141,8 @@ def shim():
     L.shim_galerkin.restype = C.c_longlong
     L.shim_pattern.argtypes = [C.c_int, i32, i32, C.c_longlong]
     L.shim_levels.argtypes = [C.c_int, i32, i32, C.c_int, i32]
+    L.shim_levels_ord.argtypes = [C.c_int, i32, i32, i32, C.c_int, i32, i32]
+    L.shim_levels_groups.argtypes = [C.c_int, i32, i32, i32, C.c_int, i32, C.c_int, i32, i32]
     return L
 
 
@@ -313,3 +316,42 @@ def test_bilu_levels_are_hyperplanes(shim, shape):
     assert nlev == nx + ny + nz - 2
     nlev_b = shim.shim_levels(n, rp, ci, 0, rows)
     assert nlev_b == nx + ny + nz - 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_group_parallel_levels_equal_the_sequential_pass(shim, seed):
+    """Dependency levels of the multi-color elimination order, computed group
+    by group in parallel, are those of the sequential pass, entry for entry;
+    an order whose groups are not independent sets is declined."""
+    rng = np.random.default_rng(100 + seed)
+    if seed < 3:
+        rp, ci, _ = synth.poisson_csr((8 + 4 * seed, 7 + 3 * seed, 5 + seed))
+    else:
+        # 27-point pattern, large enough for the threaded chunks, with a few
+        # random long-range couplings
+        dims = (26 + seed, 24, 20 + seed)
+        T = [sp.diags([1.0, 1.0, 1.0], [-1, 0, 1], shape=(d, d)) for d in dims]
+        Pm = sp.kron(sp.kron(T[2], T[1]), T[0]).tocsr()
+        n = Pm.shape[0]
+        i = rng.integers(0, n, 40)
+        j = rng.integers(0, n, 40)
+        E = sp.coo_matrix((np.ones(40), (i, j)), shape=(n, n))
+        Pm = ((Pm + E + E.T) != 0).astype(np.float64).tocsr()
+        Pm.sort_indices()
+        rp, ci = Pm.indptr.astype(np.int32), Pm.indices.astype(np.int32)
+    n = len(rp) - 1
+    col, g = _lib_color(shim, rp, ci)
+    ord_ = np.argsort(col, kind="stable").astype(np.int32)
+    grp = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=col.max() + 1))]).astype(np.int32)
+    for lower in (1, 0):
+        r1, p1 = np.zeros(n, np.int32), np.zeros(n + 1, np.int32)
+        r2, p2 = np.zeros(n, np.int32), np.zeros(n + 1, np.int32)
+        nl1 = shim.shim_levels_ord(n, rp, ci, ord_, lower, r1, p1)
+        nl2 = shim.shim_levels_groups(n, rp, ci, ord_, len(grp) - 1, grp, lower, r2, p2)
+        assert nl2 == nl1
+        assert np.array_equal(r1, r2) and np.array_equal(p1[:nl1 + 1], p2[:nl2 + 1])
+    # natural order cut in two halves: rows of one half are coupled
+    half = np.array([0, n // 2, n], dtype=np.int32)
+    nat = np.arange(n, dtype=np.int32)
+    r2, p2 = np.zeros(n, np.int32), np.zeros(n + 1, np.int32)
+    assert shim.shim_levels_groups(n, rp, ci, nat, 2, half, 1, r2, p2) == -1
