@@ -34,14 +34,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tri_sweep_traffic.md")
 KERNEL_HDR = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.h")
 
 
-def gj_panel():
+def lu_block():
     """Block size of the coarsest-level solver's block LU (kGJPanel)."""
     import re
-    m = re.search(r"constexpr int kGJPanel = (\d+);", open(KERNEL_HDR).read())
+    m = re.search(r"constexpr int kLuBlock = (\d+);", open(KERNEL_HDR).read())
     return int(m.group(1))
 
 
-GJ_PANEL = gj_panel()
+LU_BLOCK = lu_block()
 WORKLOADS = {
     "cfg0": (0, "10x10x10 cells, b=4, lognormal sigma=1, 2 wells (4,000 unknowns)"),
     "cfg1": (1, "64x64x32 cells, b=4, lognormal sigma=1.5, kz/kh=0.1, 4 wells (524,288 unknowns)"),
@@ -213,9 +213,9 @@ def main():
     # dominant kernel of a step: the GEMM steps of the triangular-inverse
     # sweeps of the coarsest-level solver (FP64 matrix cores); the timed
     # launch is the largest one, W's last block column: C = -A B with A
-    # (J P) x k and B k x P (P = GJ_PANEL, J the last block, k = sweep_depth):
+    # (J P) x k and B k x P (P = LU_BLOCK, J the last block, k = sweep_depth):
     # algorithmic work 2 J P P k flops
-    P = GJ_PANEL
+    P = LU_BLOCK
     mr = max((nL - 1) // P * P, 1)
     kd = sweep_depth(solver.level(len(last["level_rows"]) - 1), P)
     upd_flops = 2.0 * mr * P * kd
@@ -309,7 +309,7 @@ def source_hash():
     b = src.index("\n}\n", b) + 3
     c = src.index("hipError_t launch_dgemm(")
     d = src.index("\n}\n", c) + 3
-    key = src[a:b] + src[c:d] + f"tri_sweep W-last-column block={GJ_PANEL}"
+    key = src[a:b] + src[c:d] + f"tri_sweep W-last-column block={LU_BLOCK}"
     return hashlib.sha256(key.encode()).hexdigest()[:16]
 
 

@@ -513,18 +513,18 @@ std::future<void> launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &t
     // fill bound of each block step: a row first takes part in the step of
     // the block holding its first stored column, a column in that of its
     // first stored row
-    const int steps = (m + kGJPanel - 1) / kGJPanel;
+    const int steps = (m + kLuBlock - 1) / kLuBlock;
     std::vector<int> rows_end(steps, 0), cols_end(steps, 0);
     {
         std::vector<int> first_row(m, m);
         for (int i = 0; i < m; ++i) {
-            const int s0 = A.ci[A.rp[i]] / kGJPanel;  // columns ascending
+            const int s0 = A.ci[A.rp[i]] / kLuBlock;  // columns ascending
             rows_end[s0] = std::max(rows_end[s0], i + 1);
             for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
                 first_row[A.ci[k]] = std::min(first_row[A.ci[k]], i);
         }
         for (int j = 0; j < m; ++j) {
-            const int s0 = first_row[j] / kGJPanel;
+            const int s0 = first_row[j] / kLuBlock;
             cols_end[s0] = std::max(cols_end[s0], j + 1);
         }
         for (int s = 1; s < steps; ++s) {
@@ -1105,7 +1105,7 @@ void vcycle(msp_ctx *c, int l)
 {
     Level &L = c->lev[l];
     if (l == (int)c->lev.size() - 1) {
-        HIPCHK(launch_coarse_solve<T>(L.n, c->ldL, kGJPanel, c->cY, c->cinv, (const T *)L.f,
+        HIPCHK(launch_coarse_solve<T>(L.n, c->ldL, kLuBlock, c->cY, c->cinv, (const T *)L.f,
                                       c->ct, (T *)L.x, c->stream));
         return;
     }
@@ -1928,7 +1928,7 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
             // band there, on scratch operands made on first use and kept
             // with B (P the block size); C is overwritten, so every
             // repetition does the same work
-            constexpr int P = kGJPanel;
+            constexpr int P = kLuBlock;
             const int m = c->nL, kd = std::max(c->sweepK, 1);
             const int mr = std::max((m - 1) / P * P, 1);
             if (!c->tC) {
@@ -1964,11 +1964,11 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
             case MSP_STAGE_COARSE: {
                 Level &L = c->lev.back();
                 if (f32)
-                    HIPCHK(launch_coarse_solve<float>(L.n, c->ldL, kGJPanel, c->cY, c->cinv,
+                    HIPCHK(launch_coarse_solve<float>(L.n, c->ldL, kLuBlock, c->cY, c->cinv,
                                                       (const float *)L.f, c->ct, (float *)L.x,
                                                       c->stream));
                 else
-                    HIPCHK(launch_coarse_solve<double>(L.n, c->ldL, kGJPanel, c->cY, c->cinv,
+                    HIPCHK(launch_coarse_solve<double>(L.n, c->ldL, kLuBlock, c->cY, c->cinv,
                                                        (const double *)L.f, c->ct,
                                                        (double *)L.x, c->stream));
                 break;

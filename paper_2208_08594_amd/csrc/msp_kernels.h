@@ -161,7 +161,7 @@ hipError_t launch_dense_scatter(int n, int ld, const int *rp, const int *ci, con
 hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const double *B, int ldb,
                         double *C, int ldc, double alpha, double beta, hipStream_t st);
 // Direct solver of the n x n row-major matrix M (leading dimension ld), in
-// the form A^-1 = W Y.  A block LU factorisation over kGJPanel-wide blocks,
+// the form A^-1 = W Y.  A block LU factorisation over kLuBlock-wide blocks,
 // A = L U with L unit block-lower triangular, makes no row interchanges
 // across blocks; each pivot block is inverted by k_gj_diag, with partial
 // pivoting inside the block (*bad is set on a zero pivot).  Then W = U^-1
@@ -190,7 +190,7 @@ hipError_t launch_dgemm(int Mr, int Nc, int Kd, const double *A, int lda, const 
 // factorisation never touches them.  lband must hold
 // dense_inverse_lband(n, rows_end) doubles (L by block columns, then by
 // block rows) and work dense_inverse_work(n) doubles.
-constexpr int kGJPanel = 128;
+constexpr int kLuBlock = 128;
 struct GjLookAhead {
     hipStream_t main, aux, third;
     hipEvent_t ev_start, ev_done, ev_block[2], ev_inv[2], ev_l, ev_y;

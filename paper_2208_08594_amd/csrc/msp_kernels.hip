@@ -1889,8 +1889,8 @@ namespace {
 // pivot stream forms it from these rows).
 int lu_end(int n, int s, const int *ends)
 {
-    const int K = s * kGJPanel;
-    const int cover = n - K < 2 * kGJPanel ? n : K + 2 * kGJPanel;
+    const int K = s * kLuBlock;
+    const int cover = n - K < 2 * kLuBlock ? n : K + 2 * kLuBlock;
     const int e = ends ? std::max(ends[s], cover) : n;
     return std::min(e, n);
 }
@@ -1944,7 +1944,7 @@ struct LrowLayout {
 
 LrowLayout lrow_layout(int n, const int *rows_end)
 {
-    constexpr int P = kGJPanel;
+    constexpr int P = kLuBlock;
     const int steps = (n + P - 1) / P;
     LrowLayout L;
     L.f.assign(steps, 0);
@@ -1961,9 +1961,9 @@ LrowLayout lrow_layout(int n, const int *rows_end)
 size_t lband_col(int n, const int *rows_end)
 {
     size_t q = 0;
-    for (int K = 0, s = 0; K < n; K += kGJPanel, ++s) {
-        const int r0 = std::min(K + kGJPanel, n);
-        q += (size_t)(lu_end(n, s, rows_end) - r0) * kGJPanel;
+    for (int K = 0, s = 0; K < n; K += kLuBlock, ++s) {
+        const int r0 = std::min(K + kLuBlock, n);
+        q += (size_t)(lu_end(n, s, rows_end) - r0) * kLuBlock;
     }
     return q;
 }
@@ -1972,19 +1972,19 @@ size_t lband_col(int n, const int *rows_end)
 
 size_t dense_inverse_work(int n)
 {
-    return (size_t)kGJPanel * n + (size_t)2 * kGJPanel * kGJPanel;
+    return (size_t)kLuBlock * n + (size_t)2 * kLuBlock * kLuBlock;
 }
 
 size_t dense_inverse_lband(int n, const int *rows_end)
 {
-    const int steps = (n + kGJPanel - 1) / kGJPanel;
+    const int steps = (n + kLuBlock - 1) / kLuBlock;
     return lband_col(n, rows_end) + (size_t)lrow_layout(n, rows_end).off[steps];
 }
 
 
 int dense_inverse_sweep_k(int n, const int *cols_end)
 {
-    constexpr int P = kGJPanel;
+    constexpr int P = kLuBlock;
     const int steps = (n + P - 1) / P, J = steps - 1, K = J * P;
     int us = 0;
     while (us < J && lu_end(n, us, cols_end) <= K) ++us;
@@ -2001,10 +2001,10 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         st = la->main;
         if ((e = hipStreamWaitEvent(st, la->ev_start, 0)) != hipSuccess) return e;
     }
-    constexpr int P = kGJPanel;
+    constexpr int P = kLuBlock;
     const int steps = (n + P - 1) / P;
     // the pivot blocks are inverted by one k_gj_diag each, in place of M
-    static_assert(kGJPanel == kNB, "one pivot kernel per block");
+    static_assert(kLuBlock == kNB, "one pivot kernel per block");
     double *Tcol = work;                                // n x P
     double *Dblk[2] = {Tcol + (long long)P * n,         // P x P, two buffers
                        Tcol + (long long)P * n + (long long)P * P};
