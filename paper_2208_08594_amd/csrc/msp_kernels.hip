@@ -2064,12 +2064,13 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
     // whose inverses D_s replace them on the diagonal of M; the blocks of L
     // go to lband (column block s: rows [r0, r1) with ld P) and their places
     // in M are cleared.  Step s is split over the streams:
-    //  - pivot stream (aux): once the Schur update of step s - 1 is done, L's
-    //    block column s, then the next pivot block (updated in place) and
-    //    its inverse D_{s+1}; nothing of the critical chain crosses streams;
-    //  - update stream (main): L's places cleared, D_s onto the diagonal,
-    //    then the Schur update of everything but the next pivot block, the
-    //    part the pivot stream needs for step s + 1 first;
+    //  - pivot stream (aux): once the Schur update of step s - 1 is done, the
+    //    top block of L's column s (the next pivot block's rows), the next
+    //    pivot block (updated in place) and its inverse D_{s+1};
+    //  - update stream (main): the rest of L's block column s, its places in
+    //    M cleared, D_s onto the diagonal, then the Schur update of everything
+    //    but the next pivot block, the part the pivot stream needs for step
+    //    s + 1 first;
     //  - Y stream: W's column block s and Y's row block s + 1.
     for (int s = 0; s < steps; ++s) {
         const int K = s * P, kb = std::min(P, n - K);
@@ -2082,8 +2083,10 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         if (la && s > 0 && (e = hipStreamWaitEvent(aux, la->ev_block[1], 0)) != hipSuccess)
             return e;
         if (r1 > r0) {
-            if ((e = launch_dgemm(r1 - r0, kb, kb, M + (long long)r0 * ld + K, ld, D, P, Ls, P,
-                                  1.0, 0.0, aux)) != hipSuccess)
+            // only the next pivot block's rows of L here; the update stream
+            // forms the rest
+            if ((e = launch_dgemm(kb2, kb, kb, M + (long long)r0 * ld + K, ld, D, P, Ls, P, 1.0,
+                                  0.0, aux)) != hipSuccess)
                 return e;
             if ((e = launch_dgemm(kb2, kb2, kb, Ls, P, M + (long long)K * ld + r0, ld, Mn, ld,
                                   -1.0, 1.0, aux)) != hipSuccess)
@@ -2095,9 +2098,13 @@ hipError_t dense_inverse(int n, int ld, double *M, double *Y, double *lband, dou
         }
         if (r1 > r0)
             k_gj_diag<<<1, 256, 0, aux>>>(ld, r0, kb2, M, Dblk[(s + 1) & 1], bad);
-        if (r1 > r0)
+        if (r1 > r0) {
+            if ((e = launch_dgemm(r1 - r0 - kb2, kb, kb, M + (long long)(r0 + kb2) * ld + K, ld, D,
+                                  P, Ls + (long long)kb2 * P, P, 1.0, 0.0, st)) != hipSuccess)
+                return e;
             k_zero_rect<<<blocks_for((long long)(r1 - r0) * kb), kThreads, 0, st>>>(
                 r1 - r0, kb, ld, M + (long long)r0 * ld + K);
+        }
         k_copy_block<<<blocks_for((long long)kb * kb), kThreads, 0, st>>>(
             kb, D, P, M + (long long)K * ld + K, ld);
         if (la && (e = hipEventRecord(la->ev_l, st)) != hipSuccess) return e;
