@@ -35,7 +35,7 @@ KERNEL_HDR = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.h")
 
 
 def lu_block():
-    """Block size of the coarsest-level solver's block LU (kGJPanel)."""
+    """Block size of the coarsest-level solver's block LU (kLuBlock)."""
     import re
     m = re.search(r"constexpr int kLuBlock = (\d+);", open(KERNEL_HDR).read())
     return int(m.group(1))
