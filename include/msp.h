@@ -135,8 +135,11 @@ typedef struct {
 /* Fill *opt with the defaults listed above.  Returns MSP_ERR_ARG on NULL. */
 int msp_default_options(msp_options *opt);
 
-/* Create a context on the current device.  *ctx receives an opaque handle
- * owned by the caller until msp_destroy.  opt may be NULL (defaults).
+/* Create a context on the current device: the state that Sec. 3.2 carries
+ * from one Newton system to the next (the preconditioner B^(i-1), the
+ * iteration count It^(i-1) of the last solve, the setup-call counter) and the
+ * solver settings of Sec. 5.  *ctx receives an opaque handle owned by the
+ * caller until msp_destroy.  opt may be NULL (defaults).
  * Errors: MSP_ERR_ARG (ctx NULL, bad option values), MSP_ERR_NO_DEVICE,
  * MSP_ERR_NOMEM. */
 int msp_create(struct msp_ctx **ctx, const msp_options *opt);
@@ -178,14 +181,25 @@ int msp_solve(struct msp_ctx *ctx, const double *rhs, double *x, double rtol, ms
 int msp_get_info(struct msp_ctx *ctx, msp_info *info);
 
 /* Upper bound of the device memory a context needs for a system of this
- * shape (used by admission control).  bytes: host pointer. */
+ * shape: the FP64 block matrix of Sec. 2.3 (n block rows, nnzb blocks of
+ * b x b), the AMG hierarchy of Sec. 5 bounded by the coarsening limits, the
+ * block ILU(0) factors of the last stage of eq. (MSP), and the 2m+1 Krylov
+ * vectors of FGMRES(m).  The paper has no such query; it serves admission by
+ * memory when many systems share one GPU.  opt may be NULL (defaults);
+ * bytes: host pointer.  Errors: MSP_ERR_ARG (bytes NULL, n < 1, b outside
+ * 1..MSP_MAX_BLOCK, nnzb < n). */
 int msp_footprint(int n_block_rows, long long nnzb, int block_size, const msp_options *opt,
                   size_t *bytes);
 
-/* Release every resource of the context (NULL is accepted). */
+/* End a Newton sequence (Sec. 3.2): release every device and host resource
+ * of the context, after waiting for its stream.  NULL is accepted; the handle
+ * is invalid afterwards.  Returns MSP_OK, or MSP_ERR_HIP if a HIP call
+ * failed while freeing (the context is released regardless). */
 int msp_destroy(struct msp_ctx *ctx);
 
-/* Static description of a status code (never NULL). */
+/* Static, NUL-terminated description of a status code of this header
+ * (never NULL; unknown codes give a generic text).  Not from the paper:
+ * error reporting of the library. */
 const char *msp_status_string(int status);
 
 typedef struct msp_ctx msp_ctx;

@@ -61,6 +61,7 @@ def lib():
     L.or_decouple.argtypes = [C.c_int, C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p]
     L.or_color.argtypes = [C.c_int, i32p, i32p, i32p]
     L.or_npair_pass.argtypes = [C.c_int, i32p, i32p, f64p, i32p]
+    L.or_absorb_singletons.argtypes = [C.c_int, i32p, i32p, f64p, i32p, C.c_int]
     L.or_galerkin.argtypes = [C.c_int, i32p, i32p, f64p, i32p, C.c_int, i32p, i32p, f64p]
     L.or_galerkin.restype = C.c_long
     L.or_bilu0_factor.argtypes = [C.c_int, C.c_int, i32p, i32p, f64p, f64p, f64p]
@@ -152,6 +153,17 @@ def npair_pass(rp, ci, val):
     agg = np.zeros(n, dtype=np.int32)
     nc = _check(lib().or_npair_pass(n, _i32(rp), _i32(ci), _f64(val), agg), "npair")
     return agg, nc
+
+
+def absorb_singletons(rp, ci, val, agg, nc):
+    """Stalled-coarsening step: eligible rows alone in their aggregate join the
+    aggregate of their strongest neighbour in an aggregate of two or more rows;
+    returns the new aggregate map and count."""
+    n = len(rp) - 1
+    out = _i32(agg).copy()
+    k = _check(lib().or_absorb_singletons(n, _i32(rp), _i32(ci), _f64(val), out, int(nc)),
+               "absorb")
+    return out, k
 
 
 def galerkin(rp, ci, val, agg, nc):

@@ -1,12 +1,12 @@
-"""Two studies on synthetic inputs, run through the libmsp C-ABI (GPU) with
-the oracle beside it where noted.
+"""Studies on synthetic inputs, run through the libmsp C-ABI (GPU).
 
 * Smoother comparison (the analogue of Table 1, Sec. 6): the AMG smoother of
   the MSP preconditioner is PGS-MC (Alg. 4.3) or weighted point Jacobi
   (PJAC); a Newton sequence of systems is solved with mu = 0 and the total
-  FGMRES iterations and time are reported.  The oracle adds sequential
-  Gauss-Seidel in natural row order as the reference that PGS-MC is compared
-  with (iterations only).
+  FGMRES iterations and time are reported.  (The iteration counts of the
+  CPU oracle on the same sequence, including sequential Gauss-Seidel in
+  natural row order, come from oracle/smoother_iterations.py, which is test
+  infrastructure and not part of this package.)
 * Stages: the two-stage preconditioner (pressure, then R) against the
   paper's three stages (concentration, pressure, R; eq. MSP), with block
   ILU(0) or block Jacobi as R.
@@ -81,7 +81,7 @@ def _summary(infos):
             "all_converged": all(i["status"] == 0 for i in infos)}
 
 
-def smoother_study(seq, dev_arrays, oracle_systems=0):
+def smoother_study(seq, dev_arrays):
     variants = [("PGS-MC", dict(smoother=0)),
                 ("PJAC w=1", dict(smoother=1, jacobi_weight=1.0)),
                 ("PJAC w=2/3", dict(smoother=1, jacobi_weight=2.0 / 3.0))]
@@ -89,20 +89,6 @@ def smoother_study(seq, dev_arrays, oracle_systems=0):
     run_sequence(seq[:1], dev_arrays)  # warm-up
     for name, opts in variants:
         res[name] = _summary(run_sequence(seq, dev_arrays, **opts))
-    if oracle_systems > 0:
-        # iterations of the oracle on the first systems: PGS-MC versus the
-        # sequential natural-order Gauss-Seidel it is compared with, and PJAC
-        from oracle import oracle as O
-        for name, kw in [("PGS-MC", dict(smoother=0)), ("GS natural (sequential)", dict(smoother=2)),
-                         ("PJAC w=1", dict(smoother=1, jacobi_weight=1.0))]:
-            its = []
-            o = O.OracleSolver(**kw)
-            for s in seq[:oracle_systems]:
-                o.setup(s)
-                _, it, rr, st = o.solve(s.rhs, 1e-6)
-                its.append(int(it))
-            o.close()
-            res.setdefault("oracle_iterations", {})[name] = its
     return res
 
 
@@ -128,8 +114,6 @@ def main():
     ap.add_argument("--smoothers", action="store_true")
     ap.add_argument("--mu-sweep", action="store_true")
     ap.add_argument("--stages", action="store_true", help="two versus three stages")
-    ap.add_argument("--oracle-systems", type=int, default=0,
-                    help="also run the oracle on this many systems (smoother study)")
     args = ap.parse_args()
     import torch
     dev = torch.device("cuda", 0)
@@ -140,7 +124,7 @@ def main():
            "systems": args.systems, "rtol": 1e-6,
            "sequence": "5% multiplicative perturbation per step, fresh rhs"}
     if args.smoothers:
-        out["smoothers"] = smoother_study(seq, arrays, args.oracle_systems)
+        out["smoothers"] = smoother_study(seq, arrays)
     if args.mu_sweep:
         out["mu_sweep"] = mu_sweep(seq, arrays)
     if args.stages:
