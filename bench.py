@@ -4,13 +4,16 @@
 One step = one Newton-step linear solve of the synthetic reservoir Jacobian:
 msp_setup (ingest + preconditioner regeneration, mu = 0) followed by
 msp_solve to a relative true residual of 1e-6, with every input already in
-HBM.  The default workload is the 64x64x32-cell grid with 4 unknowns per cell
-(lognormal permeability sigma 1.5, kz/kh 0.1, 4 wells; 524,288 unknowns).
+HBM.  The default workload is the 128x128x64-cell grid with 7 unknowns per
+cell (lognormal permeability sigma 1.5, kz/kh 0.1, 4 wells; 7,340,032
+unknowns), the largest single-GPU workload.
 
 Printed: one JSON line with time-to-1e-6 (ms per step), p50/p99, the FP32- vs
-FP64-preconditioner comparison, SpMV and Gauss-Seidel bandwidth, the roofline
-of the dominant kernel (HIP events on the solver's stream) and the CPU oracle
-baseline on a bounded sample of the same workload.
+FP64-preconditioner comparison (both against the CPU oracle's solution),
+SpMV and Gauss-Seidel bandwidth, the roofline of the dominant kernel of the
+solve (the block SpMV, timed with HIP events around every launch of the timed
+steps), the roofline of a whole FGMRES iteration against its algorithmic
+bytes, and the CPU oracle baseline (one full step of the same system).
 """
 from __future__ import annotations
 
@@ -28,20 +31,6 @@ if ROOT not in sys.path:
 
 METRIC = "CPR-FGMRES time-to-1e-6 + SpMV/GS HBM GB/s; FP32-vs-FP64 precond; p50/p99"
 HBM_PEAK_GBS = 8000.0
-FP64_MFMA_PEAK_TFLOPS = 78.6
-KERNEL_SRC = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tri_sweep_traffic.md")
-KERNEL_HDR = os.path.join(ROOT, "paper_2208_08594_amd", "csrc", "msp_kernels.h")
-
-
-def lu_block():
-    """Block size of the coarsest-level solver's block LU (kLuBlock)."""
-    import re
-    m = re.search(r"constexpr int kLuBlock = (\d+);", open(KERNEL_HDR).read())
-    return int(m.group(1))
-
-
-LU_BLOCK = lu_block()
 WORKLOADS = {
     "cfg0": (0, "10x10x10 cells, b=4, lognormal sigma=1, 2 wells (4,000 unknowns)"),
     "cfg1": (1, "64x64x32 cells, b=4, lognormal sigma=1.5, kz/kh=0.1, 4 wells (524,288 unknowns)"),
@@ -59,14 +48,51 @@ def percentile(xs, q):
 
 
 def spmv_bytes(sys_):
+    """Algorithmic bytes of one block SpMV y = A x: every FP64 block value,
+    column index and row pointer once, x read once, y written once."""
     b = sys_.b
     return sys_.nnzb * b * b * 8 + sys_.nnzb * 4 + (sys_.n + 1) * 4 + 2 * sys_.N * 8
 
 
-def gs_sweep_bytes(level0_nnz, n, val_bytes):
-    # off-diagonal values + column indices, diagonal, f, x read once and written once
-    off = level0_nnz - n
-    return off * (val_bytes + 4) + n * val_bytes * 4
+def gs_sweep_bytes(nnz, n, s):
+    """One PGS-MC sweep (or residual) over a level of n rows and nnz stored
+    entries: off-diagonal values and column indices once, then diagonal, f and
+    x read once and x (or r) written once; s = value bytes."""
+    return (nnz - n) * (s + 4) + 4 * n * s
+
+
+def iteration_bytes(sys_, levels, bilu_nnzb, s, nu=(1, 1)):
+    """Algorithmic bytes of the parts of one FGMRES iteration other than the
+    Gram-Schmidt step: the SpMV, then the two-stage preconditioner apply in
+    value precision s (bytes): decoupling and restriction to the pressure
+    rows, the V-cycle (levels = [(rows, nnz)], the last one solved by the
+    two FP64 triangles of n_L^2 entries), the pressure-column residual, the
+    block ILU(0) solves and the final combination.  Each matrix value once,
+    each vector at its minimum passes."""
+    n, b, N, nnzb = sys_.n, sys_.b, sys_.N, sys_.nnzb
+    parts = {"spmv": spmv_bytes(sys_)}
+    parts["decouple"] = 2 * N * 8 + n * s + 2 * n * s  # w.v -> f, unpermute of e
+    amg = 0
+    for l, (nl, nnz) in enumerate(levels[:-1]):
+        nc = levels[l + 1][0]
+        amg += (nu[0] + nu[1] + 1) * gs_sweep_bytes(nnz, nl, s)  # sweeps + residual
+        amg += nl * s + 4 * nl + nc * s                         # restriction
+        amg += 4 * nl + nc * s + 2 * nl * s                     # prolongation
+    nL = levels[-1][0]
+    amg += nL * nL * 8 + 4 * nL * 8
+    parts["amg"] = amg
+    parts["pcol_residual"] = nnzb * b * s + nnzb * 4 + (n + 1) * 4 + N * 8 + n * s + N * s
+    off = bilu_nnzb - n
+    parts["bilu_solve"] = off * (b * b * s + 4) + n * b * b * s + 4 * N * s
+    parts["finish"] = N * s + n * s + N * 8
+    return parts
+
+
+def krylov_bytes(N, steps):
+    """Gram-Schmidt at the classical minimum: Arnoldi step j (0-based inside
+    its cycle) reads v_0..v_j and w for the dot products, then v_0..v_j and
+    w again for the update and writes w: 2(j+1)+3 vector passes."""
+    return sum((2 * (j + 1) + 3) * N * 8 for j in steps)
 
 
 def stage_ms(solver, stream, stage, reps, inp=None, out=None):
@@ -93,7 +119,8 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
     x = torch.zeros(sys_.N, dtype=torch.float64, device=dev)
     solver = msp.Solver(mu=0, restart=30, max_iter=1000, max_coarse=10000,
                         precond_fp32=precond_fp32, bilu_order=args.bilu_order, stream=stream)
-    infos = []
+    solver.set_timing(True)
+    infos, timings = [], []
 
     def step():
         solver.setup(n=sys_.n, b=sys_.b, p=sys_.p, row_ptr=rp, col_ind=ci, vals=vals)
@@ -112,6 +139,7 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
         torch.cuda.synchronize()
         times.append((time.perf_counter() - ts) * 1e3)
         infos.append(info)
+        timings.append(solver.timing())
         log(f"{'fp32' if precond_fp32 else 'fp64'} step {k}: {times[-1]:.2f} ms, "
             f"{info['iterations']} it, relres {info['rel_true_residual']:.2e}, "
             f"setup {info['setup_ms']:.2f} ms (rebuild {info['rebuild_ms']:.2f}), "
@@ -119,7 +147,13 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
             + " ".join(f"{v:.1f}" for v in info["phase_ms"][:8]))
     torch.cuda.synchronize()
     total_ms = (time.perf_counter() - t0) * 1e3
-    return solver, x.clone(), times, total_ms, infos, stream
+    return solver, x.clone(), times, total_ms, infos, timings, stream
+
+
+def summed(timings, part):
+    ms = sum(t[part][0] for t in timings)
+    calls = sum(t[part][1] for t in timings)
+    return ms, calls
 
 
 def main():
@@ -127,7 +161,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--bilu-order", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -139,7 +173,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solver path is single-GPU (see DESIGN.md for how "
+        print("bench.py measures one GPU: the solver path is single-GPU (DESIGN.md describes how "
               "it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -149,12 +183,14 @@ def main():
     idx, desc = WORKLOADS[args.workload]
     log("generating", desc)
     sys_ = synth.config(idx)
-    solver, x64, times, total_ms, infos, stream = run_gpu(sys_, args, False, args.steps,
-                                                          args.warmup)
+    solver, x64, times, total_ms, infos, timings, stream = run_gpu(sys_, args, False,
+                                                                   args.steps, args.warmup)
     ms_per_step = total_ms / args.steps
     last = infos[-1]
     setup_ms = float(np.median([i["setup_ms"] for i in infos]))
     solve_ms = float(np.median([i["solve_ms"] for i in infos]))
+    solve_ms_sum = sum(i["solve_ms"] for i in infos)
+    iters_sum = sum(i["iterations"] for i in infos)
 
     # reuse step (adaptive setup keeps B): ingest + solve only
     reuse = msp.Solver(mu=1000, precond_fp32=False, bilu_order=args.bilu_order, stream=stream)
@@ -174,70 +210,107 @@ def main():
         reuse_t.append((time.perf_counter() - ts) * 1e3)
     reuse.close()
 
-    # kernel timing with HIP events on the solver's stream
+    # per-stage timing with HIP events on the solver's stream (back-to-back launches)
     xin = torch.rand(sys_.N, dtype=torch.float64, device=dev)
     yout = torch.empty_like(xin)
-    reps = 50
-    t_spmv = stage_ms(solver, stream, msp.STAGE_SPMV, reps, xin, yout)
-    t_gs = stage_ms(solver, stream, msp.STAGE_GS0, reps) if last["n_levels"] > 1 else None
+    t_gs = stage_ms(solver, stream, msp.STAGE_GS0, 50) if last["n_levels"] > 1 else None
     t_bilu = stage_ms(solver, stream, msp.STAGE_BILU, 10)
     t_vc = stage_ms(solver, stream, msp.STAGE_VCYCLE, 10)
     t_pre = stage_ms(solver, stream, msp.STAGE_PRECOND, 10, xin, yout)
     t_coarse = stage_ms(solver, stream, msp.STAGE_COARSE, 20)
-    t_upd = stage_ms(solver, stream, msp.STAGE_TRI_SWEEP, 10)
-    b_spmv = spmv_bytes(sys_)
-    lev0_nnz = int(solver.level(0)["row_ptr"][-1])
-    b_gs = gs_sweep_bytes(lev0_nnz, sys_.n, 8)
-    nL = last["level_rows"][-1]
-    # the two triangles of the coarsest solve read n_L^2 entries in all
-    b_coarse = nL * nL * 8 + 4 * nL * 8
     gbs = lambda by, ms: by / (ms * 1e-3) / 1e9
-    log(f"SpMV {t_spmv*1e3:.1f} us ({gbs(b_spmv, t_spmv):.0f} GB/s); "
+
+    # sizes of the hierarchy and of the block ILU(0) pattern
+    levels = []
+    for l in range(last["n_levels"]):
+        Ld = solver.level(l)
+        levels.append((Ld["n"], int(Ld["row_ptr"][-1])))
+    lev0_nnz = levels[0][1]
+    b_gs = gs_sweep_bytes(lev0_nnz, sys_.n, 8)
+    nL = levels[-1][0]
+    b_coarse = nL * nL * 8 + 4 * nL * 8
+
+    # the dominant kernel of the solve: the block SpMV, every launch of the
+    # timed steps bracketed by HIP events on the solver's stream
+    spmv_ms, spmv_calls = summed(timings, "spmv")
+    apply_ms, apply_calls = summed(timings, "apply")
+    gsch_ms, gsch_calls = summed(timings, "gram_schmidt")
+    b_spmv = spmv_bytes(sys_)
+    t_spmv = spmv_ms / max(spmv_calls, 1)
+    roofline = {"kernel": f"k_spmv<{sys_.b}> (block SpMV w = A z of every Arnoldi step)",
+                "bound": "hbm", "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS,
+                "traffic": None, "bytes_per_launch": b_spmv,
+                "avg_launch_us": t_spmv * 1e3, "launches_timed": spmv_calls}
+
+    # a whole FGMRES iteration against its algorithmic bytes (matrices once,
+    # vectors at their minimum passes, Gram-Schmidt at the classical minimum)
+    parts = iteration_bytes(sys_, levels, sys_.nnzb, 8)
+    steps_j = []
+    for i in infos:
+        k, m = i["iterations"], 30
+        steps_j += [j % m for j in range(k)]
+    kry = krylov_bytes(sys_.N, steps_j) / len(infos)
+    it_bytes = sum(parts.values()) * iters_sum / len(infos) + kry
+    solve_gbs = it_bytes / (solve_ms_sum / len(infos) * 1e-3) / 1e9
+    roofline_solve = {"what": "one msp_solve (all FGMRES iterations) against its algorithmic "
+                              "bytes", "bound": "hbm", "achieved": solve_gbs,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_gbs / HBM_PEAK_GBS,
+                      "bytes_per_solve": it_bytes,
+                      "bytes_per_iteration_model": {k: v for k, v in parts.items()},
+                      "krylov_bytes_per_solve": kry,
+                      "ms_per_iteration": solve_ms_sum / iters_sum}
+    kernel_rows = {
+        "spmv": {"us": t_spmv * 1e3, "bytes": b_spmv, "gbs": gbs(b_spmv, t_spmv),
+                 "how": "HIP events around every SpMV of the timed solves"},
+        "gs_sweep_level0": None if t_gs is None else
+        {"us": t_gs * 1e3, "bytes": b_gs, "gbs": gbs(b_gs, t_gs),
+         "how": "50 back-to-back forward sweeps, HIP events"},
+        "bilu_solve": {"us": t_bilu * 1e3, "bytes": parts["bilu_solve"],
+                       "gbs": gbs(parts["bilu_solve"], t_bilu),
+                       "how": "10 back-to-back solves, HIP events"},
+        "vcycle": {"us": t_vc * 1e3, "bytes": parts["amg"], "gbs": gbs(parts["amg"], t_vc)},
+        "precond_apply": {"us": apply_ms / max(apply_calls, 1) * 1e3,
+                          "bytes": sum(v for k, v in parts.items() if k != "spmv"),
+                          "how": "HIP events around every apply of the timed solves"},
+        "gram_schmidt_us_per_step": gsch_ms / max(gsch_calls, 1) * 1e3,
+        "coarse_solve": {"us": t_coarse * 1e3, "bytes": b_coarse,
+                         "gbs": gbs(b_coarse, t_coarse)},
+    }
+    log(f"SpMV {t_spmv*1e3:.1f} us ({gbs(b_spmv, t_spmv):.0f} GB/s, {spmv_calls} launches); "
         f"GS0 {(t_gs or 0)*1e3:.1f} us; BILU {t_bilu*1e3:.1f} us; V-cycle {t_vc*1e3:.1f} us; "
-        f"precond {t_pre*1e3:.1f} us; coarse {t_coarse*1e3:.1f} us ({gbs(b_coarse, t_coarse):.0f} GB/s)")
+        f"apply {apply_ms / max(apply_calls, 1)*1e3:.1f} us; coarse {t_coarse*1e3:.1f} us; "
+        f"solve {solve_gbs:.0f} GB/s")
 
     # FP32 preconditioner on the same system
     fp32 = None
+    x32 = None
     if not args.no_fp32:
-        s32, x32, t32, tot32, inf32, _ = run_gpu(sys_, args, True, max(3, args.steps // 2), 1)
-        d = (x32 - x64).norm().item() / x64.norm().item()
+        s32, x32, t32, tot32, inf32, tim32, _ = run_gpu(sys_, args, True,
+                                                        max(3, args.steps // 2), 1)
         fp32 = {"ms_per_step": tot32 / len(t32),
                 "setup_ms": float(np.median([i["setup_ms"] for i in inf32])),
                 "solve_ms": float(np.median([i["solve_ms"] for i in inf32])),
                 "iterations": inf32[-1]["iterations"],
                 "rel_true_residual": inf32[-1]["rel_true_residual"],
-                "rel_diff_vs_fp64_solution": d,
-                "precond_apply_us": stage_ms(s32, stream, msp.STAGE_PRECOND, 10, xin, yout) * 1e3}
+                "precond_apply_us": summed(tim32, "apply")[0] /
+                max(summed(tim32, "apply")[1], 1) * 1e3}
         s32.close()
 
-    # dominant kernel of a step: the GEMM steps of the triangular-inverse
-    # sweeps of the coarsest-level solver (FP64 matrix cores); the timed
-    # launch is the largest one, W's last block column: C = -A B with A
-    # (J P) x k and B k x P (P = LU_BLOCK, J the last block, k = sweep_depth):
-    # algorithmic work 2 J P P k flops
-    P = LU_BLOCK
-    mr = max((nL - 1) // P * P, 1)
-    kd = sweep_depth(solver.level(len(last["level_rows"]) - 1), P)
-    upd_flops = 2.0 * mr * P * kd
-    achieved = upd_flops / (t_upd * 1e-3) / 1e12
-    roofline = {"kernel": f"k_dgemm_s (largest triangular-inverse sweep step of the coarsest-level "
-                          f"solver, {mr}x{P}x{kd}, n_L={nL})", "bound": "mfma",
-                "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                "traffic": stored_traffic(f"{mr}x{P}x{kd}"),
-                "flops_per_launch": upd_flops, "avg_launch_us": t_upd * 1e3,
-                "algorithmic_bytes_per_launch": (mr * kd + kd * P + mr * P) * 8}
-    roofline_spmv = {"kernel": f"k_spmv<{sys_.b}>", "bound": "hbm",
-                     "achieved": gbs(b_spmv, t_spmv), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs(b_spmv, t_spmv) / HBM_PEAK_GBS, "bytes_per_launch": b_spmv,
-                     "avg_launch_us": t_spmv * 1e3}
     serving = None
     if not args.no_serving:
         serving = serving_sample()
 
     cpu = None
+    errors = {}
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(sys_)
+        cpu, x_or = cpu_baseline(sys_)
+        nx = np.linalg.norm(x_or)
+        errors["fp64_precond_vs_oracle"] = float(np.linalg.norm(x64.cpu().numpy() - x_or) / nx)
+        if x32 is not None:
+            errors["fp32_precond_vs_oracle"] = float(np.linalg.norm(x32.cpu().numpy() - x_or) / nx)
+        if fp32 is not None:
+            fp32["rel_error_vs_fp64_oracle"] = errors.get("fp32_precond_vs_oracle")
 
     out = {
         "metric": METRIC, "value": ms_per_step, "unit": "ms", "n_gpus": 1,
@@ -254,18 +327,16 @@ def main():
                                     "worker_wait"],
                                    [round(v, 3) for v in last["phase_ms"][:8]])),
         "rel_true_residual": last["rel_true_residual"],
+        "solution_rel_error_vs_oracle": errors or None,
         "levels": last["level_rows"], "colors": last["n_colors"],
         "bilu_levels": [last["bilu_levels_fwd"], last["bilu_levels_bwd"]],
         "reuse_step_ms": float(np.median(reuse_t)),
         "spmv_gbs": gbs(b_spmv, t_spmv),
         "gs_gbs": gbs(b_gs, t_gs) if t_gs else None,
-        "stage_us": {"spmv": t_spmv * 1e3, "gs_sweep_level0": t_gs and t_gs * 1e3,
-                     "bilu_solve": t_bilu * 1e3, "vcycle": t_vc * 1e3,
-                     "precond_apply": t_pre * 1e3, "coarse_solve": t_coarse * 1e3},
+        "kernels": kernel_rows,
         "fp32_precond": fp32,
         "roofline": roofline,
-        "roofline_spmv": roofline_spmv,
-        "coarse_solve_gbs": gbs(b_coarse, t_coarse),
+        "roofline_solve": roofline_solve,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -273,67 +344,6 @@ def main():
     solver.close()
     torch.cuda.synchronize()
     log("done")
-
-
-def sweep_depth(level, P):
-    """Depth k of the largest sweep step of the coarsest solver, W's last block
-    column J: J P minus the first row of U's band there.  U's block row s
-    reaches columns below max(1 + the last column whose first stored row lies
-    in blocks <= s, the end of block s + 1)."""
-    rp, ci = level["row_ptr"], level["col_ind"]
-    n = len(rp) - 1
-    rows = np.repeat(np.arange(n), np.diff(rp))
-    first_row = np.full(n, n)
-    np.minimum.at(first_row, ci, rows)
-    steps = (n + P - 1) // P
-    ends = np.zeros(steps, dtype=np.int64)
-    np.maximum.at(ends, first_row // P, np.arange(n) + 1)
-    ends = np.maximum.accumulate(ends)
-    J = steps - 1
-    K = J * P
-    us = 0
-    while us < J and max(int(ends[us]), min(n, us * P + 2 * P)) <= K:
-        us += 1
-    return max(K - us * P, 1)
-
-
-def source_hash():
-    """sha256[:16] of the dominant kernel's source: the FP64 GEMM tile code
-    (from its header comment to the end of the small-tile kernel), its
-    launcher and the block size (which fixes the timed shape), so edits elsewhere in the
-    file keep the stored counters valid."""
-    import hashlib
-    src = open(KERNEL_SRC).read()
-    a = src.index("// C = alpha * A B + beta * C (row-major, FP64) on the matrix cores.")
-    b = src.index("dgemm_tile<kGTs, kGTs, 2, 2>", a)
-    b = src.index("\n}\n", b) + 3
-    c = src.index("hipError_t launch_dgemm(")
-    d = src.index("\n}\n", c) + 3
-    key = src[a:b] + src[c:d] + f"tri_sweep W-last-column block={LU_BLOCK}"
-    return hashlib.sha256(key.encode()).hexdigest()[:16]
-
-
-def stored_traffic(shape):
-    """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary, only if it was taken on the current kernel source and at the
-    launch shape timed here (M x N x K)."""
-    try:
-        txt = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
-    vals = {}
-    for line in txt.splitlines():
-        if line.startswith("- ") and ":" in line:
-            k, v = line[2:].rsplit(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel source sha256[:16]") != source_hash():
-        return None
-    if vals.get("launch shape") != shape:
-        return None
-    try:
-        return float(vals["HBM bytes per launch"])
-    except (KeyError, ValueError):
-        return None
 
 
 def calibrate_copy():
@@ -364,7 +374,8 @@ def serving_sample():
 
 
 def cpu_baseline(sys_):
-    """The oracle, as it is, on one full Newton step of the same workload."""
+    """The oracle, as it is, on one full Newton step of the same system
+    (setup + FGMRES to 1e-6) on one host thread; returns its record and x."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -381,11 +392,11 @@ def cpu_baseline(sys_):
         x, it, rr, st = s.solve(sys_.rhs, 1e-6)
         t2 = time.perf_counter()
     s.close()
-    return {"value": (t2 - t0) * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": "one full Newton step (setup + FGMRES to 1e-6) of the same system, "
-                      f"sequential FP64 oracle, LAPACK on 1 thread; setup {1e3*(t1-t0):.0f} ms, "
-                      f"solve {1e3*(t2-t1):.0f} ms, {it} iterations",
-            "iterations": it}
+    return ({"value": (t2 - t0) * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+             "sample": "one full Newton step (setup + FGMRES to 1e-6) of the same system, "
+                       f"sequential FP64 oracle, LAPACK on 1 thread; setup {1e3*(t1-t0):.0f} ms, "
+                       f"solve {1e3*(t2-t1):.0f} ms, {it} iterations, relres {rr:.2e}",
+             "iterations": it, "rel_true_residual": rr}, np.asarray(x))
 
 
 if __name__ == "__main__":

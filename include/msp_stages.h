@@ -103,6 +103,22 @@ int msp_stage_get_nstage(msp_ctx *ctx, double *Dn, double *Ann);
  * MSP_ERR_STATE. */
 int msp_stage_repeat(msp_ctx *ctx, int stage, int reps, const double *in, double *out);
 
+/* Per-part timing of msp_solve with HIP events on the context's stream, for
+ * measuring the kernels of the FGMRES iteration (Sec. 5) over a real solve
+ * rather than in isolation.  on != 0 makes every later msp_solve record four
+ * events per Arnoldi step (before the preconditioner apply, before the SpMV
+ * w = A z, before the Gram-Schmidt step, after it); each is read after the
+ * step's own host synchronisation, so no extra wait is added.  on = 0 stops
+ * recording.  Errors: MSP_ERR_ARG (ctx NULL), MSP_ERR_HIP. */
+int msp_stage_set_timing(msp_ctx *ctx, int on);
+
+/* Sums over the Arnoldi steps of the last msp_solve with timing on (HOST
+ * outputs): ms[0] SpMV, ms[1] preconditioner apply (the captured graph, or
+ * the eager launches), ms[2] Gram-Schmidt step (dot products, reductions,
+ * updates, norm); calls[i] the number of steps summed.  Zero when timing was
+ * off.  Errors: MSP_ERR_ARG (a NULL pointer). */
+int msp_stage_get_timing(msp_ctx *ctx, double *ms, int *calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,9 @@ struct MspError {
     int code;
 };
 
+// parts of an FGMRES iteration timed by msp_stage_set_timing
+constexpr int kTimedParts = 3;  // 0 SpMV, 1 preconditioner apply, 2 Gram-Schmidt step
+
 [[noreturn]] void fail(int code) { throw MspError{code}; }
 [[noreturn]] void fail_hip(hipError_t e)
 {
@@ -174,6 +177,12 @@ struct msp_ctx {
     // adaptive state and statistics
     int it_prev = -1, setup_calls = 0, solves = 0;
     msp_info info{};
+    // optional HIP-event timing of the solve's parts (SpMV, preconditioner
+    // apply, Gram-Schmidt step): summed ms and counts over the last solve
+    bool timing = false;
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double t_ms[kTimedParts] = {0, 0, 0};
+    int t_calls[kTimedParts] = {0, 0, 0};
 
     void *dalloc(size_t bytes, std::vector<void *> &list)
     {
@@ -1268,6 +1277,10 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
     iters = 0;
     restarts = 0;
     relres = 0.0;
+    for (int q = 0; q < kTimedParts; ++q) {
+        c->t_ms[q] = 0.0;
+        c->t_calls[q] = 0;
+    }
     double bn2 = device_norm2(c, rhs, N);
     if (!std::isfinite(bn2)) return MSP_ERR_NONFINITE;
     const double bnorm = std::sqrt(bn2);
@@ -1295,8 +1308,11 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
         for (int j = 0; j < m; ++j) {
             double *vj = c->V + (size_t)j * N;
             double *zj = c->Z + (size_t)j * N;
+            if (c->timing) HIPCHK(hipEventRecord(c->tev[0], c->stream));
             apply(c, vj, zj);
+            if (c->timing) HIPCHK(hipEventRecord(c->tev[1], c->stream));
             spmv(c, zj, nullptr, c->w);
+            if (c->timing) HIPCHK(hipEventRecord(c->tev[2], c->stream));
             // classical Gram-Schmidt, twice
             HIPCHK(launch_dot_multi(N, j + 1, c->V, N, c->w, c->partial, c->stream));
             HIPCHK(launch_reduce_partials(j + 1, c->partial, h1, 0, c->stream));
@@ -1306,9 +1322,20 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
             HIPCHK(launch_axpy_multi(N, j + 1, c->V, N, h2, c->w, c->stream));
             HIPCHK(launch_dot_multi(N, 1, c->w, N, c->w, c->partial, c->stream));
             HIPCHK(launch_reduce_partials(1, c->partial, hn, 0, c->stream));
+            if (c->timing) HIPCHK(hipEventRecord(c->tev[3], c->stream));
             HIPCHK(hipMemcpyAsync(c->hhost, c->hbuf, sizeof(double) * (2 * (m + 1) + 1),
                                   hipMemcpyDeviceToHost, c->stream));
             c->sync();
+            if (c->timing) {
+                for (int q = 0; q < kTimedParts; ++q) {
+                    // events 0..3 bracket apply (0,1), SpMV (1,2), Gram-Schmidt (2,3)
+                    static const int a_[kTimedParts] = {1, 0, 2}, b_[kTimedParts] = {2, 1, 3};
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, c->tev[a_[q]], c->tev[b_[q]]));
+                    c->t_ms[q] += ms;
+                    c->t_calls[q]++;
+                }
+            }
             const double *hh1 = c->hhost, *hh2 = c->hhost + (m + 1);
             const double hnorm = std::sqrt(c->hhost[2 * (m + 1)]);
             if (!std::isfinite(hnorm)) return MSP_ERR_NONFINITE;
@@ -1519,6 +1546,7 @@ int msp_destroy(msp_ctx *c)
         kill_stream(c->cap_stream);
         kill_stream(c->chain_copy);
         kill_event(c->ev_a0);
+        for (auto &e : c->tev) kill_event(e);
         kill_stream(c->side);
         kill_stream(c->gj.aux);
         kill_stream(c->gj.main);
@@ -1981,3 +2009,24 @@ int msp_stage_repeat(msp_ctx *c, int stage, int reps, const double *in, double *
 }
 
 }  // extern "C"
+
+int msp_stage_set_timing(msp_ctx *c, int on)
+{
+    if (!c) return MSP_ERR_ARG;
+    return guarded([&] {
+        if (on && !c->tev[0])
+            for (auto &e : c->tev) HIPCHK(hipEventCreate(&e));
+        c->timing = on != 0;
+        return MSP_OK;
+    });
+}
+
+int msp_stage_get_timing(msp_ctx *c, double *ms, int *calls)
+{
+    if (!c || !ms || !calls) return MSP_ERR_ARG;
+    for (int q = 0; q < kTimedParts; ++q) {
+        ms[q] = c->t_ms[q];
+        calls[q] = c->t_calls[q];
+    }
+    return MSP_OK;
+}

@@ -82,6 +82,8 @@ SIGNATURES = {
     "msp_stage_get_bilu_f32": ([_vp, _vp, _vp], _i),
     "msp_stage_repeat": ([_vp, _i, _i, _vp, _vp], _i),
     "msp_stage_get_nstage": ([_vp, _vp, _vp], _i),
+    "msp_stage_set_timing": ([_vp, _i], _i),
+    "msp_stage_get_timing": ([_vp, C.POINTER(_d), C.POINTER(_i)], _i),
 }
 STAGE_SPMV, STAGE_GS0, STAGE_PRECOND, STAGE_BILU, STAGE_VCYCLE, STAGE_COARSE, STAGE_TRI_SWEEP = \
     range(7)
@@ -299,6 +301,17 @@ class Solver:
         with self.torch.cuda.device(self.device):
             _check(self._lib.msp_stage_repeat(self.h, int(stage), int(reps), p(inp), p(out)),
                    "repeat")
+
+    def set_timing(self, on=True):
+        """msp_stage_set_timing: HIP events around the parts of every Arnoldi step."""
+        _check(self._lib.msp_stage_set_timing(self.h, 1 if on else 0), "set_timing")
+
+    def timing(self):
+        """msp_stage_get_timing of the last solve: {part: (summed ms, steps)}."""
+        ms = (C.c_double * 3)()
+        calls = (C.c_int * 3)()
+        _check(self._lib.msp_stage_get_timing(self.h, ms, calls), "get_timing")
+        return {k: (ms[i], calls[i]) for i, k in enumerate(("spmv", "apply", "gram_schmidt"))}
 
     @property
     def nlevels(self):
