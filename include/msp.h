@@ -48,9 +48,14 @@ extern "C" {
 #define MSP_ERR_NO_DEVICE (-7) /* no usable GPU */
 #define MSP_ERR_STATE (-8)     /* solve or inspection before a successful setup */
 #define MSP_ERR_COARSE (-9)    /* coarsening stalled above the dense coarsest-level limit */
+#define MSP_ERR_SCRATCH (-10)  /* msp_solve_noalloc: the FGMRES workspace of this system does
+                                  not fit MSP_NOALLOC_SCRATCH_BYTES */
 #define MSP_NOT_CONVERGED 1    /* max_iter reached; x holds the last iterate, info is filled */
 
 #define MSP_MAX_LEVELS 25
+/* Size of the fixed per-GPU device scratch that msp_solve_noalloc takes its
+ * FGMRES workspace from (128 MiB). */
+#define MSP_NOALLOC_SCRATCH_BYTES (128ull << 20)
 #define MSP_MAX_BLOCK 8
 
 /* Solver options.  msp_default_options() fills the paper's settings
@@ -176,6 +181,27 @@ int msp_setup(struct msp_ctx *ctx, int n_block_rows, int block_size, int pressur
  * MSP_NOT_CONVERGED (x = last iterate), MSP_ERR_STATE (no setup),
  * MSP_ERR_NONFINITE (rhs), MSP_ERR_ARG, MSP_ERR_HIP. */
 int msp_solve(struct msp_ctx *ctx, const double *rhs, double *x, double rtol, msp_info *info);
+
+/* msp_solve for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, tight serving loops, harnesses that forbid it): the
+ * same solve, the same arguments, errors and result as msp_solve, but no
+ * device allocation of any kind.  The FGMRES workspace (basis V of restart+1
+ * vectors, directions Z of restart vectors, one more vector and the
+ * reduction buffers; about 8 (2 restart + 2) n b bytes) comes from one fixed
+ * per-GPU array of MSP_NOALLOC_SCRATCH_BYTES that the library holds from its
+ * load until the process ends; with restart = 30 it fits systems of up to
+ * about 260,000 unknowns.  The preconditioner apply replays the HIP graph of
+ * an earlier msp_solve if one exists, and is launched kernel by kernel
+ * otherwise (the same kernels, the same result).  The context's setup must
+ * already have been done with msp_setup, which does allocate.
+ * Every call on one GPU uses that GPU's single array and leaves its last
+ * contents there (nothing in it needs to start at zero): two calls that
+ * overlap in time on the same GPU, from any contexts or threads, race and
+ * give wrong results.  Callers serialise them.
+ * Errors: those of msp_solve, and MSP_ERR_SCRATCH when the workspace does not
+ * fit (nothing is launched then). */
+int msp_solve_noalloc(struct msp_ctx *ctx, const double *rhs, double *x, double rtol,
+                      msp_info *info);
 
 /* Statistics of the last setup/solve (host pointer). */
 int msp_get_info(struct msp_ctx *ctx, msp_info *info);

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <exception>
 #include <future>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <numeric>
@@ -119,6 +120,15 @@ struct BiluData {
 
 }  // namespace
 
+// FGMRES(m) workspace for N unknowns: the Arnoldi basis V (m+1 vectors),
+// the preconditioned directions Z (m vectors), the new direction w, the
+// per-block partial dot products, the Gram-Schmidt coefficients and norms, and
+// the least-squares solution y.
+struct Krylov {
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hbuf = nullptr,
+           *ydev = nullptr;
+};
+
 struct msp_ctx {
     msp_options opt{};
     int device = 0;
@@ -160,11 +170,10 @@ struct msp_ctx {
     // streams and events of the coarsest-level solver
     GjLookAhead gj{};
     hipGraphExec_t apply_exec = nullptr;
-    // krylov workspace
+    // krylov workspace (allocated by the first msp_solve of a size)
     long long wsN = 0;
     int wsm = 0;
-    double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hbuf = nullptr,
-           *ydev = nullptr, *tmpN = nullptr, *tmpN2 = nullptr;
+    Krylov kw{};
     double *hhost = nullptr;  // pinned
     int *flag = nullptr, *flag_host = nullptr;
     int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
@@ -1219,9 +1228,9 @@ void capture_apply(msp_ctx *c)
     }
 }
 
-void apply(msp_ctx *c, const double *v, double *z)
+void apply(msp_ctx *c, const double *v, double *z, bool capture_ok = true)
 {
-    if (!c->opt.use_graphs) {
+    if (!c->opt.use_graphs || (!c->apply_exec && !capture_ok)) {
         apply_eager(c, v, z);
         return;
     }
@@ -1240,40 +1249,76 @@ void spmv(msp_ctx *c, const double *x, const double *sub, double *y)
 // --------------------------------------------------------------------------
 // FGMRES
 // --------------------------------------------------------------------------
+// Sub-buffer sizes of a Krylov workspace, in doubles, each rounded up to a
+// multiple of 32 (256 bytes): V, Z, w, partial, hbuf, ydev.
+void krylov_sizes(long long N, int m, size_t sz[6])
+{
+    auto r = [](long long d) { return (size_t)((d + 31) & ~31LL); };
+    sz[0] = r(N * (m + 1));
+    sz[1] = r(N * m);
+    sz[2] = r(N);
+    sz[3] = r((long long)kDotBlocks * (m + 2));
+    sz[4] = r(2 * (m + 2) + 2);
+    sz[5] = r(m + 1);
+}
+
+size_t krylov_bytes(long long N, int m)
+{
+    size_t sz[6], t = 0;
+    krylov_sizes(N, m, sz);
+    for (size_t v : sz) t += v;
+    return t * sizeof(double);
+}
+
+// Carve a Krylov workspace out of one device region of krylov_bytes(N, m).
+Krylov krylov_carve(double *base, long long N, int m)
+{
+    size_t sz[6];
+    krylov_sizes(N, m, sz);
+    double *ptrs[6];
+    for (int i = 0; i < 6; ++i) {
+        ptrs[i] = base;
+        base += sz[i];
+    }
+    Krylov K;
+    K.V = ptrs[0];
+    K.Z = ptrs[1];
+    K.w = ptrs[2];
+    K.partial = ptrs[3];
+    K.hbuf = ptrs[4];
+    K.ydev = ptrs[5];
+    return K;
+}
+
 void ensure_workspace(msp_ctx *c)
 {
     const long long N = (long long)c->n * c->b;
     const int m = c->opt.restart;
     if (c->wsN == N && c->wsm == m) return;
     c->release(c->allocW);
-    c->V = (double *)c->dalloc(sizeof(double) * (size_t)N * (m + 1), c->allocW);
-    c->Z = (double *)c->dalloc(sizeof(double) * (size_t)N * m, c->allocW);
-    c->w = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
-    c->tmpN = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
-    c->tmpN2 = (double *)c->dalloc(sizeof(double) * (size_t)N, c->allocW);
-    c->partial = (double *)c->dalloc(sizeof(double) * (size_t)kDotBlocks * (m + 2), c->allocW);
-    c->hbuf = (double *)c->dalloc(sizeof(double) * (size_t)(2 * (m + 2) + 2), c->allocW);
-    c->ydev = (double *)c->dalloc(sizeof(double) * (size_t)(m + 1), c->allocW);
+    c->kw = krylov_carve((double *)c->dalloc(krylov_bytes(N, m), c->allocW), N, m);
     c->wsN = N;
     c->wsm = m;
 }
 
 // sum_i x_i^2 on the device, returned to the host
-double device_norm2(msp_ctx *c, const double *x, long long N)
+double device_norm2(msp_ctx *c, const Krylov &K, const double *x, long long N)
 {
-    HIPCHK(launch_dot_multi(N, 1, x, N, x, c->partial, c->stream));
-    HIPCHK(launch_reduce_partials(1, c->partial, c->hbuf, 0, c->stream));
-    HIPCHK(hipMemcpyAsync(c->hhost, c->hbuf, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(launch_dot_multi(N, 1, x, N, x, K.partial, c->stream));
+    HIPCHK(launch_reduce_partials(1, K.partial, K.hbuf, 0, c->stream));
+    HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     c->sync();
     return c->hhost[0];
 }
 
-int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, int &restarts,
-           double &relres)
+// One FGMRES(m) solve (Sec. 5) with the workspace K.  graph_ok = false keeps
+// the preconditioner apply eager unless its graph already exists, so the
+// solve itself creates nothing on the device.
+int fgmres(msp_ctx *c, const Krylov &K, bool graph_ok, const double *rhs, double *x,
+           double rtol, int &iters, int &restarts, double &relres)
 {
     const long long N = (long long)c->n * c->b;
     const int m = c->opt.restart;
-    ensure_workspace(c);
     iters = 0;
     restarts = 0;
     relres = 0.0;
@@ -1281,7 +1326,7 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
         c->t_ms[q] = 0.0;
         c->t_calls[q] = 0;
     }
-    double bn2 = device_norm2(c, rhs, N);
+    double bn2 = device_norm2(c, K, rhs, N);
     if (!std::isfinite(bn2)) return MSP_ERR_NONFINITE;
     const double bnorm = std::sqrt(bn2);
     if (bnorm == 0.0) {
@@ -1291,39 +1336,39 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
     }
     const double tol = rtol * bnorm;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-    spmv(c, x, rhs, c->w);
-    double beta = std::sqrt(device_norm2(c, c->w, N));
+    spmv(c, x, rhs, K.w);
+    double beta = std::sqrt(device_norm2(c, K, K.w, N));
     if (!std::isfinite(beta)) return MSP_ERR_NONFINITE;
     int status = MSP_OK;
-    double *h1 = c->hbuf, *h2 = c->hbuf + (m + 1), *hn = c->hbuf + 2 * (m + 1);
+    double *h1 = K.hbuf, *h2 = K.hbuf + (m + 1), *hn = K.hbuf + 2 * (m + 1);
     while (beta > tol) {
         if (iters >= c->opt.max_iter) {
             status = MSP_NOT_CONVERGED;
             break;
         }
-        HIPCHK(launch_scale(N, c->w, beta, c->V, c->stream));
+        HIPCHK(launch_scale(N, K.w, beta, K.V, c->stream));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            double *vj = c->V + (size_t)j * N;
-            double *zj = c->Z + (size_t)j * N;
+            double *vj = K.V + (size_t)j * N;
+            double *zj = K.Z + (size_t)j * N;
             if (c->timing) HIPCHK(hipEventRecord(c->tev[0], c->stream));
-            apply(c, vj, zj);
+            apply(c, vj, zj, graph_ok);
             if (c->timing) HIPCHK(hipEventRecord(c->tev[1], c->stream));
-            spmv(c, zj, nullptr, c->w);
+            spmv(c, zj, nullptr, K.w);
             if (c->timing) HIPCHK(hipEventRecord(c->tev[2], c->stream));
             // classical Gram-Schmidt, twice
-            HIPCHK(launch_dot_multi(N, j + 1, c->V, N, c->w, c->partial, c->stream));
-            HIPCHK(launch_reduce_partials(j + 1, c->partial, h1, 0, c->stream));
-            HIPCHK(launch_axpy_multi(N, j + 1, c->V, N, h1, c->w, c->stream));
-            HIPCHK(launch_dot_multi(N, j + 1, c->V, N, c->w, c->partial, c->stream));
-            HIPCHK(launch_reduce_partials(j + 1, c->partial, h2, 0, c->stream));
-            HIPCHK(launch_axpy_multi(N, j + 1, c->V, N, h2, c->w, c->stream));
-            HIPCHK(launch_dot_multi(N, 1, c->w, N, c->w, c->partial, c->stream));
-            HIPCHK(launch_reduce_partials(1, c->partial, hn, 0, c->stream));
+            HIPCHK(launch_dot_multi(N, j + 1, K.V, N, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(j + 1, K.partial, h1, 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, j + 1, K.V, N, h1, K.w, c->stream));
+            HIPCHK(launch_dot_multi(N, j + 1, K.V, N, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(j + 1, K.partial, h2, 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, j + 1, K.V, N, h2, K.w, c->stream));
+            HIPCHK(launch_dot_multi(N, 1, K.w, N, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(1, K.partial, hn, 0, c->stream));
             if (c->timing) HIPCHK(hipEventRecord(c->tev[3], c->stream));
-            HIPCHK(hipMemcpyAsync(c->hhost, c->hbuf, sizeof(double) * (2 * (m + 1) + 1),
+            HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double) * (2 * (m + 1) + 1),
                                   hipMemcpyDeviceToHost, c->stream));
             c->sync();
             if (c->timing) {
@@ -1357,7 +1402,7 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
             ++iters;
             k = j + 1;
             if (hnorm == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c->opt.max_iter) break;
-            HIPCHK(launch_scale(N, c->w, hnorm, c->V + (size_t)(j + 1) * N, c->stream));
+            HIPCHK(launch_scale(N, K.w, hnorm, K.V + (size_t)(j + 1) * N, c->stream));
         }
         for (int i = k - 1; i >= 0; --i) {
             double acc = g[i];
@@ -1365,11 +1410,11 @@ int fgmres(msp_ctx *c, const double *rhs, double *x, double rtol, int &iters, in
             y[i] = acc / H[(size_t)i * m + i];
         }
         std::memcpy(c->hhost + 2 * (m + 2), y.data(), sizeof(double) * k);
-        HIPCHK(hipMemcpyAsync(c->ydev, c->hhost + 2 * (m + 2), sizeof(double) * k,
+        HIPCHK(hipMemcpyAsync(K.ydev, c->hhost + 2 * (m + 2), sizeof(double) * k,
                               hipMemcpyHostToDevice, c->stream));
-        HIPCHK(launch_update_x(N, k, c->Z, N, c->ydev, x, c->stream));
-        spmv(c, x, rhs, c->w);
-        beta = std::sqrt(device_norm2(c, c->w, N));
+        HIPCHK(launch_update_x(N, k, K.Z, N, K.ydev, x, c->stream));
+        spmv(c, x, rhs, K.w);
+        beta = std::sqrt(device_norm2(c, K, K.w, N));
         ++restarts;
     }
     relres = beta / bnorm;
@@ -1454,6 +1499,69 @@ void stage_bilu_T(msp_ctx *c, const double *r, double *z)
     HIPCHK(launch_to_double<T>(N, (const T *)c->ybuf, z, c->stream));
 }
 
+// Run one FGMRES solve through `run` and record its outcome in the context
+// (iteration count for the adaptive setup, info, timing).
+template <typename F>
+int finish_solve(msp_ctx *c, msp_info *info, F &&run)
+{
+    const double t0 = now_ms();
+    int iters = 0, restarts = 0;
+    double relres = 0.0;
+    int st = guarded([&]() { return run(iters, restarts, relres); });
+    c->info.status = st;
+    c->info.iterations = iters;
+    c->info.restarts = restarts;
+    c->info.rel_true_residual = relres;
+    c->info.solve_ms = now_ms() - t0;
+    c->solves++;
+    c->info.solves = c->solves;
+    c->it_prev = iters;
+    if (info) *info = c->info;
+    return st;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// Fixed device scratch of msp_solve_noalloc: the FGMRES workspace of solves
+// that may not allocate.  One copy per GPU, held from the library's load until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host that name is only a stand-in for the symbol): it passes the device
+// address found by hipGetSymbolAddress once per device, in msp_create.
+// --------------------------------------------------------------------------
+constexpr size_t kScratchBytes = MSP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Look up (once per device, with `dev` current) the device address of this
+// GPU's copy of `scratch`.  Returns MSP_OK or MSP_ERR_HIP.
+int init_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return MSP_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return MSP_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return MSP_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+    return MSP_OK;
+}
+
+double *scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -1500,6 +1608,7 @@ int msp_create(msp_ctx **ctx, const msp_options *opt)
     c->opt = o;
     int st = guarded([&]() {
         HIPCHK(hipGetDevice(&c->device));
+        if (int e = init_scratch(c->device)) return e;
         c->stream = (hipStream_t)o.stream;
         HIPCHK(hipHostMalloc((void **)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault));
@@ -1666,20 +1775,24 @@ int msp_solve(msp_ctx *c, const double *rhs, double *x, double rtol, msp_info *i
 {
     if (!c || !rhs || !x || !(rtol > 0.0)) return MSP_ERR_ARG;
     if (!c->hasB || !c->haveA) return MSP_ERR_STATE;
-    const double t0 = now_ms();
-    int iters = 0, restarts = 0;
-    double relres = 0.0;
-    int st = guarded([&]() { return fgmres(c, rhs, x, rtol, iters, restarts, relres); });
-    c->info.status = st;
-    c->info.iterations = iters;
-    c->info.restarts = restarts;
-    c->info.rel_true_residual = relres;
-    c->info.solve_ms = now_ms() - t0;
-    c->solves++;
-    c->info.solves = c->solves;
-    c->it_prev = iters;
-    if (info) *info = c->info;
-    return st;
+    return finish_solve(c, info, [&](int &iters, int &restarts, double &relres) {
+        ensure_workspace(c);
+        return fgmres(c, c->kw, true, rhs, x, rtol, iters, restarts, relres);
+    });
+}
+
+int msp_solve_noalloc(msp_ctx *c, const double *rhs, double *x, double rtol, msp_info *info)
+{
+    if (!c || !rhs || !x || !(rtol > 0.0)) return MSP_ERR_ARG;
+    if (!c->hasB || !c->haveA) return MSP_ERR_STATE;
+    const long long N = (long long)c->n * c->b;
+    if (krylov_bytes(N, c->opt.restart) > kScratchBytes) return MSP_ERR_SCRATCH;
+    double *base = scratch_ptr(c->device);
+    if (!base) return MSP_ERR_HIP;
+    const Krylov K = krylov_carve(base, N, c->opt.restart);
+    return finish_solve(c, info, [&](int &iters, int &restarts, double &relres) {
+        return fgmres(c, K, false, rhs, x, rtol, iters, restarts, relres);
+    });
 }
 
 int msp_get_info(msp_ctx *c, msp_info *info)
@@ -1725,6 +1838,8 @@ const char *msp_status_string(int s)
     case MSP_ERR_NO_DEVICE: return "no GPU device";
     case MSP_ERR_STATE: return "no preconditioner: call msp_setup first";
     case MSP_ERR_COARSE: return "coarsest level exceeds the dense limit";
+    case MSP_ERR_SCRATCH:
+        return "the solve needs more than the fixed scratch of msp_solve_noalloc";
     case MSP_NOT_CONVERGED: return "not converged within max_iter";
     default: return "unknown status";
     }

@@ -20,7 +20,8 @@ MSP_OK = 0
 MSP_NOT_CONVERGED = 1
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_PATTERN", -3: "ERR_SINGULAR", -4: "ERR_NONFINITE",
           -5: "ERR_NOMEM", -6: "ERR_HIP", -7: "ERR_NO_DEVICE", -8: "ERR_STATE",
-          -9: "ERR_COARSE", 1: "NOT_CONVERGED"}
+          -9: "ERR_COARSE", -10: "ERR_SCRATCH", 1: "NOT_CONVERGED"}
+NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_LEVELS = 25
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -64,6 +65,7 @@ SIGNATURES = {
     "msp_create": ([C.POINTER(_vp), C.POINTER(MspOptions)], _i),
     "msp_setup": ([_vp, _i, _i, _i, _vp, _vp, _vp, _ll], _i),
     "msp_solve": ([_vp, _vp, _vp, _d, C.POINTER(MspInfo)], _i),
+    "msp_solve_noalloc": ([_vp, _vp, _vp, _d, C.POINTER(MspInfo)], _i),
     "msp_get_info": ([_vp, C.POINTER(MspInfo)], _i),
     "msp_footprint": ([_i, _ll, _i, C.POINTER(MspOptions), C.POINTER(C.c_size_t)], _i),
     "msp_destroy": ([_vp], _i),
@@ -246,16 +248,18 @@ class Solver:
         self.n, self.b, self.p = int(n), int(b), int(p)
         return self.info()["rebuilt"]
 
-    def solve(self, rhs, x=None, rtol=1e-6):
-        """msp_solve; returns (x, info dict).  x is updated in place if given."""
+    def solve(self, rhs, x=None, rtol=1e-6, noalloc=False):
+        """msp_solve (msp_solve_noalloc if noalloc); returns (x, info dict).
+        x is updated in place if given."""
         t = self.torch
         rhs = self._dev(rhs, t.float64)
         if x is None:
             x = t.zeros_like(rhs)
         info = MspInfo()
+        fn = self._lib.msp_solve_noalloc if noalloc else self._lib.msp_solve
         with t.cuda.device(self.device):
-            code = self._lib.msp_solve(self.h, _ptr(rhs), _ptr(x), float(rtol), C.byref(info))
-        _check(code, "solve")
+            code = fn(self.h, _ptr(rhs), _ptr(x), float(rtol), C.byref(info))
+        _check(code, "solve_noalloc" if noalloc else "solve")
         d = info.as_dict()
         d["status"] = code
         return x, d
