@@ -205,6 +205,7 @@ class Solver:
         self.h = h
         self.n = self.b = self.p = None
         self.precond_fp32 = bool(precond_fp32)
+        self.bilu_order = int(bilu_order)
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
