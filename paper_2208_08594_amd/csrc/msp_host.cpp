@@ -117,9 +117,103 @@ Adjacency build_adjacency(int n, const int *rp, const int *ci, bool known_symmet
     return G;
 }
 
+// Alg. 4.2 on a bipartite graph, in closed form.  Let C be a connected
+// component with an edge, A its side holding its best vertex (largest
+// degree, lowest index), B the other side.  Group 1 is the union of the A
+// sides and of the isolated vertices, group 2 the union of the B sides:
+//  - a new seed is taken only when no second-ring candidate is open, and it
+//    is the best open vertex; a component is untouched until its first
+//    seed, so that seed is its best vertex, on side A;
+//  - the second ring of a vertex of A lies in A, so every later pick of
+//    the component is in A (by induction), and a vertex of A, never adjacent
+//    to another, leaves V only by being picked;
+//  - every unpicked vertex a of A is a second-ring candidate of an earlier
+//    pick: on a path from the seed to a alternating between the sides, the
+//    first unpicked vertex of A is in the second ring of the vertex of A
+//    before it.  So the component's A is picked whole before the next seed;
+//    each vertex of B then has a picked neighbour and has left V;
+//  - in group 2 the remaining vertices (the B sides) are independent, so
+//    all of them are picked.
+// An isolated vertex is picked in group 1 as a seed.  Returns false (and
+// leaves color alone) when G has an odd cycle; sets g = 2, or 1 when G has
+// no edges.
+static bool bipartite_groups(const Adjacency &G, std::vector<int> &color, int &g)
+{
+    // 2-colouring by a union-find over the edges in natural order (which
+    // reads the neighbour lists sequentially): side[v] is v's parity relative
+    // to its parent; every root is the lowest vertex of its set
+    const int n = G.n;
+    std::vector<int> parent(n);
+    std::vector<unsigned char> side(n, 0);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int v, unsigned char &par) {
+        unsigned char p = 0;
+        int r = v;
+        while (parent[r] != r) {
+            p ^= side[r];
+            r = parent[r];
+        }
+        // compress: every vertex on the path points at the root
+        unsigned char q = p;
+        while (parent[v] != r) {
+            const int nx = parent[v];
+            const unsigned char s = side[v];
+            parent[v] = r;
+            side[v] = q;
+            q ^= s;
+            v = nx;
+        }
+        par = p;
+        return r;
+    };
+    bool edges = false;
+    for (int u = 0; u < n; ++u) {
+        const int q0 = G.ptr[u], q1 = G.ptr[u + 1];
+        if (q0 == q1 || G.nbr[q0] >= u) continue;  // no lower neighbour
+        edges = true;
+        unsigned char pu;
+        int ru = find(u, pu);  // kept current as u's set is merged below
+        for (int q = q0; q < q1; ++q) {
+            const int w = G.nbr[q];
+            if (w >= u) break;  // neighbour lists ascend: each edge once
+            unsigned char pw;
+            const int rw = find(w, pw);
+            if (ru == rw) {
+                if (pu == pw) return false;  // odd cycle
+            } else if (ru < rw) {
+                parent[rw] = ru;
+                side[rw] = pu ^ pw ^ 1;
+            } else {
+                parent[ru] = rw;
+                side[ru] = pu ^ pw ^ 1;
+                pu ^= side[ru];
+                ru = rw;
+            }
+        }
+    }
+    // best vertex (largest degree, lowest index) of every component, and
+    // its parity
+    std::vector<int> best(n, -1);
+    std::vector<unsigned char> par(n);
+    for (int v = 0; v < n; ++v) {
+        const int r = find(v, par[v]);
+        const int b = best[r];
+        if (b < 0 || G.degree(v) > G.degree(b)) best[r] = v;  // v ascends: ties keep b
+    }
+    color.assign(n, 0);
+    for (int v = 0; v < n; ++v) {
+        const int r = parent[v];  // compressed above: the root
+        color[v] = par[v] == par[best[r]] ? 1 : 2;
+    }
+    g = edges ? 2 : 1;
+    return true;
+}
+
 int vertices_grouping(const Adjacency &G, std::vector<int> &color)
 {
     const int n = G.n;
+    int g_bip = 0;
+    if (bipartite_groups(G, color, g_bip)) return g_bip;
     color.assign(n, 0);
     // Static priority: larger |S_i| first, smaller index on ties (Alg. 4.1 picks
     // any vertex of maximal |S_i|; the lowest index makes the choice unique).

@@ -188,6 +188,77 @@ def test_library_grouping_large_symmetric_matches_oracle(shim, n):
     assert g_lib == g_or and np.array_equal(c_lib, c_or)
 
 
+def _pattern_from_edges(n, i, j, symmetric=True):
+    """CSR pattern with a diagonal from an edge list (both directions if
+    symmetric)."""
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    if symmetric:
+        i, j = np.concatenate([i, j]), np.concatenate([j, i])
+    key = np.unique(np.concatenate([i * n + j, np.arange(n) * (n + 1)]))
+    r, c = key // n, key % n
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp).astype(np.int32), c.astype(np.int32)
+
+
+def _bipartite_cases():
+    rng = np.random.default_rng(41)
+    cases = []
+    for shape in [(7, 5, 3), (16, 9, 1), (1, 1, 30), (12, 12, 12)]:
+        s = synth.lognormal_grid(*shape, 1, 0, 1.0, 1.0, "none")
+        cases.append((f"grid{shape}", s.row_ptr, s.col_ind))
+    # random bipartite graphs with several components and isolated vertices;
+    # vertex ids shuffled so that sides, components and degrees interleave
+    for n in (60, 500, 3000):
+        perm = rng.permutation(n)
+        half = n // 2
+        m = 3 * n
+        a = rng.integers(0, half, m)
+        b = half + rng.integers(0, n - half, m)
+        # cut the graph into components by residue of the side-A end
+        keep = (a % 3) == (b % 3)
+        a, b = perm[a[keep]], perm[b[keep]]
+        iso = perm[rng.choice(n, n // 20, replace=False)]
+        sel = ~np.isin(a, iso) & ~np.isin(b, iso)
+        rp, ci = _pattern_from_edges(n, a[sel], b[sel])
+        cases.append((f"random-bipartite-{n}", rp, ci))
+    # a star, a single edge, and no edges at all
+    cases.append(("star", *_pattern_from_edges(9, np.zeros(8, int), np.arange(1, 9))))
+    cases.append(("edge", *_pattern_from_edges(2, [0], [1])))
+    cases.append(("no-edges", *_pattern_from_edges(5, [], [])))
+    # nonsymmetric stored pattern whose symmetrisation is bipartite
+    rp, ci = _pattern_from_edges(40, np.arange(0, 38, 2), np.arange(1, 39, 2), symmetric=False)
+    cases.append(("nonsymmetric-chain", rp, ci))
+    return cases
+
+
+@pytest.mark.parametrize("case", _bipartite_cases(), ids=lambda c: c[0])
+def test_library_grouping_of_bipartite_graphs_matches_oracle(shim, case):
+    """Bipartite adjacency graphs take the library's closed form of Alg. 4.2
+    (each component's side holding its best vertex first, the other sides
+    second); the groups must equal the oracle's greedy bit for bit."""
+    name, rp, ci = case
+    c_lib, g_lib = _lib_color(shim, rp, ci)
+    c_or, g_or = O.color(rp, ci)
+    assert g_lib == g_or and np.array_equal(c_lib, c_or), name
+    assert g_or <= 2
+
+
+def test_library_grouping_with_one_odd_cycle_matches_oracle(shim):
+    """A grid with one extra edge closing an odd cycle is not bipartite: the
+    library falls back to the greedy, which must still equal the oracle."""
+    s = synth.lognormal_grid(9, 8, 3, 1, 0, 1.0, 1.0, "none")
+    n = s.n
+    rows = np.repeat(np.arange(n), np.diff(s.row_ptr))
+    rp, ci = _pattern_from_edges(n, np.concatenate([rows, [0]]),
+                                 np.concatenate([s.col_ind, [10]]))  # 0 and 10: even distance
+    c_lib, g_lib = _lib_color(shim, rp, ci)
+    c_or, g_or = O.color(rp, ci)
+    assert g_or >= 3
+    assert g_lib == g_or and np.array_equal(c_lib, c_or)
+
+
 def test_library_hierarchy_steps_match_oracle(shim):
     for sys, mc in [(synth.config(0), 64), (synth.lognormal_grid(20, 18, 9, 3, 5, 1.5, 0.1,
                                                                   "lateral4"), 200)]:
