@@ -26,6 +26,19 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Work-groups are dispatched to the 8 XCDs round-robin (work-group b to XCD
+// b mod 8), and each XCD has its own L2.  xcd_block maps the dispatch order
+// to a logical index so that every XCD works on one contiguous range of
+// logical work-groups: neighbouring slices, which gather the same x entries,
+// then share an L2.  It is a bijection on [0, nb): XCD x receives
+// q + (x < r) work-groups (q = nb / 8, r = nb mod 8), at logical indices
+// x q + min(x, r) onwards.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 inline unsigned blocks_for(long long work, int per_block = kThreads)
 {
     long long b = (work + per_block - 1) / per_block;
@@ -375,7 +388,12 @@ __global__ __launch_bounds__(64) void k_bilu_factor(BiluTasks t, double *__restr
 }
 
 // ---------------------------------------------------------------------------
-// block SpMV (FP64), one thread per block row of a 64-row slice
+// block SpMV (FP64), one thread per block row of a 64-row slice.  The matrix
+// values and column indices are read once per SpMV, so they are loaded
+// non-temporally (they do not displace the x entries that neighbouring rows
+// gather again).  A padding slot (column -1, value 0) reads the row's own x
+// block and adds nothing: no branch per entry, so the loads of consecutive
+// entries issue back to back.
 // ---------------------------------------------------------------------------
 template <int B>
 __global__ __launch_bounds__(kThreads) void k_spmv(const int4 *__restrict__ slices,
@@ -386,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int4 *__restrict__ slic
                                                    double *__restrict__ y)
 {
     constexpr int E = B * B;
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -397,26 +415,21 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int4 *__restrict__ slic
     for (int r = 0; r < B; ++r) acc[r] = 0.0;
     const int *cb = col + d.w + lane;
     const double *vb = val + (long long)(d.w >> 6) * 64 * E + lane;
-    // the column indices of a batch of 8 entries load together, then the
-    // entries' blocks and x-blocks (one round trip for the indices per batch)
-    for (int k0 = 0; k0 < d.z; k0 += 8) {
-        int cc[8];
+    for (int k = 0; k < d.z; ++k) {
+        const int c = __builtin_nontemporal_load(cb + k * 64);
+        const long long cs = c >= 0 ? c : row;
+        double xv[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = cc[q];
-            if (c >= 0) {
-                double xv[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) xv[u] = x[(long long)c * B + u];
-                const double *v = vb + (long long)(k0 + q) * 64 * E;
-#pragma unroll
-                for (int r = 0; r < B; ++r)
-#pragma unroll
-                    for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * xv[u];
-            }
+        for (int u = 0; u < B; ++u) {
+            const double t = x[cs * B + u];
+            xv[u] = c >= 0 ? t : 0.0;
         }
+        const double *v = vb + (long long)k * 64 * E;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                acc[r] += __builtin_nontemporal_load(v + (r * B + u) * 64) * xv[u];
     }
 #pragma unroll
     for (int r = 0; r < B; ++r)
@@ -469,8 +482,8 @@ __device__ inline T sell_row_dot(const int *__restrict__ cb, const T *__restrict
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const bool in = k0 + u < width;
-            c[u] = in ? cb[(k0 + u) * 64] : -1;
-            v[u] = in ? vb[(k0 + u) * 64] : T(0);
+            c[u] = in ? __builtin_nontemporal_load(cb + (k0 + u) * 64) : -1;
+            v[u] = in ? __builtin_nontemporal_load(vb + (k0 + u) * 64) : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
@@ -488,7 +501,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_color(const int4 *__restrict__ 
                                                        const T *__restrict__ diag,
                                                        const T *__restrict__ f, T *x)
 {
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -508,7 +521,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int4 *__restrict__ 
                                                        const T *__restrict__ x,
                                                        T *__restrict__ r)
 {
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -621,7 +634,7 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
     const double *__restrict__ v, const T *__restrict__ e, T *__restrict__ r)
 {
     constexpr int E = B * B;
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -635,7 +648,8 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
         int cc[8];
         T ev[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
+        for (int u = 0; u < 8; ++u)
+            cc[u] = k0 + u < d.z ? __builtin_nontemporal_load(cb + (k0 + u) * 64) : -1;
 #pragma unroll
         for (int u = 0; u < 8; ++u) ev[u] = cc[u] >= 0 ? e[cc[u]] : T(0);
 #pragma unroll
@@ -647,9 +661,9 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
             for (int q = 0; q < B; ++q) {
                 T a;
                 if (F32)
-                    a = (T)pcol32[sb * 64 * B + q * 64 + lane];
+                    a = (T)__builtin_nontemporal_load(pcol32 + sb * 64 * B + q * 64 + lane);
                 else
-                    a = (T)val64[sb * 64 * E + (q * B + p) * 64 + lane];
+                    a = (T)__builtin_nontemporal_load(val64 + sb * 64 * E + (q * B + p) * 64 + lane);
                 acc[q] += a * ec;
             }
         }
@@ -658,6 +672,11 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
     for (int q = 0; q < B; ++q) r[row * B + q] = (T)v[row * B + q] - acc[q];
 }
 
+// Block ILU(0) triangular solves, one dependency level per launch, one
+// thread per block row of a 64-row slice.  As in k_spmv: the factor values
+// and column indices are read once per solve (non-temporal loads), padding
+// slots read the row's own block and add nothing, and slices are assigned to
+// XCDs in contiguous ranges.
 template <int B, typename T>
 __global__ __launch_bounds__(kThreads) void k_bilu_fwd(const int4 *__restrict__ slices,
                                                        const int *__restrict__ col, int s0,
@@ -665,7 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_bilu_fwd(const int4 *__restrict__ 
                                                        const T *__restrict__ Lval, T *y)
 {
     constexpr int E = B * B;
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -676,24 +695,21 @@ __global__ __launch_bounds__(kThreads) void k_bilu_fwd(const int4 *__restrict__ 
     for (int r = 0; r < B; ++r) acc[r] = 0;
     const int *cb = col + d.w + lane;
     const T *vb = Lval + (long long)(d.w >> 6) * 64 * E + lane;
-    for (int k0 = 0; k0 < d.z; k0 += 8) {  // column indices in batches of 8
-        int cc[8];
+    for (int k = 0; k < d.z; ++k) {
+        const int c = __builtin_nontemporal_load(cb + k * 64);
+        const long long cs = c >= 0 ? c : i;
+        T yk[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = cc[q];
-            if (c >= 0) {
-                T yk[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) yk[u] = y[(long long)c * B + u];
-                const T *v = vb + (long long)(k0 + q) * 64 * E;
-#pragma unroll
-                for (int r = 0; r < B; ++r)
-#pragma unroll
-                    for (int u = 0; u < B; ++u) acc[r] += v[(r * B + u) * 64] * yk[u];
-            }
+        for (int u = 0; u < B; ++u) {
+            const T t = y[cs * B + u];
+            yk[u] = c >= 0 ? t : T(0);
         }
+        const T *v = vb + (long long)k * 64 * E;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                acc[r] += __builtin_nontemporal_load(v + (r * B + u) * 64) * yk[u];
     }
 #pragma unroll
     for (int r = 0; r < B; ++r) y[i * B + r] = y[i * B + r] - acc[r];
@@ -707,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
                                                        const T *__restrict__ Dval, T *z)
 {
     constexpr int E = B * B;
-    const int s = s0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
     const int4 d = slices[s];
@@ -718,26 +734,22 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
     for (int r = 0; r < B; ++r) t[r] = z[i * B + r];
     const int *cb = col + d.w + lane;
     const T *vb = Uval + (long long)(d.w >> 6) * 64 * E + lane;
-    for (int k0 = 0; k0 < d.z; k0 += 8) {  // column indices in batches of 8
-        int cc[8];
+    for (int k = 0; k < d.z; ++k) {
+        const int c = __builtin_nontemporal_load(cb + k * 64);
+        const long long cs = c >= 0 ? c : i;
+        T zk[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cc[u] = k0 + u < d.z ? cb[(k0 + u) * 64] : -1;
+        for (int u = 0; u < B; ++u) {
+            const T w = z[cs * B + u];
+            zk[u] = c >= 0 ? w : T(0);
+        }
+        const T *v = vb + (long long)k * 64 * E;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = cc[q];
-            if (c >= 0) {
-                T zk[B];
+        for (int r = 0; r < B; ++r) {
+            T a = 0;
 #pragma unroll
-                for (int u = 0; u < B; ++u) zk[u] = z[(long long)c * B + u];
-                const T *v = vb + (long long)(k0 + q) * 64 * E;
-#pragma unroll
-                for (int r = 0; r < B; ++r) {
-                    T a = 0;
-#pragma unroll
-                    for (int u = 0; u < B; ++u) a += v[(r * B + u) * 64] * zk[u];
-                    t[r] -= a;
-                }
-            }
+            for (int u = 0; u < B; ++u) a += __builtin_nontemporal_load(v + (r * B + u) * 64) * zk[u];
+            t[r] -= a;
         }
     }
     const T *D = Dval + (long long)s * 64 * E + lane;
@@ -745,7 +757,7 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
     for (int r = 0; r < B; ++r) {
         T a = 0;
 #pragma unroll
-        for (int u = 0; u < B; ++u) a += D[(r * B + u) * 64] * t[u];
+        for (int u = 0; u < B; ++u) a += __builtin_nontemporal_load(D + (r * B + u) * 64) * t[u];
         z[i * B + r] = a;
     }
 }
