@@ -60,6 +60,7 @@ struct DevSell {
     int4 *slices = nullptr;
     int *col = nullptr;
     int *src = nullptr;
+    int lanes = 1;  // lanes per row of the scalar sweep and residual kernels
     SellView view(int seg) const
     {
         SellView v;
@@ -67,6 +68,7 @@ struct DevSell {
         v.col = col;
         v.slice_begin = lay.seg_slice[seg];
         v.slice_end = lay.seg_slice[seg + 1];
+        v.lanes = lanes;
         return v;
     }
     SellView all() const
@@ -76,6 +78,7 @@ struct DevSell {
         v.col = col;
         v.slice_begin = 0;
         v.slice_end = (int)lay.slice_row0.size();
+        v.lanes = lanes;
         return v;
     }
     int nseg() const { return (int)lay.seg_slice.size() - 1; }
@@ -403,6 +406,18 @@ void level_layout(int n, const int *rp, const int *ci, const double *val,
     }
 }
 
+// Lanes per row for the sweeps and residuals of a smoothed level.  A level
+// whose rows hold more stored entries than one batch of loads (the coarse
+// levels: up to a few dozen) spreads each row over kRowLanes lanes, so a
+// sweep's chain of dependent loads is one batch long; short rows (the 7-point
+// level 0) keep one thread per row, which moves the fewest bytes.
+int row_lanes(const SellLayout &lay)
+{
+    int w = 0;
+    for (int x : lay.slice_width) w = std::max(w, x);
+    return w > 8 ? kRowLanes : 1;
+}
+
 // Device arrays of level l (its layout computed by level_layout unless it is
 // the coarsest level, whose positions are the natural order).
 void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
@@ -424,6 +439,7 @@ void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
     L.iperm = std::move(lay->iperm);
     L.seg_row = std::move(lay->seg_row);
     L.S.lay = std::move(lay->lay);
+    L.S.lanes = row_lanes(L.S.lay);
     upload_sell(c, L.S, c->allocB);
     if (c->fp32()) {
         L.val32 = c->upload(lay->v32, c->allocB);
@@ -1358,14 +1374,25 @@ int fgmres(msp_ctx *c, const Krylov &K, bool graph_ok, const double *rhs, double
             if (c->timing) HIPCHK(hipEventRecord(c->tev[1], c->stream));
             spmv(c, zj, nullptr, K.w);
             if (c->timing) HIPCHK(hipEventRecord(c->tev[2], c->stream));
-            // classical Gram-Schmidt, twice
-            HIPCHK(launch_dot_multi(N, j + 1, K.V, N, K.w, K.partial, c->stream));
-            HIPCHK(launch_reduce_partials(j + 1, K.partial, h1, 0, c->stream));
-            HIPCHK(launch_axpy_multi(N, j + 1, K.V, N, h1, K.w, c->stream));
-            HIPCHK(launch_dot_multi(N, j + 1, K.V, N, K.w, K.partial, c->stream));
-            HIPCHK(launch_reduce_partials(j + 1, K.partial, h2, 0, c->stream));
-            HIPCHK(launch_axpy_multi(N, j + 1, K.V, N, h2, K.w, c->stream));
-            HIPCHK(launch_dot_multi(N, 1, K.w, N, K.w, K.partial, c->stream));
+            // classical Gram-Schmidt, twice: h1 = V^T w, w -= V h1, h2 = V^T w,
+            // w -= V h2, hn = w^T w.  Each update pass also forms the next dot
+            // products: three passes over V
+            const int nv = j + 1;
+            if (nv <= kFusedGsMax) {
+                HIPCHK(launch_gs_pass(0, N, nv, K.V, N, nullptr, K.w, K.partial, c->stream));
+                HIPCHK(launch_reduce_partials(nv, K.partial, h1, 0, c->stream));
+                HIPCHK(launch_gs_pass(1, N, nv, K.V, N, h1, K.w, K.partial, c->stream));
+                HIPCHK(launch_reduce_partials(nv, K.partial, h2, 0, c->stream));
+                HIPCHK(launch_gs_pass(2, N, nv, K.V, N, h2, K.w, K.partial, c->stream));
+            } else {
+                HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
+                HIPCHK(launch_reduce_partials(nv, K.partial, h1, 0, c->stream));
+                HIPCHK(launch_axpy_multi(N, nv, K.V, N, h1, K.w, c->stream));
+                HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
+                HIPCHK(launch_reduce_partials(nv, K.partial, h2, 0, c->stream));
+                HIPCHK(launch_axpy_multi(N, nv, K.V, N, h2, K.w, c->stream));
+                HIPCHK(launch_dot_multi(N, 1, K.w, N, K.w, K.partial, c->stream));
+            }
             HIPCHK(launch_reduce_partials(1, K.partial, hn, 0, c->stream));
             if (c->timing) HIPCHK(hipEventRecord(c->tev[3], c->stream));
             HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double) * (2 * (m + 1) + 1),

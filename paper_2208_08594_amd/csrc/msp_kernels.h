@@ -15,7 +15,12 @@ struct SellView {
     const int4 *slices = nullptr;  // {row0, rows, width, off}
     const int *col = nullptr;
     int slice_begin = 0, slice_end = 0;
+    // lanes per row of the scalar sweep and residual kernels: 1 (one thread
+    // per row) or kRowLanes (a row's entries spread over that many lanes,
+    // for short-latency sweeps on the small coarse levels)
+    int lanes = 1;
 };
+constexpr int kRowLanes = 8;
 
 // ---- ingest / layout ----------------------------------------------------
 // Copy BSR blocks (row-major, b*b) into the sliced layout: dst entry (q, e) =
@@ -147,6 +152,13 @@ hipError_t launch_reduce_partials(int nv, const double *partial, double *out, in
 // w -= sum_i h[i] V_i
 hipError_t launch_axpy_multi(long long N, int nv, const double *V, long long ldv,
                              const double *h, double *w, hipStream_t st);
+// One pass of the Gram-Schmidt step over nv <= kFusedGsMax basis vectors,
+// each V entry read once: mode 0 the partials of V_i . w (as
+// launch_dot_multi), mode 1 w -= sum_i h[i] V_i then the partials of V_i . w,
+// mode 2 the same update then the partials of w . w (one value per block).
+constexpr int kFusedGsMax = 32;
+hipError_t launch_gs_pass(int mode, long long N, int nv, const double *V, long long ldv,
+                          const double *h, double *w, double *partial, hipStream_t st);
 // y = x / s
 hipError_t launch_scale(long long N, const double *x, double s, double *y, hipStream_t st);
 // x += sum_i y[i] Z_i

@@ -532,6 +532,80 @@ __global__ __launch_bounds__(kThreads) void k_residual(const int4 *__restrict__ 
     r[row] = fr - sum;
 }
 
+// The same sweep and residual with each row's stored entries spread over L
+// lanes (entry k on lane k mod L) and summed across them with a fixed
+// butterfly.  A wave holds 64 / L rows, so a slice takes L waves.  Lane
+// (j, t) = (entry phase, row) sits at j * (64 / L) + t: lanes of one phase
+// read consecutive rows of a slot, which are contiguous in the layout.
+template <typename T, int L, bool RESIDUAL>
+__device__ inline void sweep_row_lanes(const int4 *__restrict__ slices,
+                                       const int *__restrict__ col, int s0, int s1,
+                                       const T *__restrict__ val, const T *__restrict__ diag,
+                                       const T *__restrict__ f, T *x, T *__restrict__ r)
+{
+    constexpr int RPW = 64 / L;  // rows per wave
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int s = s0 + gw / L;
+    if (s >= s1) return;  // uniform over the wave
+    const int lane = threadIdx.x & 63, t = lane % RPW, j = lane / RPW;
+    const int4 d = slices[s];
+    const int local = (gw % L) * RPW + t;
+    const bool live = local < d.y;
+    const int row = d.x + local;
+    T fr = 0, dr = 1, xr = 0;
+    if (live && j == 0) {
+        fr = f[row];
+        dr = diag[row];
+        if (RESIDUAL) xr = x[row];
+    }
+    T sum = 0;
+    if (live) {
+        const int *cb = col + d.w + local;
+        const T *vb = val + d.w + local;
+        for (int k0 = j; k0 < d.z; k0 += 8 * L) {
+            int c[8];
+            T v[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u * L;
+                const bool in = k < d.z;
+                c[u] = in ? __builtin_nontemporal_load(cb + k * 64) : -1;
+                v[u] = in ? __builtin_nontemporal_load(vb + k * 64) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (c[u] >= 0) sum += v[u] * xv[u];
+        }
+    }
+#pragma unroll
+    for (int o = RPW; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
+    if (live && j == 0) {
+        if (RESIDUAL)
+            r[row] = fr - (dr * xr + sum);
+        else
+            x[row] = (fr - sum) / dr;
+    }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void k_gs_color_lanes(
+    const int4 *__restrict__ slices, const int *__restrict__ col, int s0, int s1,
+    const T *__restrict__ val, const T *__restrict__ diag, const T *__restrict__ f, T *x)
+{
+    sweep_row_lanes<T, L, false>(slices, col, s0, s1, val, diag, f, x, nullptr);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void k_residual_lanes(
+    const int4 *__restrict__ slices, const int *__restrict__ col, int s0, int s1,
+    const T *__restrict__ val, const T *__restrict__ diag, const T *__restrict__ f,
+    const T *__restrict__ x, T *__restrict__ r)
+{
+    sweep_row_lanes<T, L, true>(slices, col, s0, s1, val, diag, f, const_cast<T *>(x), r);
+}
+
 // Weighted point-Jacobi smoothing (the PJAC ablation of Sec. 6): the first
 // sweep from x = 0 is x = w D^-1 f; a later sweep is x += w D^-1 r with
 // r = f - A x from k_residual (all rows read the old x).
@@ -946,24 +1020,20 @@ __global__ __launch_bounds__(kThreads) void k_dot_multi(long long N, int nv,
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce_partials(int nv, int nblk,
-                                                              const double *__restrict__ partial,
-                                                              double *__restrict__ out,
-                                                              int accumulate)
+// out[i] = sum over the nblk blocks of partial[b * nv + i]: one wave per
+// vector i (lane l adds blocks l, l + 64, ... in order, then a fixed
+// butterfly across the wave), so every sum has a fixed order.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(
+    int nv, int nblk, const double *__restrict__ partial, double *__restrict__ out,
+    int accumulate)
 {
-    __shared__ double red[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = 0; i < nv; ++i) {
+    for (int i = wave; i < nv; i += kReduceThreads / 64) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kThreads) s += partial[(long long)b * nv + i];
+        for (int b = lane; b < nblk; b += 64) s += partial[(long long)b * nv + i];
         s = wave_sum(s);
-        if (lane == 0) red[wave] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = (red[0] + red[1]) + (red[2] + red[3]);
-            out[i] = accumulate ? out[i] + t : t;
-        }
-        __syncthreads();
+        if (lane == 0) out[i] = accumulate ? out[i] + s : s;
     }
 }
 
@@ -982,6 +1052,66 @@ __global__ __launch_bounds__(kThreads) void k_axpy_multi(long long N, int nv,
         for (int i = 0; i < nv; ++i) acc += hs[i] * V[(long long)i * ldv + q];
         w[q] -= acc;
     }
+}
+
+// One pass of the Gram-Schmidt step over the nv = NV basis vectors V_i (the
+// count is a template parameter, so a row's NV entries load together with no
+// per-vector tests):
+//   MODE 0: partial sums of V_i . w;
+//   MODE 1: w -= V h, then partial sums of V_i . w (the updated w);
+//   MODE 2: w -= V h, then partial sums of w . w.
+// Each V entry is read once per pass.  Every block sums a fixed chunk of rows
+// (each thread its rows in ascending order) and combines its four waves in a
+// fixed tree, so the partials are the same on every run.
+template <int NV, int MODE>
+__global__ __launch_bounds__(kThreads) void k_gs_pass(long long N, const double *__restrict__ V,
+                                                      long long ldv,
+                                                      const double *__restrict__ h,
+                                                      double *__restrict__ w,
+                                                      double *__restrict__ partial)
+{
+    constexpr int NOUT = MODE == 2 ? 1 : NV;
+    __shared__ double hs[NV];
+    __shared__ double red[4][NOUT];
+    if (MODE != 0) {
+        for (int i = threadIdx.x; i < NV; i += kThreads) hs[i] = h[i];
+        __syncthreads();
+    }
+    const long long chunk = ((N + gridDim.x - 1) / gridDim.x + 63) & ~63LL;
+    const long long b0 = (long long)blockIdx.x * chunk;
+    const long long b1 = b0 + chunk < N ? b0 + chunk : N;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc[NOUT];
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) acc[i] = 0.0;
+    for (long long q = b0 + threadIdx.x; q < b1; q += kThreads) {
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = V[(long long)i * ldv + q];
+        double wq = w[q];
+        if (MODE != 0) {
+            double a = 0.0;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) a += hs[i] * v[i];
+            wq -= a;
+            w[q] = wq;
+        }
+        if (MODE == 2) {
+            acc[0] += wq * wq;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) acc[i] += v[i] * wq;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) {
+        const double t = wave_sum(acc[i]);
+        if (lane == 0) red[wave][i] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NOUT)
+        partial[(long long)blockIdx.x * NOUT + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_scale(long long N, const double *__restrict__ x,
@@ -1588,8 +1718,14 @@ hipError_t launch_gs_color(const SellView &seg, const T *val, const T *diag, con
 {
     unsigned nb = slice_blocks(seg);
     if (!nb) return hipSuccess;
-    k_gs_color<T><<<nb, kThreads, 0, st>>>(seg.slices, seg.col, seg.slice_begin, seg.slice_end,
-                                           val, diag, f, x);
+    if (seg.lanes == kRowLanes) {
+        const int ns = seg.slice_end - seg.slice_begin;
+        k_gs_color_lanes<T, kRowLanes><<<(ns * kRowLanes + 3) / 4, kThreads, 0, st>>>(
+            seg.slices, seg.col, seg.slice_begin, seg.slice_end, val, diag, f, x);
+    } else {
+        k_gs_color<T><<<nb, kThreads, 0, st>>>(seg.slices, seg.col, seg.slice_begin,
+                                               seg.slice_end, val, diag, f, x);
+    }
     return hipGetLastError();
 }
 
@@ -1599,8 +1735,14 @@ hipError_t launch_residual(const SellView &all, const T *val, const T *diag, con
 {
     unsigned nb = slice_blocks(all);
     if (!nb) return hipSuccess;
-    k_residual<T><<<nb, kThreads, 0, st>>>(all.slices, all.col, all.slice_begin, all.slice_end,
-                                           val, diag, f, x, r);
+    if (all.lanes == kRowLanes) {
+        const int ns = all.slice_end - all.slice_begin;
+        k_residual_lanes<T, kRowLanes><<<(ns * kRowLanes + 3) / 4, kThreads, 0, st>>>(
+            all.slices, all.col, all.slice_begin, all.slice_end, val, diag, f, x, r);
+    } else {
+        k_residual<T><<<nb, kThreads, 0, st>>>(all.slices, all.col, all.slice_begin,
+                                               all.slice_end, val, diag, f, x, r);
+    }
     return hipGetLastError();
 }
 
@@ -1830,7 +1972,7 @@ hipError_t launch_dot_multi(long long N, int nv, const double *V, long long ldv,
 hipError_t launch_reduce_partials(int nv, const double *partial, double *out, int accumulate,
                                   hipStream_t st)
 {
-    k_reduce_partials<<<1, kThreads, 0, st>>>(nv, kDotBlocks, partial, out, accumulate);
+    k_reduce_partials<<<1, kReduceThreads, 0, st>>>(nv, kDotBlocks, partial, out, accumulate);
     return hipGetLastError();
 }
 
@@ -1846,6 +1988,39 @@ hipError_t launch_axpy_multi(long long N, int nv, const double *V, long long ldv
 {
     k_axpy_multi<<<stream_blocks(N), kThreads, 0, st>>>(N, nv, V, ldv, h, w);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t gs_pass(long long N, int nv, const double *V, long long ldv, const double *h,
+                          double *w, double *partial, hipStream_t st)
+{
+    switch (nv) {
+#define MSP_GS_CASE(K)                                                                    \
+    case K:                                                                               \
+        k_gs_pass<K, MODE><<<kDotBlocks, kThreads, 0, st>>>(N, V, ldv, h, w, partial);    \
+        break;
+        MSP_GS_CASE(1) MSP_GS_CASE(2) MSP_GS_CASE(3) MSP_GS_CASE(4) MSP_GS_CASE(5)
+        MSP_GS_CASE(6) MSP_GS_CASE(7) MSP_GS_CASE(8) MSP_GS_CASE(9) MSP_GS_CASE(10)
+        MSP_GS_CASE(11) MSP_GS_CASE(12) MSP_GS_CASE(13) MSP_GS_CASE(14) MSP_GS_CASE(15)
+        MSP_GS_CASE(16) MSP_GS_CASE(17) MSP_GS_CASE(18) MSP_GS_CASE(19) MSP_GS_CASE(20)
+        MSP_GS_CASE(21) MSP_GS_CASE(22) MSP_GS_CASE(23) MSP_GS_CASE(24) MSP_GS_CASE(25)
+        MSP_GS_CASE(26) MSP_GS_CASE(27) MSP_GS_CASE(28) MSP_GS_CASE(29) MSP_GS_CASE(30)
+        MSP_GS_CASE(31) MSP_GS_CASE(32)
+#undef MSP_GS_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_pass(int mode, long long N, int nv, const double *V, long long ldv,
+                          const double *h, double *w, double *partial, hipStream_t st)
+{
+    if (nv < 1 || nv > kFusedGsMax) return hipErrorInvalidValue;
+    if (mode == 0) return gs_pass<0>(N, nv, V, ldv, h, w, partial, st);
+    if (mode == 1) return gs_pass<1>(N, nv, V, ldv, h, w, partial, st);
+    if (mode == 2) return gs_pass<2>(N, nv, V, ldv, h, w, partial, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_scale(long long N, const double *x, double s, double *y, hipStream_t st)
