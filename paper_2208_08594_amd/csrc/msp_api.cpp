@@ -578,6 +578,41 @@ std::future<void> launch_coarse(msp_ctx *c, const Csr &A, std::vector<void *> &t
     });
 }
 
+// A posteriori check of the coarsest-level direct solve.  Its block LU makes
+// no row interchanges across 128-wide blocks, so a nonsingular matrix whose
+// leading blocks are singular or nearly so yields an inaccurate W Y even
+// when no pivot is exactly zero.  The setup therefore solves A_L x = f once
+// for a fixed f in [-1, 1] and requires every row of the result to satisfy
+// |(A_L x - f)_i| <= kCoarseBackwardTol (|A_L| |x| + |f|)_i (a componentwise
+// backward error; a factorisation with interchanges gives about 1e-15 on
+// these matrices).  On failure the setup reports MSP_ERR_SINGULAR instead of
+// returning a direct solve that is not one.
+constexpr double kCoarseBackwardTol = 1e-8;
+bool coarse_solve_accurate(msp_ctx *c, std::vector<void *> &tmp)
+{
+    const Csr &A = c->lev.back().A;
+    const int m = A.n;
+    std::vector<double> f(m), x(m);
+    for (int i = 0; i < m; ++i)  // a fixed, sign-changing right-hand side
+        f[i] = (double)((unsigned)(i + 1) * 2654435761u % 2001u) / 1000.0 - 1.0;
+    double *fd = c->upload(f, tmp);
+    double *xd = (double *)c->dalloc(sizeof(double) * (size_t)std::max(m, 1), tmp);
+    HIPCHK(launch_coarse_solve<double>(m, c->ldL, kLuBlock, c->cY, c->cinv, fd, c->ct, xd,
+                                       c->stream));
+    HIPCHK(hipMemcpyAsync(x.data(), xd, sizeof(double) * (size_t)m, hipMemcpyDeviceToHost,
+                          c->stream));
+    c->sync();
+    for (int i = 0; i < m; ++i) {
+        double r = -f[i], sc = std::fabs(f[i]);
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            r += A.val[k] * x[A.ci[k]];
+            sc += std::fabs(A.val[k] * x[A.ci[k]]);
+        }
+        if (!(std::fabs(r) <= kCoarseBackwardTol * sc)) return false;  // also catches NaN
+    }
+    return true;
+}
+
 // Host-only part of the block ILU(0) setup: elimination order, dependency
 // levels, factorisation tasks and the sliced layouts of L and U.  Touches no
 // device state, so it can run on a second host thread.
@@ -1057,7 +1092,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     HIPCHK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
     const int bad_bilu = c->read_flag(1) | (c->ns.on ? c->read_flag(2) : 0);
     phase(6);
-    const int bad_coarse = c->read_flag(0);
+    const int bad_coarse = c->read_flag(0) || !coarse_solve_accurate(c, tmp);
     c->release(tmp);
     if (bad_coarse || bad_bilu) fail(MSP_ERR_SINGULAR);
     phase(5);

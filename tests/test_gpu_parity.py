@@ -407,6 +407,65 @@ def test_singular_pivot_block_is_reported_and_the_context_recovers():
     o.close()
 
 
+def _leading_block_matrix(n, delta, seed):
+    """Scalar CSR, nonsingular and well conditioned, unit diagonal: a narrow
+    diagonally dominant band, except rows 0 and 1, which inside the leading
+    128 x 128 block hold only [[1, 1], [1, 1 + delta]] (row 0 is also coupled
+    to row 300, symmetrically).  That leading block is singular for delta = 0
+    and nearly so for small delta, while the whole matrix is not."""
+    rng = np.random.default_rng(seed)
+    ent = [dict() for _ in range(n)]
+    for i in range(2, n):
+        for d in (1, 2):
+            j = i + d
+            if j < n:
+                v = rng.uniform(-0.2, 0.2)
+                ent[i][j] = v
+                ent[j][i] = v * rng.uniform(0.5, 1.5)
+    for i in range(2, n):
+        ent[i][i] = 1.0
+    ent[0].update({0: 1.0, 1: 1.0, 300: 0.5})
+    ent[1].update({0: 1.0, 1: 1.0 + delta})
+    ent[300][0] = 0.5
+    rows = [sorted(e.items()) for e in ent]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([j for r in rows for j, _ in r], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in r])
+    return rp, ci, val.reshape(-1, 1, 1)
+
+
+@pytest.mark.parametrize("delta,ok", [(0.0, False), (1e-13, False), (1e-2, True)])
+def test_coarse_direct_solve_with_a_nearly_singular_leading_block(delta, ok):
+    """The coarsest solve factors 128-wide blocks without interchanges across
+    them.  A nonsingular matrix whose leading block is singular (delta = 0)
+    or nearly singular (1e-13) must be refused with MSP_ERR_SINGULAR (the
+    setup checks the direct solve's backward error), never solved silently
+    wrong; the oracle's LAPACK LU, which pivots across the whole matrix,
+    solves it.  A leading block of moderate conditioning (1e-2) is solved and
+    matches the oracle."""
+    n = 600
+    rp, ci, vals = _leading_block_matrix(n, delta, 27)
+    announce("leading block delta", delta)
+    o = O.OracleSolver(max_coarse=10000)
+    o.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+    A = K.csr(o.level(0)).toarray()
+    assert np.linalg.cond(A) < 1e3  # the whole matrix is well conditioned
+    f = np.random.default_rng(28).uniform(-1, 1, n)
+    xo = o.vcycle(f)
+    K.dense_backward_error(K.csr(o.level(0)), xo, f, 1e-14, "oracle LU")
+    g = msp.Solver(max_coarse=10000)
+    if ok:
+        g.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+        check_coarse_solve(g, o, f, "moderate leading block")
+    else:
+        with pytest.raises(msp.MspError) as e:
+            g.setup(n=n, b=1, p=0, row_ptr=rp, col_ind=ci, vals=vals)
+        assert e.value.code == -3
+    g.close()
+    o.close()
+
+
 @pytest.mark.parametrize("n", [1000, 600, 129])
 def test_coarse_direct_solve_needs_pivoting(n):
     """The whole matrix is the coarsest level (several 128-wide blocks of the
