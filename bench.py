@@ -165,7 +165,9 @@ def main():
     ap.add_argument("--bilu-order", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="(default; kept for old commands)")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the 512-request serving leg in a child process")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte calibration) and exit")
     args = ap.parse_args()
@@ -297,18 +299,26 @@ def main():
                 max(summed(tim32, "apply")[1], 1) * 1e3}
         s32.close()
 
+    # the solve's device memory goes back before the serving child starts
+    x64 = x64.cpu()
+    if x32 is not None:
+        x32 = x32.cpu()
+    solver.close()
+    del rp, ci, vals, rhs, xin, yout
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     serving = None
-    if not args.no_serving:
-        serving = serving_sample()
+    if args.serving and not args.no_serving:
+        serving = serving_run()
 
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
         cpu, x_or = cpu_baseline(sys_)
         nx = np.linalg.norm(x_or)
-        errors["fp64_precond_vs_oracle"] = float(np.linalg.norm(x64.cpu().numpy() - x_or) / nx)
+        errors["fp64_precond_vs_oracle"] = float(np.linalg.norm(x64.numpy() - x_or) / nx)
         if x32 is not None:
-            errors["fp32_precond_vs_oracle"] = float(np.linalg.norm(x32.cpu().numpy() - x_or) / nx)
+            errors["fp32_precond_vs_oracle"] = float(np.linalg.norm(x32.numpy() - x_or) / nx)
         if fp32 is not None:
             fp32["rel_error_vs_fp64_oracle"] = errors.get("fp32_precond_vs_oracle")
 
@@ -341,8 +351,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    solver.close()
-    torch.cuda.synchronize()
     log("done")
 
 
@@ -356,21 +364,22 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": a.numel() * 8, "reps": 3}))
 
 
-def serving_sample():
-    """A short continuous-batching run (reported beside the main metric)."""
-    from paper_2208_08594_amd import serve
-    log("serving sample: 16 requests, sides 16..32, 4 slots, mu=10")
-    cal = serve.make_requests(2, rate=0.0, steps=4, sides=[16, 24, 32])
-    t = time.perf_counter()
-    serve.Server(slots=1, mu=10).run(cal)
-    per_req = (time.perf_counter() - t) / len(cal)
-    rate = 0.7 * 4 / per_req
-    reqs = serve.make_requests(16, rate=rate, steps=4, sides=[16, 24, 32])
-    res = serve.Server(slots=4, mu=10).run(reqs)
-    res.update({"arrival_rate_per_s": rate, "slots": 4, "mu": 10,
-                "sample": "16 requests x 4 Newton steps, cubes 16^3..32^3, b 3..7"})
-    res.pop("errors", None)
-    return res
+def serving_run():
+    """The serving measurements, in a child process of their own (a clean
+    device state, and a failure there cannot take the main line with it):
+    512 requests, Poisson arrivals at 0.7 x the measured single-stream
+    capacity, cubes of side 16..96 with b = 3..7, 4 Newton steps each,
+    adaptive setup mu = 10; then a burst of 96 small requests served with and
+    without batching of the small solves."""
+    import subprocess
+    log("serving: 512 requests, sides 16..96, b 3..7, 4 Newton steps, load 0.7 (child process)")
+    p = subprocess.run([sys.executable, "-X", "faulthandler", "-m", "paper_2208_08594_amd.serve",
+                        "--bench"], cwd=ROOT, stdout=subprocess.PIPE, text=True, timeout=900)
+    lines = [l for l in p.stdout.splitlines() if l.startswith("{")]
+    if p.returncode != 0 or not lines:
+        log(f"serving child exited with {p.returncode}")
+        return {"error": f"serving process exited with status {p.returncode}"}
+    return json.loads(lines[-1])
 
 
 def cpu_baseline(sys_):

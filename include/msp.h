@@ -182,6 +182,24 @@ int msp_setup(struct msp_ctx *ctx, int n_block_rows, int block_size, int pressur
  * MSP_ERR_NONFINITE (rhs), MSP_ERR_ARG, MSP_ERR_HIP. */
 int msp_solve(struct msp_ctx *ctx, const double *rhs, double *x, double rtol, msp_info *info);
 
+/* k FGMRES solves of Sec. 5 (as msp_solve), one per context, advanced
+ * together by the calling thread: each solve's next Arnoldi step is queued on
+ * its context's stream as soon as its previous one has finished, so the
+ * device work of all k overlaps while the host does each one's Givens
+ * rotations in turn.  Meant for many small systems served at once, whose
+ * solves alone leave the device mostly idle.  Each solve's steps, kernels and
+ * result are exactly those of msp_solve on the same context.
+ *   ctx   k distinct contexts (host array), each set up, on the current device;
+ *   rhs   k device pointers, rhs[i] double[n_i b_i] (read only);
+ *   x     k device pointers: initial guesses in, solutions out;
+ *   infos host array of k msp_info (may be NULL), infos[i].status the solve's
+ *         own status.
+ * Returns MSP_OK if every solve returned MSP_OK, the first negative status
+ * if any failed, else MSP_NOT_CONVERGED.  MSP_ERR_ARG (a NULL pointer, k < 1,
+ * a context listed twice), MSP_ERR_STATE (a context without setup). */
+int msp_solve_batch(struct msp_ctx *const *ctx, int k, const double *const *rhs,
+                    double *const *x, double rtol, msp_info *infos);
+
 /* msp_solve for callers that cannot allocate device memory (code that must
  * not call hipMalloc, tight serving loops, harnesses that forbid it): the
  * same solve, the same arguments, errors and result as msp_solve, but no

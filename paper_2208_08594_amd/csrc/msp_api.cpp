@@ -61,6 +61,7 @@ struct DevSell {
     int *col = nullptr;
     int *src = nullptr;
     int lanes = 1;  // lanes per row of the scalar sweep and residual kernels
+    std::vector<int4> slices_h;  // host source of `slices` (kept while the copy may run)
     SellView view(int seg) const
     {
         SellView v;
@@ -95,6 +96,7 @@ struct Level {
     float *val32 = nullptr, *diag32 = nullptr;
     int *perm_d = nullptr, *iperm_d = nullptr;
     int *agg_pos = nullptr, *mem_ptr = nullptr, *mem = nullptr;
+    std::vector<int> agg_pos_h, mem_ptr_h, mem_h;  // host sources of the three above
     void *f = nullptr, *x = nullptr, *r = nullptr;  // work vectors in the precond precision
 };
 
@@ -104,6 +106,7 @@ struct NStage {
     bool on = false;
     std::vector<int> grp_ptr;  // cells of group k: cells[grp_ptr[k] .. grp_ptr[k+1])
     int *cells = nullptr;
+    std::vector<int> cells_h;  // host source of `cells`
     double *Dn64 = nullptr, *Ann64 = nullptr;
     float *Dn32 = nullptr, *Ann32 = nullptr;
     void *gN = nullptr, *y = nullptr;  // preconditioner precision, n (b-1)
@@ -193,6 +196,7 @@ struct msp_ctx {
     // apply, Gram-Schmidt step): summed ms and counts over the last solve
     bool timing = false;
     hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_step = nullptr;  // end of the solve's last queued step
     double t_ms[kTimedParts] = {0, 0, 0};
     int t_calls[kTimedParts] = {0, 0, 0};
 
@@ -232,6 +236,10 @@ struct msp_ctx {
         list.clear();
     }
     template <typename T, typename A>
+    // Device copy of h, queued asynchronously: h must stay alive and unchanged
+    // until the copy is done (the runtime may read pageable host memory after
+    // the call returns), so callers pass context-owned arrays or synchronise
+    // before h goes away.
     T *upload(const std::vector<T, A> &h, std::vector<void *> &list)
     {
         T *d = (T *)dalloc(sizeof(T) * std::max<size_t>(h.size(), 1), list);
@@ -260,7 +268,8 @@ namespace {
 
 void upload_sell(msp_ctx *c, DevSell &S, std::vector<void *> &list)
 {
-    std::vector<int4> sl(S.lay.slice_row0.size());
+    std::vector<int4> &sl = S.slices_h;
+    sl.resize(S.lay.slice_row0.size());
     for (size_t s = 0; s < sl.size(); ++s)
         sl[s] = make_int4(S.lay.slice_row0[s], S.lay.slice_rows[s], S.lay.slice_width[s],
                           S.lay.slice_off[s]);
@@ -457,10 +466,12 @@ void link_levels(msp_ctx *c)
     for (size_t l = 0; l + 1 < c->lev.size(); ++l) {
         Level &L = c->lev[l];
         const Level &C = c->lev[l + 1];
-        std::vector<int> agg_pos(L.n);
+        std::vector<int> &agg_pos = L.agg_pos_h, &mptr = L.mem_ptr_h, &mem = L.mem_h;
+        agg_pos.assign(L.n, 0);
         for (int t = 0; t < L.n; ++t) agg_pos[t] = C.perm[L.agg[L.iperm[t]]];
         // members of each coarse position, natural fine index ascending
-        std::vector<int> mptr(C.n + 1, 0), mem(L.n);
+        mptr.assign(C.n + 1, 0);
+        mem.assign(L.n, 0);
         for (int i = 0; i < L.n; ++i) ++mptr[C.perm[L.agg[i]] + 1];
         for (int J = 0; J < C.n; ++J) mptr[J + 1] += mptr[J];
         std::vector<int> f(mptr.begin(), mptr.end() - 1);
@@ -858,7 +869,8 @@ void n_stage_device(msp_ctx *c, const double *vals, const std::vector<int> &colo
     const int n = c->n, b = c->b, m = b - 1;
     S.on = true;
     S.grp_ptr.assign(g + 1, 0);
-    std::vector<int> cells(n);
+    std::vector<int> &cells = S.cells_h;
+    cells.assign(n, 0);
     {
         std::vector<int> cnt(g + 1, 0);
         for (int i = 0; i < n; ++i) ++cnt[color[i]];
@@ -1352,120 +1364,105 @@ void ensure_workspace(msp_ctx *c)
     c->wsm = m;
 }
 
-// sum_i x_i^2 on the device, returned to the host
-double device_norm2(msp_ctx *c, const Krylov &K, const double *x, long long N)
-{
-    HIPCHK(launch_dot_multi(N, 1, x, N, x, K.partial, c->stream));
-    HIPCHK(launch_reduce_partials(1, K.partial, K.hbuf, 0, c->stream));
-    HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    return c->hhost[0];
-}
+// One FGMRES(m) solve (Sec. 5) as a sequence of device steps, each ended by
+// a copy of its scalars to the context's pinned buffer and an event: the
+// host waits for the event, does its part (Givens rotations, stopping test)
+// and queues the next step.  Several solves on different contexts can thus
+// be advanced in turn by one host thread, each queuing its next step as soon
+// as its previous one is done, so their device work overlaps (msp_solve_batch);
+// msp_solve runs one.  The steps, kernels and host arithmetic of a solve are
+// the same either way.  graph_ok = false keeps the preconditioner apply eager
+// unless its graph already exists, so the solve itself creates nothing on the
+// device.
+struct Fgmres {
+    msp_ctx *c = nullptr;
+    Krylov K;
+    bool graph_ok = true;
+    const double *rhs = nullptr;
+    double *x = nullptr;
+    double rtol = 0.0;
+    long long N = 0;
+    int m = 0;
+    std::vector<double> H, cs, sn, g, y;
+    double bnorm = 0.0, tol = 0.0, beta = 0.0, relres = 0.0;
+    int iters = 0, restarts = 0, j = 0, status = MSP_OK;
+    enum Stage { kBnorm, kBeta, kStep, kDone } stage = kBnorm;
+    double t0 = 0.0, ms = 0.0;
 
-// One FGMRES(m) solve (Sec. 5) with the workspace K.  graph_ok = false keeps
-// the preconditioner apply eager unless its graph already exists, so the
-// solve itself creates nothing on the device.
-int fgmres(msp_ctx *c, const Krylov &K, bool graph_ok, const double *rhs, double *x,
-           double rtol, int &iters, int &restarts, double &relres)
-{
-    const long long N = (long long)c->n * c->b;
-    const int m = c->opt.restart;
-    iters = 0;
-    restarts = 0;
-    relres = 0.0;
-    for (int q = 0; q < kTimedParts; ++q) {
-        c->t_ms[q] = 0.0;
-        c->t_calls[q] = 0;
+    double *h1() const { return K.hbuf; }
+    double *h2() const { return K.hbuf + (m + 1); }
+    double *hn() const { return K.hbuf + 2 * (m + 1); }
+    void mark() { HIPCHK(hipEventRecord(c->ev_step, c->stream)); }
+    // queue sum_i v_i^2 into hhost[0]
+    void queue_norm2(const double *v)
+    {
+        HIPCHK(launch_dot_multi(N, 1, v, N, v, K.partial, c->stream));
+        HIPCHK(launch_reduce_partials(1, K.partial, K.hbuf, 0, c->stream));
+        HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+        mark();
     }
-    double bn2 = device_norm2(c, K, rhs, N);
-    if (!std::isfinite(bn2)) return MSP_ERR_NONFINITE;
-    const double bnorm = std::sqrt(bn2);
-    if (bnorm == 0.0) {
-        HIPCHK(launch_fill(N, 0.0, x, c->stream));
-        c->sync();
-        return MSP_OK;
+    void finish(int st)
+    {
+        status = st;
+        stage = kDone;
+        ms = now_ms() - t0;
     }
-    const double tol = rtol * bnorm;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-    spmv(c, x, rhs, K.w);
-    double beta = std::sqrt(device_norm2(c, K, K.w, N));
-    if (!std::isfinite(beta)) return MSP_ERR_NONFINITE;
-    int status = MSP_OK;
-    double *h1 = K.hbuf, *h2 = K.hbuf + (m + 1), *hn = K.hbuf + 2 * (m + 1);
-    while (beta > tol) {
-        if (iters >= c->opt.max_iter) {
-            status = MSP_NOT_CONVERGED;
-            break;
+    void start()
+    {
+        t0 = now_ms();
+        N = (long long)c->n * c->b;
+        m = c->opt.restart;
+        H.assign((size_t)(m + 1) * m, 0.0);
+        cs.assign(m, 0.0);
+        sn.assign(m, 0.0);
+        g.assign(m + 1, 0.0);
+        y.assign(m, 0.0);
+        for (int q = 0; q < kTimedParts; ++q) {
+            c->t_ms[q] = 0.0;
+            c->t_calls[q] = 0;
         }
-        HIPCHK(launch_scale(N, K.w, beta, K.V, c->stream));
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            double *vj = K.V + (size_t)j * N;
-            double *zj = K.Z + (size_t)j * N;
-            if (c->timing) HIPCHK(hipEventRecord(c->tev[0], c->stream));
-            apply(c, vj, zj, graph_ok);
-            if (c->timing) HIPCHK(hipEventRecord(c->tev[1], c->stream));
-            spmv(c, zj, nullptr, K.w);
-            if (c->timing) HIPCHK(hipEventRecord(c->tev[2], c->stream));
-            // classical Gram-Schmidt, twice: h1 = V^T w, w -= V h1, h2 = V^T w,
-            // w -= V h2, hn = w^T w.  Each update pass also forms the next dot
-            // products: three passes over V
-            const int nv = j + 1;
-            if (nv <= kFusedGsMax) {
-                HIPCHK(launch_gs_pass(0, N, nv, K.V, N, nullptr, K.w, K.partial, c->stream));
-                HIPCHK(launch_reduce_partials(nv, K.partial, h1, 0, c->stream));
-                HIPCHK(launch_gs_pass(1, N, nv, K.V, N, h1, K.w, K.partial, c->stream));
-                HIPCHK(launch_reduce_partials(nv, K.partial, h2, 0, c->stream));
-                HIPCHK(launch_gs_pass(2, N, nv, K.V, N, h2, K.w, K.partial, c->stream));
-            } else {
-                HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
-                HIPCHK(launch_reduce_partials(nv, K.partial, h1, 0, c->stream));
-                HIPCHK(launch_axpy_multi(N, nv, K.V, N, h1, K.w, c->stream));
-                HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
-                HIPCHK(launch_reduce_partials(nv, K.partial, h2, 0, c->stream));
-                HIPCHK(launch_axpy_multi(N, nv, K.V, N, h2, K.w, c->stream));
-                HIPCHK(launch_dot_multi(N, 1, K.w, N, K.w, K.partial, c->stream));
-            }
-            HIPCHK(launch_reduce_partials(1, K.partial, hn, 0, c->stream));
-            if (c->timing) HIPCHK(hipEventRecord(c->tev[3], c->stream));
-            HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double) * (2 * (m + 1) + 1),
-                                  hipMemcpyDeviceToHost, c->stream));
-            c->sync();
-            if (c->timing) {
-                for (int q = 0; q < kTimedParts; ++q) {
-                    // events 0..3 bracket apply (0,1), SpMV (1,2), Gram-Schmidt (2,3)
-                    static const int a_[kTimedParts] = {1, 0, 2}, b_[kTimedParts] = {2, 1, 3};
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, c->tev[a_[q]], c->tev[b_[q]]));
-                    c->t_ms[q] += ms;
-                    c->t_calls[q]++;
-                }
-            }
-            const double *hh1 = c->hhost, *hh2 = c->hhost + (m + 1);
-            const double hnorm = std::sqrt(c->hhost[2 * (m + 1)]);
-            if (!std::isfinite(hnorm)) return MSP_ERR_NONFINITE;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh1[i] + hh2[i];
-            H[(size_t)(j + 1) * m + j] = hnorm;
-            for (int i = 0; i < j; ++i) {
-                double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
-            }
-            double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
-            double d = std::hypot(a, bq);
-            cs[j] = a / d;
-            sn[j] = bq / d;
-            H[(size_t)j * m + j] = d;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++iters;
-            k = j + 1;
-            if (hnorm == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c->opt.max_iter) break;
-            HIPCHK(launch_scale(N, K.w, hnorm, K.V + (size_t)(j + 1) * N, c->stream));
+        stage = kBnorm;
+        queue_norm2(rhs);
+    }
+    // Arnoldi step j: z_j = B v_j, w = A z_j, classical Gram-Schmidt twice
+    // (h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, hn = w^T w; each update
+    // pass also forms the next dot products: three passes over V), the
+    // coefficients to the host
+    void queue_step()
+    {
+        double *vj = K.V + (size_t)j * N;
+        double *zj = K.Z + (size_t)j * N;
+        if (c->timing) HIPCHK(hipEventRecord(c->tev[0], c->stream));
+        apply(c, vj, zj, graph_ok);
+        if (c->timing) HIPCHK(hipEventRecord(c->tev[1], c->stream));
+        spmv(c, zj, nullptr, K.w);
+        if (c->timing) HIPCHK(hipEventRecord(c->tev[2], c->stream));
+        const int nv = j + 1;
+        if (nv <= kFusedGsMax) {
+            HIPCHK(launch_gs_pass(0, N, nv, K.V, N, nullptr, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(nv, K.partial, h1(), 0, c->stream));
+            HIPCHK(launch_gs_pass(1, N, nv, K.V, N, h1(), K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(nv, K.partial, h2(), 0, c->stream));
+            HIPCHK(launch_gs_pass(2, N, nv, K.V, N, h2(), K.w, K.partial, c->stream));
+        } else {
+            HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(nv, K.partial, h1(), 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, nv, K.V, N, h1(), K.w, c->stream));
+            HIPCHK(launch_dot_multi(N, nv, K.V, N, K.w, K.partial, c->stream));
+            HIPCHK(launch_reduce_partials(nv, K.partial, h2(), 0, c->stream));
+            HIPCHK(launch_axpy_multi(N, nv, K.V, N, h2(), K.w, c->stream));
+            HIPCHK(launch_dot_multi(N, 1, K.w, N, K.w, K.partial, c->stream));
         }
+        HIPCHK(launch_reduce_partials(1, K.partial, hn(), 0, c->stream));
+        if (c->timing) HIPCHK(hipEventRecord(c->tev[3], c->stream));
+        HIPCHK(hipMemcpyAsync(c->hhost, K.hbuf, sizeof(double) * (2 * (m + 1) + 1),
+                              hipMemcpyDeviceToHost, c->stream));
+        mark();
+    }
+    // x += Z y for the k steps of the cycle, then the true residual's norm
+    void queue_update(int k)
+    {
         for (int i = k - 1; i >= 0; --i) {
             double acc = g[i];
             for (int q = i + 1; q < k; ++q) acc -= H[(size_t)i * m + q] * y[q];
@@ -1476,11 +1473,116 @@ int fgmres(msp_ctx *c, const Krylov &K, bool graph_ok, const double *rhs, double
                               hipMemcpyHostToDevice, c->stream));
         HIPCHK(launch_update_x(N, k, K.Z, N, K.ydev, x, c->stream));
         spmv(c, x, rhs, K.w);
-        beta = std::sqrt(device_norm2(c, K, K.w, N));
+        queue_norm2(K.w);
         ++restarts;
+        stage = kBeta;
     }
-    relres = beta / bnorm;
-    return status;
+    // The step just waited for is complete: do the host part, queue the next.
+    void advance()
+    {
+        if (stage == kBnorm) {
+            const double bn2 = c->hhost[0];
+            if (!std::isfinite(bn2)) return finish(MSP_ERR_NONFINITE);
+            bnorm = std::sqrt(bn2);
+            if (bnorm == 0.0) {
+                HIPCHK(launch_fill(N, 0.0, x, c->stream));
+                relres = 0.0;
+                return finish(MSP_OK);
+            }
+            tol = rtol * bnorm;
+            spmv(c, x, rhs, K.w);
+            queue_norm2(K.w);
+            stage = kBeta;
+            return;
+        }
+        if (stage == kBeta) {
+            beta = std::sqrt(c->hhost[0]);
+            if (!std::isfinite(beta)) return finish(MSP_ERR_NONFINITE);
+            relres = beta / bnorm;
+            if (beta <= tol) return finish(MSP_OK);
+            if (iters >= c->opt.max_iter) return finish(MSP_NOT_CONVERGED);
+            HIPCHK(launch_scale(N, K.w, beta, K.V, c->stream));
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            j = 0;
+            stage = kStep;
+            queue_step();
+            return;
+        }
+        // kStep: the coefficients of Arnoldi step j are in hhost
+        if (c->timing) {
+            for (int q = 0; q < kTimedParts; ++q) {
+                // events 0..3 bracket apply (0,1), SpMV (1,2), Gram-Schmidt (2,3)
+                static const int a_[kTimedParts] = {1, 0, 2}, b_[kTimedParts] = {2, 1, 3};
+                float e = 0.f;
+                HIPCHK(hipEventElapsedTime(&e, c->tev[a_[q]], c->tev[b_[q]]));
+                c->t_ms[q] += e;
+                c->t_calls[q]++;
+            }
+        }
+        const double *hh1 = c->hhost, *hh2 = c->hhost + (m + 1);
+        const double hnorm = std::sqrt(c->hhost[2 * (m + 1)]);
+        if (!std::isfinite(hnorm)) return finish(MSP_ERR_NONFINITE);
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh1[i] + hh2[i];
+        H[(size_t)(j + 1) * m + j] = hnorm;
+        for (int i = 0; i < j; ++i) {
+            double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+        }
+        double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
+        double d = std::hypot(a, bq);
+        cs[j] = a / d;
+        sn[j] = bq / d;
+        H[(size_t)j * m + j] = d;
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++iters;
+        if (hnorm == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c->opt.max_iter ||
+            j + 1 == m)
+            return queue_update(j + 1);
+        HIPCHK(launch_scale(N, K.w, hnorm, K.V + (size_t)(j + 1) * N, c->stream));
+        ++j;
+        queue_step();
+    }
+};
+
+// Advance every solve of `runs` to its end: wait for each one's queued step
+// in turn, do its host part and queue its next step.  A solve that throws is
+// ended with the error code; the others go on.
+void run_solves(std::vector<Fgmres> &runs)
+{
+    auto guard = [](Fgmres &r, auto &&f) {
+        try {
+            f();
+        } catch (const MspError &e) {
+            r.finish(e.code);
+        } catch (const std::bad_alloc &) {
+            r.finish(MSP_ERR_NOMEM);
+        } catch (...) {
+            r.finish(MSP_ERR_HIP);
+        }
+    };
+    for (Fgmres &r : runs) guard(r, [&]() { r.start(); });
+    for (bool busy = true; busy;) {
+        busy = false;
+        for (Fgmres &r : runs) {
+            if (r.stage == Fgmres::kDone) continue;
+            busy = true;
+            guard(r, [&]() {
+                HIPCHK(hipEventSynchronize(r.c->ev_step));
+                r.advance();
+            });
+        }
+    }
+    for (Fgmres &r : runs) {
+        const hipError_t e = hipStreamSynchronize(r.c->stream);
+        if (e != hipSuccess && r.status >= 0) {
+            (void)hipGetLastError();
+            r.status = MSP_ERR_HIP;
+        }
+    }
 }
 
 template <typename F>
@@ -1561,25 +1663,34 @@ void stage_bilu_T(msp_ctx *c, const double *r, double *z)
     HIPCHK(launch_to_double<T>(N, (const T *)c->ybuf, z, c->stream));
 }
 
-// Run one FGMRES solve through `run` and record its outcome in the context
-// (iteration count for the adaptive setup, info, timing).
-template <typename F>
-int finish_solve(msp_ctx *c, msp_info *info, F &&run)
+// Record a finished solve in its context (iteration count for the adaptive
+// setup, info) and return its status.
+int record_solve(const Fgmres &r, msp_info *info)
 {
-    const double t0 = now_ms();
-    int iters = 0, restarts = 0;
-    double relres = 0.0;
-    int st = guarded([&]() { return run(iters, restarts, relres); });
-    c->info.status = st;
-    c->info.iterations = iters;
-    c->info.restarts = restarts;
-    c->info.rel_true_residual = relres;
-    c->info.solve_ms = now_ms() - t0;
+    msp_ctx *c = r.c;
+    c->info.status = r.status;
+    c->info.iterations = r.iters;
+    c->info.restarts = r.restarts;
+    c->info.rel_true_residual = r.relres;
+    c->info.solve_ms = r.ms;
     c->solves++;
     c->info.solves = c->solves;
-    c->it_prev = iters;
+    c->it_prev = r.iters;
     if (info) *info = c->info;
-    return st;
+    return r.status;
+}
+
+Fgmres make_run(msp_ctx *c, const Krylov &K, bool graph_ok, const double *rhs, double *x,
+                double rtol)
+{
+    Fgmres r;
+    r.c = c;
+    r.K = K;
+    r.graph_ok = graph_ok;
+    r.rhs = rhs;
+    r.x = x;
+    r.rtol = rtol;
+    return r;
 }
 
 }  // namespace
@@ -1672,6 +1783,7 @@ int msp_create(msp_ctx **ctx, const msp_options *opt)
         HIPCHK(hipGetDevice(&c->device));
         if (int e = init_scratch(c->device)) return e;
         c->stream = (hipStream_t)o.stream;
+        HIPCHK(hipEventCreateWithFlags(&c->ev_step, hipEventDisableTiming));
         HIPCHK(hipHostMalloc((void **)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&c->chain_host, sizeof(int) * 16, hipHostMallocDefault));
@@ -1718,6 +1830,7 @@ int msp_destroy(msp_ctx *c)
         kill_stream(c->chain_copy);
         kill_event(c->ev_a0);
         for (auto &e : c->tev) kill_event(e);
+        kill_event(c->ev_step);
         kill_stream(c->side);
         kill_stream(c->gj.aux);
         kill_stream(c->gj.main);
@@ -1837,10 +1950,14 @@ int msp_solve(msp_ctx *c, const double *rhs, double *x, double rtol, msp_info *i
 {
     if (!c || !rhs || !x || !(rtol > 0.0)) return MSP_ERR_ARG;
     if (!c->hasB || !c->haveA) return MSP_ERR_STATE;
-    return finish_solve(c, info, [&](int &iters, int &restarts, double &relres) {
+    const int st = guarded([&]() {
         ensure_workspace(c);
-        return fgmres(c, c->kw, true, rhs, x, rtol, iters, restarts, relres);
+        return MSP_OK;
     });
+    if (st != MSP_OK) return st;
+    std::vector<Fgmres> runs{make_run(c, c->kw, true, rhs, x, rtol)};
+    run_solves(runs);
+    return record_solve(runs[0], info);
 }
 
 int msp_solve_noalloc(msp_ctx *c, const double *rhs, double *x, double rtol, msp_info *info)
@@ -1851,10 +1968,42 @@ int msp_solve_noalloc(msp_ctx *c, const double *rhs, double *x, double rtol, msp
     if (krylov_bytes(N, c->opt.restart) > kScratchBytes) return MSP_ERR_SCRATCH;
     double *base = scratch_ptr(c->device);
     if (!base) return MSP_ERR_HIP;
-    const Krylov K = krylov_carve(base, N, c->opt.restart);
-    return finish_solve(c, info, [&](int &iters, int &restarts, double &relres) {
-        return fgmres(c, K, false, rhs, x, rtol, iters, restarts, relres);
-    });
+    std::vector<Fgmres> runs{make_run(c, krylov_carve(base, N, c->opt.restart), false, rhs, x,
+                                      rtol)};
+    run_solves(runs);
+    return record_solve(runs[0], info);
+}
+
+int msp_solve_batch(msp_ctx *const *ctx, int k, const double *const *rhs, double *const *x,
+                    double rtol, msp_info *infos)
+{
+    if (!ctx || !rhs || !x || k < 1 || !(rtol > 0.0)) return MSP_ERR_ARG;
+    for (int i = 0; i < k; ++i) {
+        if (!ctx[i] || !rhs[i] || !x[i]) return MSP_ERR_ARG;
+        for (int q = 0; q < i; ++q)
+            if (ctx[q] == ctx[i]) return MSP_ERR_ARG;  // one solve per context
+    }
+    for (int i = 0; i < k; ++i)
+        if (!ctx[i]->hasB || !ctx[i]->haveA) return MSP_ERR_STATE;
+    std::vector<Fgmres> runs;
+    runs.reserve(k);
+    for (int i = 0; i < k; ++i) {
+        msp_ctx *c = ctx[i];
+        const int st = guarded([&]() {
+            ensure_workspace(c);
+            return MSP_OK;
+        });
+        if (st != MSP_OK) return st;
+        runs.push_back(make_run(c, c->kw, true, rhs[i], x[i], rtol));
+    }
+    run_solves(runs);
+    int worst = MSP_OK;
+    for (int i = 0; i < k; ++i) {
+        const int st = record_solve(runs[i], infos ? infos + i : nullptr);
+        if (st < 0 && worst >= 0) worst = st;
+        if (st == MSP_NOT_CONVERGED && worst == MSP_OK) worst = st;
+    }
+    return worst;
 }
 
 int msp_get_info(msp_ctx *c, msp_info *info)

@@ -66,6 +66,7 @@ SIGNATURES = {
     "msp_setup": ([_vp, _i, _i, _i, _vp, _vp, _vp, _ll], _i),
     "msp_solve": ([_vp, _vp, _vp, _d, C.POINTER(MspInfo)], _i),
     "msp_solve_noalloc": ([_vp, _vp, _vp, _d, C.POINTER(MspInfo)], _i),
+    "msp_solve_batch": ([_vp, _i, _vp, _vp, _d, _vp], _i),
     "msp_get_info": ([_vp, C.POINTER(MspInfo)], _i),
     "msp_footprint": ([_i, _ll, _i, C.POINTER(MspOptions), C.POINTER(C.c_size_t)], _i),
     "msp_destroy": ([_vp], _i),
@@ -374,6 +375,30 @@ class Solver:
         fn = self._lib.msp_stage_get_bilu_f32 if f32 else self._lib.msp_stage_get_bilu
         _check(fn(self.h, F.ctypes.data_as(C.c_void_p), D.ctypes.data_as(C.c_void_p)), "bilu")
         return F.reshape(-1, self.b, self.b), D.reshape(self.n, self.b, self.b)
+
+
+def solve_batch(solvers, rhs, xs, rtol=1e-6):
+    """msp_solve_batch over several Solver contexts (same device): rhs and xs
+    are lists of device float64 tensors (xs updated in place); returns the
+    list of info dicts."""
+    import torch
+    k = len(solvers)
+    if not (k == len(rhs) == len(xs)) or k == 0:
+        raise ValueError("solve_batch needs equally many solvers, rhs and x")
+    ctx = (C.c_void_p * k)(*[s.h.value for s in solvers])
+    rp = (C.c_void_p * k)(*[t.data_ptr() for t in rhs])
+    xp = (C.c_void_p * k)(*[t.data_ptr() for t in xs])
+    infos = (MspInfo * k)()
+    with torch.cuda.device(solvers[0].device):
+        code = lib().msp_solve_batch(C.cast(ctx, C.c_void_p), k, C.cast(rp, C.c_void_p),
+                                     C.cast(xp, C.c_void_p), float(rtol),
+                                     C.cast(infos, C.c_void_p))
+    _check(code, "solve_batch")
+    out = []
+    for i in range(k):
+        d = infos[i].as_dict()
+        out.append(d)
+    return out
 
 
 def footprint(n, nnzb, b, mu=0, restart=30, max_coarse=10000, precond_fp32=False):

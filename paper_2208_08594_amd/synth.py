@@ -265,6 +265,81 @@ def serving_system(r: int, side: int | None = None, b: int | None = None) -> BSR
                           f"req{r}_{side}^3_b{b}")
 
 
+class DevicePatterns:
+    """Device copies of the 7-point cube patterns (one per side), reused by
+    every request of that side."""
+
+    def __init__(self, device):
+        self.device = device
+        self._cache = {}
+
+    def get(self, side):
+        import torch
+        if side not in self._cache:
+            rp, ci, direction, diag_pos = _stencil(side, side, side)
+            dev = self.device
+            self._cache[side] = dict(
+                row_ptr=torch.as_tensor(rp.astype(np.int32), device=dev),
+                col_ind=torch.as_tensor(ci.astype(np.int32), device=dev),
+                direction=torch.as_tensor(direction, device=dev),
+                diag_pos=torch.as_tensor(diag_pos, device=dev),
+                rows=torch.as_tensor(np.repeat(np.arange(len(rp) - 1), np.diff(rp)),
+                                     device=dev))
+        return self._cache[side]
+
+
+def serving_system_device(r: int, side: int, b: int, patterns: "DevicePatterns", p: int = 0):
+    """First Newton step of serving request r generated on the GPU with torch:
+    the same law as serving_system (lognormal k with sigma 1, accumulation
+    U[0.5, 2], coupling U[-0.1, 0.1] with zero diagonal, harmonic
+    transmissibilities, two corner wells, rhs U[-1, 1]) drawn from a torch
+    generator seeded with 1000 + r (other numbers than numpy's).  Serving
+    requests up to 96^3 cells with b = 7 hold 2.4 GB of values, which is why
+    they are drawn where they are solved.  Returns a dict of device tensors:
+    row_ptr, col_ind (int32), vals (float64, nnzb*b*b), rhs (float64, n*b),
+    keep (bool, nnzb*b*b: entries of the Dirichlet rows), and n, b, p."""
+    import torch
+    P = patterns.get(side)
+    dev = patterns.device
+    n = side ** 3
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1000 + r)
+    f64 = torch.float64
+    logk = torch.randn(n, generator=gen, device=dev, dtype=f64)
+    acc = 0.5 + 1.5 * torch.rand(n, generator=gen, device=dev, dtype=f64)
+    Cc = -0.1 + 0.2 * torch.rand((n, b, b), generator=gen, device=dev, dtype=f64)
+    Cc.diagonal(dim1=1, dim2=2).zero_()
+    rhs = 2.0 * torch.rand(n * b, generator=gen, device=dev, dtype=f64) - 1.0
+    k = torch.exp(logk)
+    rows, cols, direction = P["rows"], P["col_ind"].long(), P["direction"]
+    off = direction != 3
+    kr, kc = k[rows], k[cols]
+    T = torch.where(off, 2.0 * kr * kc / (kr + kc), torch.zeros_like(kr))
+    # per-cell sums in a fixed order (an index_add would use atomics)
+    T7 = torch.zeros((n, 7), device=dev, dtype=f64)
+    T7[rows, direction.long()] = T
+    Tsum = T7.sum(dim=1)
+    K = torch.zeros((b, b), device=dev, dtype=f64)
+    K[:, p] = 1.0
+    idx = torch.arange(b, device=dev)
+    K[idx, idx] += torch.tensor([0.0 if q == p else EPS_COUPLING for q in range(b)],
+                                device=dev, dtype=f64)
+    vals = -T[:, None, None] * K[None]
+    dpos = P["diag_pos"]
+    vals[dpos] = acc[:, None, None] * torch.eye(b, device=dev, dtype=f64)[None] + Cc \
+        + Tsum[:, None, None] * K[None]
+    keep = torch.zeros(vals.shape, dtype=torch.bool, device=dev)
+    rp = P["row_ptr"].long()
+    for c in corner_wells(side, side, side):
+        lo, hi = int(rp[c]), int(rp[c + 1])
+        vals[lo:hi, p, :] = 0.0
+        keep[lo:hi, p, :] = True
+    for c in corner_wells(side, side, side):
+        vals[dpos[c], p, p] = 1.0
+    return dict(row_ptr=P["row_ptr"], col_ind=P["col_ind"], vals=vals.reshape(-1),
+                rhs=rhs, keep=keep.reshape(-1), n=n, b=b, p=p)
+
+
 def newton_step(sys: BSRSystem, step: int, seed: int) -> BSRSystem:
     """Next Newton step of a request: every stored scalar outside the Dirichlet
     rows is scaled by (1 + 0.05 u), u ~ U[-1, 1]; a fresh rhs is drawn."""
