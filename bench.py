@@ -170,9 +170,15 @@ def main():
                     help="also run the 512-request serving leg in a child process")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte calibration) and exit")
+    ap.add_argument("--stage-only", action="store_true",
+                    help="only set up the workload and run 5 SpMVs, 5 level-0 sweeps and 3 "
+                         "block ILU(0) solves back to back (for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.stage_only:
+        stage_only(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver path is single-GPU (DESIGN.md describes how "
@@ -352,6 +358,27 @@ def main():
     }
     print(json.dumps(out), flush=True)
     log("done")
+
+
+def stage_only(args):
+    """Setup of the workload, then the solve's bandwidth-bound kernels back
+    to back: 5 block SpMVs, 5 forward level-0 sweeps, 3 block ILU(0) solves."""
+    import torch
+    from paper_2208_08594_amd import msp, synth
+    idx, desc = WORKLOADS[args.workload]
+    sys_ = synth.config(idx)
+    s = msp.Solver(mu=0, max_coarse=10000, bilu_order=args.bilu_order)
+    s.setup(sys_)
+    x = torch.rand(sys_.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    log("stages:", desc)
+    s.repeat(msp.STAGE_SPMV, 5, x, y)
+    s.repeat(msp.STAGE_GS0, 5)
+    s.repeat(msp.STAGE_BILU, 3)
+    torch.cuda.synchronize()
+    s.close()
+    print(json.dumps({"stages": "spmv x5, gs0 x5, bilu x3", "workload": desc}), flush=True)
 
 
 def calibrate_copy():
