@@ -167,7 +167,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="(default; kept for old commands)")
     ap.add_argument("--serving", action="store_true",
-                    help="also run the 512-request serving leg in a child process")
+                    help="also run the 512-request serving leg in a child process (refused for now: "
+                         "that run crashed the serving process; see serve.MAX_SERVED_REQUESTS)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte calibration) and exit")
     ap.add_argument("--stage-only", action="store_true",

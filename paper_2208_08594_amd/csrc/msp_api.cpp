@@ -461,25 +461,25 @@ void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
     L.iperm_d = c->upload(L.iperm, c->allocB);
 }
 
-void link_levels(msp_ctx *c)
+// Aggregation maps between level l and level l + 1 in position space (both
+// levels' device arrays built).
+void link_level(msp_ctx *c, int l)
 {
-    for (size_t l = 0; l + 1 < c->lev.size(); ++l) {
-        Level &L = c->lev[l];
-        const Level &C = c->lev[l + 1];
-        std::vector<int> &agg_pos = L.agg_pos_h, &mptr = L.mem_ptr_h, &mem = L.mem_h;
-        agg_pos.assign(L.n, 0);
-        for (int t = 0; t < L.n; ++t) agg_pos[t] = C.perm[L.agg[L.iperm[t]]];
-        // members of each coarse position, natural fine index ascending
-        mptr.assign(C.n + 1, 0);
-        mem.assign(L.n, 0);
-        for (int i = 0; i < L.n; ++i) ++mptr[C.perm[L.agg[i]] + 1];
-        for (int J = 0; J < C.n; ++J) mptr[J + 1] += mptr[J];
-        std::vector<int> f(mptr.begin(), mptr.end() - 1);
-        for (int i = 0; i < L.n; ++i) mem[f[C.perm[L.agg[i]]]++] = L.perm[i];
-        L.agg_pos = c->upload(agg_pos, c->allocB);
-        L.mem_ptr = c->upload(mptr, c->allocB);
-        L.mem = c->upload(mem, c->allocB);
-    }
+    Level &L = c->lev[l];
+    const Level &C = c->lev[l + 1];
+    std::vector<int> &agg_pos = L.agg_pos_h, &mptr = L.mem_ptr_h, &mem = L.mem_h;
+    agg_pos.assign(L.n, 0);
+    for (int t = 0; t < L.n; ++t) agg_pos[t] = C.perm[L.agg[L.iperm[t]]];
+    // members of each coarse position, natural fine index ascending
+    mptr.assign(C.n + 1, 0);
+    mem.assign(L.n, 0);
+    for (int i = 0; i < L.n; ++i) ++mptr[C.perm[L.agg[i]] + 1];
+    for (int J = 0; J < C.n; ++J) mptr[J + 1] += mptr[J];
+    std::vector<int> f(mptr.begin(), mptr.end() - 1);
+    for (int i = 0; i < L.n; ++i) mem[f[C.perm[L.agg[i]]]++] = L.perm[i];
+    L.agg_pos = c->upload(agg_pos, c->allocB);
+    L.mem_ptr = c->upload(mptr, c->allocB);
+    L.mem = c->upload(mem, c->allocB);
 }
 
 // Streams of the coarsest-level solver: the update stream and the stream of
@@ -1072,20 +1072,6 @@ void rebuild_B(msp_ctx *c, const double *vals)
         }
         phase(6);
         c->lev.resize(nlev);
-        for (int l = 0; l + 1 < nlev; ++l) {
-            Groups G;
-            if (l == 0) {
-                G = groups0.get();
-                lays[0] = layout0.get();
-            } else {
-                LevelWork W = work[l].get();
-                G = std::move(W.G);
-                lays[l] = std::move(W.lay);
-            }
-            c->lev[l].color = std::move(G.color);
-            c->lev[l].g = G.g;
-        }
-        phase(7);
         for (int l = 0; l < nlev; ++l) {
             Level &L = c->lev[l];
             L.A = std::move(H.A[l]);
@@ -1094,9 +1080,48 @@ void rebuild_B(msp_ctx *c, const double *vals)
             if (l + 1 < nlev) L.agg = std::move(H.agg[l]);
         }
         for (int l = 0; l + 1 < nlev; ++l) c->lev[l].nc = c->lev[l + 1].A.n;
-        for (int l = 0; l < nlev; ++l) build_level_device(c, l, l == nlev - 1, &lays[l]);
-        link_levels(c);
-        phase(4);
+        // Each level's device arrays are built as soon as its host work is
+        // done (the largest coarse level's groups usually end last), and the
+        // maps between two levels as soon as both exist.
+        std::vector<char> built(nlev, 0);
+        auto ready = [&](int l) {
+            if (l == nlev - 1) return true;
+            std::future_status st = l == 0 ? layout0.wait_for(std::chrono::seconds(0))
+                                           : work[l].wait_for(std::chrono::seconds(0));
+            return st == std::future_status::ready;
+        };
+        auto build = [&](int l) {
+            if (l + 1 < nlev) {
+                Groups G;
+                if (l == 0) {
+                    G = groups0.get();
+                    lays[0] = layout0.get();
+                } else {
+                    LevelWork W = work[l].get();
+                    G = std::move(W.G);
+                    lays[l] = std::move(W.lay);
+                }
+                c->lev[l].color = std::move(G.color);
+                c->lev[l].g = G.g;
+                phase(7);
+            }
+            build_level_device(c, l, l == nlev - 1, &lays[l]);
+            built[l] = 1;
+            if (l > 0 && built[l - 1]) link_level(c, l - 1);
+            if (l + 1 < nlev && built[l + 1]) link_level(c, l);
+            phase(4);
+        };
+        for (int left = nlev; left > 0;) {
+            int next = -1;
+            for (int l = 0; l < nlev && next < 0; ++l)
+                if (!built[l] && ready(l)) next = l;
+            if (next < 0) {  // none ready yet
+                std::this_thread::sleep_for(std::chrono::microseconds(100));
+                continue;
+            }
+            build(next);
+            --left;
+        }
     }
     coarse_queued.get();
     HIPCHK(hipStreamWaitEvent(c->stream, c->gj.ev_done, 0));

@@ -300,11 +300,22 @@ def calibrate(n_req=12, steps=4, sides=None, mu=10, precond_fp32=False):
     return (time.perf_counter() - t) / len(cal)
 
 
+# Runs of the full mix ended with a segmentation fault of the serving
+# process after about 150 requests (at a torch call that draws a request's
+# matrix); its cause is not yet found, so runs longer than the largest one
+# that has completed are refused.
+MAX_SERVED_REQUESTS = 128
+
+
 def serve_mix(n_req=512, load=0.7, steps=4, slots=16, mu=10, max_side=96, precond_fp32=False,
               seed=0):
     """The serving workload: n_req requests with Poisson arrivals at `load`
     times the measured single-stream capacity, cubes of side in the serving
     set up to max_side, b in 3..7, `steps` Newton steps each."""
+    if n_req > MAX_SERVED_REQUESTS:
+        raise RuntimeError(f"serving runs of more than {MAX_SERVED_REQUESTS} requests are "
+                           "disabled: the 512-request mix crashed the serving process after "
+                           "about 150 requests and the cause is not yet found")
     sides = [s for s in synth.SERVING_SIDES if s <= max_side]
     per_req = calibrate(steps=steps, sides=sides, mu=mu, precond_fp32=precond_fp32)
     rate = load / per_req
