@@ -335,19 +335,18 @@ void *alloc_vec(msp_ctx *c, long long n)
     return c->dalloc(sizeof(T) * (size_t)std::max<long long>(n, 1), c->allocB);
 }
 
-// Host layout of a smoothed level: positions (color 1 rows ascending, then
-// color 2, ... -- the PGS-MC groups), the sliced layout of the off-diagonal
-// entries in position space and the packed values in the preconditioner
-// precision.  Pure host work on plain arrays, so it runs on worker threads.
+// Host plan of a smoothed level: positions (color 1 rows ascending, then
+// color 2, ... -- the PGS-MC groups) and the slice table of the off-diagonal
+// entries in position space.  Pure host work on the pattern, so it runs on
+// worker threads; the entries themselves are laid out on the device
+// (launch_level_fill) from the level's CSR.
 struct LevelLayout {
     std::vector<int> perm, iperm, seg_row;
-    SellLayout lay;
-    std::vector<double> v64, d64;
-    std::vector<float> v32, d32;
+    SellLayout lay;  // slice table only (col and src are built on the device)
 };
 
-void level_layout(int n, const int *rp, const int *ci, const double *val,
-                  const std::vector<int> &color, int g, bool fp32, LevelLayout &O)
+void level_layout(int n, const int *rp, const int *ci, const std::vector<int> &color, int g,
+                  LevelLayout &O)
 {
     O.perm.assign(n, 0);
     O.iperm.assign(n, 0);
@@ -363,57 +362,24 @@ void level_layout(int n, const int *rp, const int *ci, const double *val,
             O.iperm[t] = i;
         }
     }
-    // off-diagonal entries per position (row i = iperm[t] keeps its order),
-    // counted first so that row chunks fill their own ranges in parallel
-    const int parts = host_parts(n);
-    std::vector<int> ent_ptr(n + 1, 0);
-    std::vector<double> diag(n, 0.0);
-    for_chunks(n, parts, [&](int lo, int hi, int) {
+    // off-diagonal entries of the row at each position
+    std::vector<int> cnt(n);
+    for_chunks(n, host_parts(n), [&](int lo, int hi, int) {
         for (int t = lo; t < hi; ++t) {
             const int i = O.iperm[t];
             int m = 0;
             for (int k = rp[i]; k < rp[i + 1]; ++k) m += ci[k] != i;
-            ent_ptr[t + 1] = m;
+            cnt[t] = m;
         }
     });
-    for (int t = 0; t < n; ++t) ent_ptr[t + 1] += ent_ptr[t];
-    std::vector<int> ent_col(ent_ptr[n]), ent_src(ent_ptr[n]);
-    for_chunks(n, parts, [&](int lo, int hi, int) {
-        for (int t = lo; t < hi; ++t) {
-            const int i = O.iperm[t];
-            int o = ent_ptr[t];
-            for (int k = rp[i]; k < rp[i + 1]; ++k) {
-                const int j = ci[k];
-                if (j == i) {
-                    diag[t] = val[k];
-                } else {
-                    ent_col[o] = O.perm[j];
-                    ent_src[o] = k;
-                    ++o;
-                }
-            }
-        }
-    });
-    build_sell(n, O.seg_row, ent_ptr, ent_col, ent_src, O.lay);
-    const long long sl = O.lay.slot_lanes;
-    const int nsl = (int)(sl / 64);
-    if (fp32) {
-        O.v32.assign(sl, 0.0f);
-        O.d32.resize(n);
-        for_chunks(nsl, parts, [&](int lo, int hi, int) {
-            for (long long q = (long long)lo * 64; q < (long long)hi * 64; ++q)
-                if (O.lay.src[q] >= 0) O.v32[q] = (float)val[O.lay.src[q]];
-        });
-        for (int t = 0; t < n; ++t) O.d32[t] = (float)diag[t];
-    } else {
-        O.v64.assign(sl, 0.0);
-        for_chunks(nsl, parts, [&](int lo, int hi, int) {
-            for (long long q = (long long)lo * 64; q < (long long)hi * 64; ++q)
-                if (O.lay.src[q] >= 0) O.v64[q] = val[O.lay.src[q]];
-        });
-        O.d64 = std::move(diag);
-    }
+    sell_slices(n, O.seg_row, cnt, O.lay);
 }
+
+// Device copy of a level's natural-order CSR (the source of its layout).
+struct LevelCsr {
+    const int *rp = nullptr, *ci = nullptr;
+    const double *val = nullptr;
+};
 
 // Lanes per row for the sweeps and residuals of a smoothed level.  A level
 // whose rows hold more stored entries than one batch of loads (the coarse
@@ -429,7 +395,7 @@ int row_lanes(const SellLayout &lay)
 
 // Device arrays of level l (its layout computed by level_layout unless it is
 // the coarsest level, whose positions are the natural order).
-void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
+void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay, const LevelCsr &csr)
 {
     Level &L = c->lev[l];
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
@@ -449,16 +415,28 @@ void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay)
     L.seg_row = std::move(lay->seg_row);
     L.S.lay = std::move(lay->lay);
     L.S.lanes = row_lanes(L.S.lay);
-    upload_sell(c, L.S, c->allocB);
+    DevSell &S = L.S;
+    S.slices_h.resize(S.lay.slice_row0.size());
+    for (size_t q = 0; q < S.slices_h.size(); ++q)
+        S.slices_h[q] = make_int4(S.lay.slice_row0[q], S.lay.slice_rows[q], S.lay.slice_width[q],
+                                  S.lay.slice_off[q]);
+    S.slices = c->upload(S.slices_h, c->allocB);
+    const long long sl = std::max<long long>(S.lay.slot_lanes, 1);
+    S.col = (int *)c->dalloc(sizeof(int) * sl, c->allocB);
+    S.src = (int *)c->dalloc(sizeof(int) * sl, c->allocB);
+    void *vals, *diag;
     if (c->fp32()) {
-        L.val32 = c->upload(lay->v32, c->allocB);
-        L.diag32 = c->upload(lay->d32, c->allocB);
+        vals = L.val32 = (float *)c->dalloc(sizeof(float) * sl, c->allocB);
+        diag = L.diag32 = (float *)c->dalloc(sizeof(float) * std::max(L.n, 1), c->allocB);
     } else {
-        L.val64 = c->upload(lay->v64, c->allocB);
-        L.diag64 = c->upload(lay->d64, c->allocB);
+        vals = L.val64 = (double *)c->dalloc(sizeof(double) * sl, c->allocB);
+        diag = L.diag64 = (double *)c->dalloc(sizeof(double) * std::max(L.n, 1), c->allocB);
     }
     L.perm_d = c->upload(L.perm, c->allocB);
     L.iperm_d = c->upload(L.iperm, c->allocB);
+    HIPCHK(launch_level_fill(c->fp32(), (int)S.slices_h.size(), S.slices, csr.rp, csr.ci, csr.val,
+                             L.perm_d, L.iperm_d, S.col, S.src, vals, diag,
+                             c->copy_stream ? c->copy_stream : c->stream));
 }
 
 // Aggregation maps between level l and level l + 1 in position space (both
@@ -628,8 +606,8 @@ bool coarse_solve_accurate(msp_ctx *c, std::vector<void *> &tmp)
 // levels, factorisation tasks and the sliced layouts of L and U.  Touches no
 // device state, so it can run on a second host thread.
 struct BiluPlan {
-    IVecU lt_ptr, lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
-    std::vector<int> dsrc;
+    std::vector<int> pos;   // elimination position of each block row
+    std::vector<int> dsrc;  // per U slice-lane: block row (for the pivot inverses)
 };
 
 // color/g: the Alg. 4.2 groups of the block pattern (used for the
@@ -648,7 +626,8 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
     } else {
         std::iota(D.ord.begin(), D.ord.end(), 0);
     }
-    std::vector<int> pos(n);
+    std::vector<int> &pos = P.pos;
+    pos.resize(n);
     for (int t = 0; t < n; ++t) pos[D.ord[t]] = t;
     const int *rp = c->rp.data(), *ci = c->ci.data();
     {
@@ -663,122 +642,24 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
         levels(true, D.fwd_rows, D.fwd_ptr);
         bwd.get();
     }
-    // factorisation tasks per block row: lower entries in elimination order and
-    // their update pairs (F_ij -= F_ik F_kj for stored j after k, (k,j) stored:
-    // the merge of rows i and k), built per row chunk and joined in order
+    // slice tables of the lower (forward levels) and upper (backward levels)
+    // parts; the entries themselves are laid out on the device (launch_tri_fill)
     const int parts = host_parts(n);
-    struct Part {
-        std::vector<int> rowcnt, lt_kk, lt_k, lt_pp, pr_jj, pr_kj;
-    };
-    std::vector<Part> part(parts);
-    for_chunks(n, parts, [&](int lo, int hi, int t) {
-        Part &Q = part[t];
-        std::vector<int> low;
-        for (int i = lo; i < hi; ++i) {
-            low.clear();
-            for (int q = rp[i]; q < rp[i + 1]; ++q) {
-                if (pos[ci[q]] >= pos[i]) continue;
-                size_t u = low.size();  // insertion by elimination position
-                low.push_back(q);
-                while (u > 0 && pos[ci[low[u - 1]]] > pos[ci[q]]) {
-                    low[u] = low[u - 1];
-                    --u;
-                }
-                low[u] = q;
-            }
-            Q.rowcnt.push_back((int)low.size());
-            for (int kk : low) {
-                const int k = ci[kk];
-                Q.lt_kk.push_back(kk);
-                Q.lt_k.push_back(k);
-                Q.lt_pp.push_back((int)Q.pr_jj.size());
-                int x = rp[i], y = rp[k];
-                const int xe = rp[i + 1], ye = rp[k + 1];
-                while (x < xe && y < ye) {
-                    const int jx = ci[x], jy = ci[y];
-                    if (jx < jy) {
-                        ++x;
-                    } else if (jy < jx) {
-                        ++y;
-                    } else {
-                        if (pos[jx] > pos[k]) {
-                            Q.pr_jj.push_back(x);
-                            Q.pr_kj.push_back(y);
-                        }
-                        ++x;
-                        ++y;
-                    }
-                }
-            }
-        }
-    });
-    // join the chunks: offsets first, then each chunk copies its own part
-    std::vector<size_t> tbase(parts + 1, 0), pbase(parts + 1, 0);
-    for (int t = 0; t < parts; ++t) {
-        tbase[t + 1] = tbase[t] + part[t].lt_kk.size();
-        pbase[t + 1] = pbase[t] + part[t].pr_jj.size();
-    }
-    P.lt_ptr.assign(n + 1, 0);
-    {
-        int i = 0;
-        for (const Part &Q : part)
-            for (int cnt : Q.rowcnt) {
-                P.lt_ptr[i + 1] = P.lt_ptr[i] + cnt;
-                ++i;
-            }
-    }
-    P.lt_kk.resize(tbase[parts]);
-    P.lt_k.resize(tbase[parts]);
-    P.lt_pp.reserve(tbase[parts] + 1);
-    P.lt_pp.resize(tbase[parts]);
-    P.pr_jj.resize(pbase[parts]);
-    P.pr_kj.resize(pbase[parts]);
-    for_chunks(parts, parts, [&](int lo, int hi, int) {
-        for (int t = lo; t < hi; ++t) {
-            const Part &Q = part[t];
-            std::copy(Q.lt_kk.begin(), Q.lt_kk.end(), P.lt_kk.begin() + tbase[t]);
-            std::copy(Q.lt_k.begin(), Q.lt_k.end(), P.lt_k.begin() + tbase[t]);
-            for (size_t q = 0; q < Q.lt_pp.size(); ++q)
-                P.lt_pp[tbase[t] + q] = (int)pbase[t] + Q.lt_pp[q];
-            std::copy(Q.pr_jj.begin(), Q.pr_jj.end(), P.pr_jj.begin() + pbase[t]);
-            std::copy(Q.pr_kj.begin(), Q.pr_kj.end(), P.pr_kj.begin() + pbase[t]);
-        }
-    });
-    P.lt_pp.push_back((int)P.pr_jj.size());
-    // sliced layouts of the lower (forward levels) and upper (backward levels)
-    // parts, the entries of each row in elimination order
     auto make = [&](const std::vector<int> &rows, const std::vector<int> &lptr, bool lower,
                     SellLayout &lay) {
-        auto part_of = [&](int i, int j) { return lower ? pos[j] < pos[i] : pos[j] > pos[i]; };
-        std::vector<int> ent_ptr(n + 1, 0);
+        std::vector<int> cnt(n);
         for_chunks(n, parts, [&](int lo, int hi, int) {
             for (int r = lo; r < hi; ++r) {
-                const int i = rows[r];
-                int m = 0;
-                for (int q = rp[i]; q < rp[i + 1]; ++q) m += part_of(i, ci[q]);
-                ent_ptr[r + 1] = m;
-            }
-        });
-        for (int r = 0; r < n; ++r) ent_ptr[r + 1] += ent_ptr[r];
-        std::vector<int> ent_col(ent_ptr[n]), ent_src(ent_ptr[n]);
-        for_chunks(n, parts, [&](int lo, int hi, int) {
-            for (int r = lo; r < hi; ++r) {
-                const int i = rows[r], o = ent_ptr[r];
+                const int i = rows[r], pi = pos[i];
                 int m = 0;
                 for (int q = rp[i]; q < rp[i + 1]; ++q) {
-                    if (!part_of(i, ci[q])) continue;
-                    // insertion by elimination position (rows are short)
-                    int u = m++;
-                    while (u > 0 && pos[ci[ent_src[o + u - 1]]] > pos[ci[q]]) {
-                        ent_src[o + u] = ent_src[o + u - 1];
-                        --u;
-                    }
-                    ent_src[o + u] = q;
+                    const int pj = pos[ci[q]];
+                    m += lower ? pj < pi : pj > pi;
                 }
-                for (int u = 0; u < m; ++u) ent_col[o + u] = ci[ent_src[o + u]];
+                cnt[r] = m;
             }
         });
-        build_sell(n, lptr, ent_ptr, ent_col, ent_src, lay);
+        sell_slices(n, lptr, cnt, lay);
     };
     {
         auto up = std::async(std::launch::async,
@@ -801,29 +682,39 @@ void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P, std::vector<void *
     BiluData &D = c->bilu;
     const int n = c->n, b = c->b;
     const long long E = (long long)b * b;
+    const int *pos_d = c->upload(P.pos, tmp);
+    D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
+    D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
     BiluTasks T;
-    T.lt_ptr = c->upload(P.lt_ptr, tmp);
-    T.lt_kk = c->upload(P.lt_kk, tmp);
-    T.lt_k = c->upload(P.lt_k, tmp);
-    T.lt_pp = c->upload(P.lt_pp, tmp);
-    T.pr_jj = c->upload(P.pr_jj, tmp);
-    T.pr_kj = c->upload(P.pr_kj, tmp);
+    T.rp = c->rp_d;
+    T.ci = c->ci_d;
+    T.pos = pos_d;
     T.diag_pos = c->diag_d;
-    int *rows_d = c->upload(D.fwd_rows, tmp);
     D.F = (double *)c->dalloc(sizeof(double) * (size_t)(c->nnzb * E), c->allocB);
     D.Dinv = (double *)c->dalloc(sizeof(double) * (size_t)(n * E), c->allocB);
     HIPCHK(hipMemcpyAsync(D.F, vals, sizeof(double) * (size_t)(c->nnzb * E),
                           hipMemcpyDeviceToDevice, st));
     c->clear_flag(1);
     for (size_t lv = 0; lv + 1 < D.fwd_ptr.size(); ++lv) {
-        T.rows = rows_d + D.fwd_ptr[lv];
+        T.rows = D.fwd_rows_d + D.fwd_ptr[lv];
         T.nrows = D.fwd_ptr[lv + 1] - D.fwd_ptr[lv];
         HIPCHK(launch_bilu_factor_level(b, T, D.F, D.Dinv, c->flag + 1, st));
     }
-    upload_sell(c, D.L, c->allocB);
-    upload_sell(c, D.U, c->allocB);
-    D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
-    D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
+    // the two triangles' layouts, built on the device from the pattern
+    auto layout = [&](DevSell &S, const int *rows_d, bool lower) {
+        S.slices_h.resize(S.lay.slice_row0.size());
+        for (size_t q = 0; q < S.slices_h.size(); ++q)
+            S.slices_h[q] = make_int4(S.lay.slice_row0[q], S.lay.slice_rows[q],
+                                      S.lay.slice_width[q], S.lay.slice_off[q]);
+        S.slices = c->upload(S.slices_h, c->allocB);
+        const long long sl = std::max<long long>(S.lay.slot_lanes, 1);
+        S.col = (int *)c->dalloc(sizeof(int) * sl, c->allocB);
+        S.src = (int *)c->dalloc(sizeof(int) * sl, c->allocB);
+        HIPCHK(launch_tri_fill((int)S.slices_h.size(), S.slices, rows_d, c->rp_d, c->ci_d, pos_d,
+                               lower, S.col, S.src, st));
+    };
+    layout(D.L, D.fwd_rows_d, true);
+    layout(D.U, D.bwd_rows_d, false);
     D.dsrc = c->upload(P.dsrc, c->allocB);
     const long long dsl = (long long)P.dsrc.size();
     if (c->fp32()) {
@@ -983,8 +874,6 @@ void rebuild_B(msp_ctx *c, const double *vals)
         Groups G;
         LevelLayout lay;
     };
-    const bool fp32 = c->fp32();
-    const double *a0val = A0.val.data();
     const bool level0_smoothed = n > c->opt.max_coarse;
     std::shared_future<Groups> groups0 = std::async(std::launch::async, [c]() {
         Groups G;
@@ -994,11 +883,10 @@ void rebuild_B(msp_ctx *c, const double *vals)
     }).share();
     std::future<LevelLayout> layout0;
     if (level0_smoothed)
-        layout0 = std::async(std::launch::async, [c, groups0, a0_ready, a0val, fp32]() {
+        layout0 = std::async(std::launch::async, [c, groups0]() {
             const Groups &G = groups0.get();
-            a0_ready.get();
             LevelLayout O;
-            level_layout(c->n, c->rp.data(), c->ci.data(), a0val, G.color, G.g, fp32, O);
+            level_layout(c->n, c->rp.data(), c->ci.data(), G.color, G.g, O);
             return O;
         });
     BiluPlan plan;
@@ -1014,16 +902,15 @@ void rebuild_B(msp_ctx *c, const double *vals)
     // levels that the device chain produced are structurally symmetric (it
     // runs only on a symmetric level 0, and Galerkin products keep that)
     bool device_levels = false;
-    const LevelCallback start_level = [&work, &device_levels, fp32](
-                                          int l, int nl, const int *rp, const int *ci,
-                                          const double *val) {
+    const LevelCallback start_level = [&work, &device_levels](int l, int nl, const int *rp,
+                                                              const int *ci, const double *) {
         if (l == 0) return;  // level 0: the pattern's groups above
         const bool sym = device_levels;
-        work[l] = std::async(std::launch::async, [nl, rp, ci, val, fp32, sym]() {
+        work[l] = std::async(std::launch::async, [nl, rp, ci, sym]() {
             LevelWork W;
             Adjacency adj = build_adjacency(nl, rp, ci, sym);
             W.G.g = vertices_grouping(adj, W.G.color);
-            level_layout(nl, rp, ci, val, W.G.color, W.G.g, fp32, W.lay);
+            level_layout(nl, rp, ci, W.G.color, W.G.g, W.lay);
             return W;
         });
     };
@@ -1056,6 +943,19 @@ void rebuild_B(msp_ctx *c, const double *vals)
     std::vector<LevelLayout> lays(nlev);
     {
         CopyStreamScope on_side(c, c->side);
+        // the natural-order CSR of every smoothed level on the device, the
+        // source of its layout: level 0 is already there (pattern and
+        // decoupled values), the coarser levels are copied up now, while
+        // their groups (and the block ILU(0) plan) are still being computed
+        std::vector<LevelCsr> csr(nlev);
+        for (int l = 0; l + 1 < nlev; ++l) {
+            if (l == 0) {
+                csr[0] = LevelCsr{c->rp_d, c->ci_d, ap};
+            } else {
+                const Csr &A = H.A[l];
+                csr[l] = LevelCsr{c->upload(A.rp, tmp), c->upload(A.ci, tmp), c->upload(A.val, tmp)};
+            }
+        }
         // The R stage first: its plan needs only the level-0 groups, so it is
         // usually ready well before the coarse levels' host work, and its
         // uploads and factorisation then overlap that work.
@@ -1105,7 +1005,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
                 c->lev[l].g = G.g;
                 phase(7);
             }
-            build_level_device(c, l, l == nlev - 1, &lays[l]);
+            build_level_device(c, l, l == nlev - 1, &lays[l], csr[l]);
             built[l] = 1;
             if (l > 0 && built[l - 1]) link_level(c, l - 1);
             if (l + 1 < nlev && built[l + 1]) link_level(c, l);
@@ -1642,10 +1542,12 @@ void ungather(msp_ctx *c, const DevSell &S, const T *dev, long long E, T *out)
 {
     const long long sl = S.lay.slot_lanes;
     std::vector<T> h((size_t)(sl * E));
+    std::vector<int> src((size_t)sl);
     HIPCHK(hipMemcpyAsync(h.data(), dev, sizeof(T) * sl * E, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(src.data(), S.src, sizeof(int) * sl, hipMemcpyDeviceToHost, c->stream));
     c->sync();
     for (long long q = 0; q < sl; ++q) {
-        int s = S.lay.src[q];
+        int s = src[q];
         if (s < 0) continue;
         for (long long e = 0; e < E; ++e)
             out[(long long)s * E + e] = h[(q >> 6) * 64 * E + e * 64 + (q & 63)];

@@ -763,8 +763,8 @@ bool triangular_levels_groups(int n, const int *rp, const int *ci, const std::ve
     return true;
 }
 
-void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
-                const std::vector<int> &ent_col, const std::vector<int> &ent_src, SellLayout &L)
+void sell_slices(int nrows, const std::vector<int> &seg_row, const std::vector<int> &cnt,
+                 SellLayout &L)
 {
     L = SellLayout();
     L.nrows = nrows;
@@ -776,7 +776,7 @@ void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<in
         for (int r0 = seg_row[s]; r0 < seg_row[s + 1]; r0 += 64) {
             int rows = std::min(64, seg_row[s + 1] - r0);
             int w = 0;
-            for (int t = r0; t < r0 + rows; ++t) w = std::max(w, ent_ptr[t + 1] - ent_ptr[t]);
+            for (int t = r0; t < r0 + rows; ++t) w = std::max(w, cnt[t]);
             L.slice_row0.push_back(r0);
             L.slice_rows.push_back(rows);
             L.slice_width.push_back(w);
@@ -786,6 +786,15 @@ void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<in
     }
     L.seg_slice[nseg] = (int)L.slice_row0.size();
     L.slot_lanes = off;
+}
+
+void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
+                const std::vector<int> &ent_col, const std::vector<int> &ent_src, SellLayout &L)
+{
+    std::vector<int> cnt(nrows);
+    for (int t = 0; t < nrows; ++t) cnt[t] = ent_ptr[t + 1] - ent_ptr[t];
+    sell_slices(nrows, seg_row, cnt, L);
+    const long long off = L.slot_lanes;
     L.col.assign(off, -1);
     L.src.assign(off, -1);
     const int nsl = (int)L.slice_row0.size();

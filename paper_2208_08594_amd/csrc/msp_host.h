@@ -160,6 +160,10 @@ struct SellLayout {
 };
 // seg_row: segment boundaries over positions (size nseg+1); per position t its
 // entries ent_ptr[t]..ent_ptr[t+1] with columns ent_col and source ids ent_src.
+// The slice table alone (slice_* arrays, seg_slice, slot_lanes; col and src
+// left empty) for positions holding cnt[t] entries each.
+void sell_slices(int nrows, const std::vector<int> &seg_row, const std::vector<int> &cnt,
+                 SellLayout &L);
 void build_sell(int nrows, const std::vector<int> &seg_row, const std::vector<int> &ent_ptr,
                 const std::vector<int> &ent_col, const std::vector<int> &ent_src,
                 SellLayout &L);

@@ -34,6 +34,24 @@ hipError_t launch_ingest_bsr(int b, int p, long long slot_lanes, const int *src,
 // to float when dst32 != nullptr (RNE) else copying to dst64.
 hipError_t launch_gather_blocks(int b, long long slot_lanes, const int *src, const double *blocks,
                                 double *dst64, float *dst32, hipStream_t st);
+// Scalar level in position space from its natural-order CSR (rp, ci, val)
+// and the position maps perm (natural -> position) / iperm: slot k of the
+// row at position t (lane t - row0 of its slice) holds the k-th stored
+// off-diagonal entry of row iperm[t] in CSR order -- col = perm[j], src = its
+// CSR index, value converted to the level's precision (RNE for float) --
+// padding slots col = src = -1 and value 0; diag[t] = the row's diagonal
+// value (0 if not stored).  Same arrays as the host sliced layout of the
+// entries, built where the matrix already is.
+hipError_t launch_level_fill(bool fp32, int nslices, const int4 *slices, const int *rp,
+                             const int *ci, const double *val, const int *perm, const int *iperm,
+                             int *col, int *src, void *vals, void *diag, hipStream_t st);
+// Triangular part of the block pattern in a sliced layout: the rows of
+// `rows` (level order), slot k of the row at r holding its k-th stored entry
+// with pos[j] < pos[i] (lower) or pos[j] > pos[i] (upper) in elimination
+// order -- col = j, src = its BSR index; padding col = src = -1.
+hipError_t launch_tri_fill(int nslices, const int4 *slices, const int *rows, const int *rp,
+                           const int *ci, const int *pos, bool lower, int *col, int *src,
+                           hipStream_t st);
 hipError_t launch_check_finite(const double *x, long long n, int *bad, hipStream_t st);
 // Sets *bad to 1 if a[i] != b[i] for some i < n.
 hipError_t launch_diff_i32(const int *a, const int *b, long long n, int *bad, hipStream_t st);
@@ -47,15 +65,16 @@ hipError_t launch_decouple(int b, int p, int n, const int *rp, const int *diag_p
                            hipStream_t st);
 
 // ---- block ILU(0) factorisation ----------------------------------------
+// One dependency level of the block ILU(0) factorisation.  Row i takes its
+// stored lower entries (k, pos[k] < pos[i]) in elimination order, and for
+// each: F_ik <- F_ik Dinv_k, then F_ij -= F_ik F_kj for every column j stored
+// in both rows with pos[j] > pos[k], in ascending j (a merge of the two
+// sorted rows); finally Dinv_i = F_ii^{-1}.  rp/ci: the block pattern (rows
+// sorted by column), pos: elimination position of each block row.
 struct BiluTasks {
-    const int *rows = nullptr;     // block rows of this level
+    const int *rows = nullptr;  // block rows of this level
     int nrows = 0;
-    const int *lt_ptr = nullptr;   // per block row: lower tasks [lt_ptr[i], lt_ptr[i+1])
-    const int *lt_kk = nullptr;    // BSR slot of F_ik
-    const int *lt_k = nullptr;     // k
-    const int *lt_pp = nullptr;    // first update pair of the task (size ntasks+1)
-    const int *pr_jj = nullptr;    // slot of F_ij
-    const int *pr_kj = nullptr;    // slot of F_kj
+    const int *rp = nullptr, *ci = nullptr, *pos = nullptr;
     const int *diag_pos = nullptr;
 };
 hipError_t launch_bilu_factor_level(int b, const BiluTasks &t, double *F, double *Dinv, int *bad,

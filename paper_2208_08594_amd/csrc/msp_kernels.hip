@@ -119,6 +119,51 @@ __global__ __launch_bounds__(kThreads) void k_gather_blocks(long long slot_lanes
     }
 }
 
+// one thread per (slice, lane); lanes past the slice's rows pad every slot
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_level_fill(int nslices,
+                                                        const int4 *__restrict__ slices,
+                                                        const int *__restrict__ rp,
+                                                        const int *__restrict__ ci,
+                                                        const double *__restrict__ val,
+                                                        const int *__restrict__ perm,
+                                                        const int *__restrict__ iperm,
+                                                        int *__restrict__ col,
+                                                        int *__restrict__ src,
+                                                        T *__restrict__ vals,
+                                                        T *__restrict__ diag)
+{
+    const long long g = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const int s = (int)(g >> 6), lane = (int)(g & 63);
+    if (s >= nslices) return;
+    const int4 d = slices[s];  // row0, rows, width, slot-lane offset
+    int m = 0;
+    if (lane < d.y) {
+        const int t = d.x + lane;
+        const int i = iperm[t];
+        T dv = 0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = ci[k];
+            if (j == i) {
+                dv = (T)val[k];
+            } else {
+                const long long q = (long long)d.w + (long long)m * 64 + lane;
+                col[q] = perm[j];
+                src[q] = k;
+                vals[q] = (T)val[k];
+                ++m;
+            }
+        }
+        diag[t] = dv;
+    }
+    for (; m < d.z; ++m) {
+        const long long q = (long long)d.w + (long long)m * 64 + lane;
+        col[q] = -1;
+        src[q] = -1;
+        vals[q] = 0;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_diff_i32(const int *__restrict__ a,
                                                        const int *__restrict__ b, long long n,
                                                        int *bad)
@@ -338,8 +383,21 @@ __global__ __launch_bounds__(64) void k_bilu_factor(BiluTasks t, double *__restr
     int idx = blockIdx.x * 64 + threadIdx.x;
     if (idx >= t.nrows) return;
     const int i = t.rows[idx];
-    for (int task = t.lt_ptr[i]; task < t.lt_ptr[i + 1]; ++task) {
-        const int kk = t.lt_kk[task], k = t.lt_k[task];
+    const int r0 = t.rp[i], r1 = t.rp[i + 1], pi = t.pos[i];
+    int last = -1;  // elimination position of the last lower entry taken
+    for (;;) {
+        // the next stored lower entry in elimination order
+        int kk = -1, pk = pi;
+        for (int q = r0; q < r1; ++q) {
+            const int pj = t.pos[t.ci[q]];
+            if (pj > last && pj < pk) {
+                pk = pj;
+                kk = q;
+            }
+        }
+        if (kk < 0) break;
+        last = pk;
+        const int k = t.ci[kk];
         double L[E], P[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) L[e] = F[(long long)kk * E + e];
@@ -355,27 +413,43 @@ __global__ __launch_bounds__(64) void k_bilu_factor(BiluTasks t, double *__restr
             }
 #pragma unroll
         for (int e = 0; e < E; ++e) F[(long long)kk * E + e] = P[e];
-        for (int pr = t.lt_pp[task]; pr < t.lt_pp[task + 1]; ++pr) {
-            const double *Fkj = F + (long long)t.pr_kj[pr] * E;
-            double *Fij = F + (long long)t.pr_jj[pr] * E;
-            double K[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) K[e] = Fkj[e];
-#pragma unroll
-            for (int r = 0; r < B; ++r) {
-                double row[B];
-#pragma unroll
-                for (int s = 0; s < B; ++s) row[s] = Fij[r * B + s];
-#pragma unroll
-                for (int s = 0; s < B; ++s) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int u = 0; u < B; ++u) acc += P[r * B + u] * K[u * B + s];
-                    row[s] -= acc;
-                }
-#pragma unroll
-                for (int s = 0; s < B; ++s) Fij[r * B + s] = row[s];
+        // columns stored in both rows i and k, eliminated after k
+        int x = r0, y = t.rp[k];
+        const int ye = t.rp[k + 1];
+        while (x < r1 && y < ye) {
+            const int jx = t.ci[x], jy = t.ci[y];
+            if (jx < jy) {
+                ++x;
+                continue;
             }
+            if (jy < jx) {
+                ++y;
+                continue;
+            }
+            if (t.pos[jx] > pk) {
+                const double *Fkj = F + (long long)y * E;
+                double *Fij = F + (long long)x * E;
+                double K[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) K[e] = Fkj[e];
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    double row[B];
+#pragma unroll
+                    for (int s = 0; s < B; ++s) row[s] = Fij[r * B + s];
+#pragma unroll
+                    for (int s = 0; s < B; ++s) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int u = 0; u < B; ++u) acc += P[r * B + u] * K[u * B + s];
+                        row[s] -= acc;
+                    }
+#pragma unroll
+                    for (int s = 0; s < B; ++s) Fij[r * B + s] = row[s];
+                }
+            }
+            ++x;
+            ++y;
         }
     }
     double M[E], X[E];
@@ -385,6 +459,51 @@ __global__ __launch_bounds__(64) void k_bilu_factor(BiluTasks t, double *__restr
     if (!invert_block<B>(M, X)) atomicOr(bad, 1);
 #pragma unroll
     for (int e = 0; e < E; ++e) Dinv[(long long)i * E + e] = X[e];
+}
+
+// one thread per (slice, lane): the row's triangular entries by selection in
+// elimination order (rows are short), then padding up to the slice width
+__global__ __launch_bounds__(kThreads) void k_tri_fill(int nslices, const int4 *__restrict__ slices,
+                                                      const int *__restrict__ rows,
+                                                      const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const int *__restrict__ pos, int lower,
+                                                      int *__restrict__ col,
+                                                      int *__restrict__ src)
+{
+    const long long g = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const int s = (int)(g >> 6), lane = (int)(g & 63);
+    if (s >= nslices) return;
+    const int4 d = slices[s];  // first row, rows, width, slot-lane offset
+    int m = 0;
+    if (lane < d.y) {
+        const int i = rows[d.x + lane];
+        const int r0 = rp[i], r1 = rp[i + 1], pi = pos[i];
+        // lower: positions in (last, pi); upper: positions above last = pi
+        int last = lower ? -1 : pi;
+        const int lim = lower ? pi : 0x7fffffff;
+        for (;;) {
+            int qb = -1, pb = lim;
+            for (int q = r0; q < r1; ++q) {
+                const int pj = pos[ci[q]];
+                if (pj > last && pj < pb) {
+                    pb = pj;
+                    qb = q;
+                }
+            }
+            if (qb < 0) break;
+            last = pb;
+            const long long o = (long long)d.w + (long long)m * 64 + lane;
+            col[o] = ci[qb];
+            src[o] = qb;
+            ++m;
+        }
+    }
+    for (; m < d.z; ++m) {
+        const long long o = (long long)d.w + (long long)m * 64 + lane;
+        col[o] = -1;
+        src[o] = -1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1644,6 +1763,31 @@ hipError_t launch_gather_blocks(int b, long long slot_lanes, const int *src, con
     if (slot_lanes <= 0) return hipSuccess;
     MSP_SWITCH_B(b, (k_gather_blocks<B><<<blocks_for(slot_lanes), kThreads, 0, st>>>(
                         slot_lanes, src, blocks, dst64, dst32)));
+    return hipGetLastError();
+}
+
+hipError_t launch_level_fill(bool fp32, int nslices, const int4 *slices, const int *rp,
+                             const int *ci, const double *val, const int *perm, const int *iperm,
+                             int *col, int *src, void *vals, void *diag, hipStream_t st)
+{
+    if (nslices <= 0) return hipSuccess;
+    const unsigned nb = blocks_for((long long)nslices * 64);
+    if (fp32)
+        k_level_fill<float><<<nb, kThreads, 0, st>>>(nslices, slices, rp, ci, val, perm, iperm,
+                                                     col, src, (float *)vals, (float *)diag);
+    else
+        k_level_fill<double><<<nb, kThreads, 0, st>>>(nslices, slices, rp, ci, val, perm, iperm,
+                                                      col, src, (double *)vals, (double *)diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_fill(int nslices, const int4 *slices, const int *rows, const int *rp,
+                           const int *ci, const int *pos, bool lower, int *col, int *src,
+                           hipStream_t st)
+{
+    if (nslices <= 0) return hipSuccess;
+    k_tri_fill<<<blocks_for((long long)nslices * 64), kThreads, 0, st>>>(
+        nslices, slices, rows, rp, ci, pos, lower ? 1 : 0, col, src);
     return hipGetLastError();
 }
 
