@@ -903,7 +903,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     // runs only on a symmetric level 0, and Galerkin products keep that)
     bool device_levels = false;
     const LevelCallback start_level = [&work, &device_levels](int l, int nl, const int *rp,
-                                                              const int *ci, const double *) {
+                                                              const int *ci) {
         if (l == 0) return;  // level 0: the pattern's groups above
         const bool sym = device_levels;
         work[l] = std::async(std::launch::async, [nl, rp, ci, sym]() {

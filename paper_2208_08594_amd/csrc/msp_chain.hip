@@ -644,7 +644,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         if (main_calls && on_smoothed) {
             if (l > 0) join();
             const Csr &hc = H.A[l];
-            on_smoothed(l, hc.n, hc.rp.data(), hc.ci.data(), hc.val.data());
+            on_smoothed(l, hc.n, hc.rp.data(), hc.ci.data());
         }
         const int nc1 = X.pass(cur, have_s, X.a1);
         have_s = false;
@@ -697,14 +697,17 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                 const long long nnzc = hn.rp[Cd.n];
                 hn.ci.resize(nnzc);
                 hn.val.resize(nnzc);
-                if (nnzc) {
+                // the pattern first: the level's host work (its groups) needs
+                // only that, and starts while the values are copied
+                if (nnzc)
                     ck(hipMemcpyAsync(hn.ci.data(), Cd.ci, sizeof(int) * nnzc,
                                       hipMemcpyDeviceToHost, copy_st));
+                ck(hipStreamSynchronize(copy_st));
+                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), hn.ci.data());
+                if (nnzc)
                     ck(hipMemcpyAsync(hn.val.data(), Cd.val, sizeof(double) * nnzc,
                                       hipMemcpyDeviceToHost, copy_st));
-                }
                 ck(hipStreamSynchronize(copy_st));
-                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), hn.ci.data(), hn.val.data());
             });
         }
         main_calls = !next_smoothed;

@@ -628,7 +628,7 @@ int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hiera
         bool last = cur.n <= max_coarse || l == max_levels - 1 ||
                     (l > 0 && (double)cur.n > 0.9 * (double)H.A[l - 1].n);
         if (last) break;
-        if (on_smoothed) on_smoothed(l, cur.n, cur.rp.data(), cur.ci.data(), cur.val.data());
+        if (on_smoothed) on_smoothed(l, cur.n, cur.rp.data(), cur.ci.data());
         if (with_colors) {
             std::vector<int> color;
             H.ncolors.push_back(color_level(cur, color));

@@ -118,11 +118,12 @@ struct Hierarchy {
 };
 // with_colors = false leaves color/ncolors empty (the groups can then be
 // computed per level with color_level, e.g. on other threads); on_smoothed
-// (if set) is called with (l, n, row_ptr, col_ind, val) as soon as level l is
-// known to be a smoothed level.  The pointed-to arrays stay valid while H
-// lives; H.A grows meanwhile, so a callee must not keep a reference to the
-// Csr itself.
-using LevelCallback = std::function<void(int, int, const int *, const int *, const double *)>;
+// (if set) is called with (l, n, row_ptr, col_ind) as soon as level l is
+// known to be a smoothed level and its pattern is on the host (its values may
+// still be on their way).  The pointed-to arrays stay valid while H lives;
+// H.A grows meanwhile, so a callee must not keep a reference to the Csr
+// itself.
+using LevelCallback = std::function<void(int, int, const int *, const int *)>;
 int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                     bool with_colors = true, const LevelCallback &on_smoothed = nullptr);
 // The final checks of build_hierarchy: 0, -3 (zero diagonal on a smoothed
