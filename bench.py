@@ -117,7 +117,7 @@ def run_gpu(sys_, args, precond_fp32, steps, warmup):
     vals = torch.as_tensor(sys_.vals.reshape(-1), device=dev)
     rhs = torch.as_tensor(sys_.rhs, device=dev)
     x = torch.zeros(sys_.N, dtype=torch.float64, device=dev)
-    solver = msp.Solver(mu=0, restart=30, max_iter=1000, max_coarse=10000,
+    solver = msp.Solver(mu=0, restart=30, max_iter=1000, max_coarse=args.max_coarse,
                         precond_fp32=precond_fp32, bilu_order=args.bilu_order, stream=stream)
     solver.set_timing(True)
     infos, timings = [], []
@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--bilu-order", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--max-coarse", type=int, default=10000,
+                    help="largest coarsest AMG level (rows) solved directly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="(default; kept for old commands)")
@@ -321,7 +323,7 @@ def main():
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
-        cpu, x_or = cpu_baseline(sys_)
+        cpu, x_or = cpu_baseline(sys_, args.max_coarse)
         nx = np.linalg.norm(x_or)
         errors["fp64_precond_vs_oracle"] = float(np.linalg.norm(x64.numpy() - x_or) / nx)
         if x32 is not None:
@@ -335,7 +337,7 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "rtol": 1e-6, "restart": 30,
-                   "mu": 0, "max_coarse": 10000, "precond": "fp64",
+                   "mu": 0, "max_coarse": args.max_coarse, "precond": "fp64",
                    "bilu_order": "natural" if args.bilu_order == 0 else "multicolor"},
         "p50_ms": percentile(times, 50), "p99_ms": percentile(times, 99),
         "setup_ms": setup_ms, "solve_ms": solve_ms, "iterations": last["iterations"],
@@ -368,7 +370,7 @@ def stage_only(args):
     from paper_2208_08594_amd import msp, synth
     idx, desc = WORKLOADS[args.workload]
     sys_ = synth.config(idx)
-    s = msp.Solver(mu=0, max_coarse=10000, bilu_order=args.bilu_order)
+    s = msp.Solver(mu=0, max_coarse=args.max_coarse, bilu_order=args.bilu_order)
     s.setup(sys_)
     x = torch.rand(sys_.N, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
@@ -410,7 +412,7 @@ def serving_run():
     return json.loads(lines[-1])
 
 
-def cpu_baseline(sys_):
+def cpu_baseline(sys_, max_coarse=10000):
     """The oracle, as it is, on one full Newton step of the same system
     (setup + FGMRES to 1e-6) on one host thread; returns its record and x."""
     try:
@@ -423,7 +425,7 @@ def cpu_baseline(sys_):
     guard = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
     with guard:
         t0 = time.perf_counter()
-        s = O.OracleSolver()
+        s = O.OracleSolver(max_coarse=max_coarse)
         s.setup(sys_)
         t1 = time.perf_counter()
         x, it, rr, st = s.solve(sys_.rhs, 1e-6)
