@@ -116,8 +116,12 @@ struct NStage {
 struct BiluData {
     std::vector<int> ord;  // elimination order
     std::vector<int> fwd_rows, fwd_ptr, bwd_rows, bwd_ptr;
+    std::vector<int> fwd_vpos, bwd_vpos;  // elimination position of each level-ordered row
+    std::vector<char> fwd_live;           // forward level with at least one stored entry
     DevSell L, U;
     int *fwd_rows_d = nullptr, *bwd_rows_d = nullptr;
+    int *pos_d = nullptr;  // elimination position of each block row: the solves' vector order
+    int *fwd_vpos_d = nullptr, *bwd_vpos_d = nullptr;
     int *dsrc = nullptr;  // per U slice-lane: block row (for the pivot inverses)
     double *F = nullptr, *Dinv = nullptr;  // natural layout FP64
     double *L64 = nullptr, *U64 = nullptr, *D64 = nullptr;
@@ -671,6 +675,18 @@ void bilu_plan(const msp_ctx *c, const std::vector<int> &color, int g, BiluData 
     for (size_t s = 0; s < D.U.lay.slice_row0.size(); ++s)
         for (int l = 0; l < D.U.lay.slice_rows[s]; ++l)
             P.dsrc[s * 64 + l] = D.bwd_rows[D.U.lay.slice_row0[s] + l];
+    // the solves run on vectors in elimination order
+    D.fwd_vpos.resize(n);
+    D.bwd_vpos.resize(n);
+    for (int r = 0; r < n; ++r) {
+        D.fwd_vpos[r] = pos[D.fwd_rows[r]];
+        D.bwd_vpos[r] = pos[D.bwd_rows[r]];
+    }
+    // a forward level whose rows have no lower entries leaves y unchanged
+    D.fwd_live.assign(D.L.nseg(), 0);
+    for (int g2 = 0; g2 < D.L.nseg(); ++g2)
+        for (int q = D.L.lay.seg_slice[g2]; q < D.L.lay.seg_slice[g2 + 1]; ++q)
+            if (D.L.lay.slice_width[q] > 0) D.fwd_live[g2] = 1;
 }
 
 // Device part: factorise level by level and lay the factors out, on the side
@@ -682,9 +698,11 @@ void bilu_device(msp_ctx *c, const double *vals, BiluPlan &P, std::vector<void *
     BiluData &D = c->bilu;
     const int n = c->n, b = c->b;
     const long long E = (long long)b * b;
-    const int *pos_d = c->upload(P.pos, tmp);
+    const int *pos_d = D.pos_d = c->upload(P.pos, c->allocB);
     D.fwd_rows_d = c->upload(D.fwd_rows, c->allocB);
     D.bwd_rows_d = c->upload(D.bwd_rows, c->allocB);
+    D.fwd_vpos_d = c->upload(D.fwd_vpos, c->allocB);
+    D.bwd_vpos_d = c->upload(D.bwd_vpos, c->allocB);
     BiluTasks T;
     T.rp = c->rp_d;
     T.ci = c->ci_d;
@@ -1142,9 +1160,17 @@ void bilu_solve(msp_ctx *c, T *y)
         Lv = (const T *)D.L64; Uv = (const T *)D.U64; Dv = (const T *)D.D64;
     }
     for (int s = 0; s < D.L.nseg(); ++s)
-        HIPCHK(launch_bilu_fwd<T>(c->b, D.L.view(s), D.fwd_rows_d, Lv, y, c->stream));
+        if (D.fwd_live[s])
+            HIPCHK(launch_bilu_fwd<T>(c->b, D.L.view(s), D.fwd_vpos_d, Lv, y, c->stream));
     for (int s = 0; s < D.U.nseg(); ++s)
-        HIPCHK(launch_bilu_bwd<T>(c->b, D.U.view(s), D.bwd_rows_d, Uv, Dv, y, c->stream));
+        HIPCHK(launch_bilu_bwd<T>(c->b, D.U.view(s), D.bwd_vpos_d, Uv, Dv, y, c->stream));
+}
+
+// Block order of the R stage's vectors: elimination order for block ILU(0),
+// natural for block Jacobi.
+const int *r_order(const msp_ctx *c)
+{
+    return c->opt.full_smoother == 0 ? c->bilu.pos_d : nullptr;
 }
 
 template <typename T>
@@ -1173,11 +1199,10 @@ void apply_T(msp_ctx *c, const double *v_in, double *z)
     vcycle<T>(c, 0);
     HIPCHK(launch_unpermute<T>(c->n, L0.perm_d, (const T *)L0.x, (T *)c->e_nat, c->stream));
     HIPCHK(launch_pcol_residual<T>(c->b, c->p, c->SA.all(), c->valA, c->pcol32, v,
-                                   (const T *)c->e_nat, (T *)c->ybuf, c->stream));
+                                   (const T *)c->e_nat, r_order(c), (T *)c->ybuf, c->stream));
     bilu_solve<T>(c, (T *)c->ybuf);
-    HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, (const T *)c->e_nat,
-                            S.on ? S.w1 : nullptr, z,
-                            c->stream));
+    HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, r_order(c),
+                            (const T *)c->e_nat, S.on ? S.w1 : nullptr, z, c->stream));
 }
 
 void apply_eager(msp_ctx *c, const double *v, double *z)
@@ -1585,9 +1610,18 @@ template <typename T>
 void stage_bilu_T(msp_ctx *c, const double *r, double *z)
 {
     const long long N = (long long)c->n * c->b;
-    HIPCHK(launch_from_double<T>(N, r, (T *)c->ybuf, c->stream));
+    const int *ord = r_order(c);
+    if (ord)
+        HIPCHK(launch_perm_blocks<T>(c->n, c->b, ord, r, (T *)c->ybuf, nullptr, nullptr,
+                                     c->stream));
+    else
+        HIPCHK(launch_from_double<T>(N, r, (T *)c->ybuf, c->stream));
     bilu_solve<T>(c, (T *)c->ybuf);
-    HIPCHK(launch_to_double<T>(N, (const T *)c->ybuf, z, c->stream));
+    if (ord)
+        HIPCHK(launch_perm_blocks<T>(c->n, c->b, ord, nullptr, nullptr, z, (const T *)c->ybuf,
+                                     c->stream));
+    else
+        HIPCHK(launch_to_double<T>(N, (const T *)c->ybuf, z, c->stream));
 }
 
 // Record a finished solve in its context (iteration count for the adaptive

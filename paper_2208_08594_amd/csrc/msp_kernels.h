@@ -48,7 +48,8 @@ hipError_t launch_level_fill(bool fp32, int nslices, const int4 *slices, const i
 // Triangular part of the block pattern in a sliced layout: the rows of
 // `rows` (level order), slot k of the row at r holding its k-th stored entry
 // with pos[j] < pos[i] (lower) or pos[j] > pos[i] (upper) in elimination
-// order -- col = j, src = its BSR index; padding col = src = -1.
+// order -- col = pos[j] (the solves index their vectors by elimination
+// position), src = its BSR index; padding col = src = -1.
 hipError_t launch_tri_fill(int nslices, const int4 *slices, const int *rows, const int *rp,
                            const int *ci, const int *pos, bool lower, int *col, int *src,
                            hipStream_t st);
@@ -128,19 +129,32 @@ template <typename T>
 hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hipStream_t st);
 // r_c[k] = v_c[k] - sum_d A_cd[k][p] e_d; pcol64: FP64 A (E = b*b, entry k*b+p);
 // pcol32: FP32 pressure columns (E = b).
+// rperm (or nullptr): r is written in that block order, r[rperm[c]] (the
+// elimination order of the block ILU(0) solves).
 template <typename T>
 hipError_t launch_pcol_residual(int b, int p, const SellView &A, const double *val64,
-                                const float *pcol32, const double *v, const T *e, T *r,
-                                hipStream_t st);
+                                const float *pcol32, const double *v, const T *e,
+                                const int *rperm, T *r, hipStream_t st);
+// The block ILU(0) solves of one dependency level, in place on y (z), a
+// block vector in elimination order: rows[r] is the elimination position of
+// the r-th row of the level order, the layouts' columns are positions too.
 template <typename T>
 hipError_t launch_bilu_fwd(int b, const SellView &L, const int *rows, const T *Lval, T *y,
                            hipStream_t st);
 template <typename T>
 hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *Uval,
                            const T *Dval, T *z, hipStream_t st);
+// z_c = zz[zperm[c]] (zperm may be nullptr: natural order) + e_c at the
+// pressure entry (+ w1_c if w1 != nullptr).
 template <typename T>
-hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, const double *w1, double *z,
-                         hipStream_t st);
+hipError_t launch_finish(int b, int p, int n, const T *zz, const int *zperm, const T *e,
+                         const double *w1, double *z, hipStream_t st);
+// Block vectors between natural and another block order pos (natural c at
+// pos[c]): dst[pos[c]] = (T)src[c] when src != nullptr, else
+// dst64[c] = (double)srcT[pos[c]].
+template <typename T>
+hipError_t launch_perm_blocks(int n, int b, const int *pos, const double *src, T *dst,
+                              double *dst64, const T *srcT, hipStream_t st);
 // N stage (concentration block, block Gauss-Seidel): setup of Dn = rows N of
 // D_c^-1 (n x (b-1) x b) and Ann = (D_c^-1 A_cd)[N, N] per stored block
 // (nnzb x (b-1)^2, identity on the diagonal blocks), FP64; the right-hand side

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_fill(int nslices, const int4 *
             if (qb < 0) break;
             last = pb;
             const long long o = (long long)d.w + (long long)m * 64 + lane;
-            col[o] = ci[qb];
+            col[o] = pb;  // the solves run on vectors in elimination order
             src[o] = qb;
             ++m;
         }
@@ -824,7 +824,8 @@ template <int B, typename T, bool F32>
 __global__ __launch_bounds__(kThreads) void k_pcol_residual(
     int p, const int4 *__restrict__ slices, const int *__restrict__ col, int s0, int s1,
     const double *__restrict__ val64, const float *__restrict__ pcol32,
-    const double *__restrict__ v, const T *__restrict__ e, T *__restrict__ r)
+    const double *__restrict__ v, const T *__restrict__ e, const int *__restrict__ rperm,
+    T *__restrict__ r)
 {
     constexpr int E = B * B;
     const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -861,8 +862,9 @@ __global__ __launch_bounds__(kThreads) void k_pcol_residual(
             }
         }
     }
+    const long long ro = rperm ? rperm[row] : row;
 #pragma unroll
-    for (int q = 0; q < B; ++q) r[row * B + q] = (T)v[row * B + q] - acc[q];
+    for (int q = 0; q < B; ++q) r[ro * B + q] = (T)v[row * B + q] - acc[q];
 }
 
 // Block ILU(0) triangular solves, one dependency level per launch, one
@@ -957,6 +959,7 @@ __global__ __launch_bounds__(kThreads) void k_bilu_bwd(const int4 *__restrict__ 
 
 template <int B, typename T>
 __global__ __launch_bounds__(kThreads) void k_finish(int p, int n, const T *__restrict__ zz,
+                                                     const int *__restrict__ zperm,
                                                      const T *__restrict__ e,
                                                      const double *__restrict__ w1,
                                                      double *__restrict__ z)
@@ -965,7 +968,8 @@ __global__ __launch_bounds__(kThreads) void k_finish(int p, int n, const T *__re
     if (q >= (long long)n * B) return;
     const int k = (int)(q % B);
     const long long c = q / B;
-    const double v = (double)zz[q] + (k == p ? (double)e[c] : 0.0);
+    const long long qz = zperm ? (long long)zperm[c] * B + k : q;
+    const double v = (double)zz[qz] + (k == p ? (double)e[c] : 0.0);
     z[q] = w1 ? v + w1[q] : v;
 }
 
@@ -1966,19 +1970,19 @@ hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hip
 
 template <typename T>
 hipError_t launch_pcol_residual(int b, int p, const SellView &A, const double *val64,
-                                const float *pcol32, const double *v, const T *e, T *r,
-                                hipStream_t st)
+                                const float *pcol32, const double *v, const T *e,
+                                const int *rperm, T *r, hipStream_t st)
 {
     unsigned nb = slice_blocks(A);
     if (!nb) return hipSuccess;
     if (pcol32) {
         MSP_SWITCH_B(b, (k_pcol_residual<B, T, true><<<nb, kThreads, 0, st>>>(
                             p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, e,
-                            r)));
+                            rperm, r)));
     } else {
         MSP_SWITCH_B(b, (k_pcol_residual<B, T, false><<<nb, kThreads, 0, st>>>(
                             p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, e,
-                            r)));
+                            rperm, r)));
     }
     return hipGetLastError();
 }
@@ -2006,12 +2010,39 @@ hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *U
     return hipGetLastError();
 }
 
+// dst_T[pos[c]*b + k] = (T)src[c*b + k] (src != nullptr), or
+// dst64[c*b + k] = (double)srcT[pos[c]*b + k]
 template <typename T>
-hipError_t launch_finish(int b, int p, int n, const T *zz, const T *e, const double *w1,
-                         double *z, hipStream_t st)
+__global__ __launch_bounds__(kThreads) void k_perm_blocks(int n, int b, const int *__restrict__ pos,
+                                                          const double *__restrict__ src,
+                                                          T *__restrict__ dst, double *__restrict__ dst64,
+                                                          const T *__restrict__ srcT)
 {
-    MSP_SWITCH_B(b, (k_finish<B, T><<<blocks_for((long long)n * B), kThreads, 0, st>>>(p, n, zz,
-                                                                                      e, w1, z)));
+    const long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long long)n * b) return;
+    const long long c = q / b, k = q % b, qp = (long long)pos[c] * b + k;
+    if (src)
+        dst[qp] = (T)src[q];
+    else
+        dst64[q] = (double)srcT[qp];
+}
+
+template <typename T>
+hipError_t launch_perm_blocks(int n, int b, const int *pos, const double *src, T *dst,
+                              double *dst64, const T *srcT, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_perm_blocks<T><<<blocks_for((long long)n * b), kThreads, 0, st>>>(n, b, pos, src, dst, dst64,
+                                                                       srcT);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finish(int b, int p, int n, const T *zz, const int *zperm, const T *e,
+                         const double *w1, double *z, hipStream_t st)
+{
+    MSP_SWITCH_B(b, (k_finish<B, T><<<blocks_for((long long)n * B), kThreads, 0, st>>>(
+                        p, n, zz, zperm, e, w1, z)));
     return hipGetLastError();
 }
 
@@ -2088,20 +2119,22 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
                                                const T *, double *, T *, hipStream_t);         \
     template hipError_t launch_unpermute<T>(int, const int *, const T *, T *, hipStream_t);    \
     template hipError_t launch_pcol_residual<T>(int, int, const SellView &, const double *,    \
-                                                const float *, const double *, const T *, T *, \
-                                                hipStream_t);                                  \
+                                                const float *, const double *, const T *,      \
+                                                const int *, T *, hipStream_t);                \
     template hipError_t launch_bilu_fwd<T>(int, const SellView &, const int *, const T *, T *, \
                                            hipStream_t);                                       \
     template hipError_t launch_bilu_bwd<T>(int, const SellView &, const int *, const T *,      \
                                            const T *, T *, hipStream_t);                       \
-    template hipError_t launch_finish<T>(int, int, int, const T *, const T *, const double *,  \
-                                         double *, hipStream_t);                               \
+    template hipError_t launch_finish<T>(int, int, int, const T *, const int *, const T *,     \
+                                         const double *, double *, hipStream_t);               \
     template hipError_t launch_n_rhs<T>(int, int, const T *, const double *, T *, hipStream_t); \
     template hipError_t launch_bgs_group<T>(int, int, const int *, const int *, const int *,   \
                                             const T *, const T *, T *, hipStream_t);           \
     template hipError_t launch_expand_n<T>(int, int, int, const T *, double *, hipStream_t);   \
     template hipError_t launch_to_double<T>(long long, const T *, double *, hipStream_t);      \
-    template hipError_t launch_from_double<T>(long long, const double *, T *, hipStream_t);
+    template hipError_t launch_from_double<T>(long long, const double *, T *, hipStream_t);    \
+    template hipError_t launch_perm_blocks<T>(int, int, const int *, const double *, T *,      \
+                                              double *, const T *, hipStream_t);
 
 MSP_INSTANTIATE(float)
 MSP_INSTANTIATE(double)
