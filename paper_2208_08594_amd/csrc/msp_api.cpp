@@ -170,6 +170,7 @@ struct msp_ctx {
     void *e_nat = nullptr, *ybuf = nullptr;
     // captured preconditioner apply (valid for the current B and A layout)
     double *vin = nullptr, *zout = nullptr;
+    ApplyIo *io = nullptr;  // the captured apply's vectors, set before each launch
     double *tC = nullptr, *tA = nullptr, *tB = nullptr;  // timing-stage scratch (with B)
     hipStream_t cap_stream = nullptr;
     // second stream of the setup: level uploads and the block ILU(0)
@@ -1056,6 +1057,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
     c->ybuf = c->dalloc(tsz * (size_t)n * b, c->allocB);
     c->vin = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
     c->zout = (double *)c->dalloc(sizeof(double) * (size_t)n * b, c->allocB);
+    c->io = (ApplyIo *)c->dalloc(sizeof(ApplyIo), c->allocB);
     c->sync();
     c->Bn = n;
     c->Bb = b;
@@ -1173,8 +1175,10 @@ const int *r_order(const msp_ctx *c)
     return c->opt.full_smoother == 0 ? c->bilu.pos_d : nullptr;
 }
 
+// io != nullptr: the vectors are read from *io when the kernels run (the
+// N stage, which is not captured this way, needs them as arguments).
 template <typename T>
-void apply_T(msp_ctx *c, const double *v_in, double *z)
+void apply_T(msp_ctx *c, const double *v_in, double *z, const ApplyIo *io = nullptr)
 {
     Level &L0 = c->lev[0];
     const double *v = v_in;
@@ -1195,27 +1199,32 @@ void apply_T(msp_ctx *c, const double *v_in, double *z)
         HIPCHK(launch_spmv(c->b, c->SA.all(), c->valA, S.w1, v_in, S.r1, c->stream));
         v = S.r1;
     }
-    HIPCHK(launch_decouple_restrict<T>(c->b, c->n, L0.iperm_d, c->omega, v, (T *)L0.f, c->stream));
+    HIPCHK(launch_decouple_restrict<T>(c->b, c->n, L0.iperm_d, c->omega, v, io, (T *)L0.f,
+                                       c->stream));
     vcycle<T>(c, 0);
     HIPCHK(launch_unpermute<T>(c->n, L0.perm_d, (const T *)L0.x, (T *)c->e_nat, c->stream));
-    HIPCHK(launch_pcol_residual<T>(c->b, c->p, c->SA.all(), c->valA, c->pcol32, v,
+    HIPCHK(launch_pcol_residual<T>(c->b, c->p, c->SA.all(), c->valA, c->pcol32, v, io,
                                    (const T *)c->e_nat, r_order(c), (T *)c->ybuf, c->stream));
     bilu_solve<T>(c, (T *)c->ybuf);
     HIPCHK(launch_finish<T>(c->b, c->p, c->n, (const T *)c->ybuf, r_order(c),
-                            (const T *)c->e_nat, S.on ? S.w1 : nullptr, z, c->stream));
+                            (const T *)c->e_nat, S.on ? S.w1 : nullptr, z, io, c->stream));
 }
 
-void apply_eager(msp_ctx *c, const double *v, double *z)
+void apply_eager(msp_ctx *c, const double *v, double *z, const ApplyIo *io = nullptr)
 {
     if (c->fp32())
-        apply_T<float>(c, v, z);
+        apply_T<float>(c, v, z, io);
     else
-        apply_T<double>(c, v, z);
+        apply_T<double>(c, v, z, io);
 }
 
-// Capture the whole preconditioner apply (vin -> zout) into a HIP graph on a
-// private capture stream; nothing runs during capture.  The graph holds only
-// kernel nodes.
+// The captured apply reads its vectors through c->io unless the N stage is
+// on; then it works on the fixed vin -> zout and the vectors are copied.
+bool apply_via_io(const msp_ctx *c) { return !c->ns.on; }
+
+// Capture the whole preconditioner apply (*io, or vin -> zout) into a HIP
+// graph on a private capture stream; nothing runs during capture.  The graph
+// holds only kernel nodes.
 void capture_apply(msp_ctx *c)
 {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1224,7 +1233,10 @@ void capture_apply(msp_ctx *c)
     c->stream = c->cap_stream;
     hipGraph_t g = nullptr;
     try {
-        apply_eager(c, c->vin, c->zout);
+        if (apply_via_io(c))
+            apply_eager(c, nullptr, nullptr, c->io);
+        else
+            apply_eager(c, c->vin, c->zout);
     } catch (...) {
         c->stream = user;
         (void)hipStreamEndCapture(c->cap_stream, &g);
@@ -1248,6 +1260,11 @@ void apply(msp_ctx *c, const double *v, double *z, bool capture_ok = true)
         return;
     }
     if (!c->apply_exec) capture_apply(c);
+    if (apply_via_io(c)) {
+        HIPCHK(launch_set_io(c->io, v, z, c->stream));
+        HIPCHK(hipGraphLaunch(c->apply_exec, c->stream));
+        return;
+    }
     const size_t bytes = sizeof(double) * (size_t)c->n * c->b;
     HIPCHK(hipMemcpyAsync(c->vin, v, bytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipGraphLaunch(c->apply_exec, c->stream));

@@ -87,9 +87,18 @@ hipError_t launch_spmv(int b, const SellView &A, const double *val, const double
                        const double *sub, double *y, hipStream_t st);
 
 // ---- preconditioner pieces (T = float or double) ------------------------
+// Input and output vectors of a preconditioner apply, read by its kernels at
+// run time, so that one captured graph of the apply serves every pair of
+// Krylov vectors.  A kernel given io != nullptr takes io->v (io->z) instead
+// of its pointer argument.
+struct ApplyIo {
+    const double *v;
+    double *z;
+};
+hipError_t launch_set_io(ApplyIo *io, const double *v, double *z, hipStream_t st);
 template <typename T>
 hipError_t launch_decouple_restrict(int b, int n, const int *iperm0, const double *omega,
-                                    const double *v, T *g, hipStream_t st);
+                                    const double *v, const ApplyIo *io, T *g, hipStream_t st);
 template <typename T>
 hipError_t launch_gs_first(const SellView &seg0, int npos, const T *diag, const T *f, T *x,
                            int seg0_begin, int seg0_end, hipStream_t st);
@@ -133,8 +142,8 @@ hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hip
 // elimination order of the block ILU(0) solves).
 template <typename T>
 hipError_t launch_pcol_residual(int b, int p, const SellView &A, const double *val64,
-                                const float *pcol32, const double *v, const T *e,
-                                const int *rperm, T *r, hipStream_t st);
+                                const float *pcol32, const double *v, const ApplyIo *io,
+                                const T *e, const int *rperm, T *r, hipStream_t st);
 // The block ILU(0) solves of one dependency level, in place on y (z), a
 // block vector in elimination order: rows[r] is the elimination position of
 // the r-th row of the level order, the layouts' columns are positions too.
@@ -148,7 +157,7 @@ hipError_t launch_bilu_bwd(int b, const SellView &U, const int *rows, const T *U
 // pressure entry (+ w1_c if w1 != nullptr).
 template <typename T>
 hipError_t launch_finish(int b, int p, int n, const T *zz, const int *zperm, const T *e,
-                         const double *w1, double *z, hipStream_t st);
+                         const double *w1, double *z, const ApplyIo *io, hipStream_t st);
 // Block vectors between natural and another block order pos (natural c at
 // pos[c]): dst[pos[c]] = (T)src[c] when src != nullptr, else
 // dst64[c] = (double)srcT[pos[c]].

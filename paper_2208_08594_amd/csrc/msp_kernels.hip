@@ -562,11 +562,13 @@ template <int B, typename T>
 __global__ __launch_bounds__(kThreads) void k_decouple_restrict(int n,
                                                                 const int *__restrict__ iperm0,
                                                                 const double *__restrict__ omega,
-                                                                const double *__restrict__ v,
+                                                                const double *v,
+                                                                const ApplyIo *io,
                                                                 T *__restrict__ g)
 {
     int t = blockIdx.x * kThreads + threadIdx.x;
     if (t >= n) return;
+    if (io) v = io->v;
     const long long c = iperm0[t];
     double acc = 0.0;
 #pragma unroll
@@ -824,10 +826,11 @@ template <int B, typename T, bool F32>
 __global__ __launch_bounds__(kThreads) void k_pcol_residual(
     int p, const int4 *__restrict__ slices, const int *__restrict__ col, int s0, int s1,
     const double *__restrict__ val64, const float *__restrict__ pcol32,
-    const double *__restrict__ v, const T *__restrict__ e, const int *__restrict__ rperm,
+    const double *v, const ApplyIo *io, const T *__restrict__ e, const int *__restrict__ rperm,
     T *__restrict__ r)
 {
     constexpr int E = B * B;
+    if (io) v = io->v;
     const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (s >= s1) return;
     const int lane = threadIdx.x & 63;
@@ -962,10 +965,11 @@ __global__ __launch_bounds__(kThreads) void k_finish(int p, int n, const T *__re
                                                      const int *__restrict__ zperm,
                                                      const T *__restrict__ e,
                                                      const double *__restrict__ w1,
-                                                     double *__restrict__ z)
+                                                     double *z, const ApplyIo *io)
 {
     long long q = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (q >= (long long)n * B) return;
+    if (io) z = io->z;
     const int k = (int)(q % B);
     const long long c = q / B;
     const long long qz = zperm ? (long long)zperm[c] * B + k : q;
@@ -1843,12 +1847,24 @@ hipError_t launch_spmv(int b, const SellView &A, const double *val, const double
     return hipGetLastError();
 }
 
+__global__ void k_set_io(ApplyIo *io, const double *v, double *z)
+{
+    io->v = v;
+    io->z = z;
+}
+
+hipError_t launch_set_io(ApplyIo *io, const double *v, double *z, hipStream_t st)
+{
+    k_set_io<<<1, 1, 0, st>>>(io, v, z);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_decouple_restrict(int b, int n, const int *iperm0, const double *omega,
-                                    const double *v, T *g, hipStream_t st)
+                                    const double *v, const ApplyIo *io, T *g, hipStream_t st)
 {
-    MSP_SWITCH_B(b, (k_decouple_restrict<B, T><<<blocks_for(n), kThreads, 0, st>>>(n, iperm0,
-                                                                                   omega, v, g)));
+    MSP_SWITCH_B(b, (k_decouple_restrict<B, T><<<blocks_for(n), kThreads, 0, st>>>(
+                        n, iperm0, omega, v, io, g)));
     return hipGetLastError();
 }
 
@@ -1970,19 +1986,19 @@ hipError_t launch_unpermute(int n, const int *perm0, const T *epos, T *enat, hip
 
 template <typename T>
 hipError_t launch_pcol_residual(int b, int p, const SellView &A, const double *val64,
-                                const float *pcol32, const double *v, const T *e,
-                                const int *rperm, T *r, hipStream_t st)
+                                const float *pcol32, const double *v, const ApplyIo *io,
+                                const T *e, const int *rperm, T *r, hipStream_t st)
 {
     unsigned nb = slice_blocks(A);
     if (!nb) return hipSuccess;
     if (pcol32) {
         MSP_SWITCH_B(b, (k_pcol_residual<B, T, true><<<nb, kThreads, 0, st>>>(
-                            p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, e,
-                            rperm, r)));
+                            p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, io,
+                            e, rperm, r)));
     } else {
         MSP_SWITCH_B(b, (k_pcol_residual<B, T, false><<<nb, kThreads, 0, st>>>(
-                            p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, e,
-                            rperm, r)));
+                            p, A.slices, A.col, A.slice_begin, A.slice_end, val64, pcol32, v, io,
+                            e, rperm, r)));
     }
     return hipGetLastError();
 }
@@ -2039,10 +2055,10 @@ hipError_t launch_perm_blocks(int n, int b, const int *pos, const double *src, T
 
 template <typename T>
 hipError_t launch_finish(int b, int p, int n, const T *zz, const int *zperm, const T *e,
-                         const double *w1, double *z, hipStream_t st)
+                         const double *w1, double *z, const ApplyIo *io, hipStream_t st)
 {
     MSP_SWITCH_B(b, (k_finish<B, T><<<blocks_for((long long)n * B), kThreads, 0, st>>>(
-                        p, n, zz, zperm, e, w1, z)));
+                        p, n, zz, zperm, e, w1, z, io)));
     return hipGetLastError();
 }
 
@@ -2101,7 +2117,8 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
 
 #define MSP_INSTANTIATE(T)                                                                     \
     template hipError_t launch_decouple_restrict<T>(int, int, const int *, const double *,     \
-                                                    const double *, T *, hipStream_t);         \
+                                                    const double *, const ApplyIo *, T *,      \
+                                                    hipStream_t);                              \
     template hipError_t launch_gs_first<T>(const SellView &, int, const T *, const T *, T *,   \
                                            int, int, hipStream_t);                             \
     template hipError_t launch_gs_color<T>(const SellView &, const T *, const T *, const T *,  \
@@ -2119,14 +2136,16 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
                                                const T *, double *, T *, hipStream_t);         \
     template hipError_t launch_unpermute<T>(int, const int *, const T *, T *, hipStream_t);    \
     template hipError_t launch_pcol_residual<T>(int, int, const SellView &, const double *,    \
-                                                const float *, const double *, const T *,      \
-                                                const int *, T *, hipStream_t);                \
+                                                const float *, const double *,                 \
+                                                const ApplyIo *, const T *, const int *, T *,  \
+                                                hipStream_t);                                  \
     template hipError_t launch_bilu_fwd<T>(int, const SellView &, const int *, const T *, T *, \
                                            hipStream_t);                                       \
     template hipError_t launch_bilu_bwd<T>(int, const SellView &, const int *, const T *,      \
                                            const T *, T *, hipStream_t);                       \
     template hipError_t launch_finish<T>(int, int, int, const T *, const int *, const T *,     \
-                                         const double *, double *, hipStream_t);               \
+                                         const double *, double *, const ApplyIo *,            \
+                                         hipStream_t);                                         \
     template hipError_t launch_n_rhs<T>(int, int, const T *, const double *, T *, hipStream_t); \
     template hipError_t launch_bgs_group<T>(int, int, const int *, const int *, const int *,   \
                                             const T *, const T *, T *, hipStream_t);           \
