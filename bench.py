@@ -293,7 +293,10 @@ def main():
         f"apply {apply_ms / max(apply_calls, 1)*1e3:.1f} us; coarse {t_coarse*1e3:.1f} us; "
         f"solve {solve_gbs:.0f} GB/s")
 
-    # FP32 preconditioner on the same system
+    # FP32 preconditioner on the same system, after the FP64 context has
+    # given its device memory back (its blocks serve the FP32 context)
+    solver.close()
+    del xin, yout
     fp32 = None
     x32 = None
     if not args.no_fp32:
@@ -312,8 +315,7 @@ def main():
     x64 = x64.cpu()
     if x32 is not None:
         x32 = x32.cpu()
-    solver.close()
-    del rp, ci, vals, rhs, xin, yout
+    del rp, ci, vals, rhs
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     serving = None
