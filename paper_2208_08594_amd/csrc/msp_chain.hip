@@ -159,9 +159,11 @@ __device__ inline int first_free_cand(int v, const int *__restrict__ rp, const i
 // ends.  A free row with no free lower row pointing at it and no free
 // candidate stays alone.  Every row evaluates this from the round's input
 // states (st) and writes only its own output state (st_next), so the two
-// ends of a taken edge reach the same verdict independently.  Free rows of
-// the input are counted into *nfree; *nfree_next is cleared for the next
-// round.
+// ends of a taken edge reach the same verdict independently.  If nfree is
+// set, the free rows of the input are counted into it (the host reads the
+// count of one round per batch only: counting in every round would put
+// thousands of atomics on one address each time); a set nfree_next is
+// cleared for the next round's count.
 __global__ void __launch_bounds__(kThreads)
 k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
         const int *__restrict__ ncand, const int *__restrict__ in_ptr,
@@ -169,7 +171,7 @@ k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
         int *__restrict__ partner, int *__restrict__ nfree, int *__restrict__ nfree_next)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0) *nfree_next = 0;
+    if (v == 0 && nfree_next) *nfree_next = 0;
     bool fr = false;
     if (v < n) {
         const int s0 = st[v];
@@ -193,8 +195,10 @@ k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
         }
         st_next[v] = s1;
     }
-    const int cnt = __syncthreads_count(fr);
-    if (threadIdx.x == 0 && cnt) atomicAdd(nfree, cnt);
+    if (nfree) {  // the same for every block
+        const int cnt = __syncthreads_count(fr);
+        if (threadIdx.x == 0 && cnt) atomicAdd(nfree, cnt);
+    }
 }
 
 // A row opens an aggregate when it is alone or the lower row of its pair.
@@ -449,11 +453,13 @@ struct Chain {
         hipGraphExec_t exec = nullptr;
         {
             ck(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            // only the batch's last round counts its free rows (into ctr[1],
+            // cleared by the round before it)
             for (int q = 0; q < kBatch; ++q) {
                 const int a = q & 1;
-                k_round<<<nblocks(n), kThreads, 0, cap>>>(n, L.rp, cj, ncand, in_ptr, in_row,
-                                                          state[a], state[a ^ 1], partner,
-                                                          ctr + a, ctr + (a ^ 1));
+                k_round<<<nblocks(n), kThreads, 0, cap>>>(
+                    n, L.rp, cj, ncand, in_ptr, in_row, state[a], state[a ^ 1], partner,
+                    q == kBatch - 1 ? ctr + 1 : nullptr, q == kBatch - 2 ? ctr + 1 : nullptr);
             }
             hipGraph_t g = nullptr;
             const hipError_t e1 = hipStreamEndCapture(cap, &g);
@@ -480,7 +486,7 @@ struct Chain {
             r += kBatch;
             // free rows at the start of the batch's last round
             const int slot = batch % 3;
-            ck(hipMemcpyAsync(pinned + slot, ctr + ((kBatch - 1) & 1), sizeof(int),
+            ck(hipMemcpyAsync(pinned + slot, ctr + 1, sizeof(int),
                               hipMemcpyDeviceToHost, st));
             ck(hipEventRecord(ev[slot], st));
             if (batch >= 2) {
