@@ -188,6 +188,10 @@ struct msp_ctx {
     double *hhost = nullptr;  // pinned
     int *flag = nullptr, *flag_host = nullptr;
     int *chain_host = nullptr;  // pinned, progress reads of the device aggregation chain
+    // pinned staging of the chain's level copies, one buffer per level, kept
+    // (and grown) across setups
+    std::vector<std::pair<void *, size_t>> chain_stage;
+    std::mutex chain_stage_mu;
     bool pattern_ok = false;    // rp/ci (host) and rp_d/ci_d hold a checked pattern
     bool pattern_sym = false;   // that pattern is structurally symmetric
     long long pattern_gen = 0;  // counts pattern changes
@@ -821,6 +825,28 @@ struct CopyStreamScope {
     ~CopyStreamScope() { c->copy_stream = nullptr; }
 };
 
+// The chain's page-locked staging buffer for level l (at least `bytes`), or
+// nullptr if none can be had (the copy then goes to pageable memory).
+void *chain_staging(msp_ctx *c, int l, size_t bytes)
+{
+    std::lock_guard<std::mutex> lock(c->chain_stage_mu);
+    if ((int)c->chain_stage.size() <= l) c->chain_stage.resize(l + 1, {nullptr, 0});
+    auto &b = c->chain_stage[l];
+    if (b.second < bytes) {
+        // a buffer of an earlier setup: nothing uses it any more
+        if (b.first) (void)hipHostFree(b.first);
+        b = {nullptr, 0};
+        const size_t sz = bytes + bytes / 8;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        b = {p, sz};
+    }
+    return b.first;
+}
+
 void rebuild_B(msp_ctx *c, const double *vals)
 {
     // Level 0 of the previous hierarchy has the same pattern arrays when the
@@ -942,7 +968,8 @@ void rebuild_B(msp_ctx *c, const double *vals)
         st = device_hierarchy(
             A0, c->rp_d, c->ci_d, ap, c->opt.max_coarse, MSP_MAX_LEVELS, 16384, H, start_level,
             [&a0_ready]() { a0_ready.get(); }, c->stream, c->cap_stream, c->chain_copy,
-            [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip, c->chain_host);
+            [c, &tmp](size_t bytes) { return c->dalloc(bytes, tmp); }, fail_hip, c->chain_host,
+            [c](int l, size_t bytes) { return chain_staging(c, l, bytes); });
     }
     if (st == 1) {
         device_levels = false;
@@ -1826,6 +1853,8 @@ int msp_destroy(msp_ctx *c)
         if (c->hhost) (void)hipHostFree(c->hhost);
         if (c->flag_host) (void)hipHostFree(c->flag_host);
         if (c->chain_host) (void)hipHostFree(c->chain_host);
+        for (auto &b : c->chain_stage)
+            if (b.first) (void)hipHostFree(b.first);
         return MSP_OK;
     });
     delete c;

@@ -26,6 +26,10 @@ namespace msp {
 // Device memory for the chain's work arrays (freed by the caller after the
 // setup; may throw).
 using DeviceAlloc = std::function<void *(size_t)>;
+// Page-locked host memory of at least `bytes` for the copy of level l (the
+// same l never gets a buffer twice in one call); valid until the caller's
+// setup ends.  May return nullptr: the copy then goes to pageable memory.
+using PinnedBuffer = std::function<void *(int l, size_t bytes)>;
 // Called with every HIP error; must not return (it throws).
 using HipFail = void (*)(hipError_t);
 
@@ -45,7 +49,10 @@ using HipFail = void (*)(hipError_t);
 // reads a_ji through the mirror entry); the caller then runs the host chain.
 // `cap` is an idle stream used only to capture batches of matching rounds
 // into a graph (nothing runs on it).  `pinned` is a host-pinned buffer of at
-// least 16 ints.  A stalled level (the two passes keep more than 90% of its
+// least 16 ints.  With `staging`, each new level is copied to page-locked
+// memory first (a fast DMA), on_smoothed gets its pattern there (so the
+// level's host work starts before the copy into H.A is done), and H.A is
+// filled from it.  A stalled level (the two passes keep more than 90% of its
 // rows) is finished on the host with absorb_singletons and galerkin, and its
 // coarse matrix uploaded.
 // Bytes of the one device allocation the chain makes for a level 0 of n0
@@ -56,6 +63,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                      const LevelCallback &on_smoothed, const std::function<void()> &level0_values,
                      hipStream_t st, hipStream_t cap, hipStream_t copy_st,
-                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned);
+                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned,
+                     const PinnedBuffer &staging = nullptr);
 
 }  // namespace msp

@@ -5,8 +5,11 @@
 // results equal the host chain bit for bit; msp_chain.h gives the argument.
 #include "msp_chain.h"
 
+#include <cstring>
+
 #include <algorithm>
 #include <future>
+#include <memory>
 #include <vector>
 
 // every sum and comparison below is a single IEEE operation, as on the host
@@ -595,7 +598,8 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                      int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                      const LevelCallback &on_smoothed, const std::function<void()> &level0_values,
                      hipStream_t st, hipStream_t cap, hipStream_t copy_st,
-                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned)
+                     const DeviceAlloc &alloc, HipFail hip_fail, int *pinned,
+                     const PinnedBuffer &staging)
 {
     const int n0 = A0.n;
     const long long nnz0 = A0.nnz();
@@ -635,9 +639,18 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
     // is joined before its device buffers can be reused: the previous level's
     // copy before this level's aggregation map is composed (aggf is shared,
     // the level buffers alternate), and every copy before the host reads it.
-    std::future<void> pending;
-    const auto join = [&pending]() {
+    // `pending` ends when the copy thread is done; `copied` as soon as its
+    // device reads are (with staging, the host copies out of the page-locked
+    // buffer may still run: they write only through pointers taken before)
+    std::future<void> pending, copied;
+    const auto join = [&pending, &copied]() {
+        if (copied.valid()) copied.get();
         if (pending.valid()) pending.get();
+    };
+    // (a failure of the copy thread before its device reads ended comes
+    // through `copied`)
+    const auto join_device = [&copied]() {
+        if (copied.valid()) copied.get();
     };
     bool have_s = true;
     bool main_calls = true;  // level l's on_smoothed is due on this thread
@@ -659,7 +672,7 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
         const int nc2 = X.pass(M1, false, X.a2);
         DevLevel &C = X.set[next];
         X.galerkin(M1, X.a2, nc2, C);
-        join();
+        join_device();
         k_compose<<<nblocks(cur.n), kThreads, 0, st>>>(cur.n, X.a1, X.a2, X.aggf);
         X.launched();
         X.ck(hipEventRecord(X.ev_lvl, st));
@@ -684,8 +697,14 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
             const hipEvent_t ready = X.ev_lvl;
             const int lnext = l + 1;
             const bool call = next_smoothed && on_smoothed;
+            const PinnedBuffer *stg = staging ? &staging : nullptr;
+            auto dev_done = std::make_shared<std::promise<void>>();
+            copied = dev_done->get_future();
             pending = std::async(std::launch::async, [&hn, &hagg, nf, Cd, aggf, ready, copy_st,
-                                                      hip_fail, call, lnext, &on_smoothed]() {
+                                                      hip_fail, call, lnext, &on_smoothed, stg,
+                                                      dev_done]() {
+              bool signalled = false;
+              try {
                 hagg.resize(nf);
                 hn.rp.resize(Cd.n + 1);
                 auto ck = [hip_fail](hipError_t e) {
@@ -695,25 +714,51 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
                     }
                 };
                 ck(hipStreamWaitEvent(copy_st, ready, 0));
-                ck(hipMemcpyAsync(hagg.data(), aggf, sizeof(int) * nf, hipMemcpyDeviceToHost,
-                                  copy_st));
                 ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
                                   hipMemcpyDeviceToHost, copy_st));
                 ck(hipStreamSynchronize(copy_st));
                 const long long nnzc = hn.rp[Cd.n];
                 hn.ci.resize(nnzc);
                 hn.val.resize(nnzc);
+                // page-locked staging: [ci | val | agg], one DMA each
+                char *sb = stg ? (char *)(*stg)(lnext, sizeof(int) * (size_t)nnzc +
+                                                           sizeof(double) * (size_t)nnzc +
+                                                           sizeof(int) * (size_t)nf)
+                               : nullptr;
+                int *sci = sb ? (int *)sb : hn.ci.data();
+                double *sval = sb ? (double *)(sb + sizeof(int) * (size_t)nnzc) : hn.val.data();
+                int *sagg = sb ? (int *)(sb + (sizeof(int) + sizeof(double)) * (size_t)nnzc)
+                               : hagg.data();
                 // the pattern first: the level's host work (its groups) needs
-                // only that, and starts while the values are copied
+                // only that, and starts while the rest is copied
                 if (nnzc)
-                    ck(hipMemcpyAsync(hn.ci.data(), Cd.ci, sizeof(int) * nnzc,
-                                      hipMemcpyDeviceToHost, copy_st));
+                    ck(hipMemcpyAsync(sci, Cd.ci, sizeof(int) * nnzc, hipMemcpyDeviceToHost,
+                                      copy_st));
                 ck(hipStreamSynchronize(copy_st));
-                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), hn.ci.data());
+                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), sci);
                 if (nnzc)
-                    ck(hipMemcpyAsync(hn.val.data(), Cd.val, sizeof(double) * nnzc,
-                                      hipMemcpyDeviceToHost, copy_st));
+                    ck(hipMemcpyAsync(sval, Cd.val, sizeof(double) * nnzc, hipMemcpyDeviceToHost,
+                                      copy_st));
+                ck(hipMemcpyAsync(sagg, aggf, sizeof(int) * nf, hipMemcpyDeviceToHost, copy_st));
+                // H grows on the main thread once the device reads are done:
+                // the destinations are taken here (moving a vector keeps its
+                // storage)
+                int *dci = hn.ci.data(), *dagg = hagg.data();
+                double *dval = hn.val.data();
+                if (sb) std::memcpy(dci, sci, sizeof(int) * (size_t)nnzc);
                 ck(hipStreamSynchronize(copy_st));
+                signalled = true;
+                dev_done->set_value();
+                if (sb) {
+                    std::memcpy(dval, sval, sizeof(double) * (size_t)nnzc);
+                    std::memcpy(dagg, sagg, sizeof(int) * (size_t)nf);
+                }
+              } catch (...) {
+                if (signalled) throw;
+                (void)hipStreamSynchronize(copy_st);
+                (void)hipGetLastError();
+                dev_done->set_exception(std::current_exception());
+              }
             });
         }
         main_calls = !next_smoothed;

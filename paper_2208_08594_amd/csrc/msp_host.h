@@ -120,9 +120,10 @@ struct Hierarchy {
 // computed per level with color_level, e.g. on other threads); on_smoothed
 // (if set) is called with (l, n, row_ptr, col_ind) as soon as level l is
 // known to be a smoothed level and its pattern is on the host (its values may
-// still be on their way).  The pointed-to arrays stay valid while H lives;
-// H.A grows meanwhile, so a callee must not keep a reference to the Csr
-// itself.
+// still be on their way).  The pointed-to arrays stay valid until the setup
+// that builds H has returned (they may be a copy of H.A[l]'s, e.g. in a
+// staging buffer); H.A grows meanwhile, so a callee must not keep a
+// reference to the Csr itself.
 using LevelCallback = std::function<void(int, int, const int *, const int *)>;
 int build_hierarchy(Csr A0, int max_coarse, int max_levels, int max_dense, Hierarchy &H,
                     bool with_colors = true, const LevelCallback &on_smoothed = nullptr);
