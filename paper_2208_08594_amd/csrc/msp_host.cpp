@@ -267,14 +267,23 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     // unc[u]: neighbours of u not yet in any group; a vertex with none has
     // nothing left to add to a second ring, so its neighbourhood is skipped
     std::vector<int> unc(n);
-    for (int u = 0; u < n; ++u) unc[u] = G.degree(u);
+    int dmax = 0;
+    for (int u = 0; u < n; ++u) {
+        unc[u] = G.degree(u);
+        dmax = std::max(dmax, unc[u]);
+    }
+    // second-ring vertices newly queued for one chosen vertex (each vertex is
+    // queued at most once per group)
+    std::vector<int> fresh((size_t)std::min<long long>((long long)dmax * dmax, n) + 1);
+    unsigned char *F = fl.data();
+    const int *ptr = G.ptr.data(), *nb = G.nbr.data();
     int left = n, g = 0;
     while (left > 0) {
         ++g;  // one call of VerticesSplitting builds group g
         int avail = 0;
         for (int i = 0; i < n; ++i) {
-            fl[i] = color[i] == 0 ? kOpen : 0;  // V: undetermined vertices
-            avail += fl[i];
+            F[i] = color[i] == 0 ? kOpen : 0;  // V: undetermined vertices
+            avail += F[i];
         }
         std::fill(bits.begin(), bits.end(), 0ull);
         std::fill(summ.begin(), summ.end(), 0ull);
@@ -285,34 +294,44 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             int v = -1;
             while (nqueued > 0) {  // second-ring candidates W^ that are still in V
                 int t = hat_pop();
-                if (fl[t] & kOpen) { v = t; break; }
+                if (F[t] & kOpen) { v = t; break; }
             }
             if (v < 0) {
-                while (!(fl[order[cursor]] & kOpen)) ++cursor;
+                while (!(F[order[cursor]] & kOpen)) ++cursor;
                 v = order[cursor];
             }
             color[v] = g;  // v joins W
-            fl[v] &= (unsigned char)~kOpen;
+            F[v] &= (unsigned char)~kOpen;
             --avail;
             --left;
-            for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // S_v leaves V (W-bar)
-                int u = G.nbr[q];
-                __builtin_prefetch(&G.nbr[G.ptr[u]]);  // read by the second ring below
+            const int p0 = ptr[v], p1 = ptr[v + 1];
+            for (int q = p0; q < p1; ++q) {  // S_v leaves V (W-bar)
+                const int u = nb[q];
+                __builtin_prefetch(&nb[ptr[u]]);  // read by the second ring below
                 --unc[u];
-                if (fl[u] & kOpen) { fl[u] &= (unsigned char)~kOpen; --avail; }
+                const unsigned char f = F[u];
+                avail -= f & kOpen;
+                F[u] = f & (unsigned char)~kOpen;
             }
-            for (int q = G.ptr[v]; q < G.ptr[v + 1]; ++q) {  // second ring enters W^
-                int u = G.nbr[q];
-                if ((fl[u] & kScanned) || unc[u] == 0) continue;
-                fl[u] |= kScanned;
-                for (int t = G.ptr[u]; t < G.ptr[u + 1]; ++t) {
-                    int w = G.nbr[t];
-                    if ((fl[w] & (kOpen | kQueued)) == kOpen) {
-                        fl[w] |= kQueued;
-                        hat_push(w);
-                    }
+            // second ring enters W^.  Whether a vertex is open is close to
+            // random here: the flags are updated without a branch and the
+            // newly queued vertices collected, then pushed together.
+            int k = 0;
+            for (int q = p0; q < p1; ++q) {
+                const int u = nb[q];
+                if ((F[u] & kScanned) || unc[u] == 0) continue;
+                F[u] |= kScanned;
+                const int e = ptr[u + 1];
+                for (int t = ptr[u]; t < e; ++t) {
+                    const int w = nb[t];
+                    const unsigned char f = F[w];
+                    const int take = (f & (kOpen | kQueued)) == kOpen;
+                    F[w] = (unsigned char)(f | take * kQueued);
+                    fresh[k] = w;
+                    k += take;
                 }
             }
+            for (int i = 0; i < k; ++i) hat_push(fresh[i]);
         }
     }
     return g;
