@@ -701,6 +701,30 @@ def test_coarse_lu_solve_exact(seed):
     np.testing.assert_allclose(x, _exact_solve(A, f), rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("n,seed", [(130, 0), (517, 1), (1200, 2)])
+def test_coarse_lu_solve_interchanges_at_coarse_sizes(n, seed):
+    """Partial pivoting at coarse-level sizes: A = P T with T well conditioned
+    and a small diagonal, and P a random row permutation, so nearly every
+    elimination step interchanges rows.  The solve must give back a known
+    x to within cond(A) eps (cond from the SVD) and a componentwise backward
+    error of a few n eps; applying an interchange to the wrong row, in the
+    wrong order or to the right-hand side twice gives O(1) errors."""
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(-1.0, 1.0, size=(n, n)) / np.sqrt(n)
+    T[np.arange(n), np.arange(n)] = 1e-3 * rng.uniform(0.5, 1.0, n)
+    T += np.tril(rng.uniform(-1.0, 1.0, size=(n, n)), -1)
+    A = T[rng.permutation(n)]
+    x_true = rng.integers(-5, 6, size=n).astype(float)
+    f = A @ x_true
+    lu, piv = O.lu_factor(A)
+    assert np.count_nonzero(piv != np.arange(n)) > n // 2
+    x = O.lu_solve(lu, piv, f)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(x - x_true) / np.linalg.norm(x_true) <= 50 * kappa * np.finfo(float).eps
+    berr = np.max(np.abs(f - A @ x) / (np.abs(A) @ np.abs(x) + np.abs(f)))
+    assert berr <= 8 * n * np.finfo(float).eps
+
+
 # --------------------------------------------------------------------------
 # O11 FGMRES -- pins P12, P13
 # --------------------------------------------------------------------------
