@@ -156,6 +156,70 @@ __device__ inline int first_free_cand(int v, const int *__restrict__ rp, const i
     return -1;
 }
 
+// Each row's first kRec in-rows and first kRec candidates (in order) held
+// inline, so that a round loads the states of a whole list at once instead of
+// walking it one dependent load after another.  kOver in a record's first
+// slot: the list is longer, and the round walks it in full.  Unused slots are
+// kNone (in-rows) and -1 (candidates).
+constexpr int kRec = 4;
+constexpr int kOver = -2;
+__global__ void k_records(int n, const int *__restrict__ rp, const int *__restrict__ cj,
+                          const int *__restrict__ ncand, const int *__restrict__ in_ptr,
+                          const int *__restrict__ in_row, int4 *__restrict__ rin,
+                          int4 *__restrict__ rcand)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int a[kRec] = {kNone, kNone, kNone, kNone};
+    const int q0 = in_ptr[v], q1 = in_ptr[v + 1];
+    if (q1 - q0 > kRec)
+        a[0] = kOver;
+    else
+        for (int q = q0; q < q1; ++q) a[q - q0] = in_row[q];
+    rin[v] = make_int4(a[0], a[1], a[2], a[3]);
+    int c[kRec] = {-1, -1, -1, -1};
+    const int m = ncand[v], b0 = rp[v];
+    if (m > kRec)
+        c[0] = kOver;
+    else
+        for (int q = 0; q < m; ++q) c[q] = cj[b0 + q];
+    rcand[v] = make_int4(c[0], c[1], c[2], c[3]);
+}
+
+// lowest_free_in / first_free_cand through the records
+__device__ inline int lowest_free_in_rec(int v, const int4 *__restrict__ rin,
+                                         const int *__restrict__ in_ptr,
+                                         const int *__restrict__ in_row,
+                                         const int *__restrict__ st)
+{
+    const int4 a = rin[v];
+    if (a.x == kOver) return lowest_free_in(v, in_ptr, in_row, st);
+    const bool f0 = a.x != kNone && st[a.x] == kFree;
+    const bool f1 = a.y != kNone && st[a.y] == kFree;
+    const bool f2 = a.z != kNone && st[a.z] == kFree;
+    const bool f3 = a.w != kNone && st[a.w] == kFree;
+    int m = kNone;
+    if (f0) m = a.x;
+    if (f1 && a.y < m) m = a.y;
+    if (f2 && a.z < m) m = a.z;
+    if (f3 && a.w < m) m = a.w;
+    return m;
+}
+
+__device__ inline int first_free_cand_rec(int v, const int4 *__restrict__ rcand,
+                                          const int *__restrict__ rp, const int *__restrict__ cj,
+                                          const int *__restrict__ ncand,
+                                          const int *__restrict__ st)
+{
+    const int4 c = rcand[v];
+    if (c.x == kOver) return first_free_cand(v, rp, cj, ncand, st);
+    const bool f0 = c.x >= 0 && st[c.x] == kFree;
+    const bool f1 = c.y >= 0 && st[c.y] == kFree;
+    const bool f2 = c.z >= 0 && st[c.z] == kFree;
+    const bool f3 = c.w >= 0 && st[c.w] == kFree;
+    return f0 ? c.x : f1 ? c.y : f2 ? c.z : f3 ? c.w : -1;
+}
+
 // One round.  An edge (i, j) between free rows is taken when i has no free
 // lower row pointing at it, j is i's first free candidate, and i is the
 // lowest free row pointing at j: the edge then comes first at both of its
@@ -170,7 +234,8 @@ __device__ inline int first_free_cand(int v, const int *__restrict__ rp, const i
 __global__ void __launch_bounds__(kThreads)
 k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
         const int *__restrict__ ncand, const int *__restrict__ in_ptr,
-        const int *__restrict__ in_row, const int *__restrict__ st, int *__restrict__ st_next,
+        const int *__restrict__ in_row, const int4 *__restrict__ rin,
+        const int4 *__restrict__ rcand, const int *__restrict__ st, int *__restrict__ st_next,
         int *__restrict__ partner, int *__restrict__ nfree, int *__restrict__ nfree_next)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -181,17 +246,17 @@ k_round(int n, const int *__restrict__ rp, const int *__restrict__ cj,
         int s1 = s0;
         if (s0 == kFree) {
             fr = true;
-            const int m = lowest_free_in(v, in_ptr, in_row, st);
+            const int m = lowest_free_in_rec(v, rin, in_ptr, in_row, st);
             if (m == kNone) {
-                const int p = first_free_cand(v, rp, cj, ncand, st);
+                const int p = first_free_cand_rec(v, rcand, rp, cj, ncand, st);
                 if (p < 0) {
                     s1 = kSingle;
-                } else if (lowest_free_in(p, in_ptr, in_row, st) == v) {
+                } else if (lowest_free_in_rec(p, rin, in_ptr, in_row, st) == v) {
                     s1 = kLow;
                     partner[v] = p;
                 }
-            } else if (lowest_free_in(m, in_ptr, in_row, st) == kNone &&
-                       first_free_cand(m, rp, cj, ncand, st) == v) {
+            } else if (lowest_free_in_rec(m, rin, in_ptr, in_row, st) == kNone &&
+                       first_free_cand_rec(m, rcand, rp, cj, ncand, st) == v) {
                 s1 = kHigh;
                 partner[v] = m;
             }
@@ -391,6 +456,7 @@ struct Chain {
     int *cj = nullptr, *ncand = nullptr, *partner = nullptr;
     int *state[2] = {nullptr, nullptr};  // round input / output, alternating
     int *in_ptr = nullptr, *in_row = nullptr;
+    int4 *rin = nullptr, *rcand = nullptr;  // per-row records of the two lists
     hipStream_t cap = nullptr;            // capture stream for the round batches
     int *pos = nullptr, *flag = nullptr, *cnt = nullptr, *tiles = nullptr, *ctr = nullptr;
     int *a1 = nullptr, *a2 = nullptr, *aggf = nullptr, *mem0 = nullptr, *mem1 = nullptr;
@@ -450,6 +516,9 @@ struct Chain {
         scan(cnt, in_ptr, n);
         k_in_fill<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, in_ptr, flag, in_row);
         launched();
+        k_records<<<nblocks(n), kThreads, 0, st>>>(n, L.rp, cj, ncand, in_ptr, in_row, rin,
+                                                   rcand);
+        launched();
         fill(state[0], kFree, n);
         fill(ctr, 0, 2);
         // kBatch rounds (an even number: the states end in state[0]) as one graph
@@ -461,7 +530,7 @@ struct Chain {
             for (int q = 0; q < kBatch; ++q) {
                 const int a = q & 1;
                 k_round<<<nblocks(n), kThreads, 0, cap>>>(
-                    n, L.rp, cj, ncand, in_ptr, in_row, state[a], state[a ^ 1], partner,
+                    n, L.rp, cj, ncand, in_ptr, in_row, rin, rcand, state[a], state[a ^ 1], partner,
                     q == kBatch - 1 ? ctr + 1 : nullptr, q == kBatch - 2 ? ctr + 1 : nullptr);
             }
             hipGraph_t g = nullptr;
@@ -578,6 +647,8 @@ size_t place(Chain &X, char *base, int n0, long long nnz0)
     X.tiles = (int *)take(ntiles, sizeof(int));
     X.ctr = (int *)take(4, sizeof(int));
     X.elig = (unsigned char *)take(n0, 1);
+    X.rin = (int4 *)take(n0, sizeof(int4));
+    X.rcand = (int4 *)take(n0, sizeof(int4));
     for (int k = 0; k < 3; ++k) {
         X.set[k].rp = (int *)take(n1, sizeof(int));
         X.set[k].ci = (int *)take(nnz0, sizeof(int));
