@@ -96,7 +96,10 @@ struct Level {
     float *val32 = nullptr, *diag32 = nullptr;
     int *perm_d = nullptr, *iperm_d = nullptr;
     int *agg_pos = nullptr, *mem_ptr = nullptr, *mem = nullptr;
-    std::vector<int> agg_pos_h, mem_ptr_h, mem_h;  // host sources of the three above
+    // the same maps in the coarse level's natural order (prepared before the
+    // coarse level's positions are known) and the host sources of uploads
+    int *natc_d = nullptr, *mptr_nat_d = nullptr, *mem_nat_d = nullptr;
+    std::vector<int> natc_h, mptr_nat_h, mem_nat_h, mem_ptr_h;
     void *f = nullptr, *x = nullptr, *r = nullptr;  // work vectors in the precond precision
 };
 
@@ -448,25 +451,44 @@ void build_level_device(msp_ctx *c, int l, bool last, LevelLayout *lay, const Le
                              c->copy_stream ? c->copy_stream : c->stream));
 }
 
+// The part of the maps between level l and level l + 1 that needs only
+// level l's positions (level l built): the coarse row of every fine
+// position, and the members of every coarse row (fine positions, natural
+// fine index ascending), both in the coarse level's natural order.
+void prepare_link(msp_ctx *c, int l, std::vector<void *> &tmp)
+{
+    Level &L = c->lev[l];
+    const int nc = L.nc;
+    L.natc_h.resize(L.n);
+    for (int t = 0; t < L.n; ++t) L.natc_h[t] = L.agg[L.iperm[t]];
+    std::vector<int> &mptr = L.mptr_nat_h, &mem = L.mem_nat_h;
+    mptr.assign(nc + 1, 0);
+    mem.resize(L.n);
+    for (int i = 0; i < L.n; ++i) ++mptr[L.agg[i] + 1];
+    for (int J = 0; J < nc; ++J) mptr[J + 1] += mptr[J];
+    std::vector<int> f(mptr.begin(), mptr.end() - 1);
+    for (int i = 0; i < L.n; ++i) mem[f[L.agg[i]]++] = L.perm[i];
+    L.natc_d = c->upload(L.natc_h, tmp);
+    L.mptr_nat_d = c->upload(mptr, tmp);
+    L.mem_nat_d = c->upload(mem, tmp);
+}
+
 // Aggregation maps between level l and level l + 1 in position space (both
-// levels' device arrays built).
+// levels built, level l's link prepared): the member offsets by coarse
+// position on the host, the rest on the device.
 void link_level(msp_ctx *c, int l)
 {
     Level &L = c->lev[l];
     const Level &C = c->lev[l + 1];
-    std::vector<int> &agg_pos = L.agg_pos_h, &mptr = L.mem_ptr_h, &mem = L.mem_h;
-    agg_pos.assign(L.n, 0);
-    for (int t = 0; t < L.n; ++t) agg_pos[t] = C.perm[L.agg[L.iperm[t]]];
-    // members of each coarse position, natural fine index ascending
+    std::vector<int> &mptr = L.mem_ptr_h;
     mptr.assign(C.n + 1, 0);
-    mem.assign(L.n, 0);
-    for (int i = 0; i < L.n; ++i) ++mptr[C.perm[L.agg[i]] + 1];
-    for (int J = 0; J < C.n; ++J) mptr[J + 1] += mptr[J];
-    std::vector<int> f(mptr.begin(), mptr.end() - 1);
-    for (int i = 0; i < L.n; ++i) mem[f[C.perm[L.agg[i]]]++] = L.perm[i];
-    L.agg_pos = c->upload(agg_pos, c->allocB);
+    for (int J = 0; J < C.n; ++J) mptr[C.perm[J] + 1] = L.mptr_nat_h[J + 1] - L.mptr_nat_h[J];
+    for (int P = 0; P < C.n; ++P) mptr[P + 1] += mptr[P];
     L.mem_ptr = c->upload(mptr, c->allocB);
-    L.mem = c->upload(mem, c->allocB);
+    L.agg_pos = (int *)c->dalloc(sizeof(int) * std::max(L.n, 1), c->allocB);
+    L.mem = (int *)c->dalloc(sizeof(int) * std::max(L.n, 1), c->allocB);
+    HIPCHK(launch_link(L.n, C.n, L.natc_d, L.mptr_nat_d, L.mem_nat_d, C.perm_d, L.mem_ptr,
+                       L.agg_pos, L.mem, c->copy_stream ? c->copy_stream : c->stream));
 }
 
 // Streams of the coarsest-level solver: the update stream and the stream of
@@ -1052,6 +1074,7 @@ void rebuild_B(msp_ctx *c, const double *vals)
                 phase(7);
             }
             build_level_device(c, l, l == nlev - 1, &lays[l], csr[l]);
+            if (l + 1 < nlev) prepare_link(c, l, tmp);
             built[l] = 1;
             if (l > 0 && built[l - 1]) link_level(c, l - 1);
             if (l + 1 < nlev && built[l + 1]) link_level(c, l);

@@ -113,6 +113,14 @@ hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *
                            hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st);
+// The restriction and prolongation maps of a level (n fine positions, nc
+// coarse rows) from their coarse-natural-order forms and the coarse level's
+// permutation cperm (natural -> position): agg_pos[t] = cperm[natc[t]], and
+// the member list of coarse row J (fine positions, mem_nat[mptr_nat[J] ..
+// mptr_nat[J+1])) copied to mem from mptr_pos[cperm[J]] on.
+hipError_t launch_link(int n, int nc, const int *natc, const int *mptr_nat, const int *mem_nat,
+                       const int *cperm, const int *mptr_pos, int *agg_pos, int *mem,
+                       hipStream_t st);
 // Coarsest-level solve x = A^-1 f = W (Y f) with the factors of
 // dense_inverse (row-major, leading dimension ld even, block size P even):
 // t = Y f (FP64 work vector of n entries), then x = W t.

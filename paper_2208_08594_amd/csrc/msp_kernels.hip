@@ -781,6 +781,27 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int n, const int *__restri
     x[t] += xc[agg_pos[t]];
 }
 
+// Maps between a level and the next coarser one in position space, from the
+// same maps in the coarse level's natural order: thread t < n sets
+// agg_pos[t] = cperm[natc[t]]; thread J < nc moves coarse row J's member list
+// (mem_nat[mptr_nat[J] .. mptr_nat[J+1])) to mem[mptr_pos[cperm[J]] ..].
+__global__ __launch_bounds__(kThreads) void k_link(int n, int nc, const int *__restrict__ natc,
+                                                   const int *__restrict__ mptr_nat,
+                                                   const int *__restrict__ mem_nat,
+                                                   const int *__restrict__ cperm,
+                                                   const int *__restrict__ mptr_pos,
+                                                   int *__restrict__ agg_pos,
+                                                   int *__restrict__ mem)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) agg_pos[i] = cperm[natc[i]];
+    if (i < nc) {
+        const int a = mptr_nat[i], b = mptr_nat[i + 1];
+        const int d = mptr_pos[cperm[i]] - a;
+        for (int k = a; k < b; ++k) mem[d + k] = mem_nat[k];
+    }
+}
+
 // x = Ainv f on the coarsest level, FP64 arithmetic, one wave per row; rows
 // are 16-byte aligned (ld even) so each lane streams pairs of doubles.
 // One triangle of the coarsest-level solve x = W (Y f), row-major FP64
@@ -1922,6 +1943,17 @@ template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st)
 {
     k_prolong<T><<<blocks_for(n), kThreads, 0, st>>>(n, agg_pos, xc, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_link(int n, int nc, const int *natc, const int *mptr_nat, const int *mem_nat,
+                       const int *cperm, const int *mptr_pos, int *agg_pos, int *mem,
+                       hipStream_t st)
+{
+    const int m = std::max(n, nc);
+    if (m <= 0) return hipSuccess;
+    k_link<<<blocks_for(m), kThreads, 0, st>>>(n, nc, natc, mptr_nat, mem_nat, cperm, mptr_pos,
+                                               agg_pos, mem);
     return hipGetLastError();
 }
 
