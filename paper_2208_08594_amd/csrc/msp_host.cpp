@@ -209,11 +209,15 @@ static bool bipartite_groups(const Adjacency &G, std::vector<int> &color, int &g
     return true;
 }
 
-int vertices_grouping(const Adjacency &G, std::vector<int> &color)
+// The greedy of Alg. 4.2 over the neighbour lists nb[ptr[u] .. ptr[u+1]):
+// with REL each entry holds w - u (16 bits: the arrays the greedy reads at
+// random then take about half the cache, which keeps it fast while other
+// host threads stream through memory), else w.  Cnt holds the counts of
+// uncoloured neighbours (at least the largest degree).
+template <bool REL, typename Off, typename Cnt>
+static int greedy_groups(const Adjacency &G, const Off *nb, int dmax, std::vector<int> &color)
 {
     const int n = G.n;
-    int g_bip = 0;
-    if (bipartite_groups(G, color, g_bip)) return g_bip;
     color.assign(n, 0);
     // Static priority: larger |S_i| first, smaller index on ties (Alg. 4.1 picks
     // any vertex of maximal |S_i|; the lowest index makes the choice unique).
@@ -221,8 +225,6 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     // ascending indices inside a bucket)
     std::vector<int> order(n);
     {
-        int dmax = 0;
-        for (int i = 0; i < n; ++i) dmax = std::max(dmax, G.degree(i));
         std::vector<int> start(dmax + 2, 0);
         for (int i = 0; i < n; ++i) ++start[dmax - G.degree(i) + 1];
         for (int d = 0; d <= dmax; ++d) start[d + 1] += start[d];
@@ -255,28 +257,24 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         --nqueued;
         return order[(w << 6) + b];
     };
-    // open: still in V; queued: already a second-ring candidate of this group;
-    // scanned: neighbourhood already enumerated for this group.  A vertex never
-    // re-enters V inside a group, so enumerating a neighbourhood a second time
-    // cannot add a candidate: each neighbourhood is scanned at most once per group.
     // per vertex: kOpen (in V), kQueued (already a second-ring candidate of this
     // group), kScanned (neighbourhood already enumerated for this group), in
-    // one byte so that each visit touches one cache line
+    // one byte so that each visit touches one cache line.  A vertex never
+    // re-enters V inside a group, so enumerating a neighbourhood a second time
+    // cannot add a candidate: each neighbourhood is scanned at most once per
+    // group.
     constexpr unsigned char kOpen = 1, kQueued = 2, kScanned = 4;
     std::vector<unsigned char> fl(n);
     // unc[u]: neighbours of u not yet in any group; a vertex with none has
     // nothing left to add to a second ring, so its neighbourhood is skipped
-    std::vector<int> unc(n);
-    int dmax = 0;
-    for (int u = 0; u < n; ++u) {
-        unc[u] = G.degree(u);
-        dmax = std::max(dmax, unc[u]);
-    }
+    std::vector<Cnt> unc(n);
+    for (int u = 0; u < n; ++u) unc[u] = (Cnt)G.degree(u);
     // second-ring vertices newly queued for one chosen vertex (each vertex is
     // queued at most once per group)
     std::vector<int> fresh((size_t)std::min<long long>((long long)dmax * dmax, n) + 1);
     unsigned char *F = fl.data();
-    const int *ptr = G.ptr.data(), *nb = G.nbr.data();
+    const int *ptr = G.ptr.data();
+    auto at = [nb](int u, int q) { return REL ? u + (int)nb[q] : (int)nb[q]; };
     int left = n, g = 0;
     while (left > 0) {
         ++g;  // one call of VerticesSplitting builds group g
@@ -306,7 +304,7 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             --left;
             const int p0 = ptr[v], p1 = ptr[v + 1];
             for (int q = p0; q < p1; ++q) {  // S_v leaves V (W-bar)
-                const int u = nb[q];
+                const int u = at(v, q);
                 __builtin_prefetch(&nb[ptr[u]]);  // read by the second ring below
                 --unc[u];
                 const unsigned char f = F[u];
@@ -318,12 +316,12 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
             // newly queued vertices collected, then pushed together.
             int k = 0;
             for (int q = p0; q < p1; ++q) {
-                const int u = nb[q];
+                const int u = at(v, q);
                 if ((F[u] & kScanned) || unc[u] == 0) continue;
                 F[u] |= kScanned;
                 const int e = ptr[u + 1];
                 for (int t = ptr[u]; t < e; ++t) {
-                    const int w = nb[t];
+                    const int w = at(u, t);
                     const unsigned char f = F[w];
                     const int take = (f & (kOpen | kQueued)) == kOpen;
                     F[w] = (unsigned char)(f | take * kQueued);
@@ -335,6 +333,37 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
         }
     }
     return g;
+}
+
+int vertices_grouping(const Adjacency &G, std::vector<int> &color)
+{
+    const int n = G.n;
+    int g_bip = 0;
+    if (bipartite_groups(G, color, g_bip)) return g_bip;
+    int dmax = 0;
+    for (int i = 0; i < n; ++i) dmax = std::max(dmax, G.degree(i));
+    // 16-bit neighbour offsets where every one fits (levels built from a mesh
+    // numbering: neighbours lie within a few planes)
+    const long long nnz = (long long)G.nbr.size();
+    std::unique_ptr<short[]> nb16(new short[std::max<long long>(nnz, 1)]);
+    const int parts = host_parts(n);
+    std::vector<unsigned char> fits(parts, 1);
+    for_chunks(n, parts, [&](int lo, int hi, int t) {
+        for (int u = lo; u < hi && fits[t]; ++u)
+            for (int q = G.ptr[u]; q < G.ptr[u + 1]; ++q) {
+                const int d = G.nbr[q] - u;
+                if (d < -32768 || d > 32767) {
+                    fits[t] = 0;
+                    break;
+                }
+                nb16[q] = (short)d;
+            }
+    });
+    const bool rel = dmax <= 65535 &&
+                     std::all_of(fits.begin(), fits.end(), [](unsigned char f) { return f != 0; });
+    if (rel) return greedy_groups<true, short, unsigned short>(G, nb16.get(), dmax, color);
+    nb16.reset();
+    return greedy_groups<false, int, int>(G, G.nbr.data(), dmax, color);
 }
 
 static inline double entry(const Csr &A, int i, int j)
