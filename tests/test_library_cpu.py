@@ -188,6 +188,31 @@ def test_library_grouping_large_symmetric_matches_oracle(shim, n):
     assert g_lib == g_or and np.array_equal(c_lib, c_or)
 
 
+@pytest.mark.parametrize("case", ["long_coupling", "hub"])
+def test_library_grouping_wide_graphs_match_oracle(shim, case):
+    """Graphs the greedy cannot hold in 16-bit neighbour offsets or counts:
+    one coupling 40,000 rows away in an otherwise local graph, and a vertex
+    with more than 65,535 neighbours (a triangle keeps both off the bipartite
+    closed form)."""
+    if case == "long_coupling":
+        n = 50000
+        rng = np.random.default_rng(7)
+        i = rng.integers(0, n - 300, 3 * n)
+        j = i + rng.integers(1, 300, 3 * n)
+        i = np.concatenate([i, [5, 5, 6]])
+        j = np.concatenate([j, [40005, 6, 40005]])
+    else:
+        n = 70000
+        i = np.concatenate([np.zeros(n - 1, dtype=np.int64), [1, 2]])
+        j = np.concatenate([np.arange(1, n), [2, 3]])
+        i = np.concatenate([i, [1]])
+        j = np.concatenate([j, [3]])
+    rp, ci = _pattern_from_edges(n, i, j)
+    c_lib, g_lib = _lib_color(shim, rp, ci)
+    c_or, g_or = O.color(rp, ci)
+    assert g_lib == g_or and np.array_equal(c_lib, c_or)
+
+
 def _pattern_from_edges(n, i, j, symmetric=True):
     """CSR pattern with a diagonal from an edge list (both directions if
     symmetric)."""
