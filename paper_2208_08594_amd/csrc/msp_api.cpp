@@ -975,8 +975,8 @@ void rebuild_B(msp_ctx *c, const double *vals)
         const bool sym = device_levels;
         work[l] = std::async(std::launch::async, [nl, rp, ci, sym]() {
             LevelWork W;
-            Adjacency adj = build_adjacency(nl, rp, ci, sym);
-            W.G.g = vertices_grouping(adj, W.G.color);
+            W.G.g = sym ? vertices_grouping_symmetric(nl, rp, ci, W.G.color)
+                        : vertices_grouping(build_adjacency(nl, rp, ci, false), W.G.color);
             level_layout(nl, rp, ci, W.G.color, W.G.g, W.lay);
             return W;
         });

@@ -215,9 +215,9 @@ static bool bipartite_groups(const Adjacency &G, std::vector<int> &color, int &g
 // host threads stream through memory), else w.  Cnt holds the counts of
 // uncoloured neighbours (at least the largest degree).
 template <bool REL, typename Off, typename Cnt>
-static int greedy_groups(const Adjacency &G, const Off *nb, int dmax, std::vector<int> &color)
+static int greedy_groups(int n, const int *ptr, const Off *nb, int dmax, std::vector<int> &color)
 {
-    const int n = G.n;
+    auto degree = [ptr](int i) { return ptr[i + 1] - ptr[i]; };
     color.assign(n, 0);
     // Static priority: larger |S_i| first, smaller index on ties (Alg. 4.1 picks
     // any vertex of maximal |S_i|; the lowest index makes the choice unique).
@@ -226,9 +226,9 @@ static int greedy_groups(const Adjacency &G, const Off *nb, int dmax, std::vecto
     std::vector<int> order(n);
     {
         std::vector<int> start(dmax + 2, 0);
-        for (int i = 0; i < n; ++i) ++start[dmax - G.degree(i) + 1];
+        for (int i = 0; i < n; ++i) ++start[dmax - degree(i) + 1];
         for (int d = 0; d <= dmax; ++d) start[d + 1] += start[d];
-        for (int i = 0; i < n; ++i) order[start[dmax - G.degree(i)]++] = i;
+        for (int i = 0; i < n; ++i) order[start[dmax - degree(i)]++] = i;
     }
     // Candidates W^ are taken in the same priority, i.e. smallest position in
     // `order` first: a two-level bit set over positions (words of 64
@@ -268,12 +268,11 @@ static int greedy_groups(const Adjacency &G, const Off *nb, int dmax, std::vecto
     // unc[u]: neighbours of u not yet in any group; a vertex with none has
     // nothing left to add to a second ring, so its neighbourhood is skipped
     std::vector<Cnt> unc(n);
-    for (int u = 0; u < n; ++u) unc[u] = (Cnt)G.degree(u);
+    for (int u = 0; u < n; ++u) unc[u] = (Cnt)degree(u);
     // second-ring vertices newly queued for one chosen vertex (each vertex is
     // queued at most once per group)
     std::vector<int> fresh((size_t)std::min<long long>((long long)dmax * dmax, n) + 1);
     unsigned char *F = fl.data();
-    const int *ptr = G.ptr.data();
     auto at = [nb](int u, int q) { return REL ? u + (int)nb[q] : (int)nb[q]; };
     int left = n, g = 0;
     while (left > 0) {
@@ -361,9 +360,54 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     });
     const bool rel = dmax <= 65535 &&
                      std::all_of(fits.begin(), fits.end(), [](unsigned char f) { return f != 0; });
-    if (rel) return greedy_groups<true, short, unsigned short>(G, nb16.get(), dmax, color);
+    if (rel)
+        return greedy_groups<true, short, unsigned short>(n, G.ptr.data(), nb16.get(), dmax, color);
     nb16.reset();
-    return greedy_groups<false, int, int>(G, G.nbr.data(), dmax, color);
+    return greedy_groups<false, int, int>(n, G.ptr.data(), G.nbr.data(), dmax, color);
+}
+
+int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color)
+{
+    // Off-diagonal lists straight from the pattern: when every row stores its
+    // diagonal exactly once, row u's neighbours go to [rp[u] - u,
+    // rp[u+1] - u - 1), ranges that are disjoint and cover [0, nnz - n).
+    // The groups of a bipartite graph come out of the greedy itself here (the
+    // closed form gives the same groups, only faster).
+    if (n <= 0) return vertices_grouping(build_adjacency(n, rp, ci, true), color);
+    const int parts = host_parts(n);
+    std::vector<unsigned char> ok(parts, 1);
+    std::vector<int> dpart(parts, 0);
+    for_chunks(n, parts, [&](int lo, int hi, int t) {
+        int dm = 0;
+        for (int u = lo; u < hi && ok[t]; ++u) {
+            int diag = 0;
+            for (int e = rp[u]; e < rp[u + 1]; ++e) {
+                const int d = ci[e] - u;
+                diag += d == 0;
+                if (d < -32768 || d > 32767) ok[t] = 0;
+            }
+            if (diag != 1) ok[t] = 0;
+            dm = std::max(dm, rp[u + 1] - rp[u] - 1);
+        }
+        dpart[t] = dm;
+    });
+    const int dmax = *std::max_element(dpart.begin(), dpart.end());
+    if (!std::all_of(ok.begin(), ok.end(), [](unsigned char f) { return f != 0; }) ||
+        dmax > 65535)
+        return vertices_grouping(build_adjacency(n, rp, ci, true), color);
+    const long long nadj = (long long)rp[n] - n;
+    std::unique_ptr<int[]> aptr(new int[(size_t)n + 1]);
+    std::unique_ptr<short[]> nb16(new short[(size_t)std::max<long long>(nadj, 1)]);
+    for_chunks(n, parts, [&](int lo, int hi, int) {
+        for (int u = lo; u < hi; ++u) {
+            int q = rp[u] - u;
+            aptr[u] = q;
+            for (int e = rp[u]; e < rp[u + 1]; ++e)
+                if (ci[e] != u) nb16[q++] = (short)(ci[e] - u);
+        }
+    });
+    aptr[n] = (int)nadj;
+    return greedy_groups<true, short, unsigned short>(n, aptr.get(), nb16.get(), dmax, color);
 }
 
 static inline double entry(const Csr &A, int i, int j)

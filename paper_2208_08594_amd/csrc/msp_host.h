@@ -92,6 +92,9 @@ bool pattern_symmetric(int n, const int *rp, const int *ci);
 // in 1..g, returns g.  Largest static degree first, lowest index on ties,
 // second-ring candidates before the rest.
 int vertices_grouping(const Adjacency &G, std::vector<int> &color);
+// The same groups for a structurally symmetric pattern (row_ptr, col_ind),
+// read without building the adjacency first.
+int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color);
 
 // One pairwise-matching pass; agg[i] in [0, nc), returns nc.
 int pairwise_pass(const Csr &A, std::vector<int> &agg);

@@ -17,6 +17,14 @@ int shim_color(int n, const int *rp, const int *ci, int *color)
     return g;
 }
 
+int shim_color_sym(int n, const int *rp, const int *ci, int *color)
+{
+    std::vector<int> c;
+    int g = msp::vertices_grouping_symmetric(n, rp, ci, c);
+    std::memcpy(color, c.data(), sizeof(int) * n);
+    return g;
+}
+
 static msp::Csr make(int n, const int *rp, const int *ci, const double *val)
 {
     msp::Csr A;

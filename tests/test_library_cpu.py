@@ -135,6 +135,7 @@ def shim():
     i32 = np.ctypeslib.ndpointer(np.int32, flags="C")
     f64 = np.ctypeslib.ndpointer(np.float64, flags="C")
     L.shim_color.argtypes = [C.c_int, i32, i32, i32]
+    L.shim_color_sym.argtypes = [C.c_int, i32, i32, i32]
     L.shim_hierarchy.argtypes = [C.c_int, i32, i32, f64, C.c_int, i32, i32, i32, i32, f64]
     L.shim_pair.argtypes = [C.c_int, i32, i32, f64, i32]
     L.shim_galerkin.argtypes = [C.c_int, i32, i32, f64, i32, C.c_int, i32, i32, f64]
@@ -225,6 +226,60 @@ def _pattern_from_edges(n, i, j, symmetric=True):
     rp = np.zeros(n + 1, dtype=np.int32)
     np.add.at(rp, r + 1, 1)
     return np.cumsum(rp).astype(np.int32), c.astype(np.int32)
+
+
+def _symmetric_cases():
+    """Structurally symmetric patterns with their diagonals: grids (bipartite
+    7-point, 27-point), random local graphs, and graphs the 16-bit lists
+    cannot hold (a long coupling, a row without its diagonal)."""
+    cases = []
+    rp, ci, _ = synth.poisson_csr((9, 7, 5))
+    cases.append(("7-point", rp, ci))
+    n3 = (6, 5, 4)
+    idx = np.arange(np.prod(n3)).reshape(n3)
+    i, j = [], []
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                a = idx[max(0, -dx):n3[0] - max(0, dx), max(0, -dy):n3[1] - max(0, dy),
+                        max(0, -dz):n3[2] - max(0, dz)]
+                b = idx[max(0, dx):n3[0] + min(0, dx), max(0, dy):n3[1] + min(0, dy),
+                        max(0, dz):n3[2] + min(0, dz)]
+                i.append(a.ravel())
+                j.append(b.ravel())
+    rp, ci = _pattern_from_edges(idx.size, np.concatenate(i), np.concatenate(j))
+    cases.append(("27-point", rp, ci))
+    for seed, n in [(3, 3000), (4, 50000)]:
+        rng = np.random.default_rng(seed)
+        a = rng.integers(0, n - 40, 4 * n)
+        rp, ci = _pattern_from_edges(n, a, a + rng.integers(1, 40, 4 * n))
+        cases.append((f"random local {n}", rp, ci))
+    n = 50000
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, n - 300, 3 * n)
+    rp, ci = _pattern_from_edges(n, np.concatenate([a, [5, 5, 6]]),
+                                 np.concatenate([a + rng.integers(1, 300, 3 * n), [40005, 6, 40005]]))
+    cases.append(("long coupling", rp, ci))
+    rp, ci = _pattern_from_edges(200, np.arange(199), np.arange(1, 200))
+    keep = np.ones(len(ci), bool)
+    keep[rp[100]:rp[101]] = ci[rp[100]:rp[101]] != 100  # row 100 without its diagonal
+    ci2 = ci[keep]
+    rp2 = rp.copy()
+    rp2[101:] -= 1
+    cases.append(("missing diagonal", rp2, ci2))
+    return cases
+
+
+@pytest.mark.parametrize("case", _symmetric_cases(), ids=lambda c: c[0])
+def test_library_grouping_from_symmetric_pattern_matches_oracle(shim, case):
+    """Groups read straight from a structurally symmetric pattern (the
+    coarse levels of the device chain) equal the oracle's."""
+    _, rp, ci = case
+    n = len(rp) - 1
+    col = np.zeros(n, dtype=np.int32)
+    g = shim.shim_color_sym(n, rp, ci, col)
+    c_or, g_or = O.color(rp, ci)
+    assert g == g_or and np.array_equal(col, c_or)
 
 
 def _bipartite_cases():
