@@ -358,7 +358,7 @@ struct LevelLayout {
 };
 
 void level_layout(int n, const int *rp, const int *ci, const std::vector<int> &color, int g,
-                  LevelLayout &O)
+                  LevelLayout &O, bool diag_once = false)
 {
     O.perm.assign(n, 0);
     O.iperm.assign(n, 0);
@@ -374,16 +374,24 @@ void level_layout(int n, const int *rp, const int *ci, const std::vector<int> &c
             O.iperm[t] = i;
         }
     }
-    // off-diagonal entries of the row at each position
+    // off-diagonal entries of the row at each position (diag_once: every row
+    // is known to hold its diagonal exactly once)
     std::vector<int> cnt(n);
-    for_chunks(n, host_parts(n), [&](int lo, int hi, int) {
-        for (int t = lo; t < hi; ++t) {
+    if (diag_once) {
+        for (int t = 0; t < n; ++t) {
             const int i = O.iperm[t];
-            int m = 0;
-            for (int k = rp[i]; k < rp[i + 1]; ++k) m += ci[k] != i;
-            cnt[t] = m;
+            cnt[t] = rp[i + 1] - rp[i] - 1;
         }
-    });
+    } else {
+        for_chunks(n, host_parts(n), [&](int lo, int hi, int) {
+            for (int t = lo; t < hi; ++t) {
+                const int i = O.iperm[t];
+                int m = 0;
+                for (int k = rp[i]; k < rp[i + 1]; ++k) m += ci[k] != i;
+                cnt[t] = m;
+            }
+        });
+    }
     sell_slices(n, O.seg_row, cnt, O.lay);
 }
 
@@ -975,9 +983,10 @@ void rebuild_B(msp_ctx *c, const double *vals)
         const bool sym = device_levels;
         work[l] = std::async(std::launch::async, [nl, rp, ci, sym]() {
             LevelWork W;
-            W.G.g = sym ? vertices_grouping_symmetric(nl, rp, ci, W.G.color)
+            bool diag_once = false;
+            W.G.g = sym ? vertices_grouping_symmetric(nl, rp, ci, W.G.color, &diag_once)
                         : vertices_grouping(build_adjacency(nl, rp, ci, false), W.G.color);
-            level_layout(nl, rp, ci, W.G.color, W.G.g, W.lay);
+            level_layout(nl, rp, ci, W.G.color, W.G.g, W.lay, diag_once);
             return W;
         });
     };

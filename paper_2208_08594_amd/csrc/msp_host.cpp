@@ -366,8 +366,10 @@ int vertices_grouping(const Adjacency &G, std::vector<int> &color)
     return greedy_groups<false, int, int>(n, G.ptr.data(), G.nbr.data(), dmax, color);
 }
 
-int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color)
+int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color,
+                                bool *diag_once)
 {
+    if (diag_once) *diag_once = false;
     // Off-diagonal lists straight from the pattern: when every row stores its
     // diagonal exactly once, row u's neighbours go to [rp[u] - u,
     // rp[u+1] - u - 1), ranges that are disjoint and cover [0, nnz - n).
@@ -395,6 +397,7 @@ int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector
     if (!std::all_of(ok.begin(), ok.end(), [](unsigned char f) { return f != 0; }) ||
         dmax > 65535)
         return vertices_grouping(build_adjacency(n, rp, ci, true), color);
+    if (diag_once) *diag_once = true;
     const long long nadj = (long long)rp[n] - n;
     std::unique_ptr<int[]> aptr(new int[(size_t)n + 1]);
     std::unique_ptr<short[]> nb16(new short[(size_t)std::max<long long>(nadj, 1)]);

@@ -93,8 +93,11 @@ bool pattern_symmetric(int n, const int *rp, const int *ci);
 // second-ring candidates before the rest.
 int vertices_grouping(const Adjacency &G, std::vector<int> &color);
 // The same groups for a structurally symmetric pattern (row_ptr, col_ind),
-// read without building the adjacency first.
-int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color);
+// read without building the adjacency first.  *diag_once (if given) is set
+// when every row was found to hold its diagonal exactly once (always false
+// on the fallback path, which does not check).
+int vertices_grouping_symmetric(int n, const int *rp, const int *ci, std::vector<int> &color,
+                                bool *diag_once = nullptr);
 
 // One pairwise-matching pass; agg[i] in [0, nc), returns nc.
 int pairwise_pass(const Csr &A, std::vector<int> &agg);

@@ -17,11 +17,13 @@ int shim_color(int n, const int *rp, const int *ci, int *color)
     return g;
 }
 
-int shim_color_sym(int n, const int *rp, const int *ci, int *color)
+int shim_color_sym(int n, const int *rp, const int *ci, int *color, int *diag_once)
 {
     std::vector<int> c;
-    int g = msp::vertices_grouping_symmetric(n, rp, ci, c);
+    bool d = false;
+    int g = msp::vertices_grouping_symmetric(n, rp, ci, c, &d);
     std::memcpy(color, c.data(), sizeof(int) * n);
+    *diag_once = d ? 1 : 0;
     return g;
 }
 

@@ -135,7 +135,7 @@ def shim():
     i32 = np.ctypeslib.ndpointer(np.int32, flags="C")
     f64 = np.ctypeslib.ndpointer(np.float64, flags="C")
     L.shim_color.argtypes = [C.c_int, i32, i32, i32]
-    L.shim_color_sym.argtypes = [C.c_int, i32, i32, i32]
+    L.shim_color_sym.argtypes = [C.c_int, i32, i32, i32, i32]
     L.shim_hierarchy.argtypes = [C.c_int, i32, i32, f64, C.c_int, i32, i32, i32, i32, f64]
     L.shim_pair.argtypes = [C.c_int, i32, i32, f64, i32]
     L.shim_galerkin.argtypes = [C.c_int, i32, i32, f64, i32, C.c_int, i32, i32, f64]
@@ -273,13 +273,21 @@ def _symmetric_cases():
 @pytest.mark.parametrize("case", _symmetric_cases(), ids=lambda c: c[0])
 def test_library_grouping_from_symmetric_pattern_matches_oracle(shim, case):
     """Groups read straight from a structurally symmetric pattern (the
-    coarse levels of the device chain) equal the oracle's."""
-    _, rp, ci = case
+    coarse levels of the device chain) equal the oracle's; the report that
+    every row holds its diagonal once (which lets the level layout count
+    entries from the row lengths) is given exactly when it is true and the
+    16-bit lists were used."""
+    name, rp, ci = case
     n = len(rp) - 1
     col = np.zeros(n, dtype=np.int32)
-    g = shim.shim_color_sym(n, rp, ci, col)
+    diag_once = np.zeros(1, dtype=np.int32)
+    g = shim.shim_color_sym(n, rp, ci, col, diag_once)
     c_or, g_or = O.color(rp, ci)
     assert g == g_or and np.array_equal(col, c_or)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    one_diag = bool(np.all(np.bincount(rows[ci == rows], minlength=n) == 1))
+    assert one_diag == (name != "missing diagonal")
+    assert bool(diag_once[0]) == (one_diag and name != "long coupling")
 
 
 def _bipartite_cases():
