@@ -1145,8 +1145,10 @@ const float *lev_diag<float>(const Level &L) { return L.diag32; }
 // nu smoothing sweeps on level L (x in place; from_zero: x starts at 0).
 // PGS-MC runs colors 1..g (forward) or g..1 (backward) per sweep, Alg. 4.3;
 // point Jacobi is direction-free and uses L.r for its residual.
+// first_done: the first color of the first forward sweep from zero has
+// already been applied (by the restriction into this level).
 template <typename T>
-void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero, int nu)
+void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero, int nu, bool first_done = false)
 {
     T *f = (T *)L.f, *x = (T *)L.x;
     const T *val = lev_val<T>(L);
@@ -1172,8 +1174,9 @@ void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero, int nu)
         if (forward) {
             int g0 = 0;
             if (from_zero && s == 0) {
-                HIPCHK(launch_gs_first<T>(L.S.all(), L.n, diag, f, x, L.seg_row[0], L.seg_row[1],
-                                          c->stream));
+                if (!first_done)
+                    HIPCHK(launch_gs_first<T>(L.S.all(), L.n, diag, f, x, L.seg_row[0],
+                                              L.seg_row[1], c->stream));
                 g0 = 1;
             }
             for (int g = g0; g < L.g; ++g)
@@ -1185,8 +1188,9 @@ void smooth(msp_ctx *c, Level &L, bool forward, bool from_zero, int nu)
     }
 }
 
+// first_done: level l's first pre-smoothing color is already applied.
 template <typename T>
-void vcycle(msp_ctx *c, int l)
+void vcycle(msp_ctx *c, int l, bool first_done = false)
 {
     Level &L = c->lev[l];
     if (l == (int)c->lev.size() - 1) {
@@ -1195,11 +1199,20 @@ void vcycle(msp_ctx *c, int l)
         return;
     }
     Level &C = c->lev[l + 1];
-    smooth<T>(c, L, true, true, c->opt.nu_pre);
+    smooth<T>(c, L, true, true, c->opt.nu_pre, first_done);
     HIPCHK(launch_residual<T>(L.S.all(), lev_val<T>(L), lev_diag<T>(L), (const T *)L.f,
                               (const T *)L.x, (T *)L.r, c->stream));
-    HIPCHK(launch_restrict<T>(C.n, L.mem_ptr, L.mem, (const T *)L.r, (T *)C.f, c->stream));
-    vcycle<T>(c, l + 1);
+    // a smoothed coarse level whose pre-smoothing starts with a Gauss-Seidel
+    // color from zero gets that color from the restriction itself
+    const bool fuse = l + 1 < (int)c->lev.size() - 1 && c->opt.smoother == 0 &&
+                      c->opt.nu_pre > 0 && C.g > 0;
+    if (fuse)
+        HIPCHK(launch_restrict_first<T>(C.n, L.mem_ptr, L.mem, (const T *)L.r, (T *)C.f,
+                                        C.seg_row[0], C.seg_row[1], lev_diag<T>(C), (T *)C.x,
+                                        c->stream));
+    else
+        HIPCHK(launch_restrict<T>(C.n, L.mem_ptr, L.mem, (const T *)L.r, (T *)C.f, c->stream));
+    vcycle<T>(c, l + 1, fuse);
     HIPCHK(launch_prolong<T>(L.n, L.agg_pos, (const T *)C.x, (T *)L.x, c->stream));
     smooth<T>(c, L, false, false, c->opt.nu_post);
 }

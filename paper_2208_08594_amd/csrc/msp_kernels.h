@@ -111,6 +111,11 @@ hipError_t launch_residual(const SellView &all, const T *val, const T *diag, con
 template <typename T>
 hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *r, T *fc,
                            hipStream_t st);
+// launch_restrict, then the first color [p0, p1) of the coarse level's forward
+// sweep from x = 0 (xc = fc / diag_c there, 0 elsewhere), in one launch.
+template <typename T>
+hipError_t launch_restrict_first(int nc, const int *mem_ptr, const int *mem, const T *r, T *fc,
+                                 int p0, int p1, const T *diag_c, T *xc, hipStream_t st);
 template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st);
 // The restriction and prolongation maps of a level (n fine positions, nc

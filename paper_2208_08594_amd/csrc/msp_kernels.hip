@@ -771,6 +771,24 @@ __global__ __launch_bounds__(kThreads) void k_restrict(int nc, const int *__rest
     fc[J] = s;
 }
 
+// k_restrict, then the first color of the coarse level's forward sweep from
+// x = 0 (k_gs_first): the same two results, in one pass.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict_first(int nc, const int *__restrict__ mem_ptr,
+                                                             const int *__restrict__ mem,
+                                                             const T *__restrict__ r,
+                                                             T *__restrict__ fc, int p0, int p1,
+                                                             const T *__restrict__ diag_c,
+                                                             T *__restrict__ xc)
+{
+    int J = blockIdx.x * kThreads + threadIdx.x;
+    if (J >= nc) return;
+    T s = 0;
+    for (int m = mem_ptr[J]; m < mem_ptr[J + 1]; ++m) s += r[mem[m]];
+    fc[J] = s;
+    xc[J] = (J >= p0 && J < p1) ? s / diag_c[J] : T(0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_prolong(int n, const int *__restrict__ agg_pos,
                                                       const T *__restrict__ xc,
@@ -1940,6 +1958,15 @@ hipError_t launch_restrict(int nc, const int *mem_ptr, const int *mem, const T *
 }
 
 template <typename T>
+hipError_t launch_restrict_first(int nc, const int *mem_ptr, const int *mem, const T *r, T *fc,
+                                 int p0, int p1, const T *diag_c, T *xc, hipStream_t st)
+{
+    k_restrict_first<T><<<blocks_for(nc), kThreads, 0, st>>>(nc, mem_ptr, mem, r, fc, p0, p1,
+                                                              diag_c, xc);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_prolong(int n, const int *agg_pos, const T *xc, T *x, hipStream_t st)
 {
     k_prolong<T><<<blocks_for(n), kThreads, 0, st>>>(n, agg_pos, xc, x);
@@ -2159,6 +2186,8 @@ hipError_t launch_from_double(long long n, const double *x, T *y, hipStream_t st
                                            const T *, T *, hipStream_t);                       \
     template hipError_t launch_restrict<T>(int, const int *, const int *, const T *, T *,      \
                                            hipStream_t);                                       \
+    template hipError_t launch_restrict_first<T>(int, const int *, const int *, const T *, T *, \
+                                                 int, int, const T *, T *, hipStream_t);       \
     template hipError_t launch_prolong<T>(int, const int *, const T *, T *, hipStream_t);      \
     template hipError_t launch_jacobi_first<T>(int, T, const T *, const T *, T *, hipStream_t); \
     template hipError_t launch_jacobi_update<T>(int, T, const T *, const T *, T *, hipStream_t); \
