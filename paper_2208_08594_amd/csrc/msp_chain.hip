@@ -226,7 +226,7 @@ __device__ inline int first_free_cand_rec(int v, const int4 *__restrict__ rcand,
 // ends.  A free row with no free lower row pointing at it and no free
 // candidate stays alone.  Every row evaluates this from the round's input
 // states (st) and writes only its own output state (st_next), so the two
-// ends of a taken edge reach the same verdict independently.  If nfree is
+// ends of a taken edge reach the same decision independently.  If nfree is
 // set, the free rows of the input are counted into it (the host reads the
 // count of one round per batch only: counting in every round would put
 // thousands of atomics on one address each time); a set nfree_next is
