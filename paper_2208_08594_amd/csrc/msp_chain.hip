@@ -774,62 +774,64 @@ int device_hierarchy(Csr &A0, const int *rp0, const int *ci0, const double *val0
             pending = std::async(std::launch::async, [&hn, &hagg, nf, Cd, aggf, ready, copy_st,
                                                       hip_fail, call, lnext, &on_smoothed, stg,
                                                       dev_done]() {
-              bool signalled = false;
-              try {
-                hagg.resize(nf);
-                hn.rp.resize(Cd.n + 1);
-                auto ck = [hip_fail](hipError_t e) {
-                    if (e != hipSuccess) {
-                        (void)hipGetLastError();
-                        hip_fail(e);
+                bool signalled = false;
+                try {
+                    hagg.resize(nf);
+                    hn.rp.resize(Cd.n + 1);
+                    auto ck = [hip_fail](hipError_t e) {
+                        if (e != hipSuccess) {
+                            (void)hipGetLastError();
+                            hip_fail(e);
+                        }
+                    };
+                    ck(hipStreamWaitEvent(copy_st, ready, 0));
+                    ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
+                                      hipMemcpyDeviceToHost, copy_st));
+                    ck(hipStreamSynchronize(copy_st));
+                    const long long nnzc = hn.rp[Cd.n];
+                    hn.ci.resize(nnzc);
+                    hn.val.resize(nnzc);
+                    // page-locked staging: [ci | val | agg], one DMA each
+                    char *sb = stg ? (char *)(*stg)(lnext, sizeof(int) * (size_t)nnzc +
+                                                               sizeof(double) * (size_t)nnzc +
+                                                               sizeof(int) * (size_t)nf)
+                                   : nullptr;
+                    int *sci = sb ? (int *)sb : hn.ci.data();
+                    double *sval =
+                        sb ? (double *)(sb + sizeof(int) * (size_t)nnzc) : hn.val.data();
+                    int *sagg = sb ? (int *)(sb + (sizeof(int) + sizeof(double)) * (size_t)nnzc)
+                                   : hagg.data();
+                    // the pattern first: the level's host work (its groups) needs
+                    // only that, and starts while the rest is copied
+                    if (nnzc)
+                        ck(hipMemcpyAsync(sci, Cd.ci, sizeof(int) * nnzc, hipMemcpyDeviceToHost,
+                                          copy_st));
+                    ck(hipStreamSynchronize(copy_st));
+                    if (call) on_smoothed(lnext, hn.n, hn.rp.data(), sci);
+                    if (nnzc)
+                        ck(hipMemcpyAsync(sval, Cd.val, sizeof(double) * nnzc,
+                                          hipMemcpyDeviceToHost, copy_st));
+                    ck(hipMemcpyAsync(sagg, aggf, sizeof(int) * nf, hipMemcpyDeviceToHost,
+                                      copy_st));
+                    // H grows on the main thread once the device reads are done:
+                    // the destinations are taken here (moving a vector keeps its
+                    // storage)
+                    int *dci = hn.ci.data(), *dagg = hagg.data();
+                    double *dval = hn.val.data();
+                    if (sb) std::memcpy(dci, sci, sizeof(int) * (size_t)nnzc);
+                    ck(hipStreamSynchronize(copy_st));
+                    signalled = true;
+                    dev_done->set_value();
+                    if (sb) {
+                        std::memcpy(dval, sval, sizeof(double) * (size_t)nnzc);
+                        std::memcpy(dagg, sagg, sizeof(int) * (size_t)nf);
                     }
-                };
-                ck(hipStreamWaitEvent(copy_st, ready, 0));
-                ck(hipMemcpyAsync(hn.rp.data(), Cd.rp, sizeof(int) * (Cd.n + 1),
-                                  hipMemcpyDeviceToHost, copy_st));
-                ck(hipStreamSynchronize(copy_st));
-                const long long nnzc = hn.rp[Cd.n];
-                hn.ci.resize(nnzc);
-                hn.val.resize(nnzc);
-                // page-locked staging: [ci | val | agg], one DMA each
-                char *sb = stg ? (char *)(*stg)(lnext, sizeof(int) * (size_t)nnzc +
-                                                           sizeof(double) * (size_t)nnzc +
-                                                           sizeof(int) * (size_t)nf)
-                               : nullptr;
-                int *sci = sb ? (int *)sb : hn.ci.data();
-                double *sval = sb ? (double *)(sb + sizeof(int) * (size_t)nnzc) : hn.val.data();
-                int *sagg = sb ? (int *)(sb + (sizeof(int) + sizeof(double)) * (size_t)nnzc)
-                               : hagg.data();
-                // the pattern first: the level's host work (its groups) needs
-                // only that, and starts while the rest is copied
-                if (nnzc)
-                    ck(hipMemcpyAsync(sci, Cd.ci, sizeof(int) * nnzc, hipMemcpyDeviceToHost,
-                                      copy_st));
-                ck(hipStreamSynchronize(copy_st));
-                if (call) on_smoothed(lnext, hn.n, hn.rp.data(), sci);
-                if (nnzc)
-                    ck(hipMemcpyAsync(sval, Cd.val, sizeof(double) * nnzc, hipMemcpyDeviceToHost,
-                                      copy_st));
-                ck(hipMemcpyAsync(sagg, aggf, sizeof(int) * nf, hipMemcpyDeviceToHost, copy_st));
-                // H grows on the main thread once the device reads are done:
-                // the destinations are taken here (moving a vector keeps its
-                // storage)
-                int *dci = hn.ci.data(), *dagg = hagg.data();
-                double *dval = hn.val.data();
-                if (sb) std::memcpy(dci, sci, sizeof(int) * (size_t)nnzc);
-                ck(hipStreamSynchronize(copy_st));
-                signalled = true;
-                dev_done->set_value();
-                if (sb) {
-                    std::memcpy(dval, sval, sizeof(double) * (size_t)nnzc);
-                    std::memcpy(dagg, sagg, sizeof(int) * (size_t)nf);
+                } catch (...) {
+                    if (signalled) throw;
+                    (void)hipStreamSynchronize(copy_st);
+                    (void)hipGetLastError();
+                    dev_done->set_exception(std::current_exception());
                 }
-              } catch (...) {
-                if (signalled) throw;
-                (void)hipStreamSynchronize(copy_st);
-                (void)hipGetLastError();
-                dev_done->set_exception(std::current_exception());
-              }
             });
         }
         main_calls = !next_smoothed;
